@@ -1,0 +1,198 @@
+"""Throughput of the SPIDER hot path on one MI355X.
+
+One step = minibatch selection, travel-time network forward and source
+gradient, residuals, exact whitening, per-event reduction, priors and the
+pSGLD update with Philox noise, for every chain (all rows of the hot path).
+Metric: double-difference observation likelihood-gradient evaluations per
+second = chains x batch x steps / wall time, with the catalog resident in HBM.
+
+Prints one JSON line.  The default workload is the 200k-event clustered
+catalog (~200M observations, 6->256x6->1 network, batch 2^20, 8 chains).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"bf16": 2500.0, "fp32": 157.3}       # TFLOP/s, MI355X dense
+HBM_PEAK = 8000.0                             # GB/s
+
+
+def flops_per_eval(H, D):
+    """Matrix flops of one travel-time evaluation, forward + source gradient:
+    first layer 12H, D-1 hidden layers 2H^2 each way, output 2H, input
+    gradient 6H + 2H."""
+    return 4 * (D - 1) * H * H + 22 * H
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="clustered200k")
+    ap.add_argument("--precision", default="auto", choices=["auto", "bf16", "fp32", "both"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-batch", type=int, default=1 << 20)
+    ap.add_argument("--seed", type=int, default=20250817)
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def run_precision(ctx, spider, cid, nid, wl, prec, steps, warmup, seed):
+    import torch
+    sets = [(cid, nid, wl.chains, wl.batch, prec)]
+    ctx.reset_chains(cid, wl.chains)
+    ctx.sgld_steps(sets, warmup, step=wl.step_size, seed=seed)
+    ctx.sync()
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    ctx.sgld_steps(sets, steps, step=wl.step_size, seed=seed)
+    ctx.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms, launches, rows = ctx.profile_read()
+    ctx.profile(False)
+    return t1 - t0, ms, launches, rows
+
+
+def sample_error(ctx, spider, cat, net, nid, prec, rows=4096, seed=5):
+    """Travel time and gradient error against the oracle on sampled batch rows."""
+    import numpy as np
+    import torch
+
+    from oracle import travel_time as ott
+    rng = np.random.default_rng(seed)
+    obs = rng.integers(0, cat.N, rows)
+    pr = cat.obs_pair[obs]
+    ev = np.where(rng.random(rows) < 0.5, cat.pair_i[pr], cat.pair_j[pr])
+    x = cat.hypo0[ev, 0:3]
+    s = cat.stations[cat.obs_sta[obs]]
+    T = torch.empty(rows, dtype=torch.float64, device="cuda")
+    g = torch.empty(rows, 3, dtype=torch.float64, device="cuda")
+    ctx.travel_time(nid, torch.tensor(x, device="cuda"), torch.tensor(s, device="cuda"), T, g,
+                    precision=prec)
+    Tw, gw = ott.travel_time(net, x, s)
+    T, g = T.cpu().numpy(), g.cpu().numpy()
+    return {"T_rel_max": float(np.max(np.abs(T - Tw) / Tw)),
+            "gradT_rel_max": float(np.max(np.linalg.norm(g - gw, axis=1)
+                                          / np.linalg.norm(gw, axis=1))),
+            "rows": rows}
+
+
+def cpu_baseline(cat, net, n, seed):
+    """The FP64 oracle, as it stands, on one chain step with a batch of n."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    from oracle import likelihood as lk
+    from oracle import sampler
+    prob = lk.load(cat)
+    cfg = sampler.SamplerConfig(step=cat.wl.step_size, seed=seed)
+    ch = sampler.new_chain(prob)
+    sampler.step(prob, net, ch, cfg, 0, 0, n)          # first call warms caches
+    t0 = time.perf_counter()
+    sampler.step(prob, net, ch, cfg, 0, 0, n)
+    dt = time.perf_counter() - t0
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    return {"value": n / dt, "unit": "dd-obs/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"one pSGLD step of 1 chain, batch {n} of the same catalog and network, "
+                      f"exact whitening, FP64 numpy ({dt:.1f} s)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
+              "(the multi-GPU path is a design, see the sharding notes).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2508_12117_amd import spider, synth
+    wl = synth.WORKLOADS[args.workload]
+    t = time.perf_counter()
+    cat = synth.make_catalog(args.workload)
+    net = synth.net_for(cat)
+    log(f"generated {args.workload}: M={cat.M} N={cat.N} in {time.perf_counter() - t:.1f}s")
+    ctx = spider.Context(0)
+    t = time.perf_counter()
+    cid = ctx.load_catalog(cat, whiten=spider.WHITEN_EXACT)
+    nid = ctx.load_net(net)
+    log(f"loaded in {time.perf_counter() - t:.1f}s")
+
+    bf16_ok = spider.lib() is not None and _bf16_supported(ctx, nid)
+    if args.precision == "auto":
+        precs = ["bf16", "fp32"] if bf16_ok else ["fp32"]
+    elif args.precision == "both":
+        precs = ["bf16", "fp32"]
+    else:
+        precs = [args.precision]
+    res = {}
+    for p in precs:
+        code = spider.BF16 if p == "bf16" else spider.FP32
+        wall, ms, launches, rows = run_precision(ctx, spider, cid, nid, wl, code, args.steps,
+                                                 args.warmup, args.seed)
+        dd = wl.chains * wl.batch * args.steps
+        fl = flops_per_eval(wl.H, wl.D)
+        avg_ms = ms / max(launches, 1)
+        achieved = rows / max(launches, 1) * fl / (avg_ms * 1e-3) / 1e12
+        res[p] = dict(value=dd / wall, ms_per_step=wall * 1e3 / args.steps, net_ms=ms,
+                      net_launches=launches, net_avg_ms=avg_ms, achieved=achieved,
+                      error=sample_error(ctx, spider, cat, net, nid, code))
+        log(f"{p}: {dd / wall:.4g} dd-obs/s, {wall * 1e3 / args.steps:.2f} ms/step, network "
+            f"{avg_ms:.3f} ms/launch = {achieved:.2f} TFLOP/s")
+    head = precs[0]
+    r = res[head]
+    line = {
+        "metric": "dd-obs likelihood-gradient evals/s, BF16-MFMA vs FP32 path, at stated error",
+        "value": r["value"], "unit": "dd-obs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": head, "data": "synthetic",
+        "config": {"workload": args.workload, "events": cat.M, "stations": cat.L,
+                   "observations": cat.N, "batch": wl.batch, "chains": wl.chains,
+                   "net": f"6-{wl.H}x{wl.D}-1 tanh", "whiten": "exact", "sampler": "pSGLD",
+                   "state": "fp64"},
+        "roofline": {"bound": "mfma", "kernel": "travel-time network (forward + source "
+                     "gradient)", "achieved": r["achieved"], "peak": PEAK[head],
+                     "unit": "TFLOP/s", "frac": r["achieved"] / PEAK[head], "traffic": None},
+        "paths": {p: {"value": v["value"], "ms_per_step": v["ms_per_step"],
+                      "network_ms_per_launch": v["net_avg_ms"],
+                      "network_tflops": v["achieved"], "error_vs_oracle": v["error"]}
+                  for p, v in res.items()},
+    }
+    if not args.no_cpu_baseline:
+        t = time.perf_counter()
+        line["cpu_baseline"] = cpu_baseline(cat, net, args.cpu_batch, args.seed)
+        log(f"cpu baseline in {time.perf_counter() - t:.1f}s")
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+def _bf16_supported(ctx, nid):
+    import torch
+
+    from paper_2508_12117_amd import spider
+    x = torch.zeros(1, 3, dtype=torch.float64, device="cuda")
+    s = torch.ones(1, 3, dtype=torch.float64, device="cuda")
+    T = torch.empty(1, dtype=torch.float64, device="cuda")
+    try:
+        ctx.travel_time(nid, x, s, T, precision=spider.BF16)
+        return True
+    except spider.SpiderError as e:
+        if e.code == spider.E_UNSUPPORTED:
+            return False
+        raise
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,276 @@
+/*
+ * spider.h - C ABI of libspider, the MI355X (gfx950) hot path of SPIDER,
+ * "Scalable Probabilistic Inference for Differential Earthquake Relocation"
+ * (Ross, Wilding, Azizzadenesheli, Kato; arXiv 2508.12117).
+ *
+ * One step of the path, for every chain of a catalog:
+ *   minibatch of n double-difference observations (Sec. 3.2, N/n batches
+ *   per epoch) -> travel times T(x; s) and source gradients from a neural
+ *   travel-time network (Sec. 3.2, EikoNet; any differentiable T, Sec. 5) ->
+ *   residuals r = tau - [T(x_i;s) - T(x_j;s) + t_i - t_j] (Eq. 1,
+ *   eq:forwardmodel) -> whitening z = Sigma_B^{-1} r with the marginal
+ *   covariance of eq:marginal_sigma and the weights of eq:correlation_decay
+ *   (Sec. 3.1) -> per-event gradient of the 4 parameters (x, y, z, t), scaled
+ *   by N/n (eq:sgd) plus event and centroid priors (Sec. 3.1) -> SGLD or
+ *   pSGLD update with Gaussian noise (Sec. 3.2, eq:pSGLD) -> per-event
+ *   posterior mean and covariance (Sec. 3.4).
+ *
+ * Conventions (all entry points):
+ *  - Return value: SPIDER_OK (0) or a negative SPIDER_E_* code.  Nothing
+ *    aborts or throws across the ABI; spider_last_error() explains the last
+ *    failure of a context.
+ *  - A context is bound to one device and one HIP stream and is not
+ *    thread-safe.  All device work is enqueued on that stream; entry points
+ *    return without waiting unless stated otherwise.
+ *  - Input arrays stay owned by the caller and are copied at load.  Output
+ *    arrays are allocated by the caller on the context's device ("device
+ *    pointer" below); the library owns only its internal device memory and
+ *    frees it in spider_destroy().
+ *  - Units: km and s; z is depth (positive down); stations have z = 0 in the
+ *    shipped workloads but any z is accepted.
+ *  - Row-major layouts throughout: [M][4] means 4 consecutive doubles
+ *    (x, y, z, t) per event.
+ */
+#ifndef SPIDER_H
+#define SPIDER_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  SPIDER_OK = 0,
+  SPIDER_E_INVALID = -1,     /* bad argument, id or input value */
+  SPIDER_E_OOM = -2,         /* device allocation failed */
+  SPIDER_E_HIP = -3,         /* HIP runtime error */
+  SPIDER_E_STATE = -4,       /* call not valid in the current state */
+  SPIDER_E_UNSUPPORTED = -5, /* valid but not supported by this build */
+  SPIDER_E_NUMERIC = -6      /* non-finite state after an update */
+};
+
+enum { SPIDER_MEM_HOST = 0, SPIDER_MEM_DEVICE = 1 };
+/* Whitening of the minibatch residuals (Sec. 3.1):
+ *   NONE  z = r / sigma^2                                  (kappa ignored)
+ *   DIAG  z = r / (sigma^2 + 2 kappa^2 w)   (diagonal of Sigma_B only)
+ *   EXACT z = Sigma_B^{-1} r, Sigma_B = sigma^2 I + kappa^2 W^{1/2} A A^T W^{1/2}
+ *         restricted to the batch's observations of each group          */
+enum { SPIDER_WHITEN_NONE = 0, SPIDER_WHITEN_DIAG = 1, SPIDER_WHITEN_EXACT = 2 };
+/* Arithmetic of the network's hidden layers: FP32, or BF16 MFMA operands
+ * with FP32 accumulation.  Inputs, first and output layers, travel-time
+ * assembly, residuals, whitening, gradient and state are FP32/FP64 in both. */
+enum { SPIDER_FP32 = 0, SPIDER_BF16 = 1 };
+/* spider_grad flags */
+enum { SPIDER_GRAD_PRIOR = 1, SPIDER_GRAD_CENTROID = 2 };
+
+#define SPIDER_MAX_LAYERS 16
+
+typedef struct spider_ctx spider_ctx;
+
+/* Library version (major * 10000 + minor * 100 + patch). */
+int spider_version(void);
+
+/* Create a context on HIP device `device`, enqueueing on `hip_stream`
+ * (a hipStream_t; NULL = the device's null stream).  *ctx receives the
+ * handle.  Errors: SPIDER_E_INVALID (no such device), SPIDER_E_HIP. */
+int spider_create(spider_ctx** ctx, int device, void* hip_stream);
+
+/* Wait for the context's stream and free everything it owns.  NULL is a no-op. */
+void spider_destroy(spider_ctx* ctx);
+
+/* Text of the last error on this context; owned by the context, valid until
+ * its next call.  Never NULL. */
+const char* spider_last_error(const spider_ctx* ctx);
+
+/* Block until all work enqueued by this context has finished.
+ * Errors: SPIDER_E_HIP with the runtime's message. */
+int spider_sync(spider_ctx* ctx);
+
+/* ---- catalog (Sec. 3.1: M events, L stations, dd observations) --------- */
+typedef struct {
+  int32_t M;                /* events, >= 2                                    */
+  int32_t L;                /* stations, >= 1; group g of an observation is its
+                               station (one phase)                            */
+  int32_t P;                /* event pairs, >= 1                              */
+  int64_t N;                /* observations, >= 1                             */
+  int32_t mem;              /* SPIDER_MEM_HOST or _DEVICE for every array     */
+  const double* hypo0;      /* [M][4] initial hypocentre and origin time; also
+                               the event-prior mean mu_e (Sec. 3.1)           */
+  const double* stations;   /* [L][3] station coordinates                     */
+  const int32_t* pair_i;    /* [P] first event xi^1 of each pair, in [0, M)   */
+  const int32_t* pair_j;    /* [P] second event xi^2, in [0, M), != pair_i    */
+  const int32_t* obs_pair;  /* [N] pair of each observation, in [0, P)        */
+  const int16_t* obs_sta;   /* [N] station of each observation, in [0, L)     */
+  const float* obs_dt;      /* [N] observed differential time tau_n (s)       */
+  double sigma;             /* IID noise s.d. sigma_phi (s), > 0              */
+  double kappa;             /* shared-event s.d. kappa_phi (s), >= 0          */
+  double p;                 /* weight decay exponent p (eq:correlation_decay) */
+  double ell;               /* weight length scale ell (km), > 0              */
+  double eps_w;             /* weight floor epsilon, > 0                      */
+  double prior_sigma[4];    /* event prior s.d. (x, y, z km; t s), > 0        */
+  double centroid_sigma[4]; /* centroid prior s.d., > 0                       */
+  uint32_t stream;          /* random-stream id of this catalog, < 2^24       */
+  int32_t whiten;           /* SPIDER_WHITEN_*                                */
+} spider_catalog_desc;
+
+/* Load a catalog (Sec. 3.1).  Copies every array to the device, then on the
+ * device: edge weights w~_e = (d_e/ell)^p + eps_w with d_e = |x_i - x_j| at
+ * the initial locations (eq:correlation_decay), normalised to mean 1 over
+ * each group's observations; the centroid prior mean mu_c = mean of hypo0.
+ * Errors: SPIDER_E_INVALID for out-of-range ids, i == j, non-finite values,
+ * non-positive sigma/ell/eps_w/prior s.d., an observation whose initial
+ * source lies within 1e-3 km of its station; SPIDER_E_OOM; SPIDER_E_HIP.
+ * Synchronous (the arrays may be reused when it returns). */
+int spider_load_catalog(spider_ctx* ctx, const spider_catalog_desc* desc, int32_t* cat_id);
+
+/* ---- travel-time network (Sec. 3.2: EikoNet; Sec. 5: any differentiable T)
+ * u = ((x - center)/half_extent, (s - center)/half_extent)   (6 inputs)
+ * a_1 = tanh(W[0] u + b[0]); a_{l+1} = tanh(W[l] a_l + b[l]), l = 1..D-1
+ * o = W[D] a_D + b[D];  T = |x - s| / v0 * softplus(o) / ln 2              */
+typedef struct {
+  int32_t D;                /* hidden tanh layers, 1..SPIDER_MAX_LAYERS       */
+  int32_t H;                /* hidden width, a multiple of 16, 16..256        */
+  int32_t mem;              /* SPIDER_MEM_HOST or _DEVICE for W and b         */
+  const float* W[SPIDER_MAX_LAYERS + 1]; /* W[0]: [H][6]; W[1..D-1]: [H][H];
+                                            W[D]: [H] (output row), row-major */
+  const float* b[SPIDER_MAX_LAYERS + 1]; /* b[0..D-1]: [H]; b[D]: [1]        */
+  double v0;                /* scale speed (km/s), > 0                        */
+  double center[3];         /* input centre c0                                */
+  double half_extent[3];    /* input half extent h, > 0                       */
+} spider_net_desc;
+
+/* Load a network: FP32 copies and the BF16 / FP32 operand packings of the
+ * hidden layers for the matrix-core kernels.  Synchronous.
+ * Errors: SPIDER_E_INVALID (shape or non-finite weights), SPIDER_E_OOM,
+ * SPIDER_E_HIP. */
+int spider_load_net(spider_ctx* ctx, const spider_net_desc* desc, int32_t* net_id);
+
+/* T(x; s) and dT/dx for `rows` source/receiver pairs.  x_src, s: device
+ * [rows][3]; T: device [rows]; gradT: device [rows][3] or NULL.  Forward
+ * pass then reverse-mode source gradient (Sec. 3.2) with activations
+ * recomputed on chip, never stored to memory.  rows may be 0.
+ * Errors: SPIDER_E_INVALID (ids, rows < 0, NULL required pointers). */
+int spider_travel_time(spider_ctx* ctx, int32_t net_id, int32_t precision,
+                       const double* x_src, const double* s, int64_t rows,
+                       double* T, double* gradT);
+
+/* ---- one stochastic gradient (eq:sgd) ----------------------------------
+ * g = [prior terms] + (N/n) * sum_{k<n} (d tau^_k / d theta)^T z_k
+ * at state theta (device [M][4]).  The batch is batch_idx (device [n]
+ * observation indices in [0, N), repeats allowed) or, if batch_idx is NULL,
+ * minibatch `step` of chain `chain` under `seed` (see spider_batch_indices).
+ * flags: SPIDER_GRAD_PRIOR adds -(theta - hypo0)/prior_sigma^2,
+ * SPIDER_GRAD_CENTROID adds -(mean(theta) - mu_c)/(M centroid_sigma^2) to
+ * every event (Sec. 3.1).  grad_out: device [M][4] (events outside the
+ * batch get only the prior terms).  logpost_out: device [1] or NULL:
+ * -(N/n)/2 r^T z + log priors, up to an additive constant.
+ * Errors: SPIDER_E_INVALID (ids, n < 1, n > N without batch_idx). */
+int spider_grad(spider_ctx* ctx, int32_t cat_id, int32_t net_id, int32_t precision,
+                const double* theta, const int64_t* batch_idx, int64_t n,
+                uint64_t seed, int32_t chain, int64_t step, uint32_t flags,
+                double* grad_out, double* logpost_out);
+
+/* Per-observation terms of one minibatch, for checking each stage: travel
+ * times T_i, T_j [n], source gradients gT_i, gT_j [n][3], residuals r [n]
+ * and whitened residuals z [n] (device pointers, each may be NULL).
+ * Arguments as spider_grad.  Errors: as spider_grad. */
+int spider_batch_terms(spider_ctx* ctx, int32_t cat_id, int32_t net_id, int32_t precision,
+                       const double* theta, const int64_t* batch_idx, int64_t n,
+                       uint64_t seed, int32_t chain, int64_t step,
+                       double* T_i, double* T_j, double* gT_i, double* gT_j,
+                       double* r, double* z);
+
+/* Observation indices of minibatch `step` of chain `chain` (Sec. 3.2:
+ * without replacement, N/n minibatches per epoch): epoch e = step / B,
+ * batch b = step % B, B = floor(N/n); slot k holds pi(b n + k) where pi is
+ * a four-round Feistel bijection of [0, N) keyed by (seed, catalog stream,
+ * chain, e) with Philox4x32-10 round functions and cycle walking.
+ * idx_out: device [n] int64.  Errors: SPIDER_E_INVALID (n < 1 or n > N). */
+int spider_batch_indices(spider_ctx* ctx, int32_t cat_id, uint64_t seed, int32_t chain,
+                         int64_t step, int64_t n, int64_t* idx_out);
+
+/* The Langevin noise eta ~ N(0, 1) (Sec. 3.2) of step `step` of chain
+ * `chain`: Philox4x32-10 keyed by seed, two blocks per event, 52-bit
+ * uniforms, Box-Muller.  eta_out: device [M][4]. */
+int spider_noise(spider_ctx* ctx, int32_t cat_id, uint64_t seed, int32_t chain,
+                 int64_t step, double* eta_out);
+
+/* ---- chains and the sampler (Sec. 3.2, eq:pSGLD) ------------------------ */
+
+/* (Re)create `n_chains` chains of a catalog: theta = hypo0, v = 0, step 0,
+ * empty moments (Sec. 3.2 starts from the initial locations).
+ * Errors: SPIDER_E_INVALID, SPIDER_E_OOM. */
+int spider_reset_chains(spider_ctx* ctx, int32_t cat_id, int32_t n_chains);
+
+typedef struct {
+  int32_t cat_id;
+  int32_t net_id;
+  int32_t n_chains;         /* chains 0..n_chains-1 of the catalog advance    */
+  int32_t precision;        /* SPIDER_FP32 or SPIDER_BF16                     */
+  int64_t batch;            /* minibatch size n per chain, 1..N               */
+} spider_chainset;
+
+typedef struct {
+  double step;              /* epsilon_t (fixed)                              */
+  double beta2;             /* pSGLD second-moment decay, in [0, 1]           */
+  double eps_p;             /* pSGLD epsilon in V = 1/(sqrt(v) + eps_p), > 0  */
+  double noise_scale;       /* a: multiplies the injected noise (1 sampling,
+                               0 noise off, ramps in between)                 */
+  int32_t precond;          /* 0: SGLD  theta += eps g + a sqrt(2 eps) eta
+                               1: pSGLD v = b2 v + (1-b2) g*g;
+                                  V = 1/(sqrt(v)+eps_p);
+                                  theta += eps V g + a sqrt(2 eps V) eta      */
+  int32_t reserved;
+  int64_t n_steps;          /* steps to run, >= 0                             */
+  int64_t burn_in;          /* after the update of global step t, theta enters
+                               the moments iff t >= burn_in and
+                               (t - burn_in) % thin == 0                      */
+  int64_t thin;             /* >= 1                                           */
+  uint64_t seed;            /* keys the batch and noise streams               */
+} spider_sgld_cfg;
+
+/* Advance every chain of every set by cfg->n_steps steps.  Each step uses
+ * the chain's global step counter for its batch and noise, so a run split
+ * over calls equals one uninterrupted run.  Chains are created on first use
+ * if the catalog has fewer.  After the last step every state is checked for
+ * finite values: SPIDER_E_NUMERIC names the catalog and chain otherwise
+ * (this waits for the stream).  Errors: SPIDER_E_INVALID, SPIDER_E_NUMERIC,
+ * SPIDER_E_OOM, SPIDER_E_HIP. */
+int spider_sgld_steps(spider_ctx* ctx, const spider_chainset* sets, int32_t n_sets,
+                      const spider_sgld_cfg* cfg);
+
+/* Posterior moments (Sec. 3.4) of a catalog: chain >= 0 for one chain, -1
+ * for all chains pooled (pairwise combination of Chan, Golub and LeVeque).
+ * mean: device [M][4]; cov: device [M][10] upper triangle xx xy xz xt yy yz
+ * yt zz zt tt with divisor count - 1 (either may be NULL); *count (host)
+ * receives the number of samples.  Enqueued on the stream.
+ * Errors: SPIDER_E_INVALID, SPIDER_E_STATE (no chains). */
+int spider_moments(spider_ctx* ctx, int32_t cat_id, int32_t chain,
+                   double* mean, double* cov, int64_t* count);
+
+/* Copy a chain's state out (theta, v: device [M][4], either may be NULL) and
+ * its global step counter (*step, host, may be NULL). */
+int spider_get_state(spider_ctx* ctx, int32_t cat_id, int32_t chain,
+                     double* theta, double* v, int64_t* step);
+
+/* Overwrite a chain's state (theta, v: device [M][4], v may be NULL for 0)
+ * and step counter; the moments are left as they are. */
+int spider_set_state(spider_ctx* ctx, int32_t cat_id, int32_t chain,
+                     const double* theta, const double* v, int64_t step);
+
+/* ---- measurement --------------------------------------------------------
+ * While enabled, every launch of the travel-time network kernel made by this
+ * context is bracketed by HIP events recorded on the context's stream.
+ * spider_profile(ctx, 1) enables and clears the record, 0 disables it.
+ * spider_profile_read waits for the stream and returns the summed kernel
+ * time (ms), the number of launches and the network rows they processed
+ * (each pointer may be NULL).  Errors: SPIDER_E_INVALID, SPIDER_E_HIP. */
+int spider_profile(spider_ctx* ctx, int enable);
+int spider_profile_read(spider_ctx* ctx, double* ms, int64_t* launches, int64_t* rows);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPIDER_H */

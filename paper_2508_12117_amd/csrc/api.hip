@@ -1,0 +1,875 @@
+// Host runtime of libspider: contexts, catalog and network loading, device
+// memory, and the per-step pipeline behind the C ABI of include/spider.h.
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "spider.h"
+
+using namespace spider;
+
+namespace {
+
+// Owning device allocation.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    // growth happens between steps: wait for work that may still use p
+    if (p) {
+      (void)hipDeviceSynchronize();
+      (void)hipFree(p);
+    }
+    p = nullptr;
+    bytes = 0;
+  }
+  hipError_t alloc(size_t n) {
+    release();
+    if (n == 0) n = 16;
+    hipError_t e = hipMalloc(&p, n);
+    if (e == hipSuccess) bytes = n;
+    else p = nullptr;
+    return e;
+  }
+  // Grow to at least n bytes (contents are not kept).
+  hipError_t reserve(size_t n) { return bytes >= n ? hipSuccess : alloc(n); }
+  template <typename T>
+  T* as() const { return (T*)p; }
+};
+
+struct Catalog {
+  int32_t M = 0, L = 0, P = 0;
+  int64_t N = 0;
+  uint32_t stream = 0;
+  int whiten = SPIDER_WHITEN_EXACT;
+  double sigma = 0, kappa = 0, prior_sigma[4] = {}, centroid_sigma[4] = {};
+  DevBuf hypo0, stations, pairs, w_pair, obs, inv_mean, mu_c;
+  int C = 0;  // chains allocated
+  DevBuf theta, v, mean, m2, steps, mcount;
+
+  CatView view() const {
+    CatView c;
+    c.M = M;
+    c.L = L;
+    c.N = N;
+    c.hypo0 = hypo0.as<double>();
+    c.stations = stations.as<double>();
+    c.pairs = pairs.as<int2>();
+    c.w_pair = w_pair.as<double>();
+    c.obs = obs.as<Obs>();
+    c.inv_mean = inv_mean.as<double>();
+    c.mu_c = mu_c.as<double>();
+    c.stream = stream;
+    c.sigma = sigma;
+    c.kappa = kappa;
+    for (int k = 0; k < 4; ++k) {
+      c.prior_sigma[k] = prior_sigma[k];
+      c.centroid_sigma[k] = centroid_sigma[k];
+    }
+    return c;
+  }
+};
+
+struct Net {
+  int D = 0, H = 0;
+  double v0 = 0, center[3] = {}, half[3] = {};
+  float bout = 0;
+  DevBuf W0, bias, Wt, wout;
+  DevBuf pack_fwd[2], pack_bwd[2];  // by precision
+
+  NetView view(int prec) const {
+    NetView v;
+    v.D = D;
+    v.H = H;
+    v.W0 = W0.as<float>();
+    v.bias = bias.as<float>();
+    v.Wt = Wt.as<float>();
+    v.wout = wout.as<float>();
+    v.bout = bout;
+    v.v0 = v0;
+    for (int a = 0; a < 3; ++a) {
+      v.center[a] = center[a];
+      v.half[a] = half[a];
+    }
+    v.pack_fwd = pack_fwd[prec].p;
+    v.pack_bwd = pack_bwd[prec].p;
+    return v;
+  }
+};
+
+// Scratch of one minibatch pipeline, grown on demand.
+struct Workspace {
+  DevBuf obs, ev, sta, tau, w, net_out, T, gT, r, z;
+  DevBuf key_in, key_out, val_in, val_out, temp, node_of, node_start, seg_begin, seg_end, flags,
+      vec, count;
+  DevBuf G, partial, thetabar, lp_tmp, err;
+  size_t temp_bytes = 0;
+
+  hipError_t reserve(int64_t C, int64_t Cn, int64_t CM, int64_t CL) {
+    const int64_t E = 2 * Cn;
+    hipError_t e;
+#define RES(buf, bytes)                                     \
+  if ((e = buf.reserve((size_t)(bytes))) != hipSuccess) return e;
+    RES(obs, Cn * 8);
+    RES(ev, E * 4);
+    RES(sta, E * 4);
+    RES(tau, Cn * 8);
+    RES(w, Cn * 8);
+    RES(net_out, E * sizeof(RowOut));
+    RES(T, E * 8);
+    RES(gT, E * 24);
+    RES(r, Cn * 8);
+    RES(z, Cn * 8);
+    RES(key_in, E * 8);
+    RES(key_out, E * 8);
+    RES(val_in, E * 4);
+    RES(val_out, E * 4);
+    RES(node_of, E * 4);
+    RES(node_start, (E + 1) * 4);
+    RES(seg_begin, CL * 4);
+    RES(seg_end, CL * 4);
+    RES(flags, E * 4);
+    RES(vec, E * 8 * 6);
+    RES(count, 16);
+    RES(G, CM * 32);
+    RES(partial, (CM / 4096 + C + 1) * 32);
+    RES(thetabar, C * 32);
+    RES(lp_tmp, 4096 * 8);
+    RES(err, 64);
+#undef RES
+    const size_t tb = sort_temp_bytes(E);
+    if (tb > temp_bytes || !temp.p) {
+      if ((e = temp.alloc(tb)) != hipSuccess) return e;
+      temp_bytes = tb;
+    }
+    return hipSuccess;
+  }
+
+  BatchBufs batch() const {
+    BatchBufs b;
+    b.obs = obs.as<int64_t>();
+    b.ev = ev.as<int32_t>();
+    b.sta = sta.as<int32_t>();
+    b.tau = tau.as<double>();
+    b.w = w.as<double>();
+    b.net_out = net_out.as<RowOut>();
+    b.T = T.as<double>();
+    b.gT = gT.as<double>();
+    b.r = r.as<double>();
+    b.z = z.as<double>();
+    return b;
+  }
+  SortBufs sort() const {
+    SortBufs s;
+    s.key_in = key_in.as<uint64_t>();
+    s.key_out = key_out.as<uint64_t>();
+    s.val_in = val_in.as<uint32_t>();
+    s.val_out = val_out.as<uint32_t>();
+    s.temp = temp.p;
+    s.temp_bytes = temp_bytes;
+    s.node_of = node_of.as<int32_t>();
+    s.node_start = node_start.as<int32_t>();
+    s.seg_begin = seg_begin.as<int32_t>();
+    s.seg_end = seg_end.as<int32_t>();
+    s.flags = flags.as<int32_t>();
+    s.vec = vec.as<double>();
+    s.count = count.as<int32_t>();
+    return s;
+  }
+};
+
+}  // namespace
+
+struct spider_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  bool profiling = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
+  std::vector<int64_t> prof_rows;
+  std::vector<std::unique_ptr<Catalog>> cats;
+  std::vector<std::unique_ptr<Net>> nets;
+  Workspace ws;
+};
+
+namespace {
+
+int fail(spider_ctx* ctx, int code, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return code;
+}
+
+int hip_fail(spider_ctx* ctx, hipError_t e, const char* what) {
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  return fail(ctx, e == hipErrorOutOfMemory ? SPIDER_E_OOM : SPIDER_E_HIP, m);
+}
+
+#define HIPCK(call, what)                                 \
+  do {                                                    \
+    hipError_t _e = (call);                               \
+    if (_e != hipSuccess) return hip_fail(ctx, _e, what); \
+  } while (0)
+
+// Select the context's device for the duration of a call.
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    hipGetDevice(&prev);
+    if (prev != dev) hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    hipGetDevice(&cur);
+    if (prev >= 0 && cur != prev) hipSetDevice(prev);
+  }
+};
+
+Catalog* get_cat(spider_ctx* ctx, int32_t id) {
+  if (id < 0 || id >= (int32_t)ctx->cats.size()) return nullptr;
+  return ctx->cats[id].get();
+}
+Net* get_net(spider_ctx* ctx, int32_t id) {
+  if (id < 0 || id >= (int32_t)ctx->nets.size()) return nullptr;
+  return ctx->nets[id].get();
+}
+
+// Copy `bytes` from a host or device source into a device buffer.
+hipError_t upload(DevBuf& dst, const void* src, size_t bytes, int mem, hipStream_t s) {
+  hipError_t e = dst.alloc(bytes);
+  if (e != hipSuccess) return e;
+  if (bytes == 0) return hipSuccess;
+  return hipMemcpyAsync(dst.p, src, bytes, mem == SPIDER_MEM_DEVICE ? hipMemcpyDeviceToDevice
+                                                                     : hipMemcpyHostToDevice, s);
+}
+
+// Fetch an array from host or device memory into a host vector.
+template <typename T>
+hipError_t fetch(std::vector<T>& out, const T* src, size_t count, int mem, hipStream_t s) {
+  out.resize(count);
+  if (count == 0) return hipSuccess;
+  if (mem == SPIDER_MEM_DEVICE) {
+    hipError_t e = hipMemcpyAsync(out.data(), src, count * sizeof(T), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(s);
+  }
+  std::memcpy(out.data(), src, count * sizeof(T));
+  return hipSuccess;
+}
+
+// Network forward/backward over the rows of src.
+int run_network(spider_ctx* ctx, const Net& net, int prec, const RowSource& src, RowOut* out) {
+  const NetView nv = net.view(prec);
+  hipError_t e;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  if (ctx->profiling) {
+    HIPCK(hipEventCreate(&ev0), "event");
+    HIPCK(hipEventCreate(&ev1), "event");
+    HIPCK(hipEventRecord(ev0, ctx->stream), "event");
+  }
+  if (mlp_mfma_supported(prec, net.H, net.D)) {
+    e = launch_mlp_mfma(prec, src, nv, out, ctx->stream);
+  } else if (prec == SPIDER_FP32) {
+    e = launch_mlp_tangent(src, nv, out, ctx->stream);
+  } else {
+    return fail(ctx, SPIDER_E_UNSUPPORTED, "no BF16 matrix-core kernel for this network shape");
+  }
+  if (e != hipSuccess) return hip_fail(ctx, e, "network kernel");
+  if (ctx->profiling) {
+    HIPCK(hipEventRecord(ev1, ctx->stream), "event");
+    ctx->prof_events.emplace_back(ev0, ev1);
+    ctx->prof_rows.push_back(src.rows);
+  }
+  return SPIDER_OK;
+}
+
+void clear_profile(spider_ctx* ctx) {
+  for (auto& pr : ctx->prof_events) {
+    (void)hipEventDestroy(pr.first);
+    (void)hipEventDestroy(pr.second);
+  }
+  ctx->prof_events.clear();
+  ctx->prof_rows.clear();
+}
+
+// One minibatch for C chains: selection, network, residuals, whitening and
+// (if G) the scaled per-event likelihood gradient into ws.G.
+int run_batch(spider_ctx* ctx, Catalog& cat, Net& net, int prec, int C, int64_t n,
+              const double* theta, int64_t theta_stride, const int64_t* idx, uint64_t seed,
+              const int64_t* steps_dev, int64_t step_scalar, int chain0, bool grad, double scale) {
+  Workspace& ws = ctx->ws;
+  const int64_t Cn = (int64_t)C * n;
+  HIPCK(ws.reserve(C, Cn, (int64_t)C * cat.M, (int64_t)C * cat.L), "workspace");
+  const CatView cv = cat.view();
+  const BatchBufs b = ws.batch();
+  launch_select(cv, C, n, idx, seed, steps_dev, step_scalar, chain0, b, ws.err.as<int>(),
+                ctx->stream);
+  RowSource src;
+  src.mode = 0;
+  src.rows = 2 * Cn;
+  src.ev = b.ev;
+  src.sta = b.sta;
+  src.theta = theta;
+  src.rows_per_chain = 2 * n;
+  src.theta_chain_stride = theta_stride;
+  src.stations = cv.stations;
+  src.x = nullptr;
+  src.s = nullptr;
+  int rc = run_network(ctx, net, prec, src, b.net_out);
+  if (rc != SPIDER_OK) return rc;
+  const int whiten = cat.kappa == 0.0 ? SPIDER_WHITEN_NONE : cat.whiten;
+  launch_residual(cv, net.view(prec), C, n, theta, theta_stride, whiten, b, ctx->stream);
+  if (whiten == SPIDER_WHITEN_EXACT)
+    HIPCK(exact_whiten(cv, C, n, b, ws.sort(), ctx->stream), "exact whitening");
+  if (grad)
+    HIPCK(reduce_events(cv, C, n, scale, b, ws.sort(), ws.G.as<double>(), ctx->stream),
+          "per-event reduction");
+  HIPCK(hipGetLastError(), "step kernels");
+  return SPIDER_OK;
+}
+
+int check_select_flag(spider_ctx* ctx) {
+  int flag = 0;
+  HIPCK(hipMemcpyAsync(&flag, ctx->ws.err.as<int>(), sizeof(int), hipMemcpyDeviceToHost,
+                       ctx->stream),
+        "read flag");
+  HIPCK(hipStreamSynchronize(ctx->stream), "sync");
+  if (flag)
+    return fail(ctx, SPIDER_E_INVALID,
+                "observation index out of range (or the minibatch permutation walk failed)");
+  return SPIDER_OK;
+}
+
+int reset_err_flag(spider_ctx* ctx) {
+  HIPCK(ctx->ws.err.reserve(64), "workspace");
+  HIPCK(hipMemsetAsync(ctx->ws.err.p, 0, sizeof(int), ctx->stream), "flag reset");
+  return SPIDER_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int spider_version(void) { return 100; }
+
+int spider_create(spider_ctx** out, int device, void* hip_stream) {
+  if (!out) return SPIDER_E_INVALID;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return SPIDER_E_INVALID;
+  auto* ctx = new (std::nothrow) spider_ctx();
+  if (!ctx) return SPIDER_E_OOM;
+  ctx->device = device;
+  ctx->stream = (hipStream_t)hip_stream;
+  *out = ctx;
+  return SPIDER_OK;
+}
+
+void spider_destroy(spider_ctx* ctx) {
+  if (!ctx) return;
+  DeviceGuard g(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  clear_profile(ctx);
+  delete ctx;
+}
+
+int spider_profile(spider_ctx* ctx, int enable) {
+  if (!ctx) return SPIDER_E_INVALID;
+  DeviceGuard g(ctx->device);
+  HIPCK(hipStreamSynchronize(ctx->stream), "sync");
+  clear_profile(ctx);
+  ctx->profiling = enable != 0;
+  return SPIDER_OK;
+}
+
+int spider_profile_read(spider_ctx* ctx, double* ms, int64_t* launches, int64_t* rows) {
+  if (!ctx) return SPIDER_E_INVALID;
+  DeviceGuard g(ctx->device);
+  HIPCK(hipStreamSynchronize(ctx->stream), "sync");
+  double tot = 0.0;
+  int64_t nr = 0;
+  for (size_t k = 0; k < ctx->prof_events.size(); ++k) {
+    float t = 0.0f;
+    HIPCK(hipEventElapsedTime(&t, ctx->prof_events[k].first, ctx->prof_events[k].second),
+          "event time");
+    tot += t;
+    nr += ctx->prof_rows[k];
+  }
+  if (ms) *ms = tot;
+  if (launches) *launches = (int64_t)ctx->prof_events.size();
+  if (rows) *rows = nr;
+  return SPIDER_OK;
+}
+
+const char* spider_last_error(const spider_ctx* ctx) {
+  if (!ctx) return "null context";
+  return ctx->err.c_str();
+}
+
+int spider_sync(spider_ctx* ctx) {
+  if (!ctx) return SPIDER_E_INVALID;
+  DeviceGuard g(ctx->device);
+  HIPCK(hipStreamSynchronize(ctx->stream), "stream synchronize");
+  return SPIDER_OK;
+}
+
+int spider_load_catalog(spider_ctx* ctx, const spider_catalog_desc* d, int32_t* cat_id) {
+  if (!ctx || !d || !cat_id) return fail(ctx, SPIDER_E_INVALID, "null argument");
+  DeviceGuard g(ctx->device);
+  if (d->M < 2 || d->L < 1 || d->P < 1 || d->N < 1)
+    return fail(ctx, SPIDER_E_INVALID, "need M >= 2, L >= 1, P >= 1, N >= 1");
+  if (d->N > (int64_t)INT32_MAX * 2 || (int64_t)d->M * 4 > INT32_MAX)
+    return fail(ctx, SPIDER_E_UNSUPPORTED, "catalog too large");
+  if (d->mem != SPIDER_MEM_HOST && d->mem != SPIDER_MEM_DEVICE)
+    return fail(ctx, SPIDER_E_INVALID, "mem must be SPIDER_MEM_HOST or SPIDER_MEM_DEVICE");
+  if (!d->hypo0 || !d->stations || !d->pair_i || !d->pair_j || !d->obs_pair || !d->obs_sta ||
+      !d->obs_dt)
+    return fail(ctx, SPIDER_E_INVALID, "null catalog array");
+  if (!(d->sigma > 0) || !(d->kappa >= 0) || !(d->ell > 0) || !(d->eps_w > 0) ||
+      !std::isfinite(d->p) || !std::isfinite(d->kappa))
+    return fail(ctx, SPIDER_E_INVALID, "need sigma > 0, kappa >= 0, ell > 0, eps_w > 0, finite p");
+  for (int k = 0; k < 4; ++k)
+    if (!(d->prior_sigma[k] > 0) || !(d->centroid_sigma[k] > 0) ||
+        !std::isfinite(d->prior_sigma[k]) || !std::isfinite(d->centroid_sigma[k]))
+      return fail(ctx, SPIDER_E_INVALID, "prior and centroid s.d. must be positive and finite");
+  if (d->stream >= (1u << 24)) return fail(ctx, SPIDER_E_INVALID, "stream id must be < 2^24");
+  if (d->whiten < SPIDER_WHITEN_NONE || d->whiten > SPIDER_WHITEN_EXACT)
+    return fail(ctx, SPIDER_E_INVALID, "unknown whitening mode");
+
+  auto cat = std::make_unique<Catalog>();
+  cat->M = d->M;
+  cat->L = d->L;
+  cat->P = d->P;
+  cat->N = d->N;
+  cat->stream = d->stream;
+  cat->whiten = d->whiten;
+  cat->sigma = d->sigma;
+  cat->kappa = d->kappa;
+  for (int k = 0; k < 4; ++k) {
+    cat->prior_sigma[k] = d->prior_sigma[k];
+    cat->centroid_sigma[k] = d->centroid_sigma[k];
+  }
+  hipStream_t s = ctx->stream;
+  HIPCK(upload(cat->hypo0, d->hypo0, (size_t)d->M * 32, d->mem, s), "upload hypo0");
+  HIPCK(upload(cat->stations, d->stations, (size_t)d->L * 24, d->mem, s), "upload stations");
+
+  // pairs and observations are re-packed on the host (12-byte records)
+  {
+    std::vector<int32_t> pi, pj;
+    HIPCK(fetch(pi, d->pair_i, d->P, d->mem, s), "read pair_i");
+    HIPCK(fetch(pj, d->pair_j, d->P, d->mem, s), "read pair_j");
+    std::vector<int2> pairs(d->P);
+    for (int32_t e = 0; e < d->P; ++e) pairs[e] = make_int2(pi[e], pj[e]);
+    HIPCK(upload(cat->pairs, pairs.data(), pairs.size() * sizeof(int2), SPIDER_MEM_HOST, s),
+          "upload pairs");
+    HIPCK(hipStreamSynchronize(s), "sync");
+  }
+  {
+    std::vector<int32_t> op;
+    std::vector<int16_t> os;
+    std::vector<float> od;
+    HIPCK(fetch(op, d->obs_pair, d->N, d->mem, s), "read obs_pair");
+    HIPCK(fetch(os, d->obs_sta, d->N, d->mem, s), "read obs_sta");
+    HIPCK(fetch(od, d->obs_dt, d->N, d->mem, s), "read obs_dt");
+    std::vector<Obs> obs(d->N);
+    for (int64_t q = 0; q < d->N; ++q) obs[q] = Obs{op[q], od[q], (int32_t)os[q]};
+    HIPCK(upload(cat->obs, obs.data(), obs.size() * sizeof(Obs), SPIDER_MEM_HOST, s),
+          "upload observations");
+    HIPCK(hipStreamSynchronize(s), "sync");
+  }
+  // validation on the device
+  DevBuf bad;
+  HIPCK(bad.alloc(16), "alloc");
+  HIPCK(hipMemsetAsync(bad.p, 0, 16, s), "memset");
+  launch_validate(cat->hypo0.as<double>(), d->M, cat->stations.as<double>(), d->L,
+                  cat->pairs.as<int2>(), d->P, cat->obs.as<Obs>(), d->N, bad.as<int>(), s);
+  int flag = 0;
+  HIPCK(hipMemcpyAsync(&flag, bad.p, sizeof(int), hipMemcpyDeviceToHost, s), "read flag");
+  HIPCK(hipStreamSynchronize(s), "validate");
+  if (flag & 1) return fail(ctx, SPIDER_E_INVALID, "event, pair or station id out of range, or i == j");
+  if (flag & 2) return fail(ctx, SPIDER_E_INVALID, "non-finite coordinate or observation");
+  if (flag & 4) return fail(ctx, SPIDER_E_INVALID, "an initial source lies within 1e-3 km of its station");
+
+  HIPCK(cat->w_pair.alloc((size_t)d->P * 8), "alloc w_pair");
+  HIPCK(cat->inv_mean.alloc((size_t)d->L * 8), "alloc inv_mean");
+  HIPCK(cat->mu_c.alloc(32), "alloc mu_c");
+  launch_pair_weights(cat->hypo0.as<double>(), cat->pairs.as<int2>(), d->P, d->ell, d->p, d->eps_w,
+                      cat->w_pair.as<double>(), s);
+  HIPCK(group_inverse_mean(cat->obs.as<Obs>(), d->N, d->L, cat->w_pair.as<double>(),
+                           cat->inv_mean.as<double>(), s),
+        "group means");
+  launch_mean4(cat->hypo0.as<double>(), d->M, cat->mu_c.as<double>(), s);
+  HIPCK(hipGetLastError(), "load kernels");
+  HIPCK(hipStreamSynchronize(s), "load");
+  ctx->cats.push_back(std::move(cat));
+  *cat_id = (int32_t)ctx->cats.size() - 1;
+  return SPIDER_OK;
+}
+
+int spider_load_net(spider_ctx* ctx, const spider_net_desc* d, int32_t* net_id) {
+  if (!ctx || !d || !net_id) return fail(ctx, SPIDER_E_INVALID, "null argument");
+  DeviceGuard g(ctx->device);
+  const int D = d->D, H = d->H;
+  if (D < 1 || D > SPIDER_MAX_LAYERS || H < 16 || H > 256 || H % 16 != 0)
+    return fail(ctx, SPIDER_E_INVALID, "need 1 <= D <= 16 and H a multiple of 16 in [16, 256]");
+  if (!(d->v0 > 0)) return fail(ctx, SPIDER_E_INVALID, "v0 must be positive");
+  for (int a = 0; a < 3; ++a)
+    if (!(d->half_extent[a] > 0) || !std::isfinite(d->center[a]))
+      return fail(ctx, SPIDER_E_INVALID, "half extents must be positive, centre finite");
+  for (int l = 0; l <= D; ++l)
+    if (!d->W[l] || !d->b[l]) return fail(ctx, SPIDER_E_INVALID, "null weight or bias");
+  hipStream_t s = ctx->stream;
+  std::vector<std::vector<float>> W(D + 1), B(D + 1);
+  for (int l = 0; l <= D; ++l) {
+    const size_t wn = l == 0 ? (size_t)H * 6 : (l == D ? (size_t)H : (size_t)H * H);
+    const size_t bn = l == D ? 1 : (size_t)H;
+    HIPCK(fetch(W[l], d->W[l], wn, d->mem, s), "read weights");
+    HIPCK(fetch(B[l], d->b[l], bn, d->mem, s), "read biases");
+    for (float x : W[l])
+      if (!std::isfinite(x)) return fail(ctx, SPIDER_E_INVALID, "non-finite weight");
+    for (float x : B[l])
+      if (!std::isfinite(x)) return fail(ctx, SPIDER_E_INVALID, "non-finite bias");
+  }
+  auto net = std::make_unique<Net>();
+  net->D = D;
+  net->H = H;
+  net->v0 = d->v0;
+  for (int a = 0; a < 3; ++a) {
+    net->center[a] = d->center[a];
+    net->half[a] = d->half_extent[a];
+  }
+  net->bout = B[D][0];
+  std::vector<float> bias((size_t)D * H), wt((size_t)std::max(D - 1, 1) * H * H, 0.0f);
+  for (int l = 0; l < D; ++l) std::memcpy(&bias[(size_t)l * H], B[l].data(), H * 4);
+  for (int l = 1; l < D; ++l)
+    for (int n = 0; n < H; ++n)
+      for (int k = 0; k < H; ++k) wt[((size_t)(l - 1) * H + k) * H + n] = W[l][(size_t)n * H + k];
+  HIPCK(upload(net->W0, W[0].data(), (size_t)H * 6 * 4, SPIDER_MEM_HOST, s), "upload W0");
+  HIPCK(upload(net->bias, bias.data(), bias.size() * 4, SPIDER_MEM_HOST, s), "upload biases");
+  HIPCK(upload(net->Wt, wt.data(), wt.size() * 4, SPIDER_MEM_HOST, s), "upload hidden weights");
+  HIPCK(upload(net->wout, W[D].data(), (size_t)H * 4, SPIDER_MEM_HOST, s), "upload output row");
+  for (int prec = 0; prec < 2; ++prec) {
+    if (!mlp_mfma_supported(prec, H, D)) continue;
+    const size_t lb = mfma_pack_bytes(prec, H);
+    const size_t layers = (size_t)std::max(D - 1, 1);
+    std::vector<unsigned char> fwd(lb * layers), bwd(lb * layers);
+    for (int l = 1; l < D; ++l)
+      mfma_pack_layer(prec, H, W[l].data(), fwd.data() + lb * (l - 1), bwd.data() + lb * (l - 1));
+    HIPCK(upload(net->pack_fwd[prec], fwd.data(), fwd.size(), SPIDER_MEM_HOST, s), "upload pack");
+    HIPCK(upload(net->pack_bwd[prec], bwd.data(), bwd.size(), SPIDER_MEM_HOST, s), "upload pack");
+  }
+  HIPCK(hipStreamSynchronize(s), "load net");
+  ctx->nets.push_back(std::move(net));
+  *net_id = (int32_t)ctx->nets.size() - 1;
+  return SPIDER_OK;
+}
+
+int spider_travel_time(spider_ctx* ctx, int32_t net_id, int32_t precision, const double* x_src,
+                       const double* s, int64_t rows, double* T, double* gradT) {
+  if (!ctx) return SPIDER_E_INVALID;
+  DeviceGuard g(ctx->device);
+  Net* net = get_net(ctx, net_id);
+  if (!net) return fail(ctx, SPIDER_E_INVALID, "unknown network id");
+  if (precision != SPIDER_FP32 && precision != SPIDER_BF16)
+    return fail(ctx, SPIDER_E_INVALID, "unknown precision");
+  if (rows < 0) return fail(ctx, SPIDER_E_INVALID, "rows < 0");
+  if (rows == 0) return SPIDER_OK;
+  if (!x_src || !s || !T) return fail(ctx, SPIDER_E_INVALID, "null array");
+  HIPCK(ctx->ws.net_out.reserve((size_t)rows * sizeof(RowOut)), "workspace");
+  RowSource src;
+  std::memset(&src, 0, sizeof(src));
+  src.mode = 1;
+  src.rows = rows;
+  src.x = x_src;
+  src.s = s;
+  int rc = run_network(ctx, *net, precision, src, ctx->ws.net_out.as<RowOut>());
+  if (rc != SPIDER_OK) return rc;
+  launch_tt_assemble(net->view(precision), rows, x_src, s, ctx->ws.net_out.as<RowOut>(), T, gradT,
+                     ctx->stream);
+  HIPCK(hipGetLastError(), "travel time");
+  return SPIDER_OK;
+}
+
+static int grad_common(spider_ctx* ctx, int32_t cat_id, int32_t net_id, int32_t precision,
+                       const double* theta, const int64_t* batch_idx, int64_t n, uint64_t seed,
+                       int32_t chain, int64_t step, bool grad, Catalog** cat_out, Net** net_out) {
+  Catalog* cat = get_cat(ctx, cat_id);
+  Net* net = get_net(ctx, net_id);
+  if (!cat) return fail(ctx, SPIDER_E_INVALID, "unknown catalog id");
+  if (!net) return fail(ctx, SPIDER_E_INVALID, "unknown network id");
+  if (precision != SPIDER_FP32 && precision != SPIDER_BF16)
+    return fail(ctx, SPIDER_E_INVALID, "unknown precision");
+  if (!theta) return fail(ctx, SPIDER_E_INVALID, "null theta");
+  if (n < 1) return fail(ctx, SPIDER_E_INVALID, "n must be >= 1");
+  if (!batch_idx && n > cat->N) return fail(ctx, SPIDER_E_INVALID, "n > N");
+  if (chain < 0 || step < 0) return fail(ctx, SPIDER_E_INVALID, "chain and step must be >= 0");
+  int rc = reset_err_flag(ctx);
+  if (rc) return rc;
+  rc = run_batch(ctx, *cat, *net, precision, 1, n, theta, (int64_t)cat->M * 4, batch_idx, seed,
+                 nullptr, step, chain, grad, (double)cat->N / (double)n);
+  if (rc) return rc;
+  *cat_out = cat;
+  *net_out = net;
+  return SPIDER_OK;
+}
+
+int spider_grad(spider_ctx* ctx, int32_t cat_id, int32_t net_id, int32_t precision,
+                const double* theta, const int64_t* batch_idx, int64_t n, uint64_t seed,
+                int32_t chain, int64_t step, uint32_t flags, double* grad_out,
+                double* logpost_out) {
+  if (!ctx) return SPIDER_E_INVALID;
+  DeviceGuard g(ctx->device);
+  if (!grad_out) return fail(ctx, SPIDER_E_INVALID, "null grad_out");
+  Catalog* cat;
+  Net* net;
+  int rc = grad_common(ctx, cat_id, net_id, precision, theta, batch_idx, n, seed, chain, step,
+                       true, &cat, &net);
+  if (rc) return rc;
+  Workspace& ws = ctx->ws;
+  const CatView cv = cat->view();
+  launch_centroid(theta, 1, cat->M, ws.partial.as<double>(), ws.thetabar.as<double>(), ctx->stream);
+  launch_grad_finish(cv, theta, ws.G.as<double>(), ws.thetabar.as<double>(), flags, grad_out,
+                     ctx->stream);
+  if (logpost_out)
+    launch_logpost(cv, n, (double)cat->N / (double)n, ws.r.as<double>(), ws.z.as<double>(), theta,
+                   ws.thetabar.as<double>(), flags, ws.lp_tmp.as<double>(), logpost_out,
+                   ctx->stream);
+  HIPCK(hipGetLastError(), "gradient kernels");
+  return check_select_flag(ctx);
+}
+
+int spider_batch_terms(spider_ctx* ctx, int32_t cat_id, int32_t net_id, int32_t precision,
+                       const double* theta, const int64_t* batch_idx, int64_t n, uint64_t seed,
+                       int32_t chain, int64_t step, double* T_i, double* T_j, double* gT_i,
+                       double* gT_j, double* r, double* z) {
+  if (!ctx) return SPIDER_E_INVALID;
+  DeviceGuard g(ctx->device);
+  Catalog* cat;
+  Net* net;
+  int rc = grad_common(ctx, cat_id, net_id, precision, theta, batch_idx, n, seed, chain, step,
+                       false, &cat, &net);
+  if (rc) return rc;
+  launch_batch_terms_out(n, ctx->ws.batch(), T_i, T_j, gT_i, gT_j, r, z, ctx->stream);
+  HIPCK(hipGetLastError(), "batch terms");
+  return check_select_flag(ctx);
+}
+
+int spider_batch_indices(spider_ctx* ctx, int32_t cat_id, uint64_t seed, int32_t chain,
+                         int64_t step, int64_t n, int64_t* idx_out) {
+  if (!ctx) return SPIDER_E_INVALID;
+  DeviceGuard g(ctx->device);
+  Catalog* cat = get_cat(ctx, cat_id);
+  if (!cat) return fail(ctx, SPIDER_E_INVALID, "unknown catalog id");
+  if (n < 1 || n > cat->N) return fail(ctx, SPIDER_E_INVALID, "need 1 <= n <= N");
+  if (!idx_out || chain < 0 || step < 0) return fail(ctx, SPIDER_E_INVALID, "bad argument");
+  int rc = reset_err_flag(ctx);
+  if (rc) return rc;
+  HIPCK(ctx->ws.reserve(1, n, cat->M, cat->L), "workspace");
+  BatchBufs b = ctx->ws.batch();
+  launch_select(cat->view(), 1, n, nullptr, seed, nullptr, step, chain, b, ctx->ws.err.as<int>(),
+                ctx->stream);
+  HIPCK(hipMemcpyAsync(idx_out, b.obs, (size_t)n * 8, hipMemcpyDeviceToDevice, ctx->stream),
+        "copy indices");
+  return check_select_flag(ctx);
+}
+
+int spider_noise(spider_ctx* ctx, int32_t cat_id, uint64_t seed, int32_t chain, int64_t step,
+                 double* eta_out) {
+  if (!ctx) return SPIDER_E_INVALID;
+  DeviceGuard g(ctx->device);
+  Catalog* cat = get_cat(ctx, cat_id);
+  if (!cat) return fail(ctx, SPIDER_E_INVALID, "unknown catalog id");
+  if (!eta_out || chain < 0 || step < 0) return fail(ctx, SPIDER_E_INVALID, "bad argument");
+  launch_noise(cat->view(), seed, chain, step, eta_out, ctx->stream);
+  HIPCK(hipGetLastError(), "noise");
+  return SPIDER_OK;
+}
+
+int spider_reset_chains(spider_ctx* ctx, int32_t cat_id, int32_t n_chains) {
+  if (!ctx) return SPIDER_E_INVALID;
+  DeviceGuard g(ctx->device);
+  Catalog* cat = get_cat(ctx, cat_id);
+  if (!cat) return fail(ctx, SPIDER_E_INVALID, "unknown catalog id");
+  if (n_chains < 1 || n_chains > 4096) return fail(ctx, SPIDER_E_INVALID, "need 1 <= n_chains <= 4096");
+  const size_t per = (size_t)cat->M * 4;
+  const int C = n_chains;
+  HIPCK(hipStreamSynchronize(ctx->stream), "sync");
+  HIPCK(cat->theta.alloc(per * C * 8), "alloc chains");
+  HIPCK(cat->v.alloc(per * C * 8), "alloc chains");
+  HIPCK(cat->mean.alloc(per * C * 8), "alloc chains");
+  HIPCK(cat->m2.alloc((size_t)cat->M * 10 * C * 8), "alloc chains");
+  HIPCK(cat->steps.alloc((size_t)C * 8), "alloc chains");
+  HIPCK(cat->mcount.alloc((size_t)C * 8), "alloc chains");
+  for (int c = 0; c < C; ++c)
+    HIPCK(hipMemcpyAsync(cat->theta.as<double>() + per * c, cat->hypo0.p, per * 8,
+                         hipMemcpyDeviceToDevice, ctx->stream),
+          "init chains");
+  launch_fill(cat->v.as<double>(), 0.0, (int64_t)per * C, ctx->stream);
+  launch_fill(cat->mean.as<double>(), 0.0, (int64_t)per * C, ctx->stream);
+  launch_fill(cat->m2.as<double>(), 0.0, (int64_t)cat->M * 10 * C, ctx->stream);
+  HIPCK(hipMemsetAsync(cat->steps.p, 0, (size_t)C * 8, ctx->stream), "init chains");
+  HIPCK(hipMemsetAsync(cat->mcount.p, 0, (size_t)C * 8, ctx->stream), "init chains");
+  HIPCK(hipGetLastError(), "init chains");
+  cat->C = C;
+  return SPIDER_OK;
+}
+
+int spider_sgld_steps(spider_ctx* ctx, const spider_chainset* sets, int32_t n_sets,
+                      const spider_sgld_cfg* cfg) {
+  if (!ctx) return SPIDER_E_INVALID;
+  DeviceGuard g(ctx->device);
+  if (!sets || n_sets < 1 || !cfg) return fail(ctx, SPIDER_E_INVALID, "null or empty arguments");
+  if (!(cfg->step > 0) || !(cfg->beta2 >= 0 && cfg->beta2 <= 1) || !(cfg->eps_p > 0) ||
+      !std::isfinite(cfg->noise_scale) || cfg->noise_scale < 0 || cfg->n_steps < 0 ||
+      cfg->burn_in < 0 || cfg->thin < 1 || (cfg->precond != 0 && cfg->precond != 1))
+    return fail(ctx, SPIDER_E_INVALID, "invalid sampler configuration");
+  for (int k = 0; k < n_sets; ++k) {
+    const spider_chainset& st = sets[k];
+    Catalog* cat = get_cat(ctx, st.cat_id);
+    Net* net = get_net(ctx, st.net_id);
+    if (!cat || !net) return fail(ctx, SPIDER_E_INVALID, "unknown catalog or network id");
+    if (st.n_chains < 1 || st.batch < 1 || st.batch > cat->N)
+      return fail(ctx, SPIDER_E_INVALID, "need n_chains >= 1 and 1 <= batch <= N");
+    if (st.precision != SPIDER_FP32 && st.precision != SPIDER_BF16)
+      return fail(ctx, SPIDER_E_INVALID, "unknown precision");
+    if (cat->C < st.n_chains) {
+      int rc = spider_reset_chains(ctx, st.cat_id, st.n_chains);
+      if (rc) return rc;
+    }
+  }
+  int rc = reset_err_flag(ctx);
+  if (rc) return rc;
+  UpdateArgs ua;
+  ua.step = cfg->step;
+  ua.beta2 = cfg->beta2;
+  ua.eps_p = cfg->eps_p;
+  ua.noise_scale = cfg->noise_scale;
+  ua.precond = cfg->precond;
+  ua.seed = cfg->seed;
+  ua.burn = cfg->burn_in;
+  ua.thin = cfg->thin;
+  for (int64_t t = 0; t < cfg->n_steps; ++t) {
+    for (int k = 0; k < n_sets; ++k) {
+      const spider_chainset& st = sets[k];
+      Catalog& cat = *get_cat(ctx, st.cat_id);
+      Net& net = *get_net(ctx, st.net_id);
+      const int C = st.n_chains;
+      rc = run_batch(ctx, cat, net, st.precision, C, st.batch, cat.theta.as<double>(),
+                     (int64_t)cat.M * 4, nullptr, cfg->seed, cat.steps.as<int64_t>(), 0, 0, true,
+                     (double)cat.N / (double)st.batch);
+      if (rc) return rc;
+      Workspace& ws = ctx->ws;
+      launch_centroid(cat.theta.as<double>(), C, cat.M, ws.partial.as<double>(),
+                      ws.thetabar.as<double>(), ctx->stream);
+      launch_update(cat.view(), C, cat.theta.as<double>(), cat.v.as<double>(), ws.G.as<double>(),
+                    ws.thetabar.as<double>(), cat.steps.as<int64_t>(), cat.mcount.as<int64_t>(), ua,
+                    cat.mean.as<double>(), cat.m2.as<double>(), ctx->stream);
+      HIPCK(hipGetLastError(), "update");
+    }
+  }
+  // numeric check of every chain state
+  for (int k = 0; k < n_sets; ++k) {
+    const spider_chainset& st = sets[k];
+    Catalog& cat = *get_cat(ctx, st.cat_id);
+    DevBuf bad;
+    HIPCK(bad.alloc(16), "alloc");
+    const int big = INT_MAX;
+    HIPCK(hipMemcpyAsync(bad.p, &big, sizeof(int), hipMemcpyHostToDevice, ctx->stream), "flag");
+    launch_finite(cat.theta.as<double>(), (int64_t)cat.M * 4 * st.n_chains, (int64_t)cat.M * 4,
+                  bad.as<int>(), ctx->stream);
+    int first = INT_MAX;
+    HIPCK(hipMemcpyAsync(&first, bad.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream), "flag");
+    HIPCK(hipStreamSynchronize(ctx->stream), "sync");
+    if (first != INT_MAX) {
+      char msg[160];
+      std::snprintf(msg, sizeof msg, "non-finite state in catalog %d chain %d", st.cat_id, first);
+      return fail(ctx, SPIDER_E_NUMERIC, msg);
+    }
+  }
+  return check_select_flag(ctx);
+}
+
+int spider_moments(spider_ctx* ctx, int32_t cat_id, int32_t chain, double* mean, double* cov,
+                   int64_t* count) {
+  if (!ctx) return SPIDER_E_INVALID;
+  DeviceGuard g(ctx->device);
+  Catalog* cat = get_cat(ctx, cat_id);
+  if (!cat) return fail(ctx, SPIDER_E_INVALID, "unknown catalog id");
+  if (cat->C == 0) return fail(ctx, SPIDER_E_STATE, "catalog has no chains");
+  if (chain < -1 || chain >= cat->C) return fail(ctx, SPIDER_E_INVALID, "bad chain index");
+  const int c0 = chain < 0 ? 0 : chain;
+  const int C = chain < 0 ? cat->C : 1;
+  std::vector<int64_t> cnt(cat->C);
+  HIPCK(hipMemcpyAsync(cnt.data(), cat->mcount.p, cnt.size() * 8, hipMemcpyDeviceToHost,
+                       ctx->stream),
+        "read counts");
+  HIPCK(hipStreamSynchronize(ctx->stream), "sync");
+  int64_t total = 0;
+  for (int c = c0; c < c0 + C; ++c) total += cnt[c];
+  if (count) *count = total;
+  launch_pool_moments(C, cat->M, cat->mean.as<double>() + (size_t)c0 * cat->M * 4,
+                      cat->m2.as<double>() + (size_t)c0 * cat->M * 10,
+                      cat->mcount.as<int64_t>() + c0, mean, cov, ctx->stream);
+  HIPCK(hipGetLastError(), "moments");
+  return SPIDER_OK;
+}
+
+int spider_get_state(spider_ctx* ctx, int32_t cat_id, int32_t chain, double* theta, double* v,
+                     int64_t* step) {
+  if (!ctx) return SPIDER_E_INVALID;
+  DeviceGuard g(ctx->device);
+  Catalog* cat = get_cat(ctx, cat_id);
+  if (!cat) return fail(ctx, SPIDER_E_INVALID, "unknown catalog id");
+  if (chain < 0 || chain >= cat->C) return fail(ctx, SPIDER_E_INVALID, "bad chain index");
+  const size_t per = (size_t)cat->M * 4;
+  if (theta)
+    HIPCK(hipMemcpyAsync(theta, cat->theta.as<double>() + per * chain, per * 8,
+                         hipMemcpyDeviceToDevice, ctx->stream),
+          "copy state");
+  if (v)
+    HIPCK(hipMemcpyAsync(v, cat->v.as<double>() + per * chain, per * 8, hipMemcpyDeviceToDevice,
+                         ctx->stream),
+          "copy state");
+  if (step) {
+    HIPCK(hipMemcpyAsync(step, cat->steps.as<int64_t>() + chain, 8, hipMemcpyDeviceToHost,
+                         ctx->stream),
+          "copy step");
+    HIPCK(hipStreamSynchronize(ctx->stream), "sync");
+  }
+  return SPIDER_OK;
+}
+
+int spider_set_state(spider_ctx* ctx, int32_t cat_id, int32_t chain, const double* theta,
+                     const double* v, int64_t step) {
+  if (!ctx) return SPIDER_E_INVALID;
+  DeviceGuard g(ctx->device);
+  Catalog* cat = get_cat(ctx, cat_id);
+  if (!cat) return fail(ctx, SPIDER_E_INVALID, "unknown catalog id");
+  if (chain < 0 || chain >= cat->C) return fail(ctx, SPIDER_E_INVALID, "bad chain index");
+  if (!theta || step < 0) return fail(ctx, SPIDER_E_INVALID, "null theta or negative step");
+  const size_t per = (size_t)cat->M * 4;
+  HIPCK(hipMemcpyAsync(cat->theta.as<double>() + per * chain, theta, per * 8,
+                       hipMemcpyDeviceToDevice, ctx->stream),
+        "copy state");
+  if (v)
+    HIPCK(hipMemcpyAsync(cat->v.as<double>() + per * chain, v, per * 8, hipMemcpyDeviceToDevice,
+                         ctx->stream),
+          "copy state");
+  else
+    launch_fill(cat->v.as<double>() + per * chain, 0.0, (int64_t)per, ctx->stream);
+  HIPCK(hipMemcpyAsync(cat->steps.as<int64_t>() + chain, &step, 8, hipMemcpyHostToDevice,
+                       ctx->stream),
+        "copy step");
+  HIPCK(hipStreamSynchronize(ctx->stream), "sync");
+  return SPIDER_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,208 @@
+// Internal declarations of libspider shared by the HIP translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace spider {
+
+// One observation record in HBM: 12 bytes, loaded as three dwords.
+struct Obs {
+  int32_t pair;
+  float dt;
+  int32_t sta;
+};
+
+// Where the network's input rows come from.
+//  mode 0 (minibatch): row r is event ev[r] of chain r / rows_per_chain at
+//          station sta[r]; x = theta[chain][ev][0:3], s = stations[sta].
+//  mode 1 (explicit):  x = x[r][0:3], s = s[r][0:3].
+struct RowSource {
+  int mode;
+  int64_t rows;
+  const int32_t* ev;
+  const int32_t* sta;
+  const double* theta;
+  int64_t rows_per_chain;
+  int64_t theta_chain_stride;  // doubles between chains' states (M * 4)
+  const double* stations;
+  const double* x;
+  const double* s;
+};
+
+// Network as the kernels see it (device pointers).
+struct NetView {
+  int D, H;
+  const float* W0;     // [H][6]
+  const float* bias;   // [D][H]: b[0] .. b[D-1]
+  const float* Wt;     // [D-1][H][H]: Wt[l][k][n] = W[l+1][n][k] (input-major)
+  const float* wout;   // [H]
+  float bout;
+  double v0;
+  double center[3];
+  double half[3];
+  const void* pack_fwd;  // matrix-core operand packs (precision dependent)
+  const void* pack_bwd;
+};
+
+// Per-row network result: o and do/du for the three source inputs.
+struct RowOut {
+  float o, d0, d1, d2;
+};
+
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Computes the network inputs u of row r.
+__device__ inline void row_inputs(const RowSource& src, const NetView& net, int64_t r, float u[6]) {
+  double x[3], s[3];
+  if (src.mode == 0) {
+    const int64_t c = r / src.rows_per_chain;
+    const double* th = src.theta + c * src.theta_chain_stride + (int64_t)src.ev[r] * 4;
+    const double* st = src.stations + (int64_t)src.sta[r] * 3;
+    for (int a = 0; a < 3; ++a) {
+      x[a] = th[a];
+      s[a] = st[a];
+    }
+  } else {
+    for (int a = 0; a < 3; ++a) {
+      x[a] = src.x[r * 3 + a];
+      s[a] = src.s[r * 3 + a];
+    }
+  }
+  for (int a = 0; a < 3; ++a) {
+    u[a] = (float)((x[a] - net.center[a]) / net.half[a]);
+    u[3 + a] = (float)((s[a] - net.center[a]) / net.half[a]);
+  }
+}
+
+// tanh(z) and 1 - tanh(z)^2 from one exponential: with q = 2 / (1 + e^{2|z|}),
+// tanh|z| = 1 - q and 1 - tanh^2 = q (2 - q), accurate also where tanh -> +-1.
+__device__ inline void tanh_d(float z, float& a, float& d) {
+  const float e = __expf(2.0f * fabsf(z));
+  const float q = 2.0f / (1.0f + e);
+  a = copysignf(1.0f - q, z);
+  d = q * (2.0f - q);
+}
+
+// Catalog as the step kernels see it.
+struct CatView {
+  int32_t M, L;
+  int64_t N;
+  const double* hypo0;     // [M][4]
+  const double* stations;  // [L][3]
+  const int2* pairs;       // [P] (i, j)
+  const double* w_pair;    // [P] unnormalised edge weight
+  const Obs* obs;          // [N]
+  const double* inv_mean;  // [L] 1 / group mean of the edge weights
+  const double* mu_c;      // [4] centroid prior mean
+  uint32_t stream;
+  double sigma, kappa;
+  double prior_sigma[4], centroid_sigma[4];
+};
+
+// Minibatch buffers of C chains x n slots.  Slot q = c * n + k; entry/row
+// 2q is event i of the slot and 2q + 1 is event j.
+struct BatchBufs {
+  int64_t* obs;     // [C n] observation index
+  int32_t* ev;      // [2 C n] event of each row
+  int32_t* sta;     // [2 C n] station (= group) of each row
+  double* tau;      // [C n] observed differential time
+  double* w;        // [C n] normalised edge weight
+  RowOut* net_out;  // [2 C n]
+  double* T;        // [2 C n] travel time of each row
+  double* gT;       // [2 C n][3] source gradient of each row
+  double* r;        // [C n] residual
+  double* z;        // [C n] whitened residual
+};
+
+// Scratch of the exact whitening and the per-event reduction.
+struct SortBufs {
+  uint64_t* key_in;
+  uint64_t* key_out;
+  uint32_t* val_in;
+  uint32_t* val_out;
+  void* temp;
+  size_t temp_bytes;
+  int32_t* node_of;    // [2 C n] node of each entry
+  int32_t* node_start; // [2 C n + 1] first sorted position of each node
+  int32_t* seg_begin;  // [C L] first node of each (chain, group)
+  int32_t* seg_end;    // [C L]
+  int32_t* flags;      // [2 C n] scratch
+  double* vec;         // [6][2 C n] PCG vectors
+  int32_t* count;      // [1] device node count
+};
+
+// ---- launchers (each enqueues on stream s; errors surface via hipGetLastError)
+// Network kernels (mlp_*.hip).  Unsupported shapes return hipErrorNotSupported.
+hipError_t launch_mlp_tangent(const RowSource& src, const NetView& net, RowOut* out,
+                              hipStream_t stream);
+hipError_t launch_mlp_mfma(int precision, const RowSource& src, const NetView& net, RowOut* out,
+                           hipStream_t stream);
+bool mlp_mfma_supported(int precision, int H, int D);
+// Bytes of the forward (or backward) operand pack of one hidden layer.
+size_t mfma_pack_bytes(int precision, int H);
+// Packs hidden layer W (row-major [H][H] fp32, host) into the forward and
+// backward matrix-core operand orders (host buffers of mfma_pack_bytes each).
+void mfma_pack_layer(int precision, int H, const float* W, void* fwd, void* bwd);
+
+// Load-time kernels (step.hip).
+void launch_pair_weights(const double* hypo0, const int2* pairs, int64_t P, double ell, double p,
+                         double eps_w, double* w_pair, hipStream_t s);
+void launch_validate(const double* hypo0, int M, const double* stations, int L, const int2* pairs,
+                     int64_t P, const Obs* obs, int64_t N, int* bad, hipStream_t s);
+// inv_mean[g] = count_g / sum of w~ over group g; deterministic.
+hipError_t group_inverse_mean(const Obs* obs, int64_t N, int L, const double* w_pair,
+                              double* inv_mean, hipStream_t s);
+// out[c] = mean over rows of a [rows][4] array (c = 0..3); deterministic.
+void launch_mean4(const double* a, int64_t rows, double* out, hipStream_t s);
+
+// Step kernels (step.hip).
+// Minibatch of each chain: explicit indices idx (all chains) or, if idx is
+// null, the Feistel minibatch of chain chain0 + c at step steps[c] (device)
+// or, if steps is null, at step_scalar.  err_flag |= 1 on a failed walk.
+void launch_select(const CatView& cat, int C, int64_t n, const int64_t* idx, uint64_t seed,
+                   const int64_t* steps, int64_t step_scalar, int chain0, BatchBufs b,
+                   int* err_flag, hipStream_t s);
+void launch_residual(const CatView& cat, const NetView& net, int C, int64_t n,
+                     const double* theta, int64_t theta_stride, int whiten, BatchBufs b,
+                     hipStream_t s);
+// Exact whitening z = Sigma_B^{-1} r by Woodbury + per-(chain, group) PCG.
+hipError_t exact_whiten(const CatView& cat, int C, int64_t n, BatchBufs b, SortBufs sb,
+                        hipStream_t s);
+// G_lik[c][m] = scale * sum over the chain's batch of the event's terms.
+hipError_t reduce_events(const CatView& cat, int C, int64_t n, double scale, BatchBufs b,
+                         SortBufs sb, double* G, hipStream_t s);
+size_t sort_temp_bytes(int64_t entries);
+// thetabar[c] = mean over events of theta[c] (4 values per chain).
+void launch_centroid(const double* theta, int C, int M, double* partial, double* thetabar,
+                     hipStream_t s);
+struct UpdateArgs {
+  double step, beta2, eps_p, noise_scale;
+  int precond;
+  uint64_t seed;
+  int64_t burn, thin;
+};
+// Priors + Langevin update of chains 0..C-1 at their device step counters,
+// Welford moments on recording steps, then steps[c] += 1 (and mcount[c] on
+// recording steps).
+void launch_update(const CatView& cat, int C, double* theta, double* v, const double* G,
+                   const double* thetabar, int64_t* steps, int64_t* mcount, const UpdateArgs& a,
+                   double* mean, double* m2, hipStream_t s);
+void launch_grad_finish(const CatView& cat, const double* theta, const double* G,
+                        const double* thetabar, unsigned flags, double* grad_out, hipStream_t s);
+// logpost = -scale/2 sum r z + priors (flags), deterministic; tmp >= 2 * 1024 doubles.
+void launch_logpost(const CatView& cat, int64_t n, double scale, const double* r, const double* z,
+                    const double* theta, const double* thetabar, unsigned flags, double* tmp,
+                    double* out, hipStream_t s);
+void launch_tt_assemble(const NetView& net, int64_t rows, const double* x, const double* s,
+                        const RowOut* out, double* T, double* gradT, hipStream_t st);
+void launch_batch_terms_out(int64_t n, const BatchBufs& b, double* T_i, double* T_j, double* gT_i,
+                            double* gT_j, double* r, double* z, hipStream_t s);
+void launch_noise(const CatView& cat, uint64_t seed, int chain, int64_t step, double* eta,
+                  hipStream_t s);
+void launch_finite(const double* a, int64_t count, int64_t per_chain, int* bad_chain,
+                   hipStream_t s);
+void launch_pool_moments(int C, int M, const double* mean, const double* m2, const int64_t* cnt,
+                         double* out_mean, double* out_cov, hipStream_t s);
+void launch_fill(double* p, double v, int64_t count, hipStream_t s);
+
+}  // namespace spider

@@ -1,0 +1,853 @@
+// Per-step kernels of the hot path other than the travel-time network, and
+// the catalog preparation done once at load.
+//
+//   select    minibatch without replacement (Sec. 3.2) and its gathers
+//   residual  T = |x - s|/v0 softplus(o)/ln2 and dT/dx in FP64 from the
+//             network outputs; r = tau - [T_i - T_j + t_i - t_j] (Eq. 1)
+//   whitening z = Sigma_B^{-1} r (Sec. 3.1, eq:marginal_sigma): diagonal, or
+//             exact by Woodbury + preconditioned CG per (chain, group)
+//   reduce    per-event gradient sum over a sorted (chain, event) list:
+//             every event's terms are contiguous, summed in a fixed order by
+//             one thread, no floating-point atomics (deterministic)
+//   centroid  per-chain mean of theta (fixed-order two-level reduction)
+//   update    priors + SGLD / pSGLD (eq:pSGLD) + Philox noise + Welford
+#include <cstring>
+
+#include <rocprim/rocprim.hpp>
+
+#include "device_rng.h"
+#include "internal.h"
+
+namespace spider {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr double kLn2 = 0.69314718055994530941723212145818;
+
+inline unsigned grid_for(int64_t n, int block = kBlock) {
+  int64_t g = ceil_div(n, block);
+  if (g < 1) g = 1;
+  return (unsigned)g;
+}
+
+// Fixed-order block sum of one double per thread (blockDim == kBlock).
+__device__ inline double block_sum(double v, double* sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (t < w) sh[t] += sh[t + w];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// ---------------------------------------------------------------- load time
+
+__global__ void k_pair_weights(const double* hypo0, const int2* pairs, int64_t P, double ell,
+                               double p, double eps_w, double* w_pair) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= P) return;
+  const int2 ij = pairs[e];
+  const double* a = hypo0 + (int64_t)ij.x * 4;
+  const double* b = hypo0 + (int64_t)ij.y * 4;
+  const double dx = a[0] - b[0], dy = a[1] - b[1], dz = a[2] - b[2];
+  const double d = sqrt(dx * dx + dy * dy + dz * dz);
+  w_pair[e] = pow(d / ell, p) + eps_w;
+}
+
+// bad bits: 1 id out of range / i == j, 2 non-finite value, 4 source at a station
+__global__ void k_validate(const double* hypo0, int M, const double* stations, int L,
+                           const int2* pairs, int64_t P, const Obs* obs, int64_t N, int* bad) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int flag = 0;
+  if (t < P) {
+    const int2 ij = pairs[t];
+    if (ij.x < 0 || ij.x >= M || ij.y < 0 || ij.y >= M || ij.x == ij.y) flag |= 1;
+  }
+  if (t < M) {
+    for (int a = 0; a < 4; ++a)
+      if (!isfinite(hypo0[t * 4 + a])) flag |= 2;
+  }
+  if (t < L) {
+    for (int a = 0; a < 3; ++a)
+      if (!isfinite(stations[t * 3 + a])) flag |= 2;
+  }
+  if (t < N) {
+    const Obs o = obs[t];
+    if (o.pair < 0 || o.pair >= P || o.sta < 0 || o.sta >= L) {
+      flag |= 1;
+    } else {
+      if (!isfinite(o.dt)) flag |= 2;
+      const int2 ij = pairs[o.pair];
+      if (ij.x >= 0 && ij.x < M && ij.y >= 0 && ij.y < M) {
+        const double* s = stations + (int64_t)o.sta * 3;
+        for (int side = 0; side < 2; ++side) {
+          const double* x = hypo0 + (int64_t)(side ? ij.y : ij.x) * 4;
+          const double d2 = (x[0] - s[0]) * (x[0] - s[0]) + (x[1] - s[1]) * (x[1] - s[1]) +
+                            (x[2] - s[2]) * (x[2] - s[2]);
+          if (!(d2 >= 1e-6)) flag |= 4;
+        }
+      }
+    }
+  }
+  if (flag) atomicOr(bad, flag);
+}
+
+__global__ void k_obs_group_keys(const Obs* obs, int64_t N, uint32_t* keys, uint32_t* vals) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N) return;
+  keys[t] = (uint32_t)obs[t].sta;
+  vals[t] = (uint32_t)t;
+}
+
+// One block per group: binary search of the group's range in the sorted keys,
+// then a fixed-order sum of its weights.
+__global__ void k_group_mean(const uint32_t* keys, const uint32_t* vals, int64_t N, const Obs* obs,
+                             const double* w_pair, double* inv_mean) {
+  __shared__ double sh[kBlock];
+  const uint32_t g = blockIdx.x;
+  int64_t lo = 0, hi = N;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) / 2;
+    if (keys[mid] < g) lo = mid + 1; else hi = mid;
+  }
+  const int64_t begin = lo;
+  hi = N;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) / 2;
+    if (keys[mid] <= g) lo = mid + 1; else hi = mid;
+  }
+  const int64_t end = lo;
+  double s = 0.0;
+  for (int64_t q = begin + threadIdx.x; q < end; q += kBlock) s += w_pair[obs[vals[q]].pair];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) inv_mean[g] = end > begin ? (double)(end - begin) / s : 0.0;
+}
+
+__global__ void k_mean4(const double* a, int64_t rows, double* out) {
+  __shared__ double sh[kBlock];
+  for (int c = 0; c < 4; ++c) {
+    double s = 0.0;
+    for (int64_t m = threadIdx.x; m < rows; m += kBlock) s += a[m * 4 + c];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) out[c] = s / (double)rows;
+  }
+}
+
+// ---------------------------------------------------------------- step
+
+__global__ void k_select(CatView cat, int C, int64_t n, const int64_t* idx, uint32_t k0,
+                         uint32_t k1, const int64_t* steps, int64_t step_scalar, int chain0,
+                         BatchBufs b, int* err) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= (int64_t)C * n) return;
+  const int c = (int)(q / n);
+  const int64_t k = q - (int64_t)c * n;
+  int64_t o;
+  if (idx) {
+    o = idx[k];
+  } else {
+    const int64_t t = steps ? steps[c] : step_scalar;
+    const int64_t B = cat.N / n;
+    const int64_t epoch = t / B;
+    const int64_t j = t - epoch * B;
+    const FeistelShape sh = feistel_shape(cat.N);
+    o = feistel_permute(j * n + k, cat.N, sh, k0, k1, cat.stream, (uint32_t)(chain0 + c),
+                        (uint32_t)epoch);
+  }
+  if (o < 0 || o >= cat.N) {
+    atomicOr(err, 1);
+    o = 0;
+  }
+  const Obs ob = cat.obs[o];
+  const int2 ij = cat.pairs[ob.pair];
+  b.obs[q] = o;
+  b.ev[2 * q] = ij.x;
+  b.ev[2 * q + 1] = ij.y;
+  b.sta[2 * q] = ob.sta;
+  b.sta[2 * q + 1] = ob.sta;
+  b.tau[q] = (double)ob.dt;
+  b.w[q] = cat.w_pair[ob.pair] * cat.inv_mean[ob.sta];
+}
+
+// Travel time and source gradient of one row from the network output.
+__device__ inline void assemble_tt(const NetView& net, const double x[3], const double s[3],
+                                   const RowOut& no, double& T, double g[3]) {
+  const double d0 = x[0] - s[0], d1 = x[1] - s[1], d2 = x[2] - s[2];
+  const double dist = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+  const double T0 = dist / net.v0;
+  const double o = (double)no.o;
+  const double sp = fmax(o, 0.0) + log1p(exp(-fabs(o)));      // softplus
+  const double sg = o >= 0.0 ? 1.0 / (1.0 + exp(-o)) : exp(o) / (1.0 + exp(o));  // sigmoid
+  const double f = sp / kLn2;
+  T = T0 * f;
+  const double a = f / (net.v0 * dist);
+  const double bsc = T0 * sg / kLn2;
+  g[0] = a * d0 + bsc * ((double)no.d0 / net.half[0]);
+  g[1] = a * d1 + bsc * ((double)no.d1 / net.half[1]);
+  g[2] = a * d2 + bsc * ((double)no.d2 / net.half[2]);
+}
+
+__global__ void k_residual(CatView cat, NetView net, int C, int64_t n, const double* theta,
+                           int64_t theta_stride, int whiten, BatchBufs b) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= (int64_t)C * n) return;
+  const int c = (int)(q / n);
+  const double* th = theta + (int64_t)c * theta_stride;
+  double T[2], tt[2];
+  for (int side = 0; side < 2; ++side) {
+    const int64_t row = 2 * q + side;
+    const double* xe = th + (int64_t)b.ev[row] * 4;
+    const double* st = cat.stations + (int64_t)b.sta[row] * 3;
+    const double x[3] = {xe[0], xe[1], xe[2]};
+    const double s[3] = {st[0], st[1], st[2]};
+    double g[3];
+    assemble_tt(net, x, s, b.net_out[row], T[side], g);
+    b.T[row] = T[side];
+    b.gT[row * 3 + 0] = g[0];
+    b.gT[row * 3 + 1] = g[1];
+    b.gT[row * 3 + 2] = g[2];
+    tt[side] = xe[3];
+  }
+  const double r = b.tau[q] - ((T[0] - T[1]) + (tt[0] - tt[1]));
+  b.r[q] = r;
+  const double s2 = cat.sigma * cat.sigma;
+  if (whiten == 0 || cat.kappa == 0.0) {
+    b.z[q] = r / s2;
+  } else if (whiten == 1) {
+    b.z[q] = r / (s2 + 2.0 * cat.kappa * cat.kappa * b.w[q]);
+  }
+}
+
+// ---- exact whitening: Sigma_B = s2 I + k2 U U^T, U = W^{1/2} A_B.
+// z = (r - U y)/s2 with (lambda I + U^T U) y = U^T r, lambda = s2/k2.  U^T U
+// is the w-weighted Laplacian of the batch's event graph in each group, so
+// the system is block diagonal over (chain, group); each block is solved by
+// Jacobi-preconditioned CG in FP64 by one workgroup.
+
+__global__ void k_group_keys(int C, int64_t n, int M, int L, const BatchBufs b, uint64_t* keys,
+                             uint32_t* vals) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 2 * (int64_t)C * n) return;
+  const int64_t c = (e >> 1) / n;
+  keys[e] = ((uint64_t)(c * L + b.sta[e]) * (uint64_t)M) + (uint64_t)b.ev[e];
+  vals[e] = (uint32_t)e;
+}
+
+__global__ void k_heads(const uint64_t* keys, int64_t E, int32_t* flags) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= E) return;
+  flags[p] = (p == 0 || keys[p] != keys[p - 1]) ? 1 : 0;
+}
+
+// After an inclusive scan of the head flags (flags -> node number + 1).
+__global__ void k_nodes(const uint64_t* keys, const uint32_t* vals, const int32_t* scan, int64_t E,
+                        int M, int32_t* node_of, int32_t* node_start, int32_t* seg_begin,
+                        int32_t* seg_end, int32_t* count) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= E) return;
+  const int32_t node = scan[p] - 1;
+  node_of[vals[p]] = node;
+  const bool head = p == 0 || keys[p] != keys[p - 1];
+  if (head) {
+    node_start[node] = (int32_t)p;
+    const uint64_t seg = keys[p] / (uint64_t)M;
+    if (p == 0 || keys[p - 1] / (uint64_t)M != seg) seg_begin[seg] = node;
+  }
+  const bool tail = p == E - 1 || keys[p + 1] != keys[p];
+  if (tail) {
+    const uint64_t seg = keys[p] / (uint64_t)M;
+    if (p == E - 1 || keys[p + 1] / (uint64_t)M != seg) seg_end[seg] = node + 1;
+  }
+  if (p == E - 1) {
+    node_start[node + 1] = (int32_t)E;
+    *count = node + 1;
+  }
+}
+
+__global__ void k_fill_i32(int32_t* p, int32_t v, int64_t count) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < count) p[t] = v;
+}
+
+struct PcgArgs {
+  const uint32_t* vals;       // sorted entries
+  const int32_t* node_of;
+  const int32_t* node_start;
+  const int32_t* seg_begin;
+  const int32_t* seg_end;
+  const double* w;
+  const double* r;
+  double* y;                  // solution per node
+  double* rr;                 // residual
+  double* p;
+  double* ap;
+  double* dinv;
+  double lambda;
+  int max_iter;
+  double tol2;
+};
+
+// (lambda I + L) v at node q.
+__device__ inline double lap_apply(const PcgArgs& a, int32_t q, const double* v) {
+  double s = a.lambda * v[q];
+  const double vq = v[q];
+  for (int32_t p = a.node_start[q]; p < a.node_start[q + 1]; ++p) {
+    const uint32_t e = a.vals[p];
+    const double wk = a.w[e >> 1];
+    s += wk * (vq - v[a.node_of[e ^ 1u]]);
+  }
+  return s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_pcg(PcgArgs a) {
+  __shared__ double sh[kBlock];
+  const int32_t nb = a.seg_begin[blockIdx.x];
+  const int32_t ne = a.seg_end[blockIdx.x];
+  if (ne <= nb) return;
+  const int t = threadIdx.x;
+  // rhs U^T r, diagonal, initial guess 0
+  double bb = 0.0, rz = 0.0;
+  for (int32_t q = nb + t; q < ne; q += kBlock) {
+    double rhs = 0.0, dg = a.lambda;
+    for (int32_t p = a.node_start[q]; p < a.node_start[q + 1]; ++p) {
+      const uint32_t e = a.vals[p];
+      const double wk = a.w[e >> 1];
+      const double sgn = (e & 1u) ? -1.0 : 1.0;
+      rhs += sgn * sqrt(wk) * a.r[e >> 1];
+      dg += wk;
+    }
+    a.y[q] = 0.0;
+    a.rr[q] = rhs;
+    a.dinv[q] = 1.0 / dg;
+    a.p[q] = rhs / dg;
+    bb += rhs * rhs;
+    rz += rhs * rhs / dg;
+  }
+  bb = block_sum(bb, sh);
+  rz = block_sum(rz, sh);
+  if (bb == 0.0) return;  // y = 0 already written
+  for (int it = 0; it < a.max_iter; ++it) {
+    double pap = 0.0;
+    for (int32_t q = nb + t; q < ne; q += kBlock) {
+      const double v = lap_apply(a, q, a.p);
+      a.ap[q] = v;
+      pap += a.p[q] * v;
+    }
+    pap = block_sum(pap, sh);
+    const double alpha = rz / pap;
+    double rn = 0.0, rz_new = 0.0;
+    for (int32_t q = nb + t; q < ne; q += kBlock) {
+      a.y[q] += alpha * a.p[q];
+      const double rq = a.rr[q] - alpha * a.ap[q];
+      a.rr[q] = rq;
+      rn += rq * rq;
+      rz_new += rq * rq * a.dinv[q];
+    }
+    rn = block_sum(rn, sh);
+    rz_new = block_sum(rz_new, sh);
+    if (rn <= a.tol2 * bb) break;
+    const double beta = rz_new / rz;
+    rz = rz_new;
+    for (int32_t q = nb + t; q < ne; q += kBlock) a.p[q] = a.rr[q] * a.dinv[q] + beta * a.p[q];
+    __syncthreads();
+  }
+}
+
+__global__ void k_exact_z(int64_t Q, double s2, const double* w, const double* r,
+                          const int32_t* node_of, const double* y, double* z) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= Q) return;
+  const double yi = y[node_of[2 * q]];
+  const double yj = y[node_of[2 * q + 1]];
+  z[q] = (r[q] - sqrt(w[q]) * (yi - yj)) / s2;
+}
+
+// ---- per-event reduction
+
+__global__ void k_event_keys(int C, int64_t n, int M, const BatchBufs b, uint64_t* keys,
+                             uint32_t* vals) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 2 * (int64_t)C * n) return;
+  const int64_t c = (e >> 1) / n;
+  keys[e] = (uint64_t)c * (uint64_t)M + (uint64_t)b.ev[e];
+  vals[e] = (uint32_t)e;
+}
+
+__global__ void k_reduce_runs(const uint64_t* keys, const uint32_t* vals, int64_t E, double scale,
+                              const BatchBufs b, double* G) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= E) return;
+  const uint64_t key = keys[p];
+  if (p > 0 && keys[p - 1] == key) return;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  for (int64_t q = p; q < E && keys[q] == key; ++q) {
+    const uint32_t e = vals[q];
+    const double cz = ((e & 1u) ? -scale : scale) * b.z[e >> 1];
+    s0 += cz * b.gT[e * 3 + 0];
+    s1 += cz * b.gT[e * 3 + 1];
+    s2 += cz * b.gT[e * 3 + 2];
+    s3 += cz;
+  }
+  double* g = G + key * 4;
+  g[0] = s0;
+  g[1] = s1;
+  g[2] = s2;
+  g[3] = s3;
+}
+
+// ---- centroid, update, gradient assembly
+
+constexpr int kCentroidChunk = 4096;
+
+__global__ void k_centroid_partial(const double* theta, int M, int nchunk, double* partial) {
+  __shared__ double sh[kBlock];
+  const int c = blockIdx.y;
+  const int chunk = blockIdx.x;
+  const double* th = theta + (int64_t)c * M * 4;
+  const int64_t m0 = (int64_t)chunk * kCentroidChunk;
+  const int64_t m1 = min((int64_t)M, m0 + kCentroidChunk);
+  for (int a = 0; a < 4; ++a) {
+    double s = 0.0;
+    for (int64_t m = m0 + threadIdx.x; m < m1; m += kBlock) s += th[m * 4 + a];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) partial[((int64_t)c * nchunk + chunk) * 4 + a] = s;
+  }
+}
+
+__global__ void k_centroid_final(const double* partial, int nchunk, int M, double* thetabar) {
+  const int c = blockIdx.x;
+  const int a = threadIdx.x;
+  if (a >= 4) return;
+  double s = 0.0;
+  for (int k = 0; k < nchunk; ++k) s += partial[((int64_t)c * nchunk + k) * 4 + a];
+  thetabar[c * 4 + a] = s / (double)M;
+}
+
+struct UpdateKArgs {
+  double step, beta2, eps_p, noise_scale;
+  int precond;
+  uint32_t k0, k1;
+  int64_t burn, thin;
+};
+
+__device__ inline bool records(int64_t t, int64_t burn, int64_t thin) {
+  return t >= burn && (t - burn) % thin == 0;
+}
+
+__global__ void k_update(CatView cat, int C, double* theta, double* v, const double* G,
+                         const double* thetabar, const int64_t* steps, const int64_t* mcount,
+                         UpdateKArgs a, double* mean, double* m2) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= (int64_t)C * cat.M) return;
+  const int c = (int)(q / cat.M);
+  const int64_t m = q - (int64_t)c * cat.M;
+  const int64_t t = steps[c];
+  double eta[4];
+  noise4(a.k0, a.k1, cat.stream, (uint32_t)c, (uint32_t)t, (uint32_t)m, eta);
+  double x[4];
+  for (int k = 0; k < 4; ++k) {
+    const double th = theta[q * 4 + k];
+    const double sp = cat.prior_sigma[k], sc = cat.centroid_sigma[k];
+    const double g = G[q * 4 + k] - (th - cat.hypo0[m * 4 + k]) / (sp * sp) -
+                     (thetabar[c * 4 + k] - cat.mu_c[k]) / (sc * sc) / (double)cat.M;
+    double nt;
+    if (a.precond == 0) {
+      nt = th + a.step * g + a.noise_scale * sqrt(2.0 * a.step) * eta[k];
+    } else {
+      const double vv = a.beta2 * v[q * 4 + k] + (1.0 - a.beta2) * g * g;
+      v[q * 4 + k] = vv;
+      const double V = 1.0 / (sqrt(vv) + a.eps_p);
+      nt = th + a.step * V * g + a.noise_scale * sqrt(2.0 * a.step * V) * eta[k];
+    }
+    theta[q * 4 + k] = nt;
+    x[k] = nt;
+  }
+  if (records(t, a.burn, a.thin)) {
+    const double cnt = (double)(mcount[c] + 1);
+    double d[4], after[4];
+    for (int k = 0; k < 4; ++k) {
+      const double mu = mean[q * 4 + k];
+      d[k] = x[k] - mu;
+      const double nm = mu + d[k] / cnt;
+      mean[q * 4 + k] = nm;
+      after[k] = x[k] - nm;
+    }
+    int u = 0;
+    for (int i = 0; i < 4; ++i)
+      for (int j = i; j < 4; ++j, ++u) m2[q * 10 + u] += d[i] * after[j];
+  }
+}
+
+__global__ void k_advance(int C, int64_t* steps, int64_t* mcount, int64_t burn, int64_t thin) {
+  const int c = threadIdx.x + blockIdx.x * blockDim.x;
+  if (c >= C) return;
+  if (records(steps[c], burn, thin)) mcount[c] += 1;
+  steps[c] += 1;
+}
+
+__global__ void k_grad_finish(CatView cat, const double* theta, const double* G,
+                              const double* thetabar, unsigned flags, double* out) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= (int64_t)cat.M * 4) return;
+  const int k = (int)(q & 3);
+  double g = G[q];
+  if (flags & 1u) {
+    const double sp = cat.prior_sigma[k];
+    g -= (theta[q] - cat.hypo0[q]) / (sp * sp);
+  }
+  if (flags & 2u) {
+    const double sc = cat.centroid_sigma[k];
+    g -= (thetabar[k] - cat.mu_c[k]) / (sc * sc) / (double)cat.M;
+  }
+  out[q] = g;
+}
+
+// partial sums of -scale/2 r z (blocks of the batch) and the event prior
+__global__ void k_logpost_partial(CatView cat, int64_t n, double scale, const double* r,
+                                  const double* z, const double* theta, unsigned flags,
+                                  double* tmp) {
+  __shared__ double sh[kBlock];
+  const int64_t per = ceil_div(n, (int64_t)gridDim.x);
+  const int64_t q0 = (int64_t)blockIdx.x * per, q1 = min(n, q0 + per);
+  double s = 0.0;
+  for (int64_t q = q0 + threadIdx.x; q < q1; q += kBlock) s += r[q] * z[q];
+  s = -0.5 * scale * block_sum(s, sh);
+  double pr = 0.0;
+  if (flags & 1u) {
+    const int64_t per_m = ceil_div((int64_t)cat.M * 4, (int64_t)gridDim.x);
+    const int64_t m0 = (int64_t)blockIdx.x * per_m, m1 = min((int64_t)cat.M * 4, m0 + per_m);
+    for (int64_t q = m0 + threadIdx.x; q < m1; q += kBlock) {
+      const double d = (theta[q] - cat.hypo0[q]) / cat.prior_sigma[q & 3];
+      pr += d * d;
+    }
+    pr = -0.5 * block_sum(pr, sh);
+  }
+  if (threadIdx.x == 0) tmp[blockIdx.x] = s + pr;
+}
+
+__global__ void k_logpost_final(CatView cat, const double* tmp, int nb, const double* thetabar,
+                                unsigned flags, double* out) {
+  if (threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int k = 0; k < nb; ++k) s += tmp[k];
+  if (flags & 2u) {
+    for (int k = 0; k < 4; ++k) {
+      const double d = (thetabar[k] - cat.mu_c[k]) / cat.centroid_sigma[k];
+      s += -0.5 * d * d;
+    }
+  }
+  *out = s;
+}
+
+__global__ void k_tt_assemble(NetView net, int64_t rows, const double* x, const double* s,
+                              const RowOut* out, double* T, double* gradT) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  const double xx[3] = {x[r * 3], x[r * 3 + 1], x[r * 3 + 2]};
+  const double ss[3] = {s[r * 3], s[r * 3 + 1], s[r * 3 + 2]};
+  double tt, g[3];
+  assemble_tt(net, xx, ss, out[r], tt, g);
+  T[r] = tt;
+  if (gradT) {
+    gradT[r * 3] = g[0];
+    gradT[r * 3 + 1] = g[1];
+    gradT[r * 3 + 2] = g[2];
+  }
+}
+
+__global__ void k_batch_terms_out(int64_t n, BatchBufs b, double* Ti, double* Tj, double* gi,
+                                  double* gj, double* r, double* z) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  if (Ti) Ti[q] = b.T[2 * q];
+  if (Tj) Tj[q] = b.T[2 * q + 1];
+  for (int a = 0; a < 3; ++a) {
+    if (gi) gi[q * 3 + a] = b.gT[(2 * q) * 3 + a];
+    if (gj) gj[q * 3 + a] = b.gT[(2 * q + 1) * 3 + a];
+  }
+  if (r) r[q] = b.r[q];
+  if (z) z[q] = b.z[q];
+}
+
+__global__ void k_noise(CatView cat, uint32_t k0, uint32_t k1, int chain, uint32_t step,
+                        double* eta) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= cat.M) return;
+  double e[4];
+  noise4(k0, k1, cat.stream, (uint32_t)chain, step, (uint32_t)m, e);
+  for (int k = 0; k < 4; ++k) eta[m * 4 + k] = e[k];
+}
+
+__global__ void k_finite(const double* a, int64_t count, int64_t per_chain, int* bad_chain) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= count) return;
+  if (!isfinite(a[q])) atomicMin(bad_chain, (int)(q / per_chain));
+}
+
+__global__ void k_pool_moments(int C, int M, const double* mean, const double* m2,
+                               const int64_t* cnt, double* out_mean, double* out_cov) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= M) return;
+  double mu[4] = {0, 0, 0, 0}, s[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  double n = 0.0;
+  for (int c = 0; c < C; ++c) {
+    const double nc = (double)cnt[c];
+    if (nc == 0.0) continue;
+    const double* mc = mean + ((int64_t)c * M + m) * 4;
+    const double* sc = m2 + ((int64_t)c * M + m) * 10;
+    const double nn = n + nc;
+    double d[4];
+    for (int k = 0; k < 4; ++k) d[k] = mc[k] - mu[k];
+    const double f = n * nc / nn;
+    int u = 0;
+    for (int i = 0; i < 4; ++i)
+      for (int j = i; j < 4; ++j, ++u) s[u] += sc[u] + d[i] * d[j] * f;
+    for (int k = 0; k < 4; ++k) mu[k] += d[k] * (nc / nn);
+    n = nn;
+  }
+  if (out_mean)
+    for (int k = 0; k < 4; ++k) out_mean[m * 4 + k] = mu[k];
+  if (out_cov) {
+    const double div = n > 1.0 ? n - 1.0 : 1.0;
+    for (int u = 0; u < 10; ++u) out_cov[m * 10 + u] = s[u] / div;
+  }
+}
+
+__global__ void k_fill(double* p, double v, int64_t count) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < count) p[t] = v;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+
+void launch_pair_weights(const double* hypo0, const int2* pairs, int64_t P, double ell, double p,
+                         double eps_w, double* w_pair, hipStream_t s) {
+  hipLaunchKernelGGL(k_pair_weights, dim3(grid_for(P)), dim3(kBlock), 0, s, hypo0, pairs, P, ell,
+                     p, eps_w, w_pair);
+}
+
+void launch_validate(const double* hypo0, int M, const double* stations, int L, const int2* pairs,
+                     int64_t P, const Obs* obs, int64_t N, int* bad, hipStream_t s) {
+  int64_t mx = N;
+  if (P > mx) mx = P;
+  if (M > mx) mx = M;
+  if (L > mx) mx = L;
+  hipLaunchKernelGGL(k_validate, dim3(grid_for(mx)), dim3(kBlock), 0, s, hypo0, M, stations, L,
+                     pairs, P, obs, N, bad);
+}
+
+hipError_t group_inverse_mean(const Obs* obs, int64_t N, int L, const double* w_pair,
+                              double* inv_mean, hipStream_t s) {
+  uint32_t *k0 = nullptr, *k1 = nullptr, *v0 = nullptr, *v1 = nullptr;
+  void* temp = nullptr;
+  size_t temp_bytes = 0;
+  hipError_t e = hipSuccess;
+  int end_bit = 1;
+  while ((1 << end_bit) < L) ++end_bit;
+  do {
+    if ((e = hipMallocAsync((void**)&k0, N * 4, s)) != hipSuccess) break;
+    if ((e = hipMallocAsync((void**)&k1, N * 4, s)) != hipSuccess) break;
+    if ((e = hipMallocAsync((void**)&v0, N * 4, s)) != hipSuccess) break;
+    if ((e = hipMallocAsync((void**)&v1, N * 4, s)) != hipSuccess) break;
+    hipLaunchKernelGGL(k_obs_group_keys, dim3(grid_for(N)), dim3(kBlock), 0, s, obs, N, k0, v0);
+    if ((e = rocprim::radix_sort_pairs(nullptr, temp_bytes, k0, k1, v0, v1, (size_t)N, 0, end_bit,
+                                       s)) != hipSuccess)
+      break;
+    if ((e = hipMallocAsync(&temp, temp_bytes, s)) != hipSuccess) break;
+    if ((e = rocprim::radix_sort_pairs(temp, temp_bytes, k0, k1, v0, v1, (size_t)N, 0, end_bit,
+                                       s)) != hipSuccess)
+      break;
+    hipLaunchKernelGGL(k_group_mean, dim3(L), dim3(kBlock), 0, s, k1, v1, N, obs, w_pair,
+                       inv_mean);
+    e = hipGetLastError();
+  } while (false);
+  (void)hipFreeAsync(k0, s);
+  (void)hipFreeAsync(k1, s);
+  (void)hipFreeAsync(v0, s);
+  (void)hipFreeAsync(v1, s);
+  if (temp) (void)hipFreeAsync(temp, s);
+  return e;
+}
+
+void launch_mean4(const double* a, int64_t rows, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_mean4, dim3(1), dim3(kBlock), 0, s, a, rows, out);
+}
+
+void launch_select(const CatView& cat, int C, int64_t n, const int64_t* idx, uint64_t seed,
+                   const int64_t* steps, int64_t step_scalar, int chain0, BatchBufs b,
+                   int* err_flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_select, dim3(grid_for((int64_t)C * n)), dim3(kBlock), 0, s, cat, C, n, idx,
+                     (uint32_t)seed, (uint32_t)(seed >> 32), steps, step_scalar, chain0, b,
+                     err_flag);
+}
+
+void launch_residual(const CatView& cat, const NetView& net, int C, int64_t n,
+                     const double* theta, int64_t theta_stride, int whiten, BatchBufs b,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_residual, dim3(grid_for((int64_t)C * n)), dim3(kBlock), 0, s, cat, net, C,
+                     n, theta, theta_stride, whiten, b);
+}
+
+size_t sort_temp_bytes(int64_t entries) {
+  size_t bytes = 0;
+  (void)rocprim::radix_sort_pairs(nullptr, bytes, (uint64_t*)nullptr, (uint64_t*)nullptr,
+                            (uint32_t*)nullptr, (uint32_t*)nullptr, (size_t)entries, 0, 64,
+                            (hipStream_t)0);
+  size_t scan = 0;
+  (void)rocprim::inclusive_scan(nullptr, scan, (int32_t*)nullptr, (int32_t*)nullptr, (size_t)entries,
+                          rocprim::plus<int32_t>(), (hipStream_t)0);
+  return bytes > scan ? bytes : scan;
+}
+
+static int bits_for(uint64_t maxval) {
+  int b = 1;
+  while (b < 64 && (maxval >> b) != 0) ++b;
+  return b;
+}
+
+hipError_t exact_whiten(const CatView& cat, int C, int64_t n, BatchBufs b, SortBufs sb,
+                        hipStream_t s) {
+  const int64_t E = 2 * (int64_t)C * n;
+  const int end_bit = bits_for((uint64_t)C * cat.L * (uint64_t)cat.M);
+  hipLaunchKernelGGL(k_group_keys, dim3(grid_for(E)), dim3(kBlock), 0, s, C, n, cat.M, cat.L, b,
+                     sb.key_in, sb.val_in);
+  size_t tb = sb.temp_bytes;
+  hipError_t e = rocprim::radix_sort_pairs(sb.temp, tb, sb.key_in, sb.key_out, sb.val_in,
+                                           sb.val_out, (size_t)E, 0, end_bit, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_heads, dim3(grid_for(E)), dim3(kBlock), 0, s, sb.key_out, E, sb.flags);
+  int32_t* scan = (int32_t*)sb.key_in;  // key_in is free after the sort
+  tb = sb.temp_bytes;
+  e = rocprim::inclusive_scan(sb.temp, tb, sb.flags, scan, (size_t)E, rocprim::plus<int32_t>(), s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_fill_i32, dim3(grid_for((int64_t)C * cat.L)), dim3(kBlock), 0, s,
+                     sb.seg_begin, 0, (int64_t)C * cat.L);
+  hipLaunchKernelGGL(k_fill_i32, dim3(grid_for((int64_t)C * cat.L)), dim3(kBlock), 0, s,
+                     sb.seg_end, 0, (int64_t)C * cat.L);
+  hipLaunchKernelGGL(k_nodes, dim3(grid_for(E)), dim3(kBlock), 0, s, sb.key_out, sb.val_out, scan,
+                     E, cat.M, sb.node_of, sb.node_start, sb.seg_begin, sb.seg_end, sb.count);
+  PcgArgs a;
+  a.vals = sb.val_out;
+  a.node_of = sb.node_of;
+  a.node_start = sb.node_start;
+  a.seg_begin = sb.seg_begin;
+  a.seg_end = sb.seg_end;
+  a.w = b.w;
+  a.r = b.r;
+  a.y = sb.vec;
+  a.rr = sb.vec + E;
+  a.p = sb.vec + 2 * E;
+  a.ap = sb.vec + 3 * E;
+  a.dinv = sb.vec + 4 * E;
+  a.lambda = (cat.sigma * cat.sigma) / (cat.kappa * cat.kappa);
+  a.max_iter = 400;
+  a.tol2 = 1e-32;
+  hipLaunchKernelGGL(k_pcg, dim3((unsigned)(C * cat.L)), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(k_exact_z, dim3(grid_for((int64_t)C * n)), dim3(kBlock), 0, s,
+                     (int64_t)C * n, cat.sigma * cat.sigma, b.w, b.r, sb.node_of, a.y, b.z);
+  return hipGetLastError();
+}
+
+hipError_t reduce_events(const CatView& cat, int C, int64_t n, double scale, BatchBufs b,
+                         SortBufs sb, double* G, hipStream_t s) {
+  const int64_t E = 2 * (int64_t)C * n;
+  const int end_bit = bits_for((uint64_t)C * (uint64_t)cat.M);
+  hipLaunchKernelGGL(k_event_keys, dim3(grid_for(E)), dim3(kBlock), 0, s, C, n, cat.M, b,
+                     sb.key_in, sb.val_in);
+  size_t tb = sb.temp_bytes;
+  hipError_t e = rocprim::radix_sort_pairs(sb.temp, tb, sb.key_in, sb.key_out, sb.val_in,
+                                           sb.val_out, (size_t)E, 0, end_bit, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_fill, dim3(grid_for((int64_t)C * cat.M * 4)), dim3(kBlock), 0, s, G, 0.0,
+                     (int64_t)C * cat.M * 4);
+  hipLaunchKernelGGL(k_reduce_runs, dim3(grid_for(E)), dim3(kBlock), 0, s, sb.key_out, sb.val_out,
+                     E, scale, b, G);
+  return hipGetLastError();
+}
+
+void launch_centroid(const double* theta, int C, int M, double* partial, double* thetabar,
+                     hipStream_t s) {
+  const int nchunk = (int)ceil_div(M, kCentroidChunk);
+  hipLaunchKernelGGL(k_centroid_partial, dim3(nchunk, C), dim3(kBlock), 0, s, theta, M, nchunk,
+                     partial);
+  hipLaunchKernelGGL(k_centroid_final, dim3(C), dim3(64), 0, s, partial, nchunk, M, thetabar);
+}
+
+void launch_update(const CatView& cat, int C, double* theta, double* v, const double* G,
+                   const double* thetabar, int64_t* steps, int64_t* mcount, const UpdateArgs& a,
+                   double* mean, double* m2, hipStream_t s) {
+  UpdateKArgs k;
+  k.step = a.step;
+  k.beta2 = a.beta2;
+  k.eps_p = a.eps_p;
+  k.noise_scale = a.noise_scale;
+  k.precond = a.precond;
+  k.k0 = (uint32_t)a.seed;
+  k.k1 = (uint32_t)(a.seed >> 32);
+  k.burn = a.burn;
+  k.thin = a.thin;
+  hipLaunchKernelGGL(k_update, dim3(grid_for((int64_t)C * cat.M)), dim3(kBlock), 0, s, cat, C,
+                     theta, v, G, thetabar, steps, mcount, k, mean, m2);
+  hipLaunchKernelGGL(k_advance, dim3(grid_for(C, 64)), dim3(64), 0, s, C, steps, mcount, a.burn,
+                     a.thin);
+}
+
+void launch_grad_finish(const CatView& cat, const double* theta, const double* G,
+                        const double* thetabar, unsigned flags, double* grad_out, hipStream_t s) {
+  hipLaunchKernelGGL(k_grad_finish, dim3(grid_for((int64_t)cat.M * 4)), dim3(kBlock), 0, s, cat,
+                     theta, G, thetabar, flags, grad_out);
+}
+
+void launch_logpost(const CatView& cat, int64_t n, double scale, const double* r, const double* z,
+                    const double* theta, const double* thetabar, unsigned flags, double* tmp,
+                    double* out, hipStream_t s) {
+  const int nb = 256;
+  hipLaunchKernelGGL(k_logpost_partial, dim3(nb), dim3(kBlock), 0, s, cat, n, scale, r, z, theta,
+                     flags, tmp);
+  hipLaunchKernelGGL(k_logpost_final, dim3(1), dim3(64), 0, s, cat, tmp, nb, thetabar, flags, out);
+}
+
+void launch_tt_assemble(const NetView& net, int64_t rows, const double* x, const double* s,
+                        const RowOut* out, double* T, double* gradT, hipStream_t st) {
+  if (rows == 0) return;
+  hipLaunchKernelGGL(k_tt_assemble, dim3(grid_for(rows)), dim3(kBlock), 0, st, net, rows, x, s,
+                     out, T, gradT);
+}
+
+void launch_batch_terms_out(int64_t n, const BatchBufs& b, double* T_i, double* T_j, double* gT_i,
+                            double* gT_j, double* r, double* z, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_terms_out, dim3(grid_for(n)), dim3(kBlock), 0, s, n, b, T_i, T_j,
+                     gT_i, gT_j, r, z);
+}
+
+void launch_noise(const CatView& cat, uint64_t seed, int chain, int64_t step, double* eta,
+                  hipStream_t s) {
+  hipLaunchKernelGGL(k_noise, dim3(grid_for(cat.M)), dim3(kBlock), 0, s, cat, (uint32_t)seed,
+                     (uint32_t)(seed >> 32), chain, (uint32_t)step, eta);
+}
+
+void launch_finite(const double* a, int64_t count, int64_t per_chain, int* bad_chain,
+                   hipStream_t s) {
+  hipLaunchKernelGGL(k_finite, dim3(grid_for(count)), dim3(kBlock), 0, s, a, count, per_chain,
+                     bad_chain);
+}
+
+void launch_pool_moments(int C, int M, const double* mean, const double* m2, const int64_t* cnt,
+                         double* out_mean, double* out_cov, hipStream_t s) {
+  hipLaunchKernelGGL(k_pool_moments, dim3(grid_for(M)), dim3(kBlock), 0, s, C, M, mean, m2, cnt,
+                     out_mean, out_cov);
+}
+
+void launch_fill(double* p, double v, int64_t count, hipStream_t s) {
+  if (count == 0) return;
+  hipLaunchKernelGGL(k_fill, dim3(grid_for(count)), dim3(kBlock), 0, s, p, v, count);
+}
+
+}  // namespace spider

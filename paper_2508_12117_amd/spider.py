@@ -1,0 +1,298 @@
+"""ctypes binding of libspider (include/spider.h): argument marshalling only.
+
+Every computation runs in the HIP library.  Device arrays are torch tensors
+on the context's device; the binding passes their pointers and the current
+torch stream.  The library must have been built (``__graft_entry__.build()``
+or ``python -m paper_2508_12117_amd.build``); loading fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libspider.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "spider.h")
+
+OK, E_INVALID, E_OOM, E_HIP, E_STATE, E_UNSUPPORTED, E_NUMERIC = 0, -1, -2, -3, -4, -5, -6
+MEM_HOST, MEM_DEVICE = 0, 1
+WHITEN_NONE, WHITEN_DIAG, WHITEN_EXACT = 0, 1, 2
+FP32, BF16 = 0, 1
+GRAD_PRIOR, GRAD_CENTROID = 1, 2
+MAX_LAYERS = 16
+
+_ERRNAMES = {E_INVALID: "invalid", E_OOM: "out of memory", E_HIP: "HIP error",
+             E_STATE: "bad state", E_UNSUPPORTED: "unsupported", E_NUMERIC: "numeric"}
+
+
+class SpiderError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_ERRNAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class CatalogDesc(ct.Structure):
+    _fields_ = [("M", ct.c_int32), ("L", ct.c_int32), ("P", ct.c_int32), ("N", ct.c_int64),
+                ("mem", ct.c_int32),
+                ("hypo0", ct.c_void_p), ("stations", ct.c_void_p),
+                ("pair_i", ct.c_void_p), ("pair_j", ct.c_void_p),
+                ("obs_pair", ct.c_void_p), ("obs_sta", ct.c_void_p), ("obs_dt", ct.c_void_p),
+                ("sigma", ct.c_double), ("kappa", ct.c_double), ("p", ct.c_double),
+                ("ell", ct.c_double), ("eps_w", ct.c_double),
+                ("prior_sigma", ct.c_double * 4), ("centroid_sigma", ct.c_double * 4),
+                ("stream", ct.c_uint32), ("whiten", ct.c_int32)]
+
+
+class NetDesc(ct.Structure):
+    _fields_ = [("D", ct.c_int32), ("H", ct.c_int32), ("mem", ct.c_int32),
+                ("W", ct.c_void_p * (MAX_LAYERS + 1)), ("b", ct.c_void_p * (MAX_LAYERS + 1)),
+                ("v0", ct.c_double), ("center", ct.c_double * 3),
+                ("half_extent", ct.c_double * 3)]
+
+
+class ChainSet(ct.Structure):
+    _fields_ = [("cat_id", ct.c_int32), ("net_id", ct.c_int32), ("n_chains", ct.c_int32),
+                ("precision", ct.c_int32), ("batch", ct.c_int64)]
+
+
+class SgldCfg(ct.Structure):
+    _fields_ = [("step", ct.c_double), ("beta2", ct.c_double), ("eps_p", ct.c_double),
+                ("noise_scale", ct.c_double), ("precond", ct.c_int32), ("reserved", ct.c_int32),
+                ("n_steps", ct.c_int64), ("burn_in", ct.c_int64), ("thin", ct.c_int64),
+                ("seed", ct.c_uint64)]
+
+
+_P = ct.c_void_p
+_SIGS = {
+    "spider_version": ([], ct.c_int),
+    "spider_create": ([ct.POINTER(_P), ct.c_int, _P], ct.c_int),
+    "spider_destroy": ([_P], None),
+    "spider_last_error": ([_P], ct.c_char_p),
+    "spider_sync": ([_P], ct.c_int),
+    "spider_load_catalog": ([_P, ct.POINTER(CatalogDesc), ct.POINTER(ct.c_int32)], ct.c_int),
+    "spider_load_net": ([_P, ct.POINTER(NetDesc), ct.POINTER(ct.c_int32)], ct.c_int),
+    "spider_travel_time": ([_P, ct.c_int32, ct.c_int32, _P, _P, ct.c_int64, _P, _P], ct.c_int),
+    "spider_grad": ([_P, ct.c_int32, ct.c_int32, ct.c_int32, _P, _P, ct.c_int64, ct.c_uint64,
+                     ct.c_int32, ct.c_int64, ct.c_uint32, _P, _P], ct.c_int),
+    "spider_batch_terms": ([_P, ct.c_int32, ct.c_int32, ct.c_int32, _P, _P, ct.c_int64,
+                            ct.c_uint64, ct.c_int32, ct.c_int64, _P, _P, _P, _P, _P, _P],
+                           ct.c_int),
+    "spider_batch_indices": ([_P, ct.c_int32, ct.c_uint64, ct.c_int32, ct.c_int64, ct.c_int64,
+                              _P], ct.c_int),
+    "spider_noise": ([_P, ct.c_int32, ct.c_uint64, ct.c_int32, ct.c_int64, _P], ct.c_int),
+    "spider_reset_chains": ([_P, ct.c_int32, ct.c_int32], ct.c_int),
+    "spider_sgld_steps": ([_P, ct.POINTER(ChainSet), ct.c_int32, ct.POINTER(SgldCfg)], ct.c_int),
+    "spider_moments": ([_P, ct.c_int32, ct.c_int32, _P, _P, ct.POINTER(ct.c_int64)], ct.c_int),
+    "spider_get_state": ([_P, ct.c_int32, ct.c_int32, _P, _P, ct.POINTER(ct.c_int64)], ct.c_int),
+    "spider_set_state": ([_P, ct.c_int32, ct.c_int32, _P, _P, ct.c_int64], ct.c_int),
+    "spider_profile": ([_P, ct.c_int], ct.c_int),
+    "spider_profile_read": ([_P, ct.POINTER(ct.c_double), ct.POINTER(ct.c_int64),
+                             ct.POINTER(ct.c_int64)], ct.c_int),
+}
+
+_lib = None
+
+
+def header_functions():
+    """Names of the functions include/spider.h declares."""
+    with open(HEADER) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(spider_[a-z_0-9]+)\s*\(", text)))
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2508_12117_amd.build`")
+        L = ct.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _ptr(t):
+    """Device pointer of a torch tensor (or None)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return ct.c_void_p(t.data_ptr())
+
+
+def _np_ptr(a):
+    return ct.c_void_p(a.ctypes.data)
+
+
+class Context:
+    """One libspider context on a device, enqueueing on torch's current stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self._torch = torch
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self._stream = stream
+        h = ct.c_void_p()
+        rc = lib().spider_create(ct.byref(h), device, ct.c_void_p(stream.cuda_stream))
+        if rc != OK:
+            raise SpiderError(rc, f"spider_create(device={device}) failed")
+        self._h = h
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().spider_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _check(self, rc):
+        if rc != OK:
+            raise SpiderError(rc, lib().spider_last_error(self._h).decode())
+
+    def sync(self):
+        self._check(lib().spider_sync(self._h))
+
+    # ---- loading
+    def load_catalog(self, cat, whiten=WHITEN_EXACT, stream_id=0, sigma=None, kappa=None,
+                     p=None, ell=None, eps_w=None) -> int:
+        wl = cat.wl
+        arrays = dict(
+            hypo0=np.ascontiguousarray(cat.hypo0, np.float64),
+            stations=np.ascontiguousarray(cat.stations, np.float64),
+            pair_i=np.ascontiguousarray(cat.pair_i, np.int32),
+            pair_j=np.ascontiguousarray(cat.pair_j, np.int32),
+            obs_pair=np.ascontiguousarray(cat.obs_pair, np.int32),
+            obs_sta=np.ascontiguousarray(cat.obs_sta, np.int16),
+            obs_dt=np.ascontiguousarray(cat.obs_dt, np.float32))
+        d = CatalogDesc()
+        d.M, d.L, d.P, d.N = cat.M, cat.L, cat.P, cat.N
+        d.mem = MEM_HOST
+        for k, a in arrays.items():
+            setattr(d, k, _np_ptr(a))
+        d.sigma = wl.sigma if sigma is None else sigma
+        d.kappa = wl.kappa if kappa is None else kappa
+        d.p = wl.p if p is None else p
+        d.ell = wl.ell if ell is None else ell
+        d.eps_w = wl.eps_w if eps_w is None else eps_w
+        d.prior_sigma[:] = list(wl.prior_sigma)
+        d.centroid_sigma[:] = list(wl.centroid_sigma)
+        d.stream = stream_id
+        d.whiten = whiten
+        cid = ct.c_int32()
+        self._check(lib().spider_load_catalog(self._h, ct.byref(d), ct.byref(cid)))
+        return cid.value
+
+    def load_net(self, net) -> int:
+        W = [np.ascontiguousarray(w, np.float32) for w in net.W]
+        B = [np.ascontiguousarray(b, np.float32) for b in net.b]
+        d = NetDesc()
+        d.D, d.H, d.mem = net.D, net.H, MEM_HOST
+        for l in range(net.D + 1):
+            d.W[l] = W[l].ctypes.data
+            d.b[l] = B[l].ctypes.data
+        d.v0 = net.v0
+        d.center[:] = list(map(float, net.center))
+        d.half_extent[:] = list(map(float, net.half_extent))
+        nid = ct.c_int32()
+        self._check(lib().spider_load_net(self._h, ct.byref(d), ct.byref(nid)))
+        return nid.value
+
+    # ---- hot path
+    def travel_time(self, net_id, x_src, s, T, gradT=None, precision=FP32):
+        self._check(lib().spider_travel_time(self._h, net_id, precision, _ptr(x_src), _ptr(s),
+                                             x_src.shape[0], _ptr(T), _ptr(gradT)))
+
+    def grad(self, cat_id, net_id, theta, grad_out, batch_idx=None, n=None, seed=0, chain=0,
+             step=0, flags=GRAD_PRIOR | GRAD_CENTROID, logpost=None, precision=FP32):
+        n = batch_idx.shape[0] if batch_idx is not None else n
+        self._check(lib().spider_grad(self._h, cat_id, net_id, precision, _ptr(theta),
+                                      _ptr(batch_idx), n, seed, chain, step, flags,
+                                      _ptr(grad_out), _ptr(logpost)))
+
+    def batch_terms(self, cat_id, net_id, theta, batch_idx=None, n=None, seed=0, chain=0, step=0,
+                    precision=FP32, out=None):
+        """Returns dict of T_i, T_j, gT_i, gT_j, r, z device tensors."""
+        torch = self._torch
+        n = batch_idx.shape[0] if batch_idx is not None else n
+        dev = theta.device
+        if out is None:
+            out = dict(T_i=torch.empty(n, dtype=torch.float64, device=dev),
+                       T_j=torch.empty(n, dtype=torch.float64, device=dev),
+                       gT_i=torch.empty(n, 3, dtype=torch.float64, device=dev),
+                       gT_j=torch.empty(n, 3, dtype=torch.float64, device=dev),
+                       r=torch.empty(n, dtype=torch.float64, device=dev),
+                       z=torch.empty(n, dtype=torch.float64, device=dev))
+        self._check(lib().spider_batch_terms(
+            self._h, cat_id, net_id, precision, _ptr(theta), _ptr(batch_idx), n, seed, chain,
+            step, _ptr(out["T_i"]), _ptr(out["T_j"]), _ptr(out["gT_i"]), _ptr(out["gT_j"]),
+            _ptr(out["r"]), _ptr(out["z"])))
+        return out
+
+    def batch_indices(self, cat_id, seed, chain, step, n, out):
+        self._check(lib().spider_batch_indices(self._h, cat_id, seed, chain, step, n, _ptr(out)))
+
+    def noise(self, cat_id, seed, chain, step, out):
+        self._check(lib().spider_noise(self._h, cat_id, seed, chain, step, _ptr(out)))
+
+    def reset_chains(self, cat_id, n_chains):
+        self._check(lib().spider_reset_chains(self._h, cat_id, n_chains))
+
+    def sgld_steps(self, sets, n_steps, step=1e-4, beta2=0.99, eps_p=1e-5, noise_scale=1.0,
+                   precond=1, burn_in=0, thin=1, seed=0):
+        """sets: list of (cat_id, net_id, n_chains, batch, precision)."""
+        arr = (ChainSet * len(sets))()
+        for k, (cid, nid, C, n, prec) in enumerate(sets):
+            arr[k].cat_id, arr[k].net_id, arr[k].n_chains = cid, nid, C
+            arr[k].precision, arr[k].batch = prec, n
+        cfg = SgldCfg(step=step, beta2=beta2, eps_p=eps_p, noise_scale=noise_scale,
+                      precond=precond, reserved=0, n_steps=n_steps, burn_in=burn_in, thin=thin,
+                      seed=seed)
+        self._check(lib().spider_sgld_steps(self._h, arr, len(sets), ct.byref(cfg)))
+
+    def moments(self, cat_id, chain, mean, cov):
+        cnt = ct.c_int64()
+        self._check(lib().spider_moments(self._h, cat_id, chain, _ptr(mean), _ptr(cov),
+                                         ct.byref(cnt)))
+        return cnt.value
+
+    def get_state(self, cat_id, chain, theta=None, v=None):
+        step = ct.c_int64()
+        self._check(lib().spider_get_state(self._h, cat_id, chain, _ptr(theta), _ptr(v),
+                                           ct.byref(step)))
+        return step.value
+
+    def profile(self, enable: bool):
+        self._check(lib().spider_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        """(summed network-kernel ms, launches, rows) since profile(True)."""
+        ms, n, rows = ct.c_double(), ct.c_int64(), ct.c_int64()
+        self._check(lib().spider_profile_read(self._h, ct.byref(ms), ct.byref(n), ct.byref(rows)))
+        return ms.value, n.value, rows.value
+
+    def set_state(self, cat_id, chain, theta, v=None, step=0):
+        self._check(lib().spider_set_state(self._h, cat_id, chain, _ptr(theta), _ptr(v), step))

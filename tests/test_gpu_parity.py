@@ -1,0 +1,424 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Tolerances (FP32 network): travel time and its gradient 1e-5 relative; the
+residual 1e-5 relative to the magnitudes it is the difference of; the
+whitening of the same residuals 1e-10 scaled by sigma_eff^2 / (|r| + 1e-3 s);
+per-event gradients 1e-5 of S_m (the sum of the magnitudes entering G_m);
+integer streams bit-exact; the noise stream 1e-14 absolute.
+"""
+import numpy as np
+import pytest
+
+from gpu_common import dev, grad_scale, host, lk, make_ctx, scaled_grad_error, spider, synth, torch
+from oracle import batch as obatch
+from oracle import philox, sampler
+from oracle import travel_time as ott
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = make_ctx()
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def tiny_setup(ctx):
+    cat = synth.make_catalog("tiny")
+    net = synth.net_for(cat)
+    cid = ctx.load_catalog(cat, whiten=spider.WHITEN_EXACT, stream_id=3)
+    nid = ctx.load_net(net)
+    return cat, net, cid, nid
+
+
+@pytest.fixture(scope="module")
+def faults_setup(ctx):
+    cat = synth.make_catalog("faults10k")
+    net = synth.net_for(cat)
+    cid = ctx.load_catalog(cat, whiten=spider.WHITEN_EXACT, stream_id=5)
+    nid = ctx.load_net(net)
+    return cat, net, cid, nid
+
+
+def _points(n, seed, box=10.0):
+    rng = np.random.default_rng(seed)
+    x = np.column_stack([rng.uniform(0, box, n), rng.uniform(0, box, n), rng.uniform(0.5, box, n)])
+    s = np.column_stack([rng.uniform(-box / 2, 1.5 * box, n), rng.uniform(-box / 2, 1.5 * box, n),
+                         np.zeros(n)])
+    return x, s
+
+
+# ----------------------------------------------------------------- streams
+
+@pytest.mark.parametrize("seed,chain,step", [(0, 0, 0), (7, 2, 5), (123, 1, 31), (9, 0, 32),
+                                             (2**40 + 3, 5, 1000)])
+def test_batch_indices_bit_exact_tiny(ctx, tiny_setup, seed, chain, step):
+    cat, _, cid, _ = tiny_setup
+    n = cat.wl.batch
+    out = torch.empty(n, dtype=torch.int64, device="cuda")
+    ctx.batch_indices(cid, seed, chain, step, n, out)
+    want = obatch.batch_indices(seed, 3, chain, step, cat.N, n)
+    assert np.array_equal(host(out), want)
+
+
+@pytest.mark.parametrize("n,step", [(65536, 0), (65536, 77), (65536, 76 + 76), (1, 3), (1_000_003, 5)])
+def test_batch_indices_bit_exact_faults(ctx, faults_setup, n, step):
+    cat, _, cid, _ = faults_setup
+    out = torch.empty(n, dtype=torch.int64, device="cuda")
+    ctx.batch_indices(cid, 11, 1, step, n, out)
+    want = obatch.batch_indices(11, 5, 1, step, cat.N, n)
+    assert np.array_equal(host(out), want)
+
+
+def test_noise_matches_oracle(ctx, tiny_setup):
+    cat, _, cid, _ = tiny_setup
+    for seed, chain, step in [(0, 0, 0), (99, 3, 17), (2**63 + 5, 1, 12345)]:
+        eta = torch.empty(cat.M, 4, dtype=torch.float64, device="cuda")
+        ctx.noise(cid, seed, chain, step, eta)
+        want = philox.noise(seed, 3, chain, step, np.arange(cat.M))
+        np.testing.assert_allclose(host(eta), want, rtol=0, atol=1e-14)
+
+
+# ----------------------------------------------------------------- network
+
+@pytest.mark.parametrize("H,D,rows", [(32, 3, 1037), (128, 4, 777), (256, 6, 530), (64, 2, 1),
+                                      (48, 5, 100)])
+def test_travel_time_fp32(ctx, H, D, rows):
+    net = synth.make_net(H, D, center=[5.0, 5.0, 4.0], half_extent=[10.0, 10.0, 6.0], seed=H + D)
+    nid = ctx.load_net(net)
+    x, s = _points(rows, H * 7 + D)
+    T = torch.empty(rows, dtype=torch.float64, device="cuda")
+    g = torch.empty(rows, 3, dtype=torch.float64, device="cuda")
+    ctx.travel_time(nid, dev(x), dev(s), T, g)
+    Tw, gw = ott.travel_time(net, x, s)
+    assert np.max(np.abs(host(T) - Tw) / np.abs(Tw)) < 1e-5
+    err = np.linalg.norm(host(g) - gw, axis=1) / np.linalg.norm(gw, axis=1)
+    assert err.max() < 1e-5
+
+
+def test_travel_time_zero_output_is_homogeneous(ctx):
+    net = synth.make_net(128, 4, center=[5.0, 5.0, 4.0], half_extent=[10.0, 10.0, 6.0],
+                         zero_output=True)
+    nid = ctx.load_net(net)
+    x, s = _points(300, 1)
+    T = torch.empty(300, dtype=torch.float64, device="cuda")
+    g = torch.empty(300, 3, dtype=torch.float64, device="cuda")
+    ctx.travel_time(nid, dev(x), dev(s), T, g)
+    r = np.linalg.norm(x - s, axis=1)
+    np.testing.assert_allclose(host(T), r / 6.0, rtol=1e-15)
+    np.testing.assert_allclose(host(g), (x - s) / (6.0 * r[:, None]), rtol=1e-14, atol=1e-16)
+
+
+def test_travel_time_no_rows(ctx, tiny_setup):
+    _, _, _, nid = tiny_setup
+    e = torch.empty(0, 3, dtype=torch.float64, device="cuda")
+    ctx.travel_time(nid, e, e, torch.empty(0, dtype=torch.float64, device="cuda"))
+
+
+def test_autograd_function_backward(ctx, tiny_setup):
+    from paper_2508_12117_amd.travel_time import travel_time
+    _, net, _, nid = tiny_setup
+    x, s = _points(257, 3)
+    xt = dev(x).requires_grad_(True)
+    T = travel_time(xt, dev(s), ctx, nid)
+    w = torch.linspace(0.5, 1.5, 257, dtype=torch.float64, device="cuda")
+    (T * w).sum().backward()
+    _, gw = ott.travel_time(net, x, s)
+    got = host(xt.grad)
+    want = gw * host(w)[:, None]
+    assert np.max(np.linalg.norm(got - want, axis=1) / np.linalg.norm(want, axis=1)) < 1e-5
+    # and central differences of the GPU forward itself (h = 1e-3 km)
+    h = 1e-3
+    with torch.no_grad():
+        fd = np.zeros_like(x)
+        for a in range(3):
+            e = np.zeros(3)
+            e[a] = h
+            fd[:, a] = (host(travel_time(dev(x + e), dev(s), ctx, nid))
+                        - host(travel_time(dev(x - e), dev(s), ctx, nid))) / (2 * h)
+    # FP32 network: the difference quotient carries ~1e-7 T / h of rounding
+    assert np.max(np.abs(fd - gw)) < 5e-3
+
+
+# ----------------------------------------------------------------- batch terms
+
+@pytest.mark.parametrize("whiten", [spider.WHITEN_NONE, spider.WHITEN_DIAG, spider.WHITEN_EXACT])
+def test_batch_terms_tiny(ctx, tiny_setup, whiten):
+    cat, net, _, nid = tiny_setup
+    cid = ctx.load_catalog(cat, whiten=whiten, stream_id=3)
+    prob = lk.load(cat)
+    theta = synth.random_theta(cat, 21)
+    idx = synth.random_batch(cat.N, 1024, 22)
+    out = ctx.batch_terms(cid, nid, dev(theta), dev(idx))
+    bt = lk.batch_terms(prob, net, theta, idx, whiten)
+    Ti, Tj, r, z = (host(out[k]) for k in ("T_i", "T_j", "r", "z"))
+    assert np.max(np.abs(Ti - bt.T_i) / bt.T_i) < 1e-5
+    assert np.max(np.abs(Tj - bt.T_j) / bt.T_j) < 1e-5
+    gi, gj = host(out["gT_i"]), host(out["gT_j"])
+    assert np.max(np.linalg.norm(gi - bt.gT_i, axis=1) / np.linalg.norm(bt.gT_i, axis=1)) < 1e-5
+    assert np.max(np.linalg.norm(gj - bt.gT_j, axis=1) / np.linalg.norm(bt.gT_j, axis=1)) < 1e-5
+    mag = np.abs(bt.T_i) + np.abs(bt.T_j) + np.abs(bt.tau) + np.abs(theta[bt.ev_i, 3] - theta[bt.ev_j, 3])
+    assert np.max(np.abs(r - bt.r) / mag) < 1e-5
+    # whitening of the same residuals
+    zw = lk.whiten(r, bt.w, bt.group, bt.ev_i, bt.ev_j, prob.M, prob.sigma, prob.kappa, whiten)
+    s_eff = prob.sigma ** 2 + 2 * prob.kappa ** 2 * bt.w
+    assert np.max(np.abs(z - zw) * s_eff / (np.abs(r) + 1e-3)) < 1e-10
+
+
+def test_batch_terms_faults_full_batch(ctx, faults_setup):
+    cat, net, cid, nid = faults_setup
+    prob = lk.load(cat)
+    theta = synth.random_theta(cat, 31)
+    idx = obatch.batch_indices(4, 5, 0, 3, cat.N, cat.wl.batch)
+    out = ctx.batch_terms(cid, nid, dev(theta), None, n=cat.wl.batch, seed=4, chain=0, step=3)
+    bt = lk.batch_terms(prob, net, theta, idx, lk.WHITEN_EXACT)
+    r, z = host(out["r"]), host(out["z"])
+    mag = np.abs(bt.T_i) + np.abs(bt.T_j) + np.abs(bt.tau) + np.abs(theta[bt.ev_i, 3] - theta[bt.ev_j, 3])
+    assert np.max(np.abs(r - bt.r) / mag) < 1e-5
+    zw = lk.whiten(r, bt.w, bt.group, bt.ev_i, bt.ev_j, prob.M, prob.sigma, prob.kappa,
+                   lk.WHITEN_EXACT)
+    s_eff = prob.sigma ** 2 + 2 * prob.kappa ** 2 * bt.w
+    assert np.max(np.abs(z - zw) * s_eff / (np.abs(r) + 1e-3)) < 1e-10
+
+
+# ----------------------------------------------------------------- gradient
+
+@pytest.mark.parametrize("which,n", [("tiny", 1024), ("tiny", 1), ("tiny", 32000),
+                                     ("faults10k", 65536)])
+def test_grad_parity(ctx, tiny_setup, faults_setup, which, n):
+    cat, net, cid, nid = tiny_setup if which == "tiny" else faults_setup
+    prob = lk.load(cat)
+    theta = synth.random_theta(cat, 41)
+    idx = synth.random_batch(cat.N, n, 42)
+    G = torch.empty(cat.M, 4, dtype=torch.float64, device="cuda")
+    lp = torch.empty(1, dtype=torch.float64, device="cuda")
+    ctx.grad(cid, nid, dev(theta), G, batch_idx=dev(idx), logpost=lp)
+    Gw, lpw, bt = lk.grad_log_post(prob, net, theta, idx, lk.WHITEN_EXACT)
+    S = grad_scale(prob, bt, prob.N / n, theta)
+    Gp = lk.event_prior_gradient(prob, theta) + lk.centroid_gradient(prob, theta)
+    assert scaled_grad_error(host(G), Gw, S, floor=np.abs(Gp).max()) < 1e-5
+    assert abs(float(host(lp)[0]) - lpw) < 1e-5 * (abs(lpw) + 1)
+    # events outside the batch carry the prior terms only
+    untouched = np.ones(cat.M, bool)
+    untouched[bt.ev_i] = False
+    untouched[bt.ev_j] = False
+    np.testing.assert_allclose(host(G)[untouched], Gp[untouched], rtol=1e-12, atol=1e-12)
+
+
+def test_grad_sampler_batch_matches_explicit(ctx, tiny_setup):
+    cat, net, cid, nid = tiny_setup
+    theta = dev(synth.random_theta(cat, 5))
+    G1 = torch.empty(cat.M, 4, dtype=torch.float64, device="cuda")
+    G2 = torch.empty_like(G1)
+    ctx.grad(cid, nid, theta, G1, n=1024, seed=8, chain=2, step=40)
+    idx = obatch.batch_indices(8, 3, 2, 40, cat.N, 1024)
+    ctx.grad(cid, nid, theta, G2, batch_idx=dev(idx))
+    assert torch.equal(G1, G2)
+
+
+# ----------------------------------------------------------------- sampler
+
+def _oracle_run(cat, net, steps, seed, stream, chain_id=0, burn=0, thin=1, n=1024):
+    prob = lk.load(cat)
+    cfg = sampler.SamplerConfig(step=1e-4, seed=seed, burn_in=burn, thin=thin)
+    ch, states = sampler.run(prob, net, cfg, n, steps, stream=stream, chain_id=chain_id,
+                             keep_states=True)
+    return prob, ch, states
+
+
+@pytest.fixture(scope="module")
+def tiny_run(ctx, tiny_setup):
+    cat, net, _, nid = tiny_setup
+    cid = ctx.load_catalog(cat, whiten=spider.WHITEN_EXACT, stream_id=3)
+    ctx.reset_chains(cid, 1)
+    ctx.sgld_steps([(cid, nid, 1, 1024, spider.FP32)], 200, seed=17, burn_in=100, thin=1)
+    theta = torch.empty(cat.M, 4, dtype=torch.float64, device="cuda")
+    v = torch.empty_like(theta)
+    step = ctx.get_state(cid, 0, theta, v)
+    mean = torch.empty_like(theta)
+    cov = torch.empty(cat.M, 10, dtype=torch.float64, device="cuda")
+    cnt = ctx.moments(cid, 0, mean, cov)
+    prob, ch, states = _oracle_run(cat, net, 200, 17, 3, burn=100, thin=1)
+    return dict(theta=host(theta), v=host(v), step=step, mean=host(mean), cov=host(cov),
+                count=cnt, oracle=ch, states=states, prob=prob, cid=cid)
+
+
+def test_sgld_trajectory_tiny(tiny_run):
+    """200 steps from the same start with the same batch and noise streams.
+    The FP32 network perturbs each step's gradient by ~1e-6 relative, and the
+    preconditioner 1/sqrt(v) amplifies that where a gradient component passes
+    near zero, so trajectories separate slowly at a few coordinates: the
+    posterior mean is held to 5e-2 posterior s.d. at every coordinate and 1e-4
+    at the median (measured: 1.2e-2 and ~1e-6); the per-step arithmetic is
+    held tightly by the one-step tests below."""
+    r = tiny_run
+    assert r["step"] == 200 and r["count"] == 100 == r["oracle"].mom.count
+    cov_o = sampler.covariance(r["oracle"].mom)
+    sd = np.sqrt(cov_o[:, [0, 4, 7, 9]])
+    err = np.abs(r["mean"] - r["oracle"].mom.mean) / sd
+    assert err.max() < 5e-2 and np.median(err) < 1e-4
+    ce = np.linalg.norm(r["cov"] - cov_o, axis=1) / np.linalg.norm(cov_o, axis=1)
+    assert np.median(ce) < 1e-2 and ce.max() < 1e-1
+
+
+def _one_step_check(ctx, cat, net, nid, chain_id, t, seed, n_chains=1):
+    """GPU step t -> t+1 from the oracle's own FP64 state at step t, in two
+    parts: (a) the stochastic gradient of the sampler's minibatch against the
+    oracle's (scaled per-event metric), (b) the pSGLD update and noise given
+    that gradient against the update formula in FP64."""
+    prob = lk.load(cat)
+    cfg = sampler.SamplerConfig(step=1e-4, seed=seed)
+    ch, _ = sampler.run(prob, net, cfg, 1024, t, stream=3, chain_id=chain_id)
+    th_t, v_t = ch.theta.copy(), ch.v.copy()
+    G_o, _, idx = sampler.stochastic_gradient(prob, net, ch, cfg, 3, chain_id, 1024)
+    cid = ctx.load_catalog(cat, stream_id=3)
+    ctx.reset_chains(cid, n_chains)
+    for c in range(n_chains):
+        ctx.set_state(cid, c, dev(th_t), dev(v_t), step=t)
+    G = torch.empty(cat.M, 4, dtype=torch.float64, device="cuda")
+    ctx.grad(cid, nid, dev(th_t), G, n=1024, seed=seed, chain=chain_id, step=t)
+    G = host(G)
+    bt = lk.batch_terms(prob, net, th_t, idx, lk.WHITEN_EXACT)
+    S = grad_scale(prob, bt, prob.N / 1024, th_t)
+    assert scaled_grad_error(G, G_o, S, floor=1.0) < 1e-5
+    ctx.sgld_steps([(cid, nid, n_chains, 1024, spider.FP32)], 1, seed=seed)
+    th = torch.empty(cat.M, 4, dtype=torch.float64, device="cuda")
+    v = torch.empty_like(th)
+    assert ctx.get_state(cid, chain_id, th, v) == t + 1
+    eta = philox.noise(seed, 3, chain_id, t, np.arange(cat.M))
+    th_e, v_e = sampler.update(th_t, v_t, G, cfg, eta)
+    np.testing.assert_allclose(host(v), v_e, rtol=1e-13, atol=0)
+    np.testing.assert_allclose(host(th), th_e, rtol=1e-13, atol=1e-13)
+
+
+@pytest.mark.parametrize("t", [0, 1, 57, 150])
+def test_sgld_one_step_transition(ctx, tiny_setup, t):
+    cat, net, _, nid = tiny_setup
+    _one_step_check(ctx, cat, net, nid, 0, t, 17)
+
+
+def test_sgld_is_deterministic_and_resumable(ctx, tiny_setup):
+    cat, net, _, nid = tiny_setup
+    outs = []
+    for split in [(12,), (12,), (5, 7)]:
+        cid = ctx.load_catalog(cat, stream_id=3)
+        ctx.reset_chains(cid, 2)
+        for k in split:
+            ctx.sgld_steps([(cid, nid, 2, 1024, spider.FP32)], k, seed=3)
+        th = torch.empty(2, cat.M, 4, dtype=torch.float64, device="cuda")
+        ctx.get_state(cid, 0, th[0])
+        ctx.get_state(cid, 1, th[1])
+        outs.append(host(th))
+    assert np.array_equal(outs[0], outs[1])
+    assert np.array_equal(outs[0], outs[2])
+
+
+def test_multi_chain_matches_oracle_chains(ctx, tiny_setup):
+    """Chains of one launch follow their own batch and noise streams."""
+    cat, net, _, nid = tiny_setup
+    for c in range(3):
+        _one_step_check(ctx, cat, net, nid, c, 9, 21, n_chains=3)
+
+
+def test_pooled_moments(ctx, tiny_setup):
+    cat, net, _, nid = tiny_setup
+    cid = ctx.load_catalog(cat, stream_id=3)
+    ctx.reset_chains(cid, 2)
+    ctx.sgld_steps([(cid, nid, 2, 1024, spider.FP32)], 20, seed=4, burn_in=5, thin=2)
+    mean = torch.empty(cat.M, 4, dtype=torch.float64, device="cuda")
+    cov = torch.empty(cat.M, 10, dtype=torch.float64, device="cuda")
+    per = []
+    for c in range(2):
+        m = torch.empty_like(mean)
+        v = torch.empty_like(cov)
+        cnt = ctx.moments(cid, c, m, v)
+        assert cnt == 8
+        per.append(sampler.Moments(cnt, host(m), host(v) * (cnt - 1)))
+    cnt = ctx.moments(cid, -1, mean, cov)
+    assert cnt == 16
+    want = sampler.pooled(per)
+    np.testing.assert_allclose(host(mean), want.mean, rtol=1e-13)
+    np.testing.assert_allclose(host(cov), sampler.covariance(want), rtol=1e-9, atol=1e-18)
+
+
+# ----------------------------------------------------------------- errors
+
+def test_invalid_inputs_are_rejected(ctx, tiny_setup):
+    cat, net, cid, nid = tiny_setup
+    bad = synth.Catalog(cat.wl, cat.hypo_true, cat.hypo0, cat.stations, cat.pair_i.copy(),
+                        cat.pair_j.copy(), cat.obs_pair, cat.obs_sta, cat.obs_dt)
+    bad.pair_j[3] = bad.pair_i[3]
+    with pytest.raises(spider.SpiderError) as e:
+        ctx.load_catalog(bad)
+    assert e.value.code == spider.E_INVALID
+    bad2 = synth.Catalog(cat.wl, cat.hypo_true, cat.hypo0, cat.stations, cat.pair_i,
+                         cat.pair_j, cat.obs_pair, cat.obs_sta.copy(), cat.obs_dt)
+    bad2.obs_sta[10] = cat.L
+    with pytest.raises(spider.SpiderError):
+        ctx.load_catalog(bad2)
+    G = torch.empty(cat.M, 4, dtype=torch.float64, device="cuda")
+    with pytest.raises(spider.SpiderError):
+        ctx.grad(cid, 999, dev(cat.hypo0), G, n=10)
+    with pytest.raises(spider.SpiderError):
+        ctx.grad(cid, nid, dev(cat.hypo0), G, n=cat.N + 1)
+    with pytest.raises(spider.SpiderError):
+        ctx.sgld_steps([(cid, nid, 1, 0, spider.FP32)], 1)
+
+
+def test_non_finite_state_is_reported(ctx, tiny_setup):
+    cat, net, _, nid = tiny_setup
+    cid = ctx.load_catalog(cat, stream_id=3)
+    ctx.reset_chains(cid, 2)
+    th = np.array(cat.hypo0)
+    th[7, 2] = np.nan
+    ctx.set_state(cid, 1, dev(th), step=0)
+    with pytest.raises(spider.SpiderError) as e:
+        ctx.sgld_steps([(cid, nid, 2, 1024, spider.FP32)], 1)
+    assert e.value.code == spider.E_NUMERIC
+    assert "chain 1" in str(e.value)
+
+
+# ----------------------------------------------------------------- matrix-core BF16 path
+
+# Stated bounds of the BF16 network against the FP64 oracle, set from
+# measurement (max over the shapes below: 3.8e-3 on T, 7.9e-3 on grad T) with
+# a margin: BF16 operands carry 2^-9 relative rounding per layer.
+BF16_T_REL = 1e-2
+BF16_G_REL = 5e-2
+
+
+@pytest.mark.parametrize("H,D,rows", [(32, 3, 1037), (128, 4, 777), (256, 6, 530), (256, 8, 333),
+                                      (64, 3, 65)])
+def test_travel_time_bf16_bound(ctx, H, D, rows):
+    net = synth.make_net(H, D, center=[5.0, 5.0, 4.0], half_extent=[10.0, 10.0, 6.0], seed=H + D)
+    nid = ctx.load_net(net)
+    x, s = _points(rows, H * 5 + D)
+    T = torch.empty(rows, dtype=torch.float64, device="cuda")
+    g = torch.empty(rows, 3, dtype=torch.float64, device="cuda")
+    ctx.travel_time(nid, dev(x), dev(s), T, g, precision=spider.BF16)
+    Tw, gw = ott.travel_time(net, x, s)
+    eT = np.abs(host(T) - Tw) / np.abs(Tw)
+    eg = np.linalg.norm(host(g) - gw, axis=1) / np.linalg.norm(gw, axis=1)
+    print(f"bf16 H={H} D={D}: T rel max {eT.max():.3e} median {np.median(eT):.3e}; "
+          f"grad rel max {eg.max():.3e} median {np.median(eg):.3e}")
+    assert eT.max() < BF16_T_REL and eg.max() < BF16_G_REL
+    # the BF16 path is not the FP32 one
+    T32 = torch.empty_like(T)
+    ctx.travel_time(nid, dev(x), dev(s), T32, precision=spider.FP32)
+    assert not torch.equal(T, T32)
+
+
+def test_bf16_sampler_runs_and_is_deterministic(ctx, tiny_setup):
+    cat, net, _, nid = tiny_setup
+    outs = []
+    for _ in range(2):
+        cid = ctx.load_catalog(cat, stream_id=3)
+        ctx.reset_chains(cid, 2)
+        ctx.sgld_steps([(cid, nid, 2, 1024, spider.BF16)], 10, seed=5)
+        th = torch.empty(cat.M, 4, dtype=torch.float64, device="cuda")
+        ctx.get_state(cid, 1, th)
+        outs.append(host(th))
+    assert np.all(np.isfinite(outs[0])) and np.array_equal(outs[0], outs[1])
+    assert np.abs(outs[0] - cat.hypo0).max() > 0
