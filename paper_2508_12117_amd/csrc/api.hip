@@ -110,7 +110,7 @@ struct Net {
 struct Workspace {
   DevBuf obs, ev, sta, tau, w, net_out, T, gT, r, z;
   DevBuf key_in, key_out, val_in, val_out, temp, node_of, node_start, seg_begin, seg_end, flags,
-      vec, count;
+      vec, ivec, count;
   DevBuf G, partial, thetabar, lp_tmp, err;
   size_t temp_bytes = 0;
 
@@ -138,7 +138,8 @@ struct Workspace {
     RES(seg_begin, CL * 4);
     RES(seg_end, CL * 4);
     RES(flags, E * 4);
-    RES(vec, E * 8 * 6);
+    RES(vec, E * 8 * 8);
+    RES(ivec, E * 4 * 3);
     RES(count, 16);
     RES(G, CM * 32);
     RES(partial, (CM / 4096 + C + 1) * 32);
@@ -182,6 +183,7 @@ struct Workspace {
     s.seg_end = seg_end.as<int32_t>();
     s.flags = flags.as<int32_t>();
     s.vec = vec.as<double>();
+    s.ivec = ivec.as<int32_t>();
     s.count = count.as<int32_t>();
     return s;
   }

@@ -127,7 +127,8 @@ struct SortBufs {
   int32_t* seg_begin;  // [C L] first node of each (chain, group)
   int32_t* seg_end;    // [C L]
   int32_t* flags;      // [2 C n] scratch
-  double* vec;         // [6][2 C n] PCG vectors
+  double* vec;         // [8][2 C n] solver vectors
+  int32_t* ivec;       // [3][2 C n] solver node states
   int32_t* count;      // [1] device node count
 };
 
@@ -165,7 +166,8 @@ void launch_select(const CatView& cat, int C, int64_t n, const int64_t* idx, uin
 void launch_residual(const CatView& cat, const NetView& net, int C, int64_t n,
                      const double* theta, int64_t theta_stride, int whiten, BatchBufs b,
                      hipStream_t s);
-// Exact whitening z = Sigma_B^{-1} r by Woodbury + per-(chain, group) PCG.
+// Exact whitening z = Sigma_B^{-1} r by Woodbury + a per-(chain, group)
+// elimination solve of the batch graph system.
 hipError_t exact_whiten(const CatView& cat, int C, int64_t n, BatchBufs b, SortBufs sb,
                         hipStream_t s);
 // G_lik[c][m] = scale * sum over the chain's batch of the event's terms.

@@ -274,86 +274,205 @@ __global__ void k_fill_i32(int32_t* p, int32_t v, int64_t count) {
   if (t < count) p[t] = v;
 }
 
-struct PcgArgs {
-  const uint32_t* vals;       // sorted entries
-  const int32_t* node_of;
-  const int32_t* node_start;
+struct SolveArgs {
+  const uint32_t* vals;       // entries sorted by (chain, group, event)
+  const int32_t* node_of;     // node of each entry
+  const int32_t* node_start;  // entries of node q: [node_start[q], node_start[q + 1])
   const int32_t* seg_begin;
   const int32_t* seg_end;
   const double* w;
   const double* r;
-  double* y;                  // solution per node
-  double* rr;                 // residual
+  double* A;        // diagonal, Schur-updated as leaves are eliminated
+  double* b;        // right-hand side, Schur-updated
+  double* y;        // solution
+  double* Wp;       // weight to the parent at elimination
+  double* rr;       // CG vectors for the nodes left on cycles
   double* p;
   double* ap;
-  double* dinv;
+  int32_t* state;   // kActive, or the round in which the node was removed
+  int32_t* nstate;
+  int32_t* par;     // parent of an eliminated node (-1: solved on its own)
   double lambda;
+  int max_rounds;
   int max_iter;
   double tol2;
 };
 
-// (lambda I + L) v at node q.
-__device__ inline double lap_apply(const PcgArgs& a, int32_t q, const double* v) {
-  double s = a.lambda * v[q];
-  const double vq = v[q];
-  for (int32_t p = a.node_start[q]; p < a.node_start[q + 1]; ++p) {
-    const uint32_t e = a.vals[p];
-    const double wk = a.w[e >> 1];
-    s += wk * (vq - v[a.node_of[e ^ 1u]]);
-  }
-  return s;
-}
+constexpr int32_t kActive = -1;
+constexpr int32_t kCore = 1 << 30;  // solved by CG after the peeling rounds
 
-__global__ __launch_bounds__(kBlock) void k_pcg(PcgArgs a) {
+// One workgroup per (chain, group) block of (lambda I + L) y = U^T r.
+//  1. Peel leaves in rounds: a node whose active neighbours are all one node
+//     p (possibly over several parallel edges of total weight W) is
+//     eliminated into p (Schur complement: A_p -= W^2/A_q, b_p += W b_q/A_q);
+//     of two nodes that are each other's only neighbour the larger one is
+//     eliminated; a node with no active neighbour is solved, y = b/A.
+//     Parents gather their leaves' updates in entry order (deterministic).
+//  2. Nodes left on cycles after the rounds: Jacobi-preconditioned CG on
+//     the Schur-complemented system of those nodes only.
+//  3. Back substitution in reverse round order: y_q = (b_q + W y_p)/A_q.
+// Exact up to FP64 rounding for forests; the minibatch graphs are forests
+// of small trees apart from rare cycles.
+__global__ __launch_bounds__(kBlock) void k_tree_solve(SolveArgs a) {
   __shared__ double sh[kBlock];
   const int32_t nb = a.seg_begin[blockIdx.x];
   const int32_t ne = a.seg_end[blockIdx.x];
   if (ne <= nb) return;
   const int t = threadIdx.x;
-  // rhs U^T r, diagonal, initial guess 0
-  double bb = 0.0, rz = 0.0;
   for (int32_t q = nb + t; q < ne; q += kBlock) {
     double rhs = 0.0, dg = a.lambda;
-    for (int32_t p = a.node_start[q]; p < a.node_start[q + 1]; ++p) {
-      const uint32_t e = a.vals[p];
-      const double wk = a.w[e >> 1];
-      const double sgn = (e & 1u) ? -1.0 : 1.0;
-      rhs += sgn * sqrt(wk) * a.r[e >> 1];
+    for (int32_t e = a.node_start[q]; e < a.node_start[q + 1]; ++e) {
+      const uint32_t en = a.vals[e];
+      const double wk = a.w[en >> 1];
+      rhs += ((en & 1u) ? -1.0 : 1.0) * sqrt(wk) * a.r[en >> 1];
       dg += wk;
     }
-    a.y[q] = 0.0;
-    a.rr[q] = rhs;
-    a.dinv[q] = 1.0 / dg;
-    a.p[q] = rhs / dg;
-    bb += rhs * rhs;
-    rz += rhs * rhs / dg;
+    a.A[q] = dg;
+    a.b[q] = rhs;
+    a.state[q] = kActive;
+    a.par[q] = -1;
   }
-  bb = block_sum(bb, sh);
-  rz = block_sum(rz, sh);
-  if (bb == 0.0) return;  // y = 0 already written
-  for (int it = 0; it < a.max_iter; ++it) {
-    double pap = 0.0;
+  __syncthreads();
+
+  int rounds = 0;
+  for (; rounds < a.max_rounds; ++rounds) {
+    // phase 1: classify active nodes
+    int changed = 0;
     for (int32_t q = nb + t; q < ne; q += kBlock) {
-      const double v = lap_apply(a, q, a.p);
-      a.ap[q] = v;
-      pap += a.p[q] * v;
+      if (a.state[q] != kActive) {
+        a.nstate[q] = a.state[q];
+        continue;
+      }
+      int32_t p0 = -1;
+      double W = 0.0;
+      bool multi = false;
+      for (int32_t e = a.node_start[q]; e < a.node_start[q + 1]; ++e) {
+        const uint32_t en = a.vals[e];
+        const int32_t pn = a.node_of[en ^ 1u];
+        if (a.state[pn] != kActive) continue;
+        if (p0 < 0) {
+          p0 = pn;
+          W = a.w[en >> 1];
+        } else if (pn == p0) {
+          W += a.w[en >> 1];
+        } else {
+          multi = true;
+          break;
+        }
+      }
+      int32_t ns = kActive;
+      if (p0 < 0) {
+        ns = rounds;  // isolated: solved directly
+        a.par[q] = -1;
+      } else if (!multi) {
+        bool p0_other = false;
+        for (int32_t e = a.node_start[p0]; e < a.node_start[p0 + 1]; ++e) {
+          const int32_t pn = a.node_of[a.vals[e] ^ 1u];
+          if (pn != q && a.state[pn] == kActive) {
+            p0_other = true;
+            break;
+          }
+        }
+        if (p0_other || q > p0) {
+          ns = rounds;
+          a.par[q] = p0;
+          a.Wp[q] = W;
+        }
+      }
+      a.nstate[q] = ns;
+      changed |= (ns != kActive);
     }
-    pap = block_sum(pap, sh);
-    const double alpha = rz / pap;
-    double rn = 0.0, rz_new = 0.0;
+    changed = __syncthreads_or(changed);
+    if (!changed) break;
+    // phase 2: parents gather the Schur updates of this round's leaves
     for (int32_t q = nb + t; q < ne; q += kBlock) {
-      a.y[q] += alpha * a.p[q];
-      const double rq = a.rr[q] - alpha * a.ap[q];
-      a.rr[q] = rq;
-      rn += rq * rq;
-      rz_new += rq * rq * a.dinv[q];
+      if (a.nstate[q] == kActive) {
+        const int32_t e0 = a.node_start[q], e1 = a.node_start[q + 1];
+        double dA = 0.0, db = 0.0;
+        for (int32_t e = e0; e < e1; ++e) {
+          const int32_t pn = a.node_of[a.vals[e] ^ 1u];
+          if (a.nstate[pn] != rounds || a.par[pn] != q) continue;
+          bool first = true;
+          for (int32_t f = e0; f < e; ++f)
+            if (a.node_of[a.vals[f] ^ 1u] == pn) {
+              first = false;
+              break;
+            }
+          if (!first) continue;
+          const double Ap = a.A[pn], Wn = a.Wp[pn];
+          dA += Wn * Wn / Ap;
+          db += Wn * a.b[pn] / Ap;
+        }
+        a.A[q] -= dA;
+        a.b[q] += db;
+      }
+      a.state[q] = a.nstate[q];
     }
-    rn = block_sum(rn, sh);
-    rz_new = block_sum(rz_new, sh);
-    if (rn <= a.tol2 * bb) break;
-    const double beta = rz_new / rz;
-    rz = rz_new;
-    for (int32_t q = nb + t; q < ne; q += kBlock) a.p[q] = a.rr[q] * a.dinv[q] + beta * a.p[q];
+    __syncthreads();
+  }
+
+  // nodes still active sit on cycles (or on paths longer than the round cap)
+  int left = 0;
+  for (int32_t q = nb + t; q < ne; q += kBlock) left += a.state[q] == kActive;
+  left = __syncthreads_or(left);
+  if (left) {
+    double bb = 0.0, rz = 0.0;
+    for (int32_t q = nb + t; q < ne; q += kBlock) {
+      const bool act = a.state[q] == kActive;
+      const double rhs = act ? a.b[q] : 0.0;
+      a.y[q] = 0.0;
+      a.rr[q] = rhs;
+      a.p[q] = act ? rhs / a.A[q] : 0.0;
+      bb += rhs * rhs;
+      rz += act ? rhs * rhs / a.A[q] : 0.0;
+    }
+    bb = block_sum(bb, sh);
+    rz = block_sum(rz, sh);
+    for (int it = 0; it < a.max_iter && bb > 0.0; ++it) {
+      double pap = 0.0;
+      for (int32_t q = nb + t; q < ne; q += kBlock) {
+        if (a.state[q] != kActive) continue;
+        double v = a.A[q] * a.p[q];
+        for (int32_t e = a.node_start[q]; e < a.node_start[q + 1]; ++e) {
+          const uint32_t en = a.vals[e];
+          const int32_t pn = a.node_of[en ^ 1u];
+          if (a.state[pn] == kActive) v -= a.w[en >> 1] * a.p[pn];
+        }
+        a.ap[q] = v;
+        pap += a.p[q] * v;
+      }
+      pap = block_sum(pap, sh);
+      const double alpha = rz / pap;
+      double rn = 0.0, rz_new = 0.0;
+      for (int32_t q = nb + t; q < ne; q += kBlock) {
+        if (a.state[q] != kActive) continue;
+        a.y[q] += alpha * a.p[q];
+        const double rq = a.rr[q] - alpha * a.ap[q];
+        a.rr[q] = rq;
+        rn += rq * rq;
+        rz_new += rq * rq / a.A[q];
+      }
+      rn = block_sum(rn, sh);
+      rz_new = block_sum(rz_new, sh);
+      if (rn <= a.tol2 * bb) break;
+      const double beta = rz_new / rz;
+      rz = rz_new;
+      for (int32_t q = nb + t; q < ne; q += kBlock)
+        if (a.state[q] == kActive) a.p[q] = a.rr[q] / a.A[q] + beta * a.p[q];
+      __syncthreads();
+    }
+    for (int32_t q = nb + t; q < ne; q += kBlock)
+      if (a.state[q] == kActive) a.state[q] = kCore;
+    __syncthreads();
+  }
+
+  // back substitution, last round first
+  for (int rnd = rounds; rnd >= 0; --rnd) {
+    for (int32_t q = nb + t; q < ne; q += kBlock) {
+      if (a.state[q] != rnd) continue;
+      const int32_t pn = a.par[q];
+      a.y[q] = pn < 0 ? a.b[q] / a.A[q] : (a.b[q] + a.Wp[q] * a.y[pn]) / a.A[q];
+    }
     __syncthreads();
   }
 }
@@ -733,7 +852,7 @@ hipError_t exact_whiten(const CatView& cat, int C, int64_t n, BatchBufs b, SortB
                      sb.seg_end, 0, (int64_t)C * cat.L);
   hipLaunchKernelGGL(k_nodes, dim3(grid_for(E)), dim3(kBlock), 0, s, sb.key_out, sb.val_out, scan,
                      E, cat.M, sb.node_of, sb.node_start, sb.seg_begin, sb.seg_end, sb.count);
-  PcgArgs a;
+  SolveArgs a;
   a.vals = sb.val_out;
   a.node_of = sb.node_of;
   a.node_start = sb.node_start;
@@ -741,15 +860,21 @@ hipError_t exact_whiten(const CatView& cat, int C, int64_t n, BatchBufs b, SortB
   a.seg_end = sb.seg_end;
   a.w = b.w;
   a.r = b.r;
-  a.y = sb.vec;
-  a.rr = sb.vec + E;
-  a.p = sb.vec + 2 * E;
-  a.ap = sb.vec + 3 * E;
-  a.dinv = sb.vec + 4 * E;
+  a.A = sb.vec;
+  a.b = sb.vec + E;
+  a.y = sb.vec + 2 * E;
+  a.Wp = sb.vec + 3 * E;
+  a.rr = sb.vec + 4 * E;
+  a.p = sb.vec + 5 * E;
+  a.ap = sb.vec + 6 * E;
+  a.state = sb.ivec;
+  a.nstate = sb.ivec + E;
+  a.par = sb.ivec + 2 * E;
   a.lambda = (cat.sigma * cat.sigma) / (cat.kappa * cat.kappa);
+  a.max_rounds = 64;
   a.max_iter = 400;
-  a.tol2 = 1e-32;
-  hipLaunchKernelGGL(k_pcg, dim3((unsigned)(C * cat.L)), dim3(kBlock), 0, s, a);
+  a.tol2 = 1e-30;
+  hipLaunchKernelGGL(k_tree_solve, dim3((unsigned)(C * cat.L)), dim3(kBlock), 0, s, a);
   hipLaunchKernelGGL(k_exact_z, dim3(grid_for((int64_t)C * n)), dim3(kBlock), 0, s,
                      (int64_t)C * n, cat.sigma * cat.sigma, b.w, b.r, sb.node_of, a.y, b.z);
   return hipGetLastError();

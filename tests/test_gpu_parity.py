@@ -167,6 +167,22 @@ def test_batch_terms_tiny(ctx, tiny_setup, whiten):
     assert np.max(np.abs(z - zw) * s_eff / (np.abs(r) + 1e-3)) < 1e-10
 
 
+def test_exact_whitening_with_cycles(ctx, tiny_setup):
+    """The whole catalog as one batch: every group is the full k-NN graph, so
+    leaf peeling leaves large cyclic cores for the CG stage."""
+    cat, net, cid, nid = tiny_setup
+    prob = lk.load(cat)
+    theta = synth.random_theta(cat, 23)
+    idx = np.arange(cat.N)
+    out = ctx.batch_terms(cid, nid, dev(theta), dev(idx))
+    bt = lk.batch_terms(prob, net, theta, idx, lk.WHITEN_EXACT)
+    r, z = host(out["r"]), host(out["z"])
+    zw = lk.whiten(r, bt.w, bt.group, bt.ev_i, bt.ev_j, prob.M, prob.sigma, prob.kappa,
+                   lk.WHITEN_EXACT)
+    s_eff = prob.sigma ** 2 + 2 * prob.kappa ** 2 * bt.w
+    assert np.max(np.abs(z - zw) * s_eff / (np.abs(r) + 1e-3)) < 1e-10
+
+
 def test_batch_terms_faults_full_batch(ctx, faults_setup):
     cat, net, cid, nid = faults_setup
     prob = lk.load(cat)
