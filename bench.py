@@ -146,11 +146,13 @@ def main():
         fl = flops_per_eval(wl.H, wl.D)
         avg_ms = ms / max(launches, 1)
         achieved = rows / max(launches, 1) * fl / (avg_ms * 1e-3) / 1e12
+        waves, tiles = ctx.network_variant(nid, code)
         res[p] = dict(value=dd / wall, ms_per_step=wall * 1e3 / args.steps, net_ms=ms,
                       net_launches=launches, net_avg_ms=avg_ms, achieved=achieved,
+                      variant={"waves_per_workgroup": waves, "rows_per_workgroup": 16 * tiles},
                       error=sample_error(ctx, spider, cat, net, nid, code))
         log(f"{p}: {dd / wall:.4g} dd-obs/s, {wall * 1e3 / args.steps:.2f} ms/step, network "
-            f"{avg_ms:.3f} ms/launch = {achieved:.2f} TFLOP/s")
+            f"{avg_ms:.3f} ms/launch = {achieved:.2f} TFLOP/s, tiles {waves} waves x {16 * tiles} rows")
     head = precs[0]
     r = res[head]
     line = {
@@ -167,7 +169,8 @@ def main():
                      "unit": "TFLOP/s", "frac": r["achieved"] / PEAK[head], "traffic": None},
         "paths": {p: {"value": v["value"], "ms_per_step": v["ms_per_step"],
                       "network_ms_per_launch": v["net_avg_ms"],
-                      "network_tflops": v["achieved"], "error_vs_oracle": v["error"]}
+                      "network_tflops": v["achieved"], "network_tiles": v["variant"],
+                      "error_vs_oracle": v["error"]}
                   for p, v in res.items()},
     }
     if not args.no_cpu_baseline:

@@ -3,9 +3,12 @@
 #include <climits>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "internal.h"
@@ -196,6 +199,8 @@ struct spider_ctx {
   hipStream_t stream = nullptr;
   std::string err;
   bool profiling = false;
+  // autotuned matrix-core variant per (precision, H, D)
+  std::map<std::tuple<int, int, int>, int> tuned;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
   std::vector<int64_t> prof_rows;
   std::vector<std::unique_ptr<Catalog>> cats;
@@ -267,18 +272,72 @@ hipError_t fetch(std::vector<T>& out, const T* src, size_t count, int mem, hipSt
   return hipSuccess;
 }
 
+constexpr int64_t kTuneRows = 1 << 16;  // tune on launches at least this large
+
+// Matrix-core variant for this launch.  On the first launch of at least
+// kTuneRows rows for a (precision, H, D), every variant is timed on these
+// very rows (one warm-up and two timed launches each, HIP events on the
+// context stream) and the fastest is kept for the context.  The variants
+// give identical results, so tuning never changes an answer.
+// SPIDER_MLP_VARIANT=<index> pins a variant (measurement runs).
+int pick_variant(spider_ctx* ctx, const NetView& nv, int prec, const RowSource& src, RowOut* out,
+                 const MlpVariant* vl, int nvar, int* chosen) {
+  *chosen = 0;
+  if (const char* env = std::getenv("SPIDER_MLP_VARIANT")) {
+    const int k = std::atoi(env);
+    *chosen = (k >= 0 && k < nvar) ? k : 0;
+    return SPIDER_OK;
+  }
+  const auto key = std::make_tuple(prec, nv.H, nv.D);
+  auto it = ctx->tuned.find(key);
+  if (it != ctx->tuned.end()) {
+    *chosen = it->second;
+    return SPIDER_OK;
+  }
+  if (nvar == 1 || src.rows < kTuneRows) return SPIDER_OK;
+  hipEvent_t a, b;
+  HIPCK(hipEventCreate(&a), "event");
+  HIPCK(hipEventCreate(&b), "event");
+  float best = 1e30f;
+  for (int k = 0; k < nvar; ++k) {
+    HIPCK(vl[k].launch(src, nv, out, ctx->stream), "network kernel (tuning)");
+    HIPCK(hipEventRecord(a, ctx->stream), "event");
+    HIPCK(vl[k].launch(src, nv, out, ctx->stream), "network kernel (tuning)");
+    HIPCK(vl[k].launch(src, nv, out, ctx->stream), "network kernel (tuning)");
+    HIPCK(hipEventRecord(b, ctx->stream), "event");
+    HIPCK(hipEventSynchronize(b), "event");
+    float ms = 0.0f;
+    HIPCK(hipEventElapsedTime(&ms, a, b), "event");
+    if (ms < best) {
+      best = ms;
+      *chosen = k;
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  ctx->tuned[key] = *chosen;
+  return SPIDER_OK;
+}
+
 // Network forward/backward over the rows of src.
 int run_network(spider_ctx* ctx, const Net& net, int prec, const RowSource& src, RowOut* out) {
   const NetView nv = net.view(prec);
   hipError_t e;
+  const MlpVariant* vl = nullptr;
+  const int nvar = mlp_variants(prec, net.H, net.D, &vl);
+  int vi = 0;
+  if (nvar > 0 && src.rows > 0) {
+    int rc = pick_variant(ctx, nv, prec, src, out, vl, nvar, &vi);
+    if (rc != SPIDER_OK) return rc;
+  }
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   if (ctx->profiling) {
     HIPCK(hipEventCreate(&ev0), "event");
     HIPCK(hipEventCreate(&ev1), "event");
     HIPCK(hipEventRecord(ev0, ctx->stream), "event");
   }
-  if (mlp_mfma_supported(prec, net.H, net.D)) {
-    e = launch_mlp_mfma(prec, src, nv, out, ctx->stream);
+  if (nvar > 0) {
+    e = src.rows > 0 ? vl[vi].launch(src, nv, out, ctx->stream) : hipSuccess;
   } else if (prec == SPIDER_FP32) {
     e = launch_mlp_tangent(src, nv, out, ctx->stream);
   } else {
@@ -389,6 +448,29 @@ int spider_profile(spider_ctx* ctx, int enable) {
   HIPCK(hipStreamSynchronize(ctx->stream), "sync");
   clear_profile(ctx);
   ctx->profiling = enable != 0;
+  return SPIDER_OK;
+}
+
+int spider_network_variant(spider_ctx* ctx, int32_t net_id, int32_t precision, int32_t* waves,
+                           int32_t* row_tiles) {
+  if (!ctx) return SPIDER_E_INVALID;
+  Net* net = get_net(ctx, net_id);
+  if (!net) return fail(ctx, SPIDER_E_INVALID, "unknown network id");
+  const MlpVariant* vl = nullptr;
+  const int nvar = mlp_variants(precision, net->H, net->D, &vl);
+  int32_t w = 0, r = 0;
+  if (nvar > 0) {
+    auto it = ctx->tuned.find(std::make_tuple((int)precision, net->H, net->D));
+    int k = it == ctx->tuned.end() ? 0 : it->second;
+    if (const char* env = std::getenv("SPIDER_MLP_VARIANT")) {
+      const int e = std::atoi(env);
+      k = (e >= 0 && e < nvar) ? e : 0;
+    }
+    w = vl[k].nw;
+    r = vl[k].rt;
+  }
+  if (waves) *waves = w;
+  if (row_tiles) *row_tiles = r;
   return SPIDER_OK;
 }
 

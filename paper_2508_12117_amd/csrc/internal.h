@@ -74,13 +74,15 @@ __device__ inline void row_inputs(const RowSource& src, const NetView& net, int6
   }
 }
 
-// tanh(z) and 1 - tanh(z)^2 from one exponential: with q = 2 / (1 + e^{2|z|}),
-// tanh|z| = 1 - q and 1 - tanh^2 = q (2 - q), accurate also where tanh -> +-1.
+// tanh(z) and 1 - tanh(z)^2 from one exponential and one reciprocal: with
+// e = exp(2|z|) and r = 1/(1 + e), tanh|z| = 1 - 2r and 1 - tanh^2 = 4r(1 - r),
+// accurate also where tanh -> +-1 (e = inf gives r = 0).  exp uses the
+// hardware base-2 exponential on 2 log2(e) |z|.
 __device__ inline void tanh_d(float z, float& a, float& d) {
-  const float e = __expf(2.0f * fabsf(z));
-  const float q = 2.0f / (1.0f + e);
-  a = copysignf(1.0f - q, z);
-  d = q * (2.0f - q);
+  const float e = __builtin_amdgcn_exp2f(fabsf(z) * 2.8853900817779268f);
+  const float r = __builtin_amdgcn_rcpf(1.0f + e);
+  a = copysignf(fmaf(r, -2.0f, 1.0f), z);
+  d = 4.0f * r * (1.0f - r);
 }
 
 // Catalog as the step kernels see it.
@@ -136,8 +138,17 @@ struct SortBufs {
 // Network kernels (mlp_*.hip).  Unsupported shapes return hipErrorNotSupported.
 hipError_t launch_mlp_tangent(const RowSource& src, const NetView& net, RowOut* out,
                               hipStream_t stream);
-hipError_t launch_mlp_mfma(int precision, const RowSource& src, const NetView& net, RowOut* out,
-                           hipStream_t stream);
+// Matrix-core kernel variants (tile shapes) of one network shape: NW waves
+// per workgroup, RT 16-row tiles per workgroup.  Every variant computes the
+// same per-row arithmetic in the same order, so they agree bit for bit.
+struct MlpVariant {
+  int nw, rt;
+  hipError_t (*launch)(const RowSource&, const NetView&, RowOut*, hipStream_t);
+};
+// Number of variants for (precision, H, D) and the list (0: no kernel).
+int mlp_variants(int precision, int H, int D, const MlpVariant** list);
+int mlp_variants_bf16(int H, int D, const MlpVariant** list);
+int mlp_variants_f32(int H, int D, const MlpVariant** list);
 bool mlp_mfma_supported(int precision, int H, int D);
 // Bytes of the forward (or backward) operand pack of one hidden layer.
 size_t mfma_pack_bytes(int precision, int H);

@@ -1,4 +1,4 @@
-// Matrix-core travel-time network kernel for gfx950: forward pass and
+// Matrix-core travel-time network kernel template for gfx950: forward pass and
 // reverse-mode source gradient (Sec. 3.2) in one launch, BF16 operands with
 // FP32 accumulation (v_mfma_f32_16x16x32_bf16) or FP32 throughout
 // (v_mfma_f32_16x16x4_f32).
@@ -21,6 +21,7 @@
 //   C: column c, rows 4 g .. 4 g + 3
 // The k index of slot (g, s, j) is g H/4 + s KPL + j for both operands; any
 // such consistent assignment gives the full dot product.
+#pragma once
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -29,7 +30,7 @@
 
 namespace spider {
 
-namespace {
+namespace mfma {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
@@ -38,7 +39,6 @@ struct PolBF16 {
   using T = __bf16;
   using V = bf16x8;                 // one MFMA operand per lane
   static constexpr int KPL = 8;     // k values per lane per MFMA
-  static constexpr int RT = 4;      // row tiles per workgroup
   static constexpr bool kBF16 = true;
   __device__ static floatx4 mma(const V& a, const V& b, const floatx4& c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
@@ -49,7 +49,6 @@ struct PolF32 {
   using T = float;
   using V = float;
   static constexpr int KPL = 1;
-  static constexpr int RT = 2;
   static constexpr bool kBF16 = false;
   __device__ static floatx4 mma(const V& a, const V& b, const floatx4& c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -70,10 +69,10 @@ constexpr int chunks_per_layer(int H) {
   return (H / 4) / Chunk<P>::ELEMS;
 }
 
-template <class P, int H, int D, int NW>
+template <class P, int H, int D, int NW, int RT_>
 struct Shape {
   static constexpr int CT = H / 16 / NW;       // column tiles per wave
-  static constexpr int RT = P::RT;
+  static constexpr int RT = RT_;
   static constexpr int R = 16 * RT;            // rows per workgroup
   static constexpr int KG = H / 4;             // k per lane group
   static constexpr int NQ = chunks_per_layer<P>(H);
@@ -81,12 +80,19 @@ struct Shape {
   static constexpr int LDW = H + PAD;          // LDS row stride (elements)
   static constexpr int NL = D > 1 ? D - 1 : 1;  // stored derivative layers
   // derivative layers kept in registers; the rest go to LDS (BF16 pairs)
-  static constexpr int NLR = (P::kBF16 && H * RT / NW > 64) ? (NL < 4 ? NL : 4) : NL;
+  static constexpr size_t LAYER_BYTES = (size_t)R * H * 2;  // one BF16 derivative layer
+  static constexpr int LDS_LAYERS_MAX =
+      (int)((160 * 1024 - (size_t)R * LDW * sizeof(typename P::T) - (size_t)R * 6 * 4 -
+             (size_t)(H / 16) * R * 4 * 4) / LAYER_BYTES);
+  static constexpr int NLR_PREF = NL < 3 ? NL : 3;
+  static constexpr int NLR = (P::kBF16 && H * RT / NW > 64)
+                                 ? (NLR_PREF > NL - LDS_LAYERS_MAX ? NLR_PREF : NL - LDS_LAYERS_MAX)
+                                 : NL;
   static constexpr int NLDS = NL - NLR;
   static constexpr int NT = NW * 64;
   static constexpr size_t ACT_BYTES = (size_t)R * LDW * sizeof(typename P::T);
   static constexpr size_t DLDS_BYTES = (size_t)NLDS * RT * CT * 2 * NT * 4;
-  static constexpr size_t FIXED_BYTES = (size_t)R * 6 * 4 + (size_t)NW * R * 4 * 4;
+  static constexpr size_t FIXED_BYTES = (size_t)R * 6 * 4 + (size_t)(H / 16) * R * 4 * 4;
   // two activation buffers when they fit in 160 KB of LDS, else one buffer
   // and an extra barrier per layer
   static constexpr int NBUF = 2 * ACT_BYTES + DLDS_BYTES + FIXED_BYTES <= 156 * 1024 ? 2 : 1;
@@ -94,6 +100,13 @@ struct Shape {
   static_assert(CT * NW * 16 == H, "H must split into 16-wide tiles over the waves");
   static_assert(NQ * Chunk<P>::ELEMS == KG, "H/4 must be a whole number of chunks");
 };
+
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
+  const bf16x2 v = {(__bf16)lo, (__bf16)hi};
+  return __builtin_bit_cast(uint32_t, v);
+}
 
 // Derivative factors 1 - a^2 kept between the passes: FP32 registers, or in
 // the BF16 path BF16 pairs (round to nearest even), the first NLR layers in
@@ -103,6 +116,10 @@ template <class P, int NL, int NLR, int RT, int CT, int NT>
 struct DStore {
   float v[NL][RT][CT][4];
   __device__ void set(int l, int rt, int ct, int i, float x) { v[l][rt][ct][i] = x; }
+  __device__ void set4(int l, int rt, int ct, const float x[4]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[l][rt][ct][i] = x[i];
+  }
   __device__ float get(int l, int rt, int ct, int i) const { return v[l][rt][ct][i]; }
 };
 
@@ -122,6 +139,14 @@ struct DStore<PolBF16, NL, NLR, RT, CT, NT> {
     if (l < NLR) v[l][rt][ct][i >> 1] = w;
     else lds[(((l - NLR) * RT * CT + rt * CT + ct) * 2 + (i >> 1)) * NT + tid] = w;
   }
+  __device__ void set4(int l, int rt, int ct, const float x[4]) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const uint32_t w = pack_bf16x2(x[2 * h], x[2 * h + 1]);
+      if (l < NLR) v[l][rt][ct][h] = w;
+      else lds[(((l - NLR) * RT * CT + rt * CT + ct) * 2 + h) * NT + tid] = w;
+    }
+  }
   __device__ float get(int l, int rt, int ct, int i) const {
     const uint32_t w = l < NLR ? v[l][rt][ct][i >> 1]
                                : lds[(((l - NLR) * RT * CT + rt * CT + ct) * 2 + (i >> 1)) * NT + tid];
@@ -135,9 +160,92 @@ union Pack16 {
   float f[4];
 };
 
-template <class P, int H, int D, int NW>
+template <int CTRL>
+__device__ __forceinline__ float dpp(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+
+// Sum over the 16 lanes of a row (quad swaps, then half-row and row mirror
+// exchanges).  Every lane ends with the same value, added in the same order
+// for every tile shape.
+__device__ __forceinline__ float row16_sum(float v) {
+  v += dpp<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  v += dpp<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  v += dpp<0x141>(v);  // row_half_mirror
+  v += dpp<0x140>(v);  // row_mirror
+  return v;
+}
+
+// Store a C-layout 4-row column fragment (rows row0 .. row0 + 3 of column n,
+// one lane per column) as pairs of adjacent columns: neighbouring lanes swap
+// two values, the even lane stores rows 0-1 and the odd lane rows 2-3 of the
+// column pair (n & ~1, n | 1), one 32-bit (BF16) or 64-bit (FP32) store each.
+template <class T>
+__device__ __forceinline__ void store_col_pairs(T* buf, int ldw, int row0, int n, const float v[4]) {
+  const bool odd = n & 1;
+  const float r0 = dpp<0xB1>(odd ? v[0] : v[2]);
+  const float r1 = dpp<0xB1>(odd ? v[1] : v[3]);
+  const int col = n & ~1;
+  const float a0 = odd ? r0 : v[0], b0 = odd ? v[2] : r0;
+  const float a1 = odd ? r1 : v[1], b1 = odd ? v[3] : r1;
+  const int ra = row0 + (odd ? 2 : 0);
+  if constexpr (sizeof(T) == 2) {
+    *(uint32_t*)(buf + ra * ldw + col) = pack_bf16x2(a0, b0);
+    *(uint32_t*)(buf + (ra + 1) * ldw + col) = pack_bf16x2(a1, b1);
+  } else {
+    *(float2*)(buf + ra * ldw + col) = make_float2(a0, b0);
+    *(float2*)(buf + (ra + 1) * ldw + col) = make_float2(a1, b1);
+  }
+}
+
+// acc[rt][ct] += A[16 rt + row][k] . B[k][col tile wave*CT + ct] over the
+// layer's K = H, A from LDS (row stride LDW), B from the packed operand
+// stream pl.  The B chunks are prefetched PF chunks ahead through a rotating
+// register buffer so that their L2 latency overlaps the MFMAs.
+template <class P, int RT, int CT, int NQ, int LDW, int KG>
+__device__ __forceinline__ void layer_mma(const typename P::T* A, const uint4* pl, int wave,
+                                          int lane, int c, int g, floatx4 (&acc)[RT][CT]) {
+  constexpr int ELEMS = Chunk<P>::ELEMS, SPC = Chunk<P>::SPC;
+  constexpr int PF = NQ < 4 ? NQ : 4;
+  static_assert(NQ % PF == 0, "chunks must split evenly over the prefetch ring");
+  Pack16 bq[PF][CT];
+#pragma unroll
+  for (int j = 0; j < PF; ++j)
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) bq[j][ct].u = pl[((wave * CT + ct) * NQ + j) * 64 + lane];
+#pragma unroll 1
+  for (int q0 = 0; q0 < NQ; q0 += PF) {
+#pragma unroll
+    for (int j = 0; j < PF; ++j) {
+      const int q = q0 + j;
+      Pack16 a[RT];
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+        a[rt].u = *(const uint4*)(A + (rt * 16 + c) * LDW + g * KG + q * ELEMS);
+#pragma unroll
+      for (int s = 0; s < SPC; ++s)
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+          for (int ct = 0; ct < CT; ++ct) {
+            if constexpr (P::kBF16) {
+              acc[rt][ct] = P::mma(a[rt].b, bq[j][ct].b, acc[rt][ct]);
+            } else {
+              acc[rt][ct] = P::mma(a[rt].f[s], bq[j][ct].f[s], acc[rt][ct]);
+            }
+          }
+      if (q + PF < NQ) {
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
+          bq[j][ct].u = pl[((wave * CT + ct) * NQ + q + PF) * 64 + lane];
+      }
+    }
+  }
+}
+
+template <class P, int H, int D, int NW, int RT_>
 __global__ __launch_bounds__(NW * 64) void k_mlp(RowSource src, NetView net, RowOut* out) {
-  using S = Shape<P, H, D, NW>;
+  using S = Shape<P, H, D, NW, RT_>;
   using T = typename P::T;
   constexpr int CT = S::CT, RT = S::RT, R = S::R, NQ = S::NQ, LDW = S::LDW, KG = S::KG;
   constexpr int ELEMS = Chunk<P>::ELEMS, SPC = Chunk<P>::SPC;
@@ -146,7 +254,10 @@ __global__ __launch_bounds__(NW * 64) void k_mlp(RowSource src, NetView net, Row
   __shared__ __attribute__((aligned(16))) T act[NBUF][R * LDW];
   __shared__ uint32_t dlds[S::NLDS > 0 ? S::NLDS * RT * CT * 2 * NT : 1];
   __shared__ float u_s[R][6];
-  __shared__ float part[NW][R][4];
+  // per 16-neuron column tile partial sums of the output layer and the input
+  // gradient; summed over tiles in a fixed order, so the result does not
+  // depend on how the tiles are split over the waves
+  __shared__ float part[H / 16][R][4];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -187,19 +298,19 @@ __global__ __launch_bounds__(NW * 64) void k_mlp(RowSource src, NetView net, Row
       const float b = net.bias[n];
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt) {
+        float av[4], dv[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int row = rt * 16 + g * 4 + i;
           float z = b;
 #pragma unroll
           for (int a = 0; a < 6; ++a) z += w[a] * u_s[row][a];
-          float av, dv;
-          tanh_d(z, av, dv);
-          if (D > 1) dst.set(0, rt, ct, i, dv);
-          else eD[rt][ct][i] = wo[ct] * dv;
-          acc[rt][ct][i] = av;
-          out_act[row * LDW + n] = (T)av;
+          tanh_d(z, av[i], dv[i]);
+          if (D == 1) eD[rt][ct][i] = wo[ct] * dv[i];
+          acc[rt][ct][i] = av[i];
         }
+        if (D > 1) dst.set4(0, rt, ct, dv);
+        store_col_pairs<T>(out_act, LDW, rt * 16 + g * 4, n, av);
       }
     }
   }
@@ -213,49 +324,32 @@ __global__ __launch_bounds__(NW * 64) void k_mlp(RowSource src, NetView net, Row
   for (int l = 1; l < D; ++l) {
     const T* in = act[cur];
     T* outp = act[NBUF == 2 ? cur ^ 1 : 0];
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-      for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = floatx4{0, 0, 0, 0};
-    const uint4* pl = packf + (size_t)(l - 1) * (H / 16) * NQ * 64;
-#pragma unroll 1
-    for (int q = 0; q < NQ; ++q) {
-      Pack16 a[RT], b[CT];
-#pragma unroll
-      for (int rt = 0; rt < RT; ++rt)
-        a[rt].u = *(const uint4*)(in + (rt * 16 + c) * LDW + g * KG + q * ELEMS);
-#pragma unroll
-      for (int ct = 0; ct < CT; ++ct) b[ct].u = pl[((wave * CT + ct) * NQ + q) * 64 + lane];
-#pragma unroll
-      for (int s = 0; s < SPC; ++s)
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-          for (int ct = 0; ct < CT; ++ct) {
-            if constexpr (P::kBF16) {
-              acc[rt][ct] = P::mma(a[rt].b, b[ct].b, acc[rt][ct]);
-            } else {
-              acc[rt][ct] = P::mma(a[rt].f[s], b[ct].f[s], acc[rt][ct]);
-            }
-          }
-    }
     const float* bl = net.bias + l * H;
+    // the accumulators start from the bias: z = b + W a
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      const float bn = bl[(wave * CT + ct) * 16 + c];
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) acc[rt][ct] = floatx4{bn, bn, bn, bn};
+    }
+    const uint4* pl = packf + (size_t)(l - 1) * (H / 16) * NQ * 64;
+    layer_mma<P, RT, CT, NQ, LDW, KG>(in, pl, wave, lane, c, g, acc);
     if constexpr (NBUF == 1) __syncthreads();  // every wave done reading `in`
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
       const int n = (wave * CT + ct) * 16 + c;
-      const float bn = bl[n];
 #pragma unroll
-      for (int rt = 0; rt < RT; ++rt)
+      for (int rt = 0; rt < RT; ++rt) {
+        float av[4], dv[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          float av, dv;
-          tanh_d(acc[rt][ct][i] + bn, av, dv);
-          if (l < D - 1) dst.set(l, rt, ct, i, dv);
-          else eD[rt][ct][i] = wo[ct] * dv;
-          acc[rt][ct][i] = av;
-          outp[(rt * 16 + g * 4 + i) * LDW + n] = (T)av;
+          tanh_d(acc[rt][ct][i], av[i], dv[i]);
+          if (l == D - 1) eD[rt][ct][i] = wo[ct] * dv[i];
+          acc[rt][ct][i] = av[i];
         }
+        if (l < D - 1) dst.set4(l, rt, ct, dv);
+        store_col_pairs<T>(outp, LDW, rt * 16 + g * 4, n, av);
+      }
     }
     __syncthreads();
     if constexpr (NBUF == 2) cur ^= 1;
@@ -266,16 +360,13 @@ __global__ __launch_bounds__(NW * 64) void k_mlp(RowSource src, NetView net, Row
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        float p = 0.0f;
+      for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int ct = 0; ct < CT; ++ct) p += wo[ct] * acc[rt][ct][i];
-        p += __shfl_xor(p, 1, 16);
-        p += __shfl_xor(p, 2, 16);
-        p += __shfl_xor(p, 4, 16);
-        p += __shfl_xor(p, 8, 16);
-        if (c == 0) part[wave][rt * 16 + g * 4 + i][0] = p;
-      }
+        for (int ct = 0; ct < CT; ++ct) {
+          float p = wo[ct] * acc[rt][ct][i];
+          p = row16_sum(p);
+          if (c == 0) part[wave * CT + ct][rt * 16 + g * 4 + i][0] = p;
+        }
   }
 
   // ---- backward l = D-1 .. 1: e_l = (e_{l+1} W_l) * d_l
@@ -291,9 +382,7 @@ __global__ __launch_bounds__(NW * 64) void k_mlp(RowSource src, NetView net, Row
     for (int ct = 0; ct < CT; ++ct) {
       const int n = (wave * CT + ct) * 16 + c;
 #pragma unroll
-      for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) eb[(rt * 16 + g * 4 + i) * LDW + n] = (T)eD[rt][ct][i];
+      for (int rt = 0; rt < RT; ++rt) store_col_pairs<T>(eb, LDW, rt * 16 + g * 4, n, eD[rt][ct]);
     }
     __syncthreads();
 #pragma unroll
@@ -301,27 +390,7 @@ __global__ __launch_bounds__(NW * 64) void k_mlp(RowSource src, NetView net, Row
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = floatx4{0, 0, 0, 0};
     const uint4* pl = packb + (size_t)(l - 1) * (H / 16) * NQ * 64;
-#pragma unroll 1
-    for (int q = 0; q < NQ; ++q) {
-      Pack16 a[RT], b[CT];
-#pragma unroll
-      for (int rt = 0; rt < RT; ++rt)
-        a[rt].u = *(const uint4*)(eb + (rt * 16 + c) * LDW + g * KG + q * ELEMS);
-#pragma unroll
-      for (int ct = 0; ct < CT; ++ct) b[ct].u = pl[((wave * CT + ct) * NQ + q) * 64 + lane];
-#pragma unroll
-      for (int s = 0; s < SPC; ++s)
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-          for (int ct = 0; ct < CT; ++ct) {
-            if constexpr (P::kBF16) {
-              acc[rt][ct] = P::mma(a[rt].b, b[ct].b, acc[rt][ct]);
-            } else {
-              acc[rt][ct] = P::mma(a[rt].f[s], b[ct].f[s], acc[rt][ct]);
-            }
-          }
-    }
+    layer_mma<P, RT, CT, NQ, LDW, KG>(eb, pl, wave, lane, c, g, acc);
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
@@ -345,26 +414,22 @@ __global__ __launch_bounds__(NW * 64) void k_mlp(RowSource src, NetView net, Row
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        float p[3] = {0.0f, 0.0f, 0.0f};
+      for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int ct = 0; ct < CT; ++ct)
+        for (int ct = 0; ct < CT; ++ct) {
+          float p[3];
 #pragma unroll
-          for (int a = 0; a < 3; ++a) p[a] += w[ct][a] * eD[rt][ct][i];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          p[a] += __shfl_xor(p[a], 1, 16);
-          p[a] += __shfl_xor(p[a], 2, 16);
-          p[a] += __shfl_xor(p[a], 4, 16);
-          p[a] += __shfl_xor(p[a], 8, 16);
+          for (int a = 0; a < 3; ++a) {
+            p[a] = w[ct][a] * eD[rt][ct][i];
+            p[a] = row16_sum(p[a]);
+          }
+          if (c == 0) {
+            const int row = rt * 16 + g * 4 + i;
+            part[wave * CT + ct][row][1] = p[0];
+            part[wave * CT + ct][row][2] = p[1];
+            part[wave * CT + ct][row][3] = p[2];
+          }
         }
-        if (c == 0) {
-          const int row = rt * 16 + g * 4 + i;
-          part[wave][row][1] = p[0];
-          part[wave][row][2] = p[1];
-          part[wave][row][3] = p[2];
-        }
-      }
   }
   __syncthreads();
   for (int r = tid; r < R; r += NW * 64) {
@@ -372,11 +437,11 @@ __global__ __launch_bounds__(NW * 64) void k_mlp(RowSource src, NetView net, Row
     if (row >= src.rows) continue;
     float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
 #pragma unroll
-    for (int w = 0; w < NW; ++w) {
-      s0 += part[w][r][0];
-      s1 += part[w][r][1];
-      s2 += part[w][r][2];
-      s3 += part[w][r][3];
+    for (int tile = 0; tile < H / 16; ++tile) {
+      s0 += part[tile][r][0];
+      s1 += part[tile][r][1];
+      s2 += part[tile][r][2];
+      s3 += part[tile][r][3];
     }
     RowOut o;
     o.o = s0 + net.bout;
@@ -387,37 +452,15 @@ __global__ __launch_bounds__(NW * 64) void k_mlp(RowSource src, NetView net, Row
   }
 }
 
-// ---------------------------------------------------------------- dispatch
+// ---------------------------------------------------------------- launch
 
-template <class P, int H, int D, int NW>
-hipError_t launch_one(const RowSource& src, const NetView& net, RowOut* out, hipStream_t s) {
-  using Sh = Shape<P, H, D, NW>;
+template <class P, int H, int D, int NW, int RT>
+hipError_t launch_variant(const RowSource& src, const NetView& net, RowOut* out, hipStream_t s) {
+  using Sh = Shape<P, H, D, NW, RT>;
   const int64_t blocks = ceil_div(src.rows, Sh::R);
-  hipLaunchKernelGGL((k_mlp<P, H, D, NW>), dim3((unsigned)blocks), dim3(NW * 64), 0, s, src, net,
-                     out);
+  hipLaunchKernelGGL((k_mlp<P, H, D, NW, RT>), dim3((unsigned)blocks), dim3(NW * 64), 0, s, src,
+                     net, out);
   return hipGetLastError();
-}
-
-template <class P>
-hipError_t dispatch(int H, int D, const RowSource& src, const NetView& net, RowOut* out,
-                    hipStream_t s, bool probe) {
-#define SPIDER_CASE(HH, DD, NWW)                                         \
-  if (H == HH && D == DD) return probe ? hipSuccess : launch_one<P, HH, DD, NWW>(src, net, out, s);
-  SPIDER_CASE(32, 2, 2)
-  SPIDER_CASE(32, 3, 2)
-  SPIDER_CASE(32, 4, 2)
-  SPIDER_CASE(64, 3, 4)
-  SPIDER_CASE(64, 4, 4)
-  SPIDER_CASE(128, 3, 4)
-  SPIDER_CASE(128, 4, 4)
-  SPIDER_CASE(128, 5, 4)
-  SPIDER_CASE(256, 4, 8)
-  SPIDER_CASE(256, 5, 8)
-  SPIDER_CASE(256, 6, 8)
-  SPIDER_CASE(256, 7, 8)
-  SPIDER_CASE(256, 8, 8)
-#undef SPIDER_CASE
-  return hipErrorNotSupported;
 }
 
 inline uint16_t bf16_rne(float f) {
@@ -427,6 +470,7 @@ inline uint16_t bf16_rne(float f) {
   return (uint16_t)((x + 0x7FFFu + lsb) >> 16);
 }
 
+// Host-side packing of one hidden layer into the operand order above.
 template <class P>
 void pack_layer(int H, const float* W, unsigned char* fwd, unsigned char* bwd) {
   using T = typename P::T;
@@ -454,31 +498,6 @@ void pack_layer(int H, const float* W, unsigned char* fwd, unsigned char* bwd) {
         }
 }
 
-}  // namespace
-
-bool mlp_mfma_supported(int precision, int H, int D) {
-  RowSource src{};
-  NetView net{};
-  if (precision == 1) return dispatch<PolBF16>(H, D, src, net, nullptr, 0, true) == hipSuccess;
-  return dispatch<PolF32>(H, D, src, net, nullptr, 0, true) == hipSuccess;
-}
-
-size_t mfma_pack_bytes(int precision, int H) {
-  return (size_t)H * H * (precision == 1 ? 2 : 4);
-}
-
-void mfma_pack_layer(int precision, int H, const float* W, void* fwd, void* bwd) {
-  if (precision == 1)
-    pack_layer<PolBF16>(H, W, (unsigned char*)fwd, (unsigned char*)bwd);
-  else
-    pack_layer<PolF32>(H, W, (unsigned char*)fwd, (unsigned char*)bwd);
-}
-
-hipError_t launch_mlp_mfma(int precision, const RowSource& src, const NetView& net, RowOut* out,
-                           hipStream_t stream) {
-  if (src.rows == 0) return hipSuccess;
-  if (precision == 1) return dispatch<PolBF16>(net.H, net.D, src, net, out, stream, false);
-  return dispatch<PolF32>(net.H, net.D, src, net, out, stream, false);
-}
+}  // namespace mfma
 
 }  // namespace spider

@@ -89,6 +89,8 @@ _SIGS = {
     "spider_get_state": ([_P, ct.c_int32, ct.c_int32, _P, _P, ct.POINTER(ct.c_int64)], ct.c_int),
     "spider_set_state": ([_P, ct.c_int32, ct.c_int32, _P, _P, ct.c_int64], ct.c_int),
     "spider_profile": ([_P, ct.c_int], ct.c_int),
+    "spider_network_variant": ([_P, ct.c_int32, ct.c_int32, ct.POINTER(ct.c_int32),
+                                ct.POINTER(ct.c_int32)], ct.c_int),
     "spider_profile_read": ([_P, ct.POINTER(ct.c_double), ct.POINTER(ct.c_int64),
                              ct.POINTER(ct.c_int64)], ct.c_int),
 }
@@ -287,6 +289,13 @@ class Context:
 
     def profile(self, enable: bool):
         self._check(lib().spider_profile(self._h, 1 if enable else 0))
+
+    def network_variant(self, net_id, precision=FP32):
+        """(waves per workgroup, 16-row tiles per workgroup) of the chosen kernel."""
+        w, r = ct.c_int32(), ct.c_int32()
+        self._check(lib().spider_network_variant(self._h, net_id, precision, ct.byref(w),
+                                                 ct.byref(r)))
+        return w.value, r.value
 
     def profile_read(self):
         """(summed network-kernel ms, launches, rows) since profile(True)."""

@@ -438,3 +438,23 @@ def test_bf16_sampler_runs_and_is_deterministic(ctx, tiny_setup):
         outs.append(host(th))
     assert np.all(np.isfinite(outs[0])) and np.array_equal(outs[0], outs[1])
     assert np.abs(outs[0] - cat.hypo0).max() > 0
+
+
+@pytest.mark.parametrize("H,D", [(256, 6), (128, 4), (256, 8)])
+@pytest.mark.parametrize("prec", [spider.BF16, spider.FP32])
+def test_kernel_variants_agree_bitwise(ctx, monkeypatch, H, D, prec):
+    """Every tile variant the autotuner may pick computes the same bits."""
+    net = synth.make_net(H, D, center=[5.0, 5.0, 4.0], half_extent=[10.0, 10.0, 6.0], seed=3)
+    nid = ctx.load_net(net)
+    x, s = _points(3001, 9)
+    outs, shapes = [], []
+    for k in range(4):
+        monkeypatch.setenv("SPIDER_MLP_VARIANT", str(k))
+        T = torch.empty(3001, dtype=torch.float64, device="cuda")
+        g = torch.empty(3001, 3, dtype=torch.float64, device="cuda")
+        ctx.travel_time(nid, dev(x), dev(s), T, g, precision=prec)
+        outs.append((host(T), host(g)))
+        shapes.append(ctx.network_variant(nid, prec))
+    for T, g in outs[1:]:
+        assert np.array_equal(T, outs[0][0]) and np.array_equal(g, outs[0][1])
+    assert all(w > 0 and r > 0 for w, r in shapes)
