@@ -142,7 +142,7 @@ struct Workspace {
     RES(seg_end, CL * 4);
     RES(flags, E * 4);
     RES(vec, E * 8 * 8);
-    RES(ivec, E * 4 * 3);
+    RES(ivec, E * 4 * 4);
     RES(count, 16);
     RES(G, CM * 32);
     RES(partial, (CM / 4096 + C + 1) * 32);

@@ -130,7 +130,7 @@ struct SortBufs {
   int32_t* seg_end;    // [C L]
   int32_t* flags;      // [2 C n] scratch
   double* vec;         // [8][2 C n] solver vectors
-  int32_t* ivec;       // [3][2 C n] solver node states
+  int32_t* ivec;       // [4][2 C n] solver node states and lists
   int32_t* count;      // [1] device node count
 };
 

@@ -9,6 +9,9 @@ using mfma::PolBF16;
 
 #define SPIDER_V(H, D, NW, RT) \
   MlpVariant { NW, RT, &launch_variant<PolBF16, H, D, NW, RT> }
+// two resident workgroups per CU, shallower weight prefetch
+#define SPIDER_V2(H, D, NW, RT) \
+  MlpVariant { NW, RT, &launch_variant<PolBF16, H, D, NW, RT, 2, 2> }
 
 int mlp_variants_bf16(int H, int D, const MlpVariant** list) {
   static const MlpVariant h32d2[] = {SPIDER_V(32, 2, 2, 4)};
@@ -23,10 +26,10 @@ int mlp_variants_bf16(int H, int D, const MlpVariant** list) {
   static const MlpVariant h256d4[] = {SPIDER_V(256, 4, 8, 4)};
   static const MlpVariant h256d5[] = {SPIDER_V(256, 5, 8, 4)};
   static const MlpVariant h256d6[] = {SPIDER_V(256, 6, 8, 4), SPIDER_V(256, 6, 4, 4),
-                                      SPIDER_V(256, 6, 8, 2), SPIDER_V(256, 6, 4, 2)};
+                                      SPIDER_V(256, 6, 8, 2), SPIDER_V2(256, 6, 4, 2)};
   static const MlpVariant h256d7[] = {SPIDER_V(256, 7, 8, 4)};
-  static const MlpVariant h256d8[] = {SPIDER_V(256, 8, 8, 4),
-                                      SPIDER_V(256, 8, 8, 2), SPIDER_V(256, 8, 4, 2)};
+  static const MlpVariant h256d8[] = {SPIDER_V(256, 8, 8, 4), SPIDER_V(256, 8, 8, 2),
+                                      SPIDER_V2(256, 8, 4, 2)};
 #define SPIDER_L(HH, DD, arr)                \
   if (H == HH && D == DD) {                  \
     *list = arr;                             \

@@ -202,11 +202,11 @@ __device__ __forceinline__ void store_col_pairs(T* buf, int ldw, int row0, int n
 // layer's K = H, A from LDS (row stride LDW), B from the packed operand
 // stream pl.  The B chunks are prefetched PF chunks ahead through a rotating
 // register buffer so that their L2 latency overlaps the MFMAs.
-template <class P, int RT, int CT, int NQ, int LDW, int KG>
+template <class P, int RT, int CT, int NQ, int LDW, int KG, int PF_>
 __device__ __forceinline__ void layer_mma(const typename P::T* A, const uint4* pl, int wave,
                                           int lane, int c, int g, floatx4 (&acc)[RT][CT]) {
   constexpr int ELEMS = Chunk<P>::ELEMS, SPC = Chunk<P>::SPC;
-  constexpr int PF = NQ < 4 ? NQ : 4;
+  constexpr int PF = NQ < PF_ ? NQ : PF_;
   static_assert(NQ % PF == 0, "chunks must split evenly over the prefetch ring");
   Pack16 bq[PF][CT];
 #pragma unroll
@@ -243,8 +243,11 @@ __device__ __forceinline__ void layer_mma(const typename P::T* A, const uint4* p
   }
 }
 
-template <class P, int H, int D, int NW, int RT_>
-__global__ __launch_bounds__(NW * 64) void k_mlp(RowSource src, NetView net, RowOut* out) {
+// MINB workgroups per CU are targeted (MINB = 2 asks the compiler for at most
+// 256 registers per wave so that two independent workgroups share each SIMD
+// and one's vector epilogue overlaps the other's matrix work).
+template <class P, int H, int D, int NW, int RT_, int PF = 4, int MINB = 1>
+__global__ __launch_bounds__(NW * 64, MINB) void k_mlp(RowSource src, NetView net, RowOut* out) {
   using S = Shape<P, H, D, NW, RT_>;
   using T = typename P::T;
   constexpr int CT = S::CT, RT = S::RT, R = S::R, NQ = S::NQ, LDW = S::LDW, KG = S::KG;
@@ -333,7 +336,7 @@ __global__ __launch_bounds__(NW * 64) void k_mlp(RowSource src, NetView net, Row
       for (int rt = 0; rt < RT; ++rt) acc[rt][ct] = floatx4{bn, bn, bn, bn};
     }
     const uint4* pl = packf + (size_t)(l - 1) * (H / 16) * NQ * 64;
-    layer_mma<P, RT, CT, NQ, LDW, KG>(in, pl, wave, lane, c, g, acc);
+    layer_mma<P, RT, CT, NQ, LDW, KG, PF>(in, pl, wave, lane, c, g, acc);
     if constexpr (NBUF == 1) __syncthreads();  // every wave done reading `in`
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
@@ -390,7 +393,7 @@ __global__ __launch_bounds__(NW * 64) void k_mlp(RowSource src, NetView net, Row
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = floatx4{0, 0, 0, 0};
     const uint4* pl = packb + (size_t)(l - 1) * (H / 16) * NQ * 64;
-    layer_mma<P, RT, CT, NQ, LDW, KG>(eb, pl, wave, lane, c, g, acc);
+    layer_mma<P, RT, CT, NQ, LDW, KG, PF>(eb, pl, wave, lane, c, g, acc);
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
@@ -454,12 +457,12 @@ __global__ __launch_bounds__(NW * 64) void k_mlp(RowSource src, NetView net, Row
 
 // ---------------------------------------------------------------- launch
 
-template <class P, int H, int D, int NW, int RT>
+template <class P, int H, int D, int NW, int RT, int PF = 4, int MINB = 1>
 hipError_t launch_variant(const RowSource& src, const NetView& net, RowOut* out, hipStream_t s) {
   using Sh = Shape<P, H, D, NW, RT>;
   const int64_t blocks = ceil_div(src.rows, Sh::R);
-  hipLaunchKernelGGL((k_mlp<P, H, D, NW, RT>), dim3((unsigned)blocks), dim3(NW * 64), 0, s, src,
-                     net, out);
+  hipLaunchKernelGGL((k_mlp<P, H, D, NW, RT, PF, MINB>), dim3((unsigned)blocks), dim3(NW * 64), 0,
+                     s, src, net, out);
   return hipGetLastError();
 }
 

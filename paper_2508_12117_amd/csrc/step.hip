@@ -292,6 +292,7 @@ struct SolveArgs {
   int32_t* state;   // kActive, or the round in which the node was removed
   int32_t* nstate;
   int32_t* par;     // parent of an eliminated node (-1: solved on its own)
+  int32_t* core;    // scratch list of the nodes left on cycles
   double lambda;
   int max_rounds;
   int max_iter;
@@ -411,27 +412,53 @@ __global__ __launch_bounds__(kBlock) void k_tree_solve(SolveArgs a) {
     __syncthreads();
   }
 
-  // nodes still active sit on cycles (or on paths longer than the round cap)
-  int left = 0;
-  for (int32_t q = nb + t; q < ne; q += kBlock) left += a.state[q] == kActive;
-  left = __syncthreads_or(left);
-  if (left) {
+  // nodes still active sit on cycles (or on paths longer than the round cap):
+  // gather them into a list (fixed order: block-wide prefix count over the
+  // node range) and run CG on them only
+  __shared__ int32_t n_core_sh;
+  __shared__ int32_t warp_base[kBlock / 64 + 1];
+  int32_t* core = a.core + nb;  // room for every node of the block
+  if (t == 0) n_core_sh = 0;
+  __syncthreads();
+  for (int32_t q0 = nb; q0 < ne; q0 += kBlock) {
+    const int32_t q = q0 + t;
+    const bool act = q < ne && a.state[q] == kActive;
+    const uint64_t mask = __ballot(act);
+    const int lane = t & 63, w = t >> 6;
+    const int before = __popcll(mask & ((1ull << lane) - 1ull));
+    if (lane == 0) warp_base[w] = __popcll(mask);
+    __syncthreads();
+    if (t == 0) {
+      int run = n_core_sh;
+      for (int k = 0; k < kBlock / 64; ++k) {
+        const int c = warp_base[k];
+        warp_base[k] = run;
+        run += c;
+      }
+      n_core_sh = run;
+    }
+    __syncthreads();
+    if (act) core[warp_base[w] + before] = q;
+    __syncthreads();
+  }
+  const int32_t ncore = n_core_sh;
+  if (ncore > 0) {
     double bb = 0.0, rz = 0.0;
-    for (int32_t q = nb + t; q < ne; q += kBlock) {
-      const bool act = a.state[q] == kActive;
-      const double rhs = act ? a.b[q] : 0.0;
+    for (int32_t k = t; k < ncore; k += kBlock) {
+      const int32_t q = core[k];
+      const double rhs = a.b[q];
       a.y[q] = 0.0;
       a.rr[q] = rhs;
-      a.p[q] = act ? rhs / a.A[q] : 0.0;
+      a.p[q] = rhs / a.A[q];
       bb += rhs * rhs;
-      rz += act ? rhs * rhs / a.A[q] : 0.0;
+      rz += rhs * rhs / a.A[q];
     }
     bb = block_sum(bb, sh);
     rz = block_sum(rz, sh);
     for (int it = 0; it < a.max_iter && bb > 0.0; ++it) {
       double pap = 0.0;
-      for (int32_t q = nb + t; q < ne; q += kBlock) {
-        if (a.state[q] != kActive) continue;
+      for (int32_t k = t; k < ncore; k += kBlock) {
+        const int32_t q = core[k];
         double v = a.A[q] * a.p[q];
         for (int32_t e = a.node_start[q]; e < a.node_start[q + 1]; ++e) {
           const uint32_t en = a.vals[e];
@@ -444,8 +471,8 @@ __global__ __launch_bounds__(kBlock) void k_tree_solve(SolveArgs a) {
       pap = block_sum(pap, sh);
       const double alpha = rz / pap;
       double rn = 0.0, rz_new = 0.0;
-      for (int32_t q = nb + t; q < ne; q += kBlock) {
-        if (a.state[q] != kActive) continue;
+      for (int32_t k = t; k < ncore; k += kBlock) {
+        const int32_t q = core[k];
         a.y[q] += alpha * a.p[q];
         const double rq = a.rr[q] - alpha * a.ap[q];
         a.rr[q] = rq;
@@ -457,12 +484,13 @@ __global__ __launch_bounds__(kBlock) void k_tree_solve(SolveArgs a) {
       if (rn <= a.tol2 * bb) break;
       const double beta = rz_new / rz;
       rz = rz_new;
-      for (int32_t q = nb + t; q < ne; q += kBlock)
-        if (a.state[q] == kActive) a.p[q] = a.rr[q] / a.A[q] + beta * a.p[q];
+      for (int32_t k = t; k < ncore; k += kBlock) {
+        const int32_t q = core[k];
+        a.p[q] = a.rr[q] / a.A[q] + beta * a.p[q];
+      }
       __syncthreads();
     }
-    for (int32_t q = nb + t; q < ne; q += kBlock)
-      if (a.state[q] == kActive) a.state[q] = kCore;
+    for (int32_t k = t; k < ncore; k += kBlock) a.state[core[k]] = kCore;
     __syncthreads();
   }
 
@@ -870,10 +898,11 @@ hipError_t exact_whiten(const CatView& cat, int C, int64_t n, BatchBufs b, SortB
   a.state = sb.ivec;
   a.nstate = sb.ivec + E;
   a.par = sb.ivec + 2 * E;
+  a.core = sb.ivec + 3 * E;
   a.lambda = (cat.sigma * cat.sigma) / (cat.kappa * cat.kappa);
   a.max_rounds = 64;
-  a.max_iter = 400;
-  a.tol2 = 1e-30;
+  a.max_iter = 200;
+  a.tol2 = 1e-28;
   hipLaunchKernelGGL(k_tree_solve, dim3((unsigned)(C * cat.L)), dim3(kBlock), 0, s, a);
   hipLaunchKernelGGL(k_exact_z, dim3(grid_for((int64_t)C * n)), dim3(kBlock), 0, s,
                      (int64_t)C * n, cat.sigma * cat.sigma, b.w, b.r, sb.node_of, a.y, b.z);
