@@ -86,7 +86,7 @@ struct Net {
   int D = 0, H = 0;
   double v0 = 0, center[3] = {}, half[3] = {};
   float bout = 0;
-  DevBuf W0, bias, Wt, wout;
+  DevBuf W0, bias, W0s, bias_s, Wt, wout;
   DevBuf pack_fwd[2], pack_bwd[2];  // by precision
 
   NetView view(int prec) const {
@@ -95,6 +95,8 @@ struct Net {
     v.H = H;
     v.W0 = W0.as<float>();
     v.bias = bias.as<float>();
+    v.W0s = W0s.as<float>();
+    v.bias_s = bias_s.as<float>();
     v.Wt = Wt.as<float>();
     v.wout = wout.as<float>();
     v.bout = bout;
@@ -638,6 +640,11 @@ int spider_load_net(spider_ctx* ctx, const spider_net_desc* d, int32_t* net_id) 
       for (int k = 0; k < H; ++k) wt[((size_t)(l - 1) * H + k) * H + n] = W[l][(size_t)n * H + k];
   HIPCK(upload(net->W0, W[0].data(), (size_t)H * 6 * 4, SPIDER_MEM_HOST, s), "upload W0");
   HIPCK(upload(net->bias, bias.data(), bias.size() * 4, SPIDER_MEM_HOST, s), "upload biases");
+  std::vector<float> w0s(W[0].size()), bias_s(bias.size());
+  for (size_t i = 0; i < w0s.size(); ++i) w0s[i] = (float)(kTanhScale * (double)W[0][i]);
+  for (size_t i = 0; i < bias_s.size(); ++i) bias_s[i] = (float)(kTanhScale * (double)bias[i]);
+  HIPCK(upload(net->W0s, w0s.data(), w0s.size() * 4, SPIDER_MEM_HOST, s), "upload W0");
+  HIPCK(upload(net->bias_s, bias_s.data(), bias_s.size() * 4, SPIDER_MEM_HOST, s), "upload biases");
   HIPCK(upload(net->Wt, wt.data(), wt.size() * 4, SPIDER_MEM_HOST, s), "upload hidden weights");
   HIPCK(upload(net->wout, W[D].data(), (size_t)H * 4, SPIDER_MEM_HOST, s), "upload output row");
   for (int prec = 0; prec < 2; ++prec) {

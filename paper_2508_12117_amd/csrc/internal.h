@@ -34,6 +34,8 @@ struct NetView {
   int D, H;
   const float* W0;     // [H][6]
   const float* bias;   // [D][H]: b[0] .. b[D-1]
+  const float* W0s;    // kTanhScale * W0 (matrix-core kernels)
+  const float* bias_s; // kTanhScale * bias
   const float* Wt;     // [D-1][H][H]: Wt[l][k][n] = W[l+1][n][k] (input-major)
   const float* wout;   // [H]
   float bout;
@@ -73,6 +75,10 @@ __device__ inline void row_inputs(const RowSource& src, const NetView& net, int6
     u[3 + a] = (float)((s[a] - net.center[a]) / net.half[a]);
   }
 }
+
+// 2 log2(e): the matrix-core kernels carry it in their forward weights and
+// biases, so that exp(2z) = 2^(kTanhScale z) is one hardware exponential.
+constexpr double kTanhScale = 2.8853900817779268;
 
 // tanh(z) and 1 - tanh(z)^2 from one exponential and one reciprocal: with
 // e = exp(2|z|) and r = 1/(1 + e), tanh|z| = 1 - 2r and 1 - tanh^2 = 4r(1 - r),

@@ -18,9 +18,9 @@ size_t mfma_pack_bytes(int precision, int H) {
 
 void mfma_pack_layer(int precision, int H, const float* W, void* fwd, void* bwd) {
   if (precision == 1)
-    mfma::pack_layer<mfma::PolBF16>(H, W, (unsigned char*)fwd, (unsigned char*)bwd);
+    mfma::pack_layer<mfma::PolBF16>(H, W, kTanhScale, (unsigned char*)fwd, (unsigned char*)bwd);
   else
-    mfma::pack_layer<mfma::PolF32>(H, W, (unsigned char*)fwd, (unsigned char*)bwd);
+    mfma::pack_layer<mfma::PolF32>(H, W, kTanhScale, (unsigned char*)fwd, (unsigned char*)bwd);
 }
 
 hipError_t launch_mlp_mfma(int precision, const RowSource& src, const NetView& net, RowOut* out,

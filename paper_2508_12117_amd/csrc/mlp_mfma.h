@@ -4,23 +4,29 @@
 // (v_mfma_f32_16x16x4_f32).
 //
 // Work split.  A workgroup of NW waves handles R = 16 RT rows.  Wave w owns
-// the output neurons [16 CT w, 16 CT (w + 1)) of every hidden layer, in the
-// forward pass and in the backward pass alike:
-//   forward   z_{l+1}[:, own] = a_l[R, H] . W_l[own, H]^T      (A from LDS)
-//   backward  e_l[:, own]     = e_{l+1}[R, H] . W_l[H, own]    (A from LDS)
-// so the derivative factors d_l = 1 - a_l^2 that the backward pass needs at
-// its own neurons were produced by the same lanes, in the same accumulator
-// layout, and stay in registers between the passes: activations are never
-// written to memory and nothing is recomputed.  Hidden-layer weights stream
-// from L2 as pre-packed B operands: one 16-byte coalesced load per lane per
-// chunk.  The 6-input first layer and the 1-output last layer are FP32 vector
-// arithmetic on the accumulator layout.
+// the neurons [16 CT w, 16 CT (w + 1)) of every hidden layer, in the forward
+// pass and in the backward pass alike.  Every layer is computed transposed,
+// neurons by rows:
+//   forward   z_{l+1}[own, R] = W_l[own, H] . a_l[R, H]^T         (B from LDS)
+//   backward  e_l[own, R]     = W_l[H, own]^T . e_{l+1}[R, H]^T   (B from LDS)
+// so that in the accumulator layout each lane holds four consecutive neurons
+// of one row.  Activations go back to LDS as one 8-byte (BF16) or 16-byte
+// (FP32) store per fragment, with no exchange between lanes, and the
+// derivative factors d_l = 1 - a_l^2 that the backward pass needs at its own
+// neurons were produced by the same lanes in the same layout and stay on chip
+// between the passes: activations are never written to memory and nothing is
+// recomputed.  Hidden-layer weights stream from L2 as pre-packed A operands,
+// one 16-byte coalesced load per lane per chunk.  The forward weights and
+// biases carry the factor 2 log2(e) so that tanh starts from a bare base-2
+// exponential.  The 6-input first layer and the 1-output last layer are FP32
+// vector arithmetic on the accumulator layout.
 //
 // MFMA 16x16xK layouts used (lane l, c = l % 16, g = l / 16):
 //   A: row c,  k-slots of group g      B: column c, k-slots of group g
 //   C: column c, rows 4 g .. 4 g + 3
-// The k index of slot (g, s, j) is g H/4 + s KPL + j for both operands; any
-// such consistent assignment gives the full dot product.
+// with A rows = neurons, B and C columns = network rows.  The k index of slot
+// (g, s, j) is g H/4 + s KPL + j for both operands; any such consistent
+// assignment gives the full dot product.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -63,7 +69,7 @@ struct Chunk {
 };
 
 // Packed layout of one hidden layer (forward and backward alike):
-// [col tile ct][chunk q][lane][ELEMS], column tile over the layer's outputs.
+// [neuron tile ct][chunk q][lane][ELEMS], tiles over the layer's outputs.
 template <class P>
 constexpr int chunks_per_layer(int H) {
   return (H / 4) / Chunk<P>::ELEMS;
@@ -82,7 +88,7 @@ struct Shape {
   // derivative layers kept in registers; the rest go to LDS (BF16 pairs)
   static constexpr size_t LAYER_BYTES = (size_t)R * H * 2;  // one BF16 derivative layer
   static constexpr int LDS_LAYERS_MAX =
-      (int)((160 * 1024 - (size_t)R * LDW * sizeof(typename P::T) - (size_t)R * 6 * 4 -
+      (int)((160 * 1024 - (size_t)R * LDW * sizeof(typename P::T) - (size_t)R * 8 * 4 -
              (size_t)(H / 16) * R * 4 * 4) / LAYER_BYTES);
   static constexpr int NLR_PREF = NL < 3 ? NL : 3;
   static constexpr int NLR = (P::kBF16 && H * RT / NW > 64)
@@ -92,7 +98,7 @@ struct Shape {
   static constexpr int NT = NW * 64;
   static constexpr size_t ACT_BYTES = (size_t)R * LDW * sizeof(typename P::T);
   static constexpr size_t DLDS_BYTES = (size_t)NLDS * RT * CT * 2 * NT * 4;
-  static constexpr size_t FIXED_BYTES = (size_t)R * 6 * 4 + (size_t)(H / 16) * R * 4 * 4;
+  static constexpr size_t FIXED_BYTES = (size_t)R * 8 * 4 + (size_t)(H / 16) * R * 4 * 4;
   // two activation buffers when they fit in 160 KB of LDS, else one buffer
   // and an extra barrier per layer
   static constexpr int NBUF = 2 * ACT_BYTES + DLDS_BYTES + FIXED_BYTES <= 156 * 1024 ? 2 : 1;
@@ -108,6 +114,15 @@ __device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
   return __builtin_bit_cast(uint32_t, v);
 }
 
+// tanh(z) and 1 - tanh(z)^2 from y = 2 log2(e) z (the forward weights and
+// biases carry the factor): with e = 2^y = exp(2z) and r = 1/(1 + e),
+// tanh z = 1 - 2r; e = inf gives +1 and e = 0 gives -1.
+__device__ __forceinline__ void tanh_scaled(float y, float& a, float& d) {
+  const float r = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(y));
+  a = fmaf(r, -2.0f, 1.0f);
+  d = fmaf(-a, a, 1.0f);
+}
+
 // Derivative factors 1 - a^2 kept between the passes: FP32 registers, or in
 // the BF16 path BF16 pairs (round to nearest even), the first NLR layers in
 // registers and the rest in LDS, where each lane reads back only what it
@@ -115,7 +130,6 @@ __device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
 template <class P, int NL, int NLR, int RT, int CT, int NT>
 struct DStore {
   float v[NL][RT][CT][4];
-  __device__ void set(int l, int rt, int ct, int i, float x) { v[l][rt][ct][i] = x; }
   __device__ void set4(int l, int rt, int ct, const float x[4]) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) v[l][rt][ct][i] = x[i];
@@ -128,17 +142,6 @@ struct DStore<PolBF16, NL, NLR, RT, CT, NT> {
   uint32_t v[NLR][RT][CT][2];
   uint32_t* lds;  // [NL - NLR][RT * CT * 2][NT]
   int tid;
-  uint32_t lo;
-  __device__ void set(int l, int rt, int ct, int i, float x) {
-    const uint32_t b = (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)x);
-    if ((i & 1) == 0) {
-      lo = b;
-      return;
-    }
-    const uint32_t w = lo | (b << 16);
-    if (l < NLR) v[l][rt][ct][i >> 1] = w;
-    else lds[(((l - NLR) * RT * CT + rt * CT + ct) * 2 + (i >> 1)) * NT + tid] = w;
-  }
   __device__ void set4(int l, int rt, int ct, const float x[4]) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -160,68 +163,57 @@ union Pack16 {
   float f[4];
 };
 
-template <int CTRL>
-__device__ __forceinline__ float dpp(float x) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
-}
-
-// Sum over the 16 lanes of a row (quad swaps, then half-row and row mirror
-// exchanges).  Every lane ends with the same value, added in the same order
-// for every tile shape.
-__device__ __forceinline__ float row16_sum(float v) {
-  v += dpp<0xB1>(v);   // quad_perm [1, 0, 3, 2]
-  v += dpp<0x4E>(v);   // quad_perm [2, 3, 0, 1]
-  v += dpp<0x141>(v);  // row_half_mirror
-  v += dpp<0x140>(v);  // row_mirror
-  return v;
-}
-
-// Store a C-layout 4-row column fragment (rows row0 .. row0 + 3 of column n,
-// one lane per column) as pairs of adjacent columns: neighbouring lanes swap
-// two values, the even lane stores rows 0-1 and the odd lane rows 2-3 of the
-// column pair (n & ~1, n | 1), one 32-bit (BF16) or 64-bit (FP32) store each.
+// Store the lane's accumulator fragment (four consecutive neurons n0 .. n0+3
+// of one row) into a row-major activation buffer with row stride ldw.
 template <class T>
-__device__ __forceinline__ void store_col_pairs(T* buf, int ldw, int row0, int n, const float v[4]) {
-  const bool odd = n & 1;
-  const float r0 = dpp<0xB1>(odd ? v[0] : v[2]);
-  const float r1 = dpp<0xB1>(odd ? v[1] : v[3]);
-  const int col = n & ~1;
-  const float a0 = odd ? r0 : v[0], b0 = odd ? v[2] : r0;
-  const float a1 = odd ? r1 : v[1], b1 = odd ? v[3] : r1;
-  const int ra = row0 + (odd ? 2 : 0);
+__device__ __forceinline__ void store_row4(T* buf, int ldw, int row, int n0, const float v[4]) {
   if constexpr (sizeof(T) == 2) {
-    *(uint32_t*)(buf + ra * ldw + col) = pack_bf16x2(a0, b0);
-    *(uint32_t*)(buf + (ra + 1) * ldw + col) = pack_bf16x2(a1, b1);
+    *(uint2*)(buf + row * ldw + n0) = make_uint2(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]));
   } else {
-    *(float2*)(buf + ra * ldw + col) = make_float2(a0, b0);
-    *(float2*)(buf + (ra + 1) * ldw + col) = make_float2(a1, b1);
+    *(float4*)(buf + row * ldw + n0) = make_float4(v[0], v[1], v[2], v[3]);
   }
 }
 
-// acc[rt][ct] += A[16 rt + row][k] . B[k][col tile wave*CT + ct] over the
-// layer's K = H, A from LDS (row stride LDW), B from the packed operand
-// stream pl.  The B chunks are prefetched PF chunks ahead through a rotating
-// register buffer so that their L2 latency overlaps the MFMAs.
+// The four lane groups g = 0..3 of a 16-lane column each hold four partial
+// sums x[0..3] (over their own four neurons of a tile).  Returns, in group g,
+// component g summed over the groups as (x[0] + x[1]) + (x[2] + x[3]), the
+// same order for every tile shape: two exchange steps in which each lane
+// keeps half of what it still holds and sends the other half.
+__device__ __forceinline__ float group_reduce_scatter(const float x[4], int g) {
+  const bool b0 = g & 1, b1 = (g >> 1) & 1;
+  const float keep0 = b0 ? x[1] : x[0], keep1 = b0 ? x[3] : x[2];
+  const float send0 = b0 ? x[0] : x[1], send1 = b0 ? x[2] : x[3];
+  const float y0 = keep0 + __shfl_xor(send0, 16);  // component b0
+  const float y1 = keep1 + __shfl_xor(send1, 16);  // component b0 + 2
+  const float keep = b1 ? y1 : y0, send = b1 ? y0 : y1;
+  return keep + __shfl_xor(send, 32);
+}
+
+// acc[rt][ct] += W[neuron tile wave*CT + ct][k] . X[16 rt + row][k] over the
+// layer's K = H: the weights are the A operand, streamed from the packed
+// operand stream pl and prefetched PF chunks ahead through a rotating register
+// buffer so that their L2 latency overlaps the MFMAs; the rows X are the B
+// operand, read from LDS (row stride LDW).
 template <class P, int RT, int CT, int NQ, int LDW, int KG, int PF_>
-__device__ __forceinline__ void layer_mma(const typename P::T* A, const uint4* pl, int wave,
+__device__ __forceinline__ void layer_mma(const typename P::T* X, const uint4* pl, int wave,
                                           int lane, int c, int g, floatx4 (&acc)[RT][CT]) {
   constexpr int ELEMS = Chunk<P>::ELEMS, SPC = Chunk<P>::SPC;
   constexpr int PF = NQ < PF_ ? NQ : PF_;
   static_assert(NQ % PF == 0, "chunks must split evenly over the prefetch ring");
-  Pack16 bq[PF][CT];
+  Pack16 wq[PF][CT];
 #pragma unroll
   for (int j = 0; j < PF; ++j)
 #pragma unroll
-    for (int ct = 0; ct < CT; ++ct) bq[j][ct].u = pl[((wave * CT + ct) * NQ + j) * 64 + lane];
+    for (int ct = 0; ct < CT; ++ct) wq[j][ct].u = pl[((wave * CT + ct) * NQ + j) * 64 + lane];
 #pragma unroll 1
   for (int q0 = 0; q0 < NQ; q0 += PF) {
 #pragma unroll
     for (int j = 0; j < PF; ++j) {
       const int q = q0 + j;
-      Pack16 a[RT];
+      Pack16 x[RT];
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt)
-        a[rt].u = *(const uint4*)(A + (rt * 16 + c) * LDW + g * KG + q * ELEMS);
+        x[rt].u = *(const uint4*)(X + (rt * 16 + c) * LDW + g * KG + q * ELEMS);
 #pragma unroll
       for (int s = 0; s < SPC; ++s)
 #pragma unroll
@@ -229,15 +221,15 @@ __device__ __forceinline__ void layer_mma(const typename P::T* A, const uint4* p
 #pragma unroll
           for (int ct = 0; ct < CT; ++ct) {
             if constexpr (P::kBF16) {
-              acc[rt][ct] = P::mma(a[rt].b, bq[j][ct].b, acc[rt][ct]);
+              acc[rt][ct] = P::mma(wq[j][ct].b, x[rt].b, acc[rt][ct]);
             } else {
-              acc[rt][ct] = P::mma(a[rt].f[s], bq[j][ct].f[s], acc[rt][ct]);
+              acc[rt][ct] = P::mma(wq[j][ct].f[s], x[rt].f[s], acc[rt][ct]);
             }
           }
       if (q + PF < NQ) {
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct)
-          bq[j][ct].u = pl[((wave * CT + ct) * NQ + q + PF) * 64 + lane];
+          wq[j][ct].u = pl[((wave * CT + ct) * NQ + q + PF) * 64 + lane];
       }
     }
   }
@@ -251,16 +243,15 @@ __global__ __launch_bounds__(NW * 64, MINB) void k_mlp(RowSource src, NetView ne
   using S = Shape<P, H, D, NW, RT_>;
   using T = typename P::T;
   constexpr int CT = S::CT, RT = S::RT, R = S::R, NQ = S::NQ, LDW = S::LDW, KG = S::KG;
-  constexpr int ELEMS = Chunk<P>::ELEMS, SPC = Chunk<P>::SPC;
   constexpr int NL = S::NL, NLR = S::NLR, NT = S::NT, NBUF = S::NBUF;
 
   __shared__ __attribute__((aligned(16))) T act[NBUF][R * LDW];
   __shared__ uint32_t dlds[S::NLDS > 0 ? S::NLDS * RT * CT * 2 * NT : 1];
-  __shared__ float u_s[R][6];
-  // per 16-neuron column tile partial sums of the output layer and the input
+  __shared__ __attribute__((aligned(16))) float u_s[R][8];
+  // per 16-neuron tile partial sums of the output layer and the input
   // gradient; summed over tiles in a fixed order, so the result does not
   // depend on how the tiles are split over the waves
-  __shared__ float part[H / 16][R][4];
+  __shared__ __attribute__((aligned(16))) float part[H / 16][R][4];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -274,6 +265,8 @@ __global__ __launch_bounds__(NW * 64, MINB) void k_mlp(RowSource src, NetView ne
     if (row0 + r < src.rows) row_inputs(src, net, row0 + r, u);
 #pragma unroll
     for (int a = 0; a < 6; ++a) u_s[r][a] = u[a];
+    u_s[r][6] = 0.0f;
+    u_s[r][7] = 0.0f;
   }
   __syncthreads();
 
@@ -285,41 +278,65 @@ __global__ __launch_bounds__(NW * 64, MINB) void k_mlp(RowSource src, NetView ne
   }
   float eD[RT][CT][4];  // backward seed e_D = w_out * d_D, then e_l
   floatx4 acc[RT][CT];
-  float wo[CT];
+  float po[RT][CT];     // output layer over the lane's four neurons of a tile
+  float wo[CT][4];
 #pragma unroll
-  for (int ct = 0; ct < CT; ++ct) wo[ct] = net.wout[(wave * CT + ct) * 16 + c];
+  for (int ct = 0; ct < CT; ++ct) {
+    const float4 w = *(const float4*)(net.wout + (wave * CT + ct) * 16 + 4 * g);
+    wo[ct][0] = w.x;
+    wo[ct][1] = w.y;
+    wo[ct][2] = w.z;
+    wo[ct][3] = w.w;
+  }
 
   // ---- first layer (6 -> H), FP32 vector arithmetic in the C layout
   {
+    float u[RT][6];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      const float4 p = *(const float4*)&u_s[rt * 16 + c][0];
+      const float2 q = *(const float2*)&u_s[rt * 16 + c][4];
+      u[rt][0] = p.x;
+      u[rt][1] = p.y;
+      u[rt][2] = p.z;
+      u[rt][3] = p.w;
+      u[rt][4] = q.x;
+      u[rt][5] = q.y;
+    }
     T* out_act = act[0];
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
-      const int n = (wave * CT + ct) * 16 + c;
-      float w[6];
+      const int n0 = (wave * CT + ct) * 16 + 4 * g;
+      float w[4][6], b[4];
 #pragma unroll
-      for (int a = 0; a < 6; ++a) w[a] = net.W0[n * 6 + a];
-      const float b = net.bias[n];
+      for (int i = 0; i < 4; ++i) {
+        b[i] = net.bias_s[n0 + i];
+#pragma unroll
+        for (int a = 0; a < 6; ++a) w[i][a] = net.W0s[(n0 + i) * 6 + a];
+      }
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt) {
         float av[4], dv[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const int row = rt * 16 + g * 4 + i;
-          float z = b;
+          float z = b[i];
 #pragma unroll
-          for (int a = 0; a < 6; ++a) z += w[a] * u_s[row][a];
-          tanh_d(z, av[i], dv[i]);
-          if (D == 1) eD[rt][ct][i] = wo[ct] * dv[i];
+          for (int a = 0; a < 6; ++a) z = fmaf(w[i][a], u[rt][a], z);
+          tanh_scaled(z, av[i], dv[i]);
+          if (D == 1) eD[rt][ct][i] = wo[ct][i] * dv[i];
           acc[rt][ct][i] = av[i];
         }
-        if (D > 1) dst.set4(0, rt, ct, dv);
-        store_col_pairs<T>(out_act, LDW, rt * 16 + g * 4, n, av);
+        if (D > 1) {
+          dst.set4(0, rt, ct, dv);
+          store_row4<T>(out_act, LDW, rt * 16 + c, n0, av);
+        }
       }
     }
   }
-  __syncthreads();
+  if (D > 1) __syncthreads();
 
-  // ---- hidden layers l = 1 .. D-1
+  // ---- hidden layers l = 1 .. D-1; the last one's activations feed only the
+  // output layer, from registers
   const uint4* packf = (const uint4*)net.pack_fwd;
   const uint4* packb = (const uint4*)net.pack_bwd;
   int cur = 0;
@@ -327,52 +344,52 @@ __global__ __launch_bounds__(NW * 64, MINB) void k_mlp(RowSource src, NetView ne
   for (int l = 1; l < D; ++l) {
     const T* in = act[cur];
     T* outp = act[NBUF == 2 ? cur ^ 1 : 0];
-    const float* bl = net.bias + l * H;
     // the accumulators start from the bias: z = b + W a
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
-      const float bn = bl[(wave * CT + ct) * 16 + c];
+      const float4 bn = *(const float4*)(net.bias_s + l * H + (wave * CT + ct) * 16 + 4 * g);
 #pragma unroll
-      for (int rt = 0; rt < RT; ++rt) acc[rt][ct] = floatx4{bn, bn, bn, bn};
+      for (int rt = 0; rt < RT; ++rt) acc[rt][ct] = floatx4{bn.x, bn.y, bn.z, bn.w};
     }
     const uint4* pl = packf + (size_t)(l - 1) * (H / 16) * NQ * 64;
     layer_mma<P, RT, CT, NQ, LDW, KG, PF>(in, pl, wave, lane, c, g, acc);
     if constexpr (NBUF == 1) __syncthreads();  // every wave done reading `in`
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
-      const int n = (wave * CT + ct) * 16 + c;
+      const int n0 = (wave * CT + ct) * 16 + 4 * g;
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt) {
         float av[4], dv[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          tanh_d(acc[rt][ct][i], av[i], dv[i]);
-          if (l == D - 1) eD[rt][ct][i] = wo[ct] * dv[i];
+          tanh_scaled(acc[rt][ct][i], av[i], dv[i]);
+          if (l == D - 1) eD[rt][ct][i] = wo[ct][i] * dv[i];
           acc[rt][ct][i] = av[i];
         }
-        if (l < D - 1) dst.set4(l, rt, ct, dv);
-        store_col_pairs<T>(outp, LDW, rt * 16 + g * 4, n, av);
+        if (l < D - 1) {
+          dst.set4(l, rt, ct, dv);
+          store_row4<T>(outp, LDW, rt * 16 + c, n0, av);
+        }
       }
     }
-    __syncthreads();
+    if (l < D - 1) __syncthreads();
     if constexpr (NBUF == 2) cur ^= 1;
   }
 
-  // ---- output layer o = w_out . a_D + b_out
-  {
+  // ---- output layer o = w_out . a_D + b_out, the lane's four neurons
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
+  for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+    for (int ct = 0; ct < CT; ++ct) {
+      float p = wo[ct][0] * acc[rt][ct][0];
 #pragma unroll
-        for (int ct = 0; ct < CT; ++ct) {
-          float p = wo[ct] * acc[rt][ct][i];
-          p = row16_sum(p);
-          if (c == 0) part[wave * CT + ct][rt * 16 + g * 4 + i][0] = p;
-        }
-  }
+      for (int i = 1; i < 4; ++i) p = fmaf(wo[ct][i], acc[rt][ct][i], p);
+      po[rt][ct] = p;
+    }
 
-  // ---- backward l = D-1 .. 1: e_l = (e_{l+1} W_l) * d_l
+  // ---- backward l = D-1 .. 1: e_l = (e_{l+1} W_l) * d_l.  With two buffers
+  // the first write goes to the one that layer D-2 read, which every wave
+  // finished before the barrier that closed that layer.
 #pragma unroll
   for (int l = D - 1; l >= 1; --l) {
     T* eb = act[cur];
@@ -383,9 +400,9 @@ __global__ __launch_bounds__(NW * 64, MINB) void k_mlp(RowSource src, NetView ne
     // publish e_{l+1} at the wave's neurons
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
-      const int n = (wave * CT + ct) * 16 + c;
+      const int n0 = (wave * CT + ct) * 16 + 4 * g;
 #pragma unroll
-      for (int rt = 0; rt < RT; ++rt) store_col_pairs<T>(eb, LDW, rt * 16 + g * 4, n, eD[rt][ct]);
+      for (int rt = 0; rt < RT; ++rt) store_row4<T>(eb, LDW, rt * 16 + c, n0, eD[rt][ct]);
     }
     __syncthreads();
 #pragma unroll
@@ -405,34 +422,29 @@ __global__ __launch_bounds__(NW * 64, MINB) void k_mlp(RowSource src, NetView ne
     if constexpr (NBUF == 2) cur ^= 1;
   }
 
-  // ---- input gradient do/du_src = W_0[:, 0:3]^T e_1
-  {
-    float w[CT][3];
+  // ---- input gradient do/du_src = W_0[:, 0:3]^T e_1, with the output layer
+  // partial, reduced over each tile's 16 neurons
 #pragma unroll
-    for (int ct = 0; ct < CT; ++ct) {
-      const int n = (wave * CT + ct) * 16 + c;
+  for (int ct = 0; ct < CT; ++ct) {
+    const int n0 = (wave * CT + ct) * 16 + 4 * g;
+    float w[4][3];
 #pragma unroll
-      for (int a = 0; a < 3; ++a) w[ct][a] = net.W0[n * 6 + a];
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) w[i][a] = net.W0[(n0 + i) * 6 + a];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      float x[4];
+      x[0] = po[rt][ct];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        float p = w[0][a] * eD[rt][ct][0];
+#pragma unroll
+        for (int i = 1; i < 4; ++i) p = fmaf(w[i][a], eD[rt][ct][i], p);
+        x[1 + a] = p;
+      }
+      part[wave * CT + ct][rt * 16 + c][g] = group_reduce_scatter(x, g);
     }
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int ct = 0; ct < CT; ++ct) {
-          float p[3];
-#pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            p[a] = w[ct][a] * eD[rt][ct][i];
-            p[a] = row16_sum(p[a]);
-          }
-          if (c == 0) {
-            const int row = rt * 16 + g * 4 + i;
-            part[wave * CT + ct][row][1] = p[0];
-            part[wave * CT + ct][row][2] = p[1];
-            part[wave * CT + ct][row][3] = p[2];
-          }
-        }
   }
   __syncthreads();
   for (int r = tid; r < R; r += NW * 64) {
@@ -441,10 +453,11 @@ __global__ __launch_bounds__(NW * 64, MINB) void k_mlp(RowSource src, NetView ne
     float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
 #pragma unroll
     for (int tile = 0; tile < H / 16; ++tile) {
-      s0 += part[tile][r][0];
-      s1 += part[tile][r][1];
-      s2 += part[tile][r][2];
-      s3 += part[tile][r][3];
+      const float4 p = *(const float4*)&part[tile][r][0];
+      s0 += p.x;
+      s1 += p.y;
+      s2 += p.z;
+      s3 += p.w;
     }
     RowOut o;
     o.o = s0 + net.bout;
@@ -473,9 +486,10 @@ inline uint16_t bf16_rne(float f) {
   return (uint16_t)((x + 0x7FFFu + lsb) >> 16);
 }
 
-// Host-side packing of one hidden layer into the operand order above.
+// Host-side packing of one hidden layer into the operand order above; the
+// forward operand holds fscale W (the tanh argument scale), rounded once.
 template <class P>
-void pack_layer(int H, const float* W, unsigned char* fwd, unsigned char* bwd) {
+void pack_layer(int H, const float* W, double fscale, unsigned char* fwd, unsigned char* bwd) {
   using T = typename P::T;
   constexpr int ELEMS = Chunk<P>::ELEMS;
   const int NQ = chunks_per_layer<P>(H);
@@ -485,11 +499,12 @@ void pack_layer(int H, const float* W, unsigned char* fwd, unsigned char* bwd) {
     for (int q = 0; q < NQ; ++q)
       for (int lane = 0; lane < 64; ++lane)
         for (int e = 0; e < ELEMS; ++e) {
-          const int col = ct * 16 + (lane & 15);
+          const int n = ct * 16 + (lane & 15);
           const int k = (lane >> 4) * KG + q * ELEMS + e;
           const size_t off = ((((size_t)ct * NQ + q) * 64 + lane) * ELEMS + e) * esz;
-          const float vf = W[(size_t)col * H + k];  // forward: B[k][n = col] = W[n][k]
-          const float vb = W[(size_t)k * H + col];  // backward: B[n = k][col] = W[n][col]
+          // forward: A[n][k] = W[n][k]; backward: A[n][k] = W[k][n]
+          const float vf = (float)(fscale * (double)W[(size_t)n * H + k]);
+          const float vb = W[(size_t)k * H + n];
           if constexpr (P::kBF16) {
             const uint16_t a = bf16_rne(vf), b = bf16_rne(vb);
             std::memcpy(fwd + off, &a, 2);
