@@ -1,6 +1,7 @@
 // BF16 instantiations of the matrix-core network kernel and their tile
 // variants (the autotuner in the host runtime picks one per network shape).
 #include "mlp_mfma.h"
+#include "mlp_pp.h"
 
 namespace spider {
 
@@ -9,6 +10,12 @@ using mfma::PolBF16;
 
 #define SPIDER_V(H, D, NW, RT) \
   MlpVariant { NW, RT, &launch_variant<PolBF16, H, D, NW, RT> }
+// shallower weight prefetch ring
+#define SPIDER_VP(H, D, NW, RT, PF) \
+  MlpVariant { NW, RT, &launch_variant<PolBF16, H, D, NW, RT, PF, 1> }
+// row halves in ping-pong
+#define SPIDER_PP(H, D, NW, RT) \
+  MlpVariant { NW, RT, &mfma::launch_pp<PolBF16, H, D, NW, RT> }
 // two resident workgroups per CU, shallower weight prefetch
 #define SPIDER_V2(H, D, NW, RT) \
   MlpVariant { NW, RT, &launch_variant<PolBF16, H, D, NW, RT, 2, 2> }
@@ -25,7 +32,7 @@ int mlp_variants_bf16(int H, int D, const MlpVariant** list) {
   static const MlpVariant h128d5[] = {SPIDER_V(128, 5, 4, 4)};
   static const MlpVariant h256d4[] = {SPIDER_V(256, 4, 8, 4)};
   static const MlpVariant h256d5[] = {SPIDER_V(256, 5, 8, 4)};
-  static const MlpVariant h256d6[] = {SPIDER_V(256, 6, 8, 4), SPIDER_V(256, 6, 4, 4),
+  static const MlpVariant h256d6[] = {SPIDER_V(256, 6, 8, 4), SPIDER_PP(256, 6, 8, 4),
                                       SPIDER_V(256, 6, 8, 2), SPIDER_V2(256, 6, 4, 2)};
   static const MlpVariant h256d7[] = {SPIDER_V(256, 7, 8, 4)};
   static const MlpVariant h256d8[] = {SPIDER_V(256, 8, 8, 4), SPIDER_V(256, 8, 8, 2),

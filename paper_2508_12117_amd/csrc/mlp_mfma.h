@@ -82,8 +82,12 @@ struct Shape {
   static constexpr int R = 16 * RT;            // rows per workgroup
   static constexpr int KG = H / 4;             // k per lane group
   static constexpr int NQ = chunks_per_layer<P>(H);
-  static constexpr int PAD = 16 / sizeof(typename P::T);
-  static constexpr int LDW = H + PAD;          // LDS row stride (elements)
+  // LDS rows of H elements, unpadded; the 16-byte chunks of row r sit at
+  // chunk index ^ (r & SWM), which spreads the B-operand reads (16 rows, one
+  // chunk column) and the fragment stores over all banks
+  static constexpr int LDW = H;
+  static constexpr int CPR = H / Chunk<P>::ELEMS;  // chunks per row
+  static constexpr int SWM = CPR >= 8 ? 7 : CPR - 1;
   static constexpr int NL = D > 1 ? D - 1 : 1;  // stored derivative layers
   // derivative layers kept in registers; the rest go to LDS (BF16 pairs)
   static constexpr size_t LAYER_BYTES = (size_t)R * H * 2;  // one BF16 derivative layer
@@ -163,14 +167,23 @@ union Pack16 {
   float f[4];
 };
 
-// Store the lane's accumulator fragment (four consecutive neurons n0 .. n0+3
-// of one row) into a row-major activation buffer with row stride ldw.
+// Element offset of (row, k) in an activation buffer: row stride ldw, 16-byte
+// chunk index XOR-swizzled by the row's low bits (swm = mask).
 template <class T>
-__device__ __forceinline__ void store_row4(T* buf, int ldw, int row, int n0, const float v[4]) {
+__device__ __forceinline__ int act_index(int ldw, int swm, int row, int k) {
+  constexpr int E = 16 / sizeof(T);
+  return row * ldw + (((k / E) ^ (row & swm)) * E) + (k % E);
+}
+
+// Store the lane's accumulator fragment (four consecutive neurons n0 .. n0+3
+// of one row, n0 a multiple of 4) into an activation buffer.
+template <class T>
+__device__ __forceinline__ void store_row4(T* buf, int ldw, int swm, int row, int n0, const float v[4]) {
+  T* p = buf + act_index<T>(ldw, swm, row, n0);
   if constexpr (sizeof(T) == 2) {
-    *(uint2*)(buf + row * ldw + n0) = make_uint2(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]));
+    *(uint2*)p = make_uint2(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]));
   } else {
-    *(float4*)(buf + row * ldw + n0) = make_float4(v[0], v[1], v[2], v[3]);
+    *(float4*)p = make_float4(v[0], v[1], v[2], v[3]);
   }
 }
 
@@ -189,31 +202,60 @@ __device__ __forceinline__ float group_reduce_scatter(const float x[4], int g) {
   return keep + __shfl_xor(send, 32);
 }
 
-// acc[rt][ct] += W[neuron tile wave*CT + ct][k] . X[16 rt + row][k] over the
-// layer's K = H: the weights are the A operand, streamed from the packed
-// operand stream pl and prefetched PF chunks ahead through a rotating register
-// buffer so that their L2 latency overlaps the MFMAs; the rows X are the B
-// operand, read from LDS (row stride LDW).
-template <class P, int RT, int CT, int NQ, int LDW, int KG, int PF_>
-__device__ __forceinline__ void layer_mma(const typename P::T* X, const uint4* pl, int wave,
-                                          int lane, int c, int g, floatx4 (&acc)[RT][CT]) {
-  constexpr int ELEMS = Chunk<P>::ELEMS, SPC = Chunk<P>::SPC;
-  constexpr int PF = NQ < PF_ ? NQ : PF_;
-  static_assert(NQ % PF == 0, "chunks must split evenly over the prefetch ring");
-  Pack16 wq[PF][CT];
+// Weight operand ring: PF chunks of the layer stream in flight per column
+// tile.  The layer products of one launch (forward layers, then backward
+// layers) form one stream: while a layer consumes its last chunks, the ring
+// already fetches the first chunks of the next layer's operands, so their L2
+// latency overlaps the epilogue and the barrier instead of stalling the next
+// layer's first MFMAs.
+template <int PF, int CT>
+struct WRing {
+  Pack16 w[PF][CT];
+};
+
+template <int NQ, int PF, int CT>
+__device__ __forceinline__ void ring_prime(WRing<PF, CT>& r, const uint4* pl, int wave, int lane) {
 #pragma unroll
   for (int j = 0; j < PF; ++j)
 #pragma unroll
-    for (int ct = 0; ct < CT; ++ct) wq[j][ct].u = pl[((wave * CT + ct) * NQ + j) * 64 + lane];
+    for (int ct = 0; ct < CT; ++ct) r.w[j][ct].u = pl[((wave * CT + ct) * NQ + j) * 64 + lane];
+}
+
+// acc[rt][ct] += W[neuron tile wave*CT + ct][k] . X[16 rt + row][k] over the
+// layer's K = H: the weights are the A operand, taken from the ring (chunk q
+// in slot q % PF), which is refilled PF chunks ahead from pl and then from
+// pl_next (for the last layer of the launch pass pl again: the refill is then
+// unused); the rows X are the B operand, read from LDS (row stride LDW,
+// swizzled chunks) one chunk ahead of the MFMAs that use them.  Every load is
+// issued without a branch around it, so the wait counts stay exact and the
+// ring keeps PF chunks in flight.
+template <class P, int RT, int CT, int NQ, int LDW, int SWM, int PF>
+__device__ __forceinline__ void layer_mma(const typename P::T* X, const uint4* pl,
+                                          const uint4* pl_next, WRing<PF, CT>& ring, int wave,
+                                          int lane, int c, int g, floatx4 (&acc)[RT][CT]) {
+  constexpr int ELEMS = Chunk<P>::ELEMS, SPC = Chunk<P>::SPC;
+  static_assert(NQ % PF == 0, "chunks must split evenly over the prefetch ring");
+  static_assert(PF % 2 == 0 || PF == NQ, "the B double buffer alternates with the chunk parity");
+  static_assert((NQ & (NQ - 1)) == 0, "chunks per lane group must be a power of two");
+  // rows 16 rt + c share the swizzle c & SWM (SWM < 16)
+  const typename P::T* xr = X + c * LDW;
+  const int sw = c & SWM;
+  Pack16 x[2][RT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+    x[0][rt].u = *(const uint4*)(xr + rt * 16 * LDW + ((g * NQ) ^ sw) * ELEMS);
 #pragma unroll 1
   for (int q0 = 0; q0 < NQ; q0 += PF) {
 #pragma unroll
     for (int j = 0; j < PF; ++j) {
       const int q = q0 + j;
-      Pack16 x[RT];
+      const int b = j & 1;  // q0 is even whenever PF < NQ
+      // next chunk (the last one wraps to chunk 0: an unused read)
+      const int qn = (q + 1) & (NQ - 1);
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt)
-        x[rt].u = *(const uint4*)(X + (rt * 16 + c) * LDW + g * KG + q * ELEMS);
+        x[b ^ 1][rt].u = *(const uint4*)(xr + rt * 16 * LDW + ((g * NQ + qn) ^ sw) * ELEMS);
+      __builtin_amdgcn_sched_barrier(0);  // issue them before this chunk's MFMAs
 #pragma unroll
       for (int s = 0; s < SPC; ++s)
 #pragma unroll
@@ -221,16 +263,17 @@ __device__ __forceinline__ void layer_mma(const typename P::T* X, const uint4* p
 #pragma unroll
           for (int ct = 0; ct < CT; ++ct) {
             if constexpr (P::kBF16) {
-              acc[rt][ct] = P::mma(wq[j][ct].b, x[rt].b, acc[rt][ct]);
+              acc[rt][ct] = P::mma(ring.w[j][ct].b, x[b][rt].b, acc[rt][ct]);
             } else {
-              acc[rt][ct] = P::mma(wq[j][ct].f[s], x[rt].f[s], acc[rt][ct]);
+              acc[rt][ct] = P::mma(ring.w[j][ct].f[s], x[b][rt].f[s], acc[rt][ct]);
             }
           }
-      if (q + PF < NQ) {
+      const bool here = q + PF < NQ;
+      const uint4* src = (here ? pl : pl_next) + (here ? q + PF : q + PF - NQ) * 64 + lane;
 #pragma unroll
-        for (int ct = 0; ct < CT; ++ct)
-          wq[j][ct].u = pl[((wave * CT + ct) * NQ + q + PF) * 64 + lane];
-      }
+      for (int ct = 0; ct < CT; ++ct) ring.w[j][ct].u = src[(wave * CT + ct) * NQ * 64];
+      // keep the refill here, right after the MFMAs that free the slot
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
 }
@@ -242,7 +285,7 @@ template <class P, int H, int D, int NW, int RT_, int PF = 4, int MINB = 1>
 __global__ __launch_bounds__(NW * 64, MINB) void k_mlp(RowSource src, NetView net, RowOut* out) {
   using S = Shape<P, H, D, NW, RT_>;
   using T = typename P::T;
-  constexpr int CT = S::CT, RT = S::RT, R = S::R, NQ = S::NQ, LDW = S::LDW, KG = S::KG;
+  constexpr int CT = S::CT, RT = S::RT, R = S::R, NQ = S::NQ, LDW = S::LDW, SWM = S::SWM;
   constexpr int NL = S::NL, NLR = S::NLR, NT = S::NT, NBUF = S::NBUF;
 
   __shared__ __attribute__((aligned(16))) T act[NBUF][R * LDW];
@@ -259,6 +302,39 @@ __global__ __launch_bounds__(NW * 64, MINB) void k_mlp(RowSource src, NetView ne
   const int c = lane & 15;
   const int g = lane >> 4;
   const int64_t row0 = (int64_t)blockIdx.x * R;
+
+  // hidden-layer operand stream: forward layers 1 .. D-1, then backward
+  // layers D-1 .. 1; the ring starts filling now, under the first layer
+  const uint4* packf = (const uint4*)net.pack_fwd;
+  const uint4* packb = (const uint4*)net.pack_bwd;
+  constexpr size_t LSTRIDE = (size_t)(H / 16) * NQ * 64;  // uint4 per packed layer
+  constexpr int PFR = NQ < PF ? NQ : PF;
+  WRing<PFR, CT> ring;
+  if (D > 1) ring_prime<NQ, PFR, CT>(ring, packf, wave, lane);
+  // first-layer and output weights of the wave's neurons, loaded before the
+  // row inputs so that both latencies overlap
+  float w1[CT][4][6], b1[CT][4], wo[CT][4];
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct) {
+    const int n0 = (wave * CT + ct) * 16 + 4 * g;
+    const float4 bb = *(const float4*)(net.bias_s + n0);
+    const float4 ww = *(const float4*)(net.wout + n0);
+    b1[ct][0] = bb.x;
+    b1[ct][1] = bb.y;
+    b1[ct][2] = bb.z;
+    b1[ct][3] = bb.w;
+    wo[ct][0] = ww.x;
+    wo[ct][1] = ww.y;
+    wo[ct][2] = ww.z;
+    wo[ct][3] = ww.w;
+#pragma unroll
+    for (int v = 0; v < 6; ++v) {  // 24 consecutive floats W0s[n0 .. n0+3][0 .. 5]
+      const float4 q = *(const float4*)(net.W0s + n0 * 6 + 4 * v);
+      const float e[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+      for (int t = 0; t < 4; ++t) w1[ct][(4 * v + t) / 6][(4 * v + t) % 6] = e[t];
+    }
+  }
 
   for (int r = tid; r < R; r += NW * 64) {
     float u[6] = {0, 0, 0, 0, 0, 0};
@@ -279,15 +355,6 @@ __global__ __launch_bounds__(NW * 64, MINB) void k_mlp(RowSource src, NetView ne
   float eD[RT][CT][4];  // backward seed e_D = w_out * d_D, then e_l
   floatx4 acc[RT][CT];
   float po[RT][CT];     // output layer over the lane's four neurons of a tile
-  float wo[CT][4];
-#pragma unroll
-  for (int ct = 0; ct < CT; ++ct) {
-    const float4 w = *(const float4*)(net.wout + (wave * CT + ct) * 16 + 4 * g);
-    wo[ct][0] = w.x;
-    wo[ct][1] = w.y;
-    wo[ct][2] = w.z;
-    wo[ct][3] = w.w;
-  }
 
   // ---- first layer (6 -> H), FP32 vector arithmetic in the C layout
   {
@@ -307,28 +374,21 @@ __global__ __launch_bounds__(NW * 64, MINB) void k_mlp(RowSource src, NetView ne
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
       const int n0 = (wave * CT + ct) * 16 + 4 * g;
-      float w[4][6], b[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        b[i] = net.bias_s[n0 + i];
-#pragma unroll
-        for (int a = 0; a < 6; ++a) w[i][a] = net.W0s[(n0 + i) * 6 + a];
-      }
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt) {
         float av[4], dv[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          float z = b[i];
+          float z = b1[ct][i];
 #pragma unroll
-          for (int a = 0; a < 6; ++a) z = fmaf(w[i][a], u[rt][a], z);
+          for (int a = 0; a < 6; ++a) z = fmaf(w1[ct][i][a], u[rt][a], z);
           tanh_scaled(z, av[i], dv[i]);
           if (D == 1) eD[rt][ct][i] = wo[ct][i] * dv[i];
           acc[rt][ct][i] = av[i];
         }
         if (D > 1) {
           dst.set4(0, rt, ct, dv);
-          store_row4<T>(out_act, LDW, rt * 16 + c, n0, av);
+          store_row4<T>(out_act, LDW, SWM, rt * 16 + c, n0, av);
         }
       }
     }
@@ -337,8 +397,6 @@ __global__ __launch_bounds__(NW * 64, MINB) void k_mlp(RowSource src, NetView ne
 
   // ---- hidden layers l = 1 .. D-1; the last one's activations feed only the
   // output layer, from registers
-  const uint4* packf = (const uint4*)net.pack_fwd;
-  const uint4* packb = (const uint4*)net.pack_bwd;
   int cur = 0;
 #pragma unroll
   for (int l = 1; l < D; ++l) {
@@ -351,8 +409,9 @@ __global__ __launch_bounds__(NW * 64, MINB) void k_mlp(RowSource src, NetView ne
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt) acc[rt][ct] = floatx4{bn.x, bn.y, bn.z, bn.w};
     }
-    const uint4* pl = packf + (size_t)(l - 1) * (H / 16) * NQ * 64;
-    layer_mma<P, RT, CT, NQ, LDW, KG, PF>(in, pl, wave, lane, c, g, acc);
+    const uint4* pl = packf + (size_t)(l - 1) * LSTRIDE;
+    const uint4* pn = l < D - 1 ? packf + (size_t)l * LSTRIDE : packb + (size_t)(D - 2) * LSTRIDE;
+    layer_mma<P, RT, CT, NQ, LDW, SWM, PFR>(in, pl, pn, ring, wave, lane, c, g, acc);
     if constexpr (NBUF == 1) __syncthreads();  // every wave done reading `in`
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
@@ -368,7 +427,7 @@ __global__ __launch_bounds__(NW * 64, MINB) void k_mlp(RowSource src, NetView ne
         }
         if (l < D - 1) {
           dst.set4(l, rt, ct, dv);
-          store_row4<T>(outp, LDW, rt * 16 + c, n0, av);
+          store_row4<T>(outp, LDW, SWM, rt * 16 + c, n0, av);
         }
       }
     }
@@ -387,6 +446,18 @@ __global__ __launch_bounds__(NW * 64, MINB) void k_mlp(RowSource src, NetView ne
       po[rt][ct] = p;
     }
 
+  // source columns of W_0 for the input gradient, loaded ahead of the
+  // backward pass
+  float wg[CT][4][3];
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct) {
+    const int n0 = (wave * CT + ct) * 16 + 4 * g;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) wg[ct][i][a] = net.W0[(n0 + i) * 6 + a];
+  }
+
   // ---- backward l = D-1 .. 1: e_l = (e_{l+1} W_l) * d_l.  With two buffers
   // the first write goes to the one that layer D-2 read, which every wave
   // finished before the barrier that closed that layer.
@@ -402,15 +473,16 @@ __global__ __launch_bounds__(NW * 64, MINB) void k_mlp(RowSource src, NetView ne
     for (int ct = 0; ct < CT; ++ct) {
       const int n0 = (wave * CT + ct) * 16 + 4 * g;
 #pragma unroll
-      for (int rt = 0; rt < RT; ++rt) store_row4<T>(eb, LDW, rt * 16 + c, n0, eD[rt][ct]);
+      for (int rt = 0; rt < RT; ++rt) store_row4<T>(eb, LDW, SWM, rt * 16 + c, n0, eD[rt][ct]);
     }
     __syncthreads();
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = floatx4{0, 0, 0, 0};
-    const uint4* pl = packb + (size_t)(l - 1) * (H / 16) * NQ * 64;
-    layer_mma<P, RT, CT, NQ, LDW, KG, PF>(eb, pl, wave, lane, c, g, acc);
+    const uint4* pl = packb + (size_t)(l - 1) * LSTRIDE;
+    const uint4* pn = l > 1 ? packb + (size_t)(l - 2) * LSTRIDE : pl;
+    layer_mma<P, RT, CT, NQ, LDW, SWM, PFR>(eb, pl, pn, ring, wave, lane, c, g, acc);
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
@@ -426,12 +498,7 @@ __global__ __launch_bounds__(NW * 64, MINB) void k_mlp(RowSource src, NetView ne
   // partial, reduced over each tile's 16 neurons
 #pragma unroll
   for (int ct = 0; ct < CT; ++ct) {
-    const int n0 = (wave * CT + ct) * 16 + 4 * g;
-    float w[4][3];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int a = 0; a < 3; ++a) w[i][a] = net.W0[(n0 + i) * 6 + a];
+    const float (&w)[4][3] = wg[ct];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
       float x[4];

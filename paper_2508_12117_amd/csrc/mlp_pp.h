@@ -1,0 +1,362 @@
+// Ping-pong variant of the matrix-core network kernel (BF16): the same
+// forward pass and reverse-mode source gradient (Sec. 3.2) as k_mlp, with
+// each wave's rows split into two halves whose layer products and epilogues
+// alternate, so that one half's MFMAs run while the other half's vector
+// epilogue (tanh, activation stores, derivative factors) executes.
+//
+// Schedule.  The layer products of a workgroup form the job sequence
+//   F1A F1B F2A F2B ... F(D-1)A F(D-1)B  B(D-1)A B(D-1)B ... B1A B1B
+// (F: forward hidden layer, B: backward, A/B: row half).  Phase p runs job p
+// and, interleaved with its MFMAs, the epilogue of job p-1 (the first phase
+// pairs F1A with the first layer of half B; the first layer of half A runs
+// alone before it, the epilogue of B1B alone after the last).  A barrier
+// closes every phase.  Every epilogue writes the rows of one half, which the
+// job of the previous phase finished reading, while the MFMAs of the current
+// phase read the other half: one activation buffer serves the whole pass.
+//
+// Weights.  The ring holds all chunks of the current layer's operands (both
+// halves use them); job ..B refills each chunk, as it frees it, with the next
+// layer's chunk, so the next layer's operands stream in one phase ahead.
+#pragma once
+#include "mlp_mfma.h"
+
+namespace spider {
+
+namespace mfma {
+
+template <class P, int H, int D, int NW, int RT_>
+struct ShapePP {
+  static constexpr int CT = H / 16 / NW;
+  static constexpr int RT = RT_;
+  static constexpr int RH = RT / 2;
+  static constexpr int R = 16 * RT;
+  static constexpr int NQ = chunks_per_layer<P>(H);
+  static constexpr int LDW = H;
+  static constexpr int CPR = H / Chunk<P>::ELEMS;
+  static constexpr int SWM = CPR >= 8 ? 7 : CPR - 1;
+  static constexpr int NL = D - 1;  // stored derivative layers
+  static constexpr int NT = NW * 64;
+  static constexpr size_t ACT_BYTES = (size_t)R * LDW * sizeof(typename P::T);
+  static constexpr size_t FIXED_BYTES = (size_t)R * 8 * 4 + (size_t)(H / 16) * R * 4 * 4;
+  static constexpr size_t LAYER_BYTES = (size_t)R * H * 2;
+  static constexpr int LDS_LAYERS_MAX = (int)((160 * 1024 - ACT_BYTES - FIXED_BYTES) / LAYER_BYTES);
+  // derivative layers go to LDS first: registers hold the weight ring
+  static constexpr int NLDS = NL < LDS_LAYERS_MAX ? NL : LDS_LAYERS_MAX;
+  static constexpr int NLR = NL - NLDS;
+  static_assert(CT * NW * 16 == H, "H must split into 16-wide tiles over the waves");
+  static_assert(RT % 2 == 0, "two row halves");
+  static_assert(D >= 2, "at least one hidden layer product");
+  static_assert(ACT_BYTES + FIXED_BYTES + NLDS * LAYER_BYTES <= 160 * 1024, "LDS budget");
+};
+
+// The layer product of row half h (rows 16 (h RH + i) + c) over all NQ chunks
+// of the ring.  With REFILL, chunk q of the ring is replaced after its MFMAs
+// by chunk q of the next layer's stream `refill`.  work(q) runs after the
+// MFMAs of chunk q: the interleaved epilogue of the other half.
+template <class P, int h, int RT, int CT, int NQ, int LDW, int SWM, bool REFILL, class F>
+__device__ __forceinline__ void mma_half(const typename P::T* X, WRing<NQ, CT>& ring,
+                                         const uint4* refill, int wave, int lane, int c, int g,
+                                         floatx4 (&acc)[RT][CT], F&& work) {
+  constexpr int RH = RT / 2, ELEMS = Chunk<P>::ELEMS;
+  const typename P::T* xr = X + (h * RH * 16 + c) * LDW;
+  const int sw = c & SWM;
+  Pack16 x[2][RH];
+#pragma unroll
+  for (int i = 0; i < RH; ++i)
+    x[0][i].u = *(const uint4*)(xr + i * 16 * LDW + ((g * NQ) ^ sw) * ELEMS);
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int b = q & 1;
+    if (q + 1 < NQ) {
+#pragma unroll
+      for (int i = 0; i < RH; ++i)
+        x[b ^ 1][i].u = *(const uint4*)(xr + i * 16 * LDW + ((g * NQ + q + 1) ^ sw) * ELEMS);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int i = 0; i < RH; ++i)
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct)
+        acc[h * RH + i][ct] = P::mma(ring.w[q][ct].b, x[b][i].b, acc[h * RH + i][ct]);
+    if constexpr (REFILL) {
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct)
+        ring.w[q][ct].u = refill[((wave * CT + ct) * NQ + q) * 64 + lane];
+    }
+    work(q);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// Calls epi(f) for the NF epilogue fragments spread over the NQ chunk steps.
+template <int NQ, int NF, class E>
+__device__ __forceinline__ void spread(int q, E&& epi) {
+#pragma unroll
+  for (int f = 0; f < NF; ++f)
+    if (f >= (q * NF) / NQ && f < ((q + 1) * NF) / NQ) epi(f);
+}
+
+template <class P, int H, int D, int NW, int RT_>
+__global__ __launch_bounds__(NW * 64, 1) void k_mlp_pp(RowSource src, NetView net, RowOut* out) {
+  static_assert(P::kBF16, "the ping-pong kernel is BF16 only");
+  using S = ShapePP<P, H, D, NW, RT_>;
+  using T = typename P::T;
+  constexpr int CT = S::CT, RT = S::RT, RH = S::RH, R = S::R, NQ = S::NQ, LDW = S::LDW;
+  constexpr int SWM = S::SWM, NL = S::NL, NLR = S::NLR, NT = S::NT;
+  constexpr int NF = RH * CT;  // epilogue fragments per half
+  constexpr size_t LSTRIDE = (size_t)(H / 16) * NQ * 64;
+
+  __shared__ __attribute__((aligned(16))) T act[R * LDW];
+  __shared__ uint32_t dlds[S::NLDS > 0 ? S::NLDS * RT * CT * 2 * NT : 1];
+  __shared__ __attribute__((aligned(16))) float u_s[R][8];
+  __shared__ __attribute__((aligned(16))) float part[H / 16][R][4];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int c = lane & 15;
+  const int g = lane >> 4;
+  const int64_t row0 = (int64_t)blockIdx.x * R;
+
+  const uint4* packf = (const uint4*)net.pack_fwd;
+  const uint4* packb = (const uint4*)net.pack_bwd;
+  WRing<NQ, CT> ring;
+  ring_prime<NQ, NQ, CT>(ring, packf, wave, lane);
+  float w1[CT][4][6], b1[CT][4], wo[CT][4];
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct) {
+    const int n0 = (wave * CT + ct) * 16 + 4 * g;
+    const float4 bb = *(const float4*)(net.bias_s + n0);
+    const float4 ww = *(const float4*)(net.wout + n0);
+    b1[ct][0] = bb.x;
+    b1[ct][1] = bb.y;
+    b1[ct][2] = bb.z;
+    b1[ct][3] = bb.w;
+    wo[ct][0] = ww.x;
+    wo[ct][1] = ww.y;
+    wo[ct][2] = ww.z;
+    wo[ct][3] = ww.w;
+#pragma unroll
+    for (int v = 0; v < 6; ++v) {
+      const float4 q = *(const float4*)(net.W0s + n0 * 6 + 4 * v);
+      const float e[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+      for (int t = 0; t < 4; ++t) w1[ct][(4 * v + t) / 6][(4 * v + t) % 6] = e[t];
+    }
+  }
+
+  for (int r = tid; r < R; r += NT) {
+    float u[6] = {0, 0, 0, 0, 0, 0};
+    if (row0 + r < src.rows) row_inputs(src, net, row0 + r, u);
+#pragma unroll
+    for (int a = 0; a < 6; ++a) u_s[r][a] = u[a];
+    u_s[r][6] = 0.0f;
+    u_s[r][7] = 0.0f;
+  }
+  __syncthreads();
+
+  DStore<P, NL, NLR, RT, CT, NT> dst;
+  dst.lds = dlds;
+  dst.tid = tid;
+  floatx4 acc[RT][CT];
+  float eD[RT][CT][4];  // e_1 at the end
+  float po[RT][CT];
+  float u[RT][6];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+    const float4 p = *(const float4*)&u_s[rt * 16 + c][0];
+    const float2 q = *(const float2*)&u_s[rt * 16 + c][4];
+    u[rt][0] = p.x;
+    u[rt][1] = p.y;
+    u[rt][2] = p.z;
+    u[rt][3] = p.w;
+    u[rt][4] = q.x;
+    u[rt][5] = q.y;
+  }
+
+  // fragment f of half h: rows 16 (h RH + f / CT) + c, neurons of tile f % CT
+  auto n0_of = [&](int f) __attribute__((always_inline)) { return (wave * CT + f % CT) * 16 + 4 * g; };
+  auto first_layer = [&](int h, int f) __attribute__((always_inline)) {
+    const int rt = h * RH + f / CT, ct = f % CT;
+    float av[4], dv[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      float z = b1[ct][i];
+#pragma unroll
+      for (int a = 0; a < 6; ++a) z = fmaf(w1[ct][i][a], u[rt][a], z);
+      tanh_scaled(z, av[i], dv[i]);
+    }
+    dst.set4(0, rt, ct, dv);
+    store_row4<T>(act, LDW, SWM, rt * 16 + c, n0_of(f), av);
+  };
+  // epilogue of forward layer l (1 <= l <= D-1) for fragment f of half h
+  auto fwd_epi = [&](int l, int h, int f) __attribute__((always_inline)) {
+    const int rt = h * RH + f / CT, ct = f % CT;
+    float av[4], dv[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) tanh_scaled(acc[rt][ct][i], av[i], dv[i]);
+    if (l < D - 1) {
+      dst.set4(l, rt, ct, dv);
+      store_row4<T>(act, LDW, SWM, rt * 16 + c, n0_of(f), av);
+    } else {
+      // output layer partial and the backward seed e_D = w_out * d_D
+      float p = wo[ct][0] * av[0], e[4];
+#pragma unroll
+      for (int i = 1; i < 4; ++i) p = fmaf(wo[ct][i], av[i], p);
+      po[rt][ct] = p;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) e[i] = wo[ct][i] * dv[i];
+      store_row4<T>(act, LDW, SWM, rt * 16 + c, n0_of(f), e);
+    }
+  };
+  // epilogue of backward layer l: e_l = (e_{l+1} W_l) * d_l, published for
+  // layer l-1 or kept for the input gradient
+  auto bwd_epi = [&](int l, int h, int f) __attribute__((always_inline)) {
+    const int rt = h * RH + f / CT, ct = f % CT;
+    float e[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) e[i] = acc[rt][ct][i] * dst.get(l - 1, rt, ct, i);
+    if (l > 1) {
+      store_row4<T>(act, LDW, SWM, rt * 16 + c, n0_of(f), e);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) eD[rt][ct][i] = e[i];
+    }
+  };
+  // bias of the current forward layer at the wave's neurons, loaded one
+  // phase ahead of the first job that uses it
+  float4 breg[CT];
+  auto load_bias = [&](int l) __attribute__((always_inline)) {
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct)
+      breg[ct] = *(const float4*)(net.bias_s + l * H + (wave * CT + ct) * 16 + 4 * g);
+  };
+  auto set_bias = [&](int h) __attribute__((always_inline)) {
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+      for (int i = 0; i < RH; ++i)
+        acc[h * RH + i][ct] = floatx4{breg[ct].x, breg[ct].y, breg[ct].z, breg[ct].w};
+  };
+  load_bias(1);
+  auto set_zero = [&](int h) __attribute__((always_inline)) {
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+      for (int i = 0; i < RH; ++i) acc[h * RH + i][ct] = floatx4{0, 0, 0, 0};
+  };
+
+  // ---- phase 0: first layer of half A
+#pragma unroll
+  for (int f = 0; f < NF; ++f) first_layer(0, f);
+  __syncthreads();
+
+  // ---- forward hidden layers
+#pragma unroll
+  for (int l = 1; l < D; ++l) {
+    const uint4* pl = packf + (size_t)(l - 1) * LSTRIDE;
+    const uint4* pn = l < D - 1 ? packf + (size_t)l * LSTRIDE : packb + (size_t)(D - 2) * LSTRIDE;
+    // job F(l)A with the epilogue of the previous job (first layer B, or F(l-1)B)
+    set_bias(0);
+    mma_half<P, 0, RT, CT, NQ, LDW, SWM, false>(act, ring, pl, wave, lane, c, g, acc, [&](int q) {
+      spread<NQ, NF>(q, [&](int f) {
+        if (l == 1) first_layer(1, f);
+        else fwd_epi(l - 1, 1, f);
+      });
+    });
+    __syncthreads();
+    // job F(l)B with the epilogue of F(l)A; the ring refills with the next layer
+    set_bias(1);
+    if (l + 1 < D) load_bias(l + 1);
+    mma_half<P, 1, RT, CT, NQ, LDW, SWM, true>(act, ring, pn, wave, lane, c, g, acc, [&](int q) {
+      spread<NQ, NF>(q, [&](int f) { fwd_epi(l, 0, f); });
+    });
+    __syncthreads();
+  }
+
+  // ---- backward layers D-1 .. 1
+#pragma unroll
+  for (int l = D - 1; l >= 1; --l) {
+    const uint4* pl = packb + (size_t)(l - 1) * LSTRIDE;
+    const uint4* pn = l > 1 ? packb + (size_t)(l - 2) * LSTRIDE : pl;
+    set_zero(0);
+    mma_half<P, 0, RT, CT, NQ, LDW, SWM, false>(act, ring, pl, wave, lane, c, g, acc, [&](int q) {
+      spread<NQ, NF>(q, [&](int f) {
+        if (l == D - 1) fwd_epi(D - 1, 1, f);
+        else bwd_epi(l + 1, 1, f);
+      });
+    });
+    __syncthreads();
+    set_zero(1);
+    if (l > 1) {
+      mma_half<P, 1, RT, CT, NQ, LDW, SWM, true>(act, ring, pn, wave, lane, c, g, acc, [&](int q) {
+        spread<NQ, NF>(q, [&](int f) { bwd_epi(l, 0, f); });
+      });
+      __syncthreads();
+    } else {
+      mma_half<P, 1, RT, CT, NQ, LDW, SWM, false>(act, ring, pn, wave, lane, c, g, acc, [&](int q) {
+        spread<NQ, NF>(q, [&](int f) { bwd_epi(1, 0, f); });
+      });
+    }
+  }
+  // ---- epilogue of B1B
+#pragma unroll
+  for (int f = 0; f < NF; ++f) bwd_epi(1, 1, f);
+
+  // ---- input gradient and output-layer partials, reduced per tile
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct) {
+    const int n0 = (wave * CT + ct) * 16 + 4 * g;
+    float w[4][3];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) w[i][a] = net.W0[(n0 + i) * 6 + a];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      float x[4];
+      x[0] = po[rt][ct];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        float p = w[0][a] * eD[rt][ct][0];
+#pragma unroll
+        for (int i = 1; i < 4; ++i) p = fmaf(w[i][a], eD[rt][ct][i], p);
+        x[1 + a] = p;
+      }
+      part[wave * CT + ct][rt * 16 + c][g] = group_reduce_scatter(x, g);
+    }
+  }
+  __syncthreads();
+  for (int r = tid; r < R; r += NT) {
+    const int64_t row = row0 + r;
+    if (row >= src.rows) continue;
+    float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
+#pragma unroll
+    for (int tile = 0; tile < H / 16; ++tile) {
+      const float4 p = *(const float4*)&part[tile][r][0];
+      s0 += p.x;
+      s1 += p.y;
+      s2 += p.z;
+      s3 += p.w;
+    }
+    RowOut o;
+    o.o = s0 + net.bout;
+    o.d0 = s1;
+    o.d1 = s2;
+    o.d2 = s3;
+    out[row] = o;
+  }
+}
+
+template <class P, int H, int D, int NW, int RT>
+hipError_t launch_pp(const RowSource& src, const NetView& net, RowOut* out, hipStream_t s) {
+  using Sh = ShapePP<P, H, D, NW, RT>;
+  const int64_t blocks = ceil_div(src.rows, Sh::R);
+  hipLaunchKernelGGL((k_mlp_pp<P, H, D, NW, RT>), dim3((unsigned)blocks), dim3(NW * 64), 0, s, src,
+                     net, out);
+  return hipGetLastError();
+}
+
+}  // namespace mfma
+
+}  // namespace spider
