@@ -31,12 +31,13 @@ inline unsigned grid_for(int64_t n, int block = kBlock) {
   return (unsigned)g;
 }
 
-// Fixed-order block sum of one double per thread (blockDim == kBlock).
+// Fixed-order block sum of one double per thread (blockDim == TB).
+template <int TB = kBlock>
 __device__ inline double block_sum(double v, double* sh) {
   const int t = threadIdx.x;
   sh[t] = v;
   __syncthreads();
-  for (int w = kBlock / 2; w > 0; w >>= 1) {
+  for (int w = TB / 2; w > 0; w >>= 1) {
     if (t < w) sh[t] += sh[t + w];
     __syncthreads();
   }
@@ -277,6 +278,8 @@ __global__ void k_fill_i32(int32_t* p, int32_t v, int64_t count) {
 struct SolveArgs {
   const uint32_t* vals;       // entries sorted by (chain, group, event)
   const int32_t* node_of;     // node of each entry
+  const int32_t* nbr;         // per sorted entry: the node at the other end of its edge
+  const double* wgt;          // per sorted entry: the edge weight w
   const int32_t* node_start;  // entries of node q: [node_start[q], node_start[q + 1])
   const int32_t* seg_begin;
   const int32_t* seg_end;
@@ -292,7 +295,8 @@ struct SolveArgs {
   int32_t* state;   // kActive, or the round in which the node was removed
   int32_t* nstate;
   int32_t* par;     // parent of an eliminated node (-1: solved on its own)
-  int32_t* core;    // scratch list of the nodes left on cycles
+  int32_t* core;    // scratch list of the nodes that need the rounds
+  int32_t* core2;   // scratch list of the nodes left on cycles
   double lambda;
   int max_rounds;
   int max_iter;
@@ -300,9 +304,98 @@ struct SolveArgs {
 };
 
 constexpr int32_t kActive = -1;
-constexpr int32_t kCore = 1 << 30;  // solved by CG after the peeling rounds
+constexpr int kTreeBlock = 1024;  // threads per (chain, group) system
 
-// One workgroup per (chain, group) block of (lambda I + L) y = U^T r.
+// Neighbour node and weight of every sorted entry, so that the elimination
+// rounds read them with one load each instead of a chain of lookups.
+__global__ void k_edges(int64_t E, const uint32_t* vals, const int32_t* node_of, const double* w,
+                        int32_t* nbr, double* wgt) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  const uint32_t en = vals[e];
+  nbr[e] = node_of[en ^ 1u];
+  wgt[e] = w[en >> 1];
+}
+constexpr int32_t kCore = 1 << 30;  // solved by CG after the peeling rounds
+constexpr int32_t kPair = -2;       // solved directly: an isolated single edge
+
+
+// Appends, in order, the n items item(k) that satisfy keep(k) to out (fixed
+// order: per-wave ballot, then a block-wide prefix over the waves); returns
+// the number appended.  All threads of the block call it.
+template <int TB, class Keep, class Item>
+__device__ int32_t block_compact(int32_t n, Keep&& keep, Item&& item, int32_t* out,
+                                 int32_t* warp_base, int32_t* total) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  if (t == 0) *total = 0;
+  __syncthreads();
+  for (int32_t k0 = 0; k0 < n; k0 += TB) {
+    const int32_t k = k0 + t;
+    const bool on = k < n && keep(k);
+    const uint64_t mask = __ballot(on);
+    const int before = __popcll(mask & ((1ull << lane) - 1ull));
+    if (lane == 0) warp_base[w] = __popcll(mask);
+    __syncthreads();
+    if (t == 0) {
+      int32_t run = *total;
+      for (int v = 0; v < TB / 64; ++v) {
+        const int32_t cnt = warp_base[v];
+        warp_base[v] = run;
+        run += cnt;
+      }
+      *total = run;
+    }
+    __syncthreads();
+    if (on) out[warp_base[w] + before] = item(k);
+    __syncthreads();
+  }
+  return *total;
+}
+
+// Diagonal lambda + sum w and right-hand side (U^T r)_q of every node, one
+// thread per node over all (chain, group) blocks.
+__global__ void k_node_init(const int32_t* count, const int32_t* node_start, const uint32_t* vals,
+                            const double* w, const double* r, double lambda, double* A, double* b,
+                            int32_t* state, int32_t* par) {
+  const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= *count) return;
+  double rhs = 0.0, dg = lambda;
+  for (int32_t e = node_start[q]; e < node_start[q + 1]; ++e) {
+    const uint32_t en = vals[e];
+    const double wk = w[en >> 1];
+    rhs += ((en & 1u) ? -1.0 : 1.0) * sqrt(wk) * r[en >> 1];
+    dg += wk;
+  }
+  A[q] = dg;
+  b[q] = rhs;
+  state[q] = kActive;
+  par[q] = -1;
+}
+
+// Isolated single edges (both ends have one entry: at minibatch density
+// nearly every component) solved directly as 2x2 systems by their smaller
+// end, one thread per node.
+__global__ void k_pairs(const int32_t* count, const int32_t* node_start, const int32_t* nbr,
+                        const double* wgt, const double* A, const double* b, double* y,
+                        int32_t* state) {
+  const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= *count) return;
+  const int32_t e = node_start[q];
+  if (node_start[q + 1] - e != 1) return;
+  const int32_t p = nbr[e];
+  if (p <= q || node_start[p + 1] - node_start[p] != 1) return;
+  const double w = wgt[e], Aq = A[q], Ap = A[p], bq = b[q], bp = b[p];
+  const double det = Aq * Ap - w * w;
+  y[q] = (Ap * bq + w * bp) / det;
+  y[p] = (Aq * bp + w * bq) / det;
+  state[q] = kPair;
+  state[p] = kPair;
+}
+
+// One workgroup per (chain, group) block of (lambda I + L) y = U^T r, after
+// k_node_init and k_pairs.
+//  0. Isolated single edges are already solved (k_pairs); the other nodes
+//     are listed in node order and only they take part in 1-3.
 //  1. Peel leaves in rounds: a node whose active neighbours are all one node
 //     p (possibly over several parallel edges of total weight W) is
 //     eliminated into p (Schur complement: A_p -= W^2/A_q, b_p += W b_q/A_q);
@@ -314,32 +407,27 @@ constexpr int32_t kCore = 1 << 30;  // solved by CG after the peeling rounds
 //  3. Back substitution in reverse round order: y_q = (b_q + W y_p)/A_q.
 // Exact up to FP64 rounding for forests; the minibatch graphs are forests
 // of small trees apart from rare cycles.
-__global__ __launch_bounds__(kBlock) void k_tree_solve(SolveArgs a) {
-  __shared__ double sh[kBlock];
+template <int TB>
+__global__ __launch_bounds__(TB) void k_tree_solve(SolveArgs a) {
+  __shared__ double sh[TB];
+  __shared__ int32_t warp_base[TB / 64];
+  __shared__ int32_t total_sh;
   const int32_t nb = a.seg_begin[blockIdx.x];
   const int32_t ne = a.seg_end[blockIdx.x];
   if (ne <= nb) return;
   const int t = threadIdx.x;
-  for (int32_t q = nb + t; q < ne; q += kBlock) {
-    double rhs = 0.0, dg = a.lambda;
-    for (int32_t e = a.node_start[q]; e < a.node_start[q + 1]; ++e) {
-      const uint32_t en = a.vals[e];
-      const double wk = a.w[en >> 1];
-      rhs += ((en & 1u) ? -1.0 : 1.0) * sqrt(wk) * a.r[en >> 1];
-      dg += wk;
-    }
-    a.A[q] = dg;
-    a.b[q] = rhs;
-    a.state[q] = kActive;
-    a.par[q] = -1;
-  }
-  __syncthreads();
+  int32_t* list = a.core + nb;
+  const int32_t nl = block_compact<TB>(
+      ne - nb, [&](int32_t k) { return a.state[nb + k] != kPair; }, [&](int32_t k) { return nb + k; },
+      list, warp_base, &total_sh);
 
+  // ---- 1. peeling rounds over the listed nodes
   int rounds = 0;
-  for (; rounds < a.max_rounds; ++rounds) {
+  for (; rounds < a.max_rounds && nl > 0; ++rounds) {
     // phase 1: classify active nodes
     int changed = 0;
-    for (int32_t q = nb + t; q < ne; q += kBlock) {
+    for (int32_t k = t; k < nl; k += TB) {
+      const int32_t q = list[k];
       if (a.state[q] != kActive) {
         a.nstate[q] = a.state[q];
         continue;
@@ -348,14 +436,13 @@ __global__ __launch_bounds__(kBlock) void k_tree_solve(SolveArgs a) {
       double W = 0.0;
       bool multi = false;
       for (int32_t e = a.node_start[q]; e < a.node_start[q + 1]; ++e) {
-        const uint32_t en = a.vals[e];
-        const int32_t pn = a.node_of[en ^ 1u];
+        const int32_t pn = a.nbr[e];
         if (a.state[pn] != kActive) continue;
         if (p0 < 0) {
           p0 = pn;
-          W = a.w[en >> 1];
+          W = a.wgt[e];
         } else if (pn == p0) {
-          W += a.w[en >> 1];
+          W += a.wgt[e];
         } else {
           multi = true;
           break;
@@ -368,7 +455,7 @@ __global__ __launch_bounds__(kBlock) void k_tree_solve(SolveArgs a) {
       } else if (!multi) {
         bool p0_other = false;
         for (int32_t e = a.node_start[p0]; e < a.node_start[p0 + 1]; ++e) {
-          const int32_t pn = a.node_of[a.vals[e] ^ 1u];
+          const int32_t pn = a.nbr[e];
           if (pn != q && a.state[pn] == kActive) {
             p0_other = true;
             break;
@@ -386,16 +473,17 @@ __global__ __launch_bounds__(kBlock) void k_tree_solve(SolveArgs a) {
     changed = __syncthreads_or(changed);
     if (!changed) break;
     // phase 2: parents gather the Schur updates of this round's leaves
-    for (int32_t q = nb + t; q < ne; q += kBlock) {
+    for (int32_t k = t; k < nl; k += TB) {
+      const int32_t q = list[k];
       if (a.nstate[q] == kActive) {
         const int32_t e0 = a.node_start[q], e1 = a.node_start[q + 1];
         double dA = 0.0, db = 0.0;
         for (int32_t e = e0; e < e1; ++e) {
-          const int32_t pn = a.node_of[a.vals[e] ^ 1u];
+          const int32_t pn = a.nbr[e];
           if (a.nstate[pn] != rounds || a.par[pn] != q) continue;
           bool first = true;
           for (int32_t f = e0; f < e; ++f)
-            if (a.node_of[a.vals[f] ^ 1u] == pn) {
+            if (a.nbr[f] == pn) {
               first = false;
               break;
             }
@@ -412,39 +500,16 @@ __global__ __launch_bounds__(kBlock) void k_tree_solve(SolveArgs a) {
     __syncthreads();
   }
 
-  // nodes still active sit on cycles (or on paths longer than the round cap):
-  // gather them into a list (fixed order: block-wide prefix count over the
-  // node range) and run CG on them only
-  __shared__ int32_t n_core_sh;
-  __shared__ int32_t warp_base[kBlock / 64 + 1];
-  int32_t* core = a.core + nb;  // room for every node of the block
-  if (t == 0) n_core_sh = 0;
-  __syncthreads();
-  for (int32_t q0 = nb; q0 < ne; q0 += kBlock) {
-    const int32_t q = q0 + t;
-    const bool act = q < ne && a.state[q] == kActive;
-    const uint64_t mask = __ballot(act);
-    const int lane = t & 63, w = t >> 6;
-    const int before = __popcll(mask & ((1ull << lane) - 1ull));
-    if (lane == 0) warp_base[w] = __popcll(mask);
-    __syncthreads();
-    if (t == 0) {
-      int run = n_core_sh;
-      for (int k = 0; k < kBlock / 64; ++k) {
-        const int c = warp_base[k];
-        warp_base[k] = run;
-        run += c;
-      }
-      n_core_sh = run;
-    }
-    __syncthreads();
-    if (act) core[warp_base[w] + before] = q;
-    __syncthreads();
-  }
-  const int32_t ncore = n_core_sh;
+  // ---- 2. nodes still active sit on cycles (or on paths longer than the
+  // round cap): CG on them only
+  int32_t* core = a.core2 + nb;
+  const int32_t ncore = nl == 0 ? 0
+                                : block_compact<TB>(
+                                      nl, [&](int32_t k) { return a.state[list[k]] == kActive; },
+                                      [&](int32_t k) { return list[k]; }, core, warp_base, &total_sh);
   if (ncore > 0) {
     double bb = 0.0, rz = 0.0;
-    for (int32_t k = t; k < ncore; k += kBlock) {
+    for (int32_t k = t; k < ncore; k += TB) {
       const int32_t q = core[k];
       const double rhs = a.b[q];
       a.y[q] = 0.0;
@@ -453,25 +518,24 @@ __global__ __launch_bounds__(kBlock) void k_tree_solve(SolveArgs a) {
       bb += rhs * rhs;
       rz += rhs * rhs / a.A[q];
     }
-    bb = block_sum(bb, sh);
-    rz = block_sum(rz, sh);
+    bb = block_sum<TB>(bb, sh);
+    rz = block_sum<TB>(rz, sh);
     for (int it = 0; it < a.max_iter && bb > 0.0; ++it) {
       double pap = 0.0;
-      for (int32_t k = t; k < ncore; k += kBlock) {
+      for (int32_t k = t; k < ncore; k += TB) {
         const int32_t q = core[k];
         double v = a.A[q] * a.p[q];
         for (int32_t e = a.node_start[q]; e < a.node_start[q + 1]; ++e) {
-          const uint32_t en = a.vals[e];
-          const int32_t pn = a.node_of[en ^ 1u];
-          if (a.state[pn] == kActive) v -= a.w[en >> 1] * a.p[pn];
+          const int32_t pn = a.nbr[e];
+          if (a.state[pn] == kActive) v -= a.wgt[e] * a.p[pn];
         }
         a.ap[q] = v;
         pap += a.p[q] * v;
       }
-      pap = block_sum(pap, sh);
+      pap = block_sum<TB>(pap, sh);
       const double alpha = rz / pap;
       double rn = 0.0, rz_new = 0.0;
-      for (int32_t k = t; k < ncore; k += kBlock) {
+      for (int32_t k = t; k < ncore; k += TB) {
         const int32_t q = core[k];
         a.y[q] += alpha * a.p[q];
         const double rq = a.rr[q] - alpha * a.ap[q];
@@ -479,24 +543,25 @@ __global__ __launch_bounds__(kBlock) void k_tree_solve(SolveArgs a) {
         rn += rq * rq;
         rz_new += rq * rq / a.A[q];
       }
-      rn = block_sum(rn, sh);
-      rz_new = block_sum(rz_new, sh);
+      rn = block_sum<TB>(rn, sh);
+      rz_new = block_sum<TB>(rz_new, sh);
       if (rn <= a.tol2 * bb) break;
       const double beta = rz_new / rz;
       rz = rz_new;
-      for (int32_t k = t; k < ncore; k += kBlock) {
+      for (int32_t k = t; k < ncore; k += TB) {
         const int32_t q = core[k];
         a.p[q] = a.rr[q] / a.A[q] + beta * a.p[q];
       }
       __syncthreads();
     }
-    for (int32_t k = t; k < ncore; k += kBlock) a.state[core[k]] = kCore;
+    for (int32_t k = t; k < ncore; k += TB) a.state[core[k]] = kCore;
     __syncthreads();
   }
 
-  // back substitution, last round first
-  for (int rnd = rounds; rnd >= 0; --rnd) {
-    for (int32_t q = nb + t; q < ne; q += kBlock) {
+  // ---- 3. back substitution over the listed nodes, last round first
+  for (int rnd = rounds; rnd >= 0 && nl > 0; --rnd) {
+    for (int32_t k = t; k < nl; k += TB) {
+      const int32_t q = list[k];
       if (a.state[q] != rnd) continue;
       const int32_t pn = a.par[q];
       a.y[q] = pn < 0 ? a.b[q] / a.A[q] : (a.b[q] + a.Wp[q] * a.y[pn]) / a.A[q];
@@ -862,6 +927,7 @@ static int bits_for(uint64_t maxval) {
 hipError_t exact_whiten(const CatView& cat, int C, int64_t n, BatchBufs b, SortBufs sb,
                         hipStream_t s) {
   const int64_t E = 2 * (int64_t)C * n;
+  if (E <= 0) return hipSuccess;  // the node kernels read the node count k_nodes writes
   const int end_bit = bits_for((uint64_t)C * cat.L * (uint64_t)cat.M);
   hipLaunchKernelGGL(k_group_keys, dim3(grid_for(E)), dim3(kBlock), 0, s, C, n, cat.M, cat.L, b,
                      sb.key_in, sb.val_in);
@@ -880,9 +946,16 @@ hipError_t exact_whiten(const CatView& cat, int C, int64_t n, BatchBufs b, SortB
                      sb.seg_end, 0, (int64_t)C * cat.L);
   hipLaunchKernelGGL(k_nodes, dim3(grid_for(E)), dim3(kBlock), 0, s, sb.key_out, sb.val_out, scan,
                      E, cat.M, sb.node_of, sb.node_start, sb.seg_begin, sb.seg_end, sb.count);
+  // key_in and key_out are free after k_nodes; vec slot 7 is unused by the solver
+  int32_t* nbr = (int32_t*)sb.key_out;
+  double* wgt = sb.vec + 7 * E;
+  hipLaunchKernelGGL(k_edges, dim3(grid_for(E)), dim3(kBlock), 0, s, E, sb.val_out, sb.node_of,
+                     b.w, nbr, wgt);
   SolveArgs a;
   a.vals = sb.val_out;
   a.node_of = sb.node_of;
+  a.nbr = nbr;
+  a.wgt = wgt;
   a.node_start = sb.node_start;
   a.seg_begin = sb.seg_begin;
   a.seg_end = sb.seg_end;
@@ -899,11 +972,17 @@ hipError_t exact_whiten(const CatView& cat, int C, int64_t n, BatchBufs b, SortB
   a.nstate = sb.ivec + E;
   a.par = sb.ivec + 2 * E;
   a.core = sb.ivec + 3 * E;
+  a.core2 = (int32_t*)sb.key_in;  // free after k_nodes (room for 2E entries)
   a.lambda = (cat.sigma * cat.sigma) / (cat.kappa * cat.kappa);
   a.max_rounds = 64;
   a.max_iter = 200;
   a.tol2 = 1e-28;
-  hipLaunchKernelGGL(k_tree_solve, dim3((unsigned)(C * cat.L)), dim3(kBlock), 0, s, a);
+  // nodes: at most one per entry; the kernels stop at the node count on the device
+  hipLaunchKernelGGL(k_node_init, dim3(grid_for(E)), dim3(kBlock), 0, s, sb.count, a.node_start,
+                     a.vals, a.w, a.r, a.lambda, a.A, a.b, a.state, a.par);
+  hipLaunchKernelGGL(k_pairs, dim3(grid_for(E)), dim3(kBlock), 0, s, sb.count, a.node_start, a.nbr,
+                     a.wgt, a.A, a.b, a.y, a.state);
+  hipLaunchKernelGGL(k_tree_solve<kTreeBlock>, dim3((unsigned)(C * cat.L)), dim3(kTreeBlock), 0, s, a);
   hipLaunchKernelGGL(k_exact_z, dim3(grid_for((int64_t)C * n)), dim3(kBlock), 0, s,
                      (int64_t)C * n, cat.sigma * cat.sigma, b.w, b.r, sb.node_of, a.y, b.z);
   return hipGetLastError();
