@@ -306,15 +306,19 @@ struct SolveArgs {
 constexpr int32_t kActive = -1;
 constexpr int kTreeBlock = 1024;  // threads per (chain, group) system
 
-// Neighbour node and weight of every sorted entry, so that the elimination
-// rounds read them with one load each instead of a chain of lookups.
+// Neighbour node, weight and right-hand-side term (+-sqrt(w) r, the entry's
+// row of U^T r) of every sorted entry, so that the node kernels and the
+// elimination rounds read them contiguously instead of through a chain of
+// lookups.
 __global__ void k_edges(int64_t E, const uint32_t* vals, const int32_t* node_of, const double* w,
-                        int32_t* nbr, double* wgt) {
+                        const double* r, int32_t* nbr, double* wgt, double* rv) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= E) return;
   const uint32_t en = vals[e];
+  const double wk = w[en >> 1];
   nbr[e] = node_of[en ^ 1u];
-  wgt[e] = w[en >> 1];
+  wgt[e] = wk;
+  rv[e] = ((en & 1u) ? -1.0 : 1.0) * sqrt(wk) * r[en >> 1];
 }
 constexpr int32_t kCore = 1 << 30;  // solved by CG after the peeling rounds
 constexpr int32_t kPair = -2;       // solved directly: an isolated single edge
@@ -354,17 +358,15 @@ __device__ int32_t block_compact(int32_t n, Keep&& keep, Item&& item, int32_t* o
 
 // Diagonal lambda + sum w and right-hand side (U^T r)_q of every node, one
 // thread per node over all (chain, group) blocks.
-__global__ void k_node_init(const int32_t* count, const int32_t* node_start, const uint32_t* vals,
-                            const double* w, const double* r, double lambda, double* A, double* b,
-                            int32_t* state, int32_t* par) {
+__global__ void k_node_init(const int32_t* count, const int32_t* node_start, const double* wgt,
+                            const double* rv, double lambda, double* A, double* b, int32_t* state,
+                            int32_t* par) {
   const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= *count) return;
   double rhs = 0.0, dg = lambda;
   for (int32_t e = node_start[q]; e < node_start[q + 1]; ++e) {
-    const uint32_t en = vals[e];
-    const double wk = w[en >> 1];
-    rhs += ((en & 1u) ? -1.0 : 1.0) * sqrt(wk) * r[en >> 1];
-    dg += wk;
+    rhs += rv[e];
+    dg += wgt[e];
   }
   A[q] = dg;
   b[q] = rhs;
@@ -946,11 +948,14 @@ hipError_t exact_whiten(const CatView& cat, int C, int64_t n, BatchBufs b, SortB
                      sb.seg_end, 0, (int64_t)C * cat.L);
   hipLaunchKernelGGL(k_nodes, dim3(grid_for(E)), dim3(kBlock), 0, s, sb.key_out, sb.val_out, scan,
                      E, cat.M, sb.node_of, sb.node_start, sb.seg_begin, sb.seg_end, sb.count);
-  // key_in and key_out are free after k_nodes; vec slot 7 is unused by the solver
+  // key_in and key_out are free after k_nodes; vec slot 7 is unused by the
+  // solver, and slot 4 (the CG residual, written only later) holds the
+  // right-hand-side terms until k_node_init has summed them
   int32_t* nbr = (int32_t*)sb.key_out;
   double* wgt = sb.vec + 7 * E;
+  double* rv = sb.vec + 4 * E;
   hipLaunchKernelGGL(k_edges, dim3(grid_for(E)), dim3(kBlock), 0, s, E, sb.val_out, sb.node_of,
-                     b.w, nbr, wgt);
+                     b.w, b.r, nbr, wgt, rv);
   SolveArgs a;
   a.vals = sb.val_out;
   a.node_of = sb.node_of;
@@ -979,7 +984,7 @@ hipError_t exact_whiten(const CatView& cat, int C, int64_t n, BatchBufs b, SortB
   a.tol2 = 1e-28;
   // nodes: at most one per entry; the kernels stop at the node count on the device
   hipLaunchKernelGGL(k_node_init, dim3(grid_for(E)), dim3(kBlock), 0, s, sb.count, a.node_start,
-                     a.vals, a.w, a.r, a.lambda, a.A, a.b, a.state, a.par);
+                     wgt, rv, a.lambda, a.A, a.b, a.state, a.par);
   hipLaunchKernelGGL(k_pairs, dim3(grid_for(E)), dim3(kBlock), 0, s, sb.count, a.node_start, a.nbr,
                      a.wgt, a.A, a.b, a.y, a.state);
   hipLaunchKernelGGL(k_tree_solve<kTreeBlock>, dim3((unsigned)(C * cat.L)), dim3(kTreeBlock), 0, s, a);
