@@ -16,9 +16,6 @@ using mfma::PolBF16;
 // row halves in ping-pong
 #define SPIDER_PP(H, D, NW, RT) \
   MlpVariant { NW, RT, &mfma::launch_pp<PolBF16, H, D, NW, RT> }
-// two resident workgroups per CU, shallower weight prefetch
-#define SPIDER_V2(H, D, NW, RT) \
-  MlpVariant { NW, RT, &launch_variant<PolBF16, H, D, NW, RT, 2, 2> }
 
 int mlp_variants_bf16(int H, int D, const MlpVariant** list) {
   static const MlpVariant h32d2[] = {SPIDER_V(32, 2, 2, 4)};
@@ -27,16 +24,15 @@ int mlp_variants_bf16(int H, int D, const MlpVariant** list) {
   static const MlpVariant h64d3[] = {SPIDER_V(64, 3, 4, 4)};
   static const MlpVariant h64d4[] = {SPIDER_V(64, 4, 4, 4)};
   static const MlpVariant h128d3[] = {SPIDER_V(128, 3, 4, 4)};
-  static const MlpVariant h128d4[] = {SPIDER_V(128, 4, 4, 4), SPIDER_V(128, 4, 2, 4),
-                                      SPIDER_V(128, 4, 4, 2), SPIDER_V(128, 4, 2, 2)};
+  static const MlpVariant h128d4[] = {SPIDER_V(128, 4, 4, 4), SPIDER_PP(128, 4, 4, 4),
+                                      SPIDER_V(128, 4, 4, 2)};
   static const MlpVariant h128d5[] = {SPIDER_V(128, 5, 4, 4)};
-  static const MlpVariant h256d4[] = {SPIDER_V(256, 4, 8, 4)};
-  static const MlpVariant h256d5[] = {SPIDER_V(256, 5, 8, 4)};
+  static const MlpVariant h256d4[] = {SPIDER_V(256, 4, 8, 4), SPIDER_PP(256, 4, 8, 4)};
+  static const MlpVariant h256d5[] = {SPIDER_V(256, 5, 8, 4), SPIDER_PP(256, 5, 8, 4)};
   static const MlpVariant h256d6[] = {SPIDER_V(256, 6, 8, 4), SPIDER_PP(256, 6, 8, 4),
-                                      SPIDER_V(256, 6, 8, 2), SPIDER_V2(256, 6, 4, 2)};
-  static const MlpVariant h256d7[] = {SPIDER_V(256, 7, 8, 4)};
-  static const MlpVariant h256d8[] = {SPIDER_V(256, 8, 8, 4), SPIDER_V(256, 8, 8, 2),
-                                      SPIDER_V2(256, 8, 4, 2)};
+                                      SPIDER_V(256, 6, 8, 2), SPIDER_VP(256, 6, 8, 4, 2)};
+  static const MlpVariant h256d7[] = {SPIDER_V(256, 7, 8, 4), SPIDER_PP(256, 7, 8, 4)};
+  static const MlpVariant h256d8[] = {SPIDER_V(256, 8, 8, 4), SPIDER_V(256, 8, 8, 2)};
 #define SPIDER_L(HH, DD, arr)                \
   if (H == HH && D == DD) {                  \
     *list = arr;                             \

@@ -24,9 +24,11 @@
 // MFMA 16x16xK layouts used (lane l, c = l % 16, g = l / 16):
 //   A: row c,  k-slots of group g      B: column c, k-slots of group g
 //   C: column c, rows 4 g .. 4 g + 3
-// with A rows = neurons, B and C columns = network rows.  The k index of slot
-// (g, s, j) is g H/4 + s KPL + j for both operands; any such consistent
-// assignment gives the full dot product.
+// with A rows = neurons, B and C columns = network rows.  Operands move in
+// 16-byte chunks per lane (ELEMS elements); element j of chunk q in lane group
+// g has k = (4 q + g) ELEMS + j for both operands (any consistent assignment
+// gives the full dot product), so chunk q spans the 4 ELEMS consecutive
+// inputs [4 q ELEMS, 4 (q + 1) ELEMS) of the layer.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -213,26 +215,47 @@ struct WRing {
   Pack16 w[PF][CT];
 };
 
+// Order of the K chunks.  BF16 products add their chunks starting at the
+// chunk of the output neuron's own 32-neuron block (n / 32) and wrapping
+// around, so that a wave can begin with the chunk it produced itself; the
+// order depends on the neuron only, so every tile variant adds in the same
+// order (waves own at most one 32-neuron block: CT <= 2).  FP32 products add
+// chunks in index order.
+template <class P, int CT>
+__device__ __forceinline__ int chunk_start(int wave, int NQ) {
+  if constexpr (P::kBF16) {
+    static_assert(CT <= 2, "a wave's neurons lie in one 32-neuron block");
+    return ((wave * CT) / 2) & (NQ - 1);
+  } else {
+    return 0;
+  }
+}
+
+// Prefetch ring slots j = 0 .. PF-1 with chunks s0 + j (mod NQ) of pl.
 template <int NQ, int PF, int CT>
-__device__ __forceinline__ void ring_prime(WRing<PF, CT>& r, const uint4* pl, int wave, int lane) {
+__device__ __forceinline__ void ring_prime(WRing<PF, CT>& r, const uint4* pl, int wave, int lane,
+                                           int s0) {
 #pragma unroll
   for (int j = 0; j < PF; ++j)
 #pragma unroll
-    for (int ct = 0; ct < CT; ++ct) r.w[j][ct].u = pl[((wave * CT + ct) * NQ + j) * 64 + lane];
+    for (int ct = 0; ct < CT; ++ct)
+      r.w[j][ct].u = pl[((wave * CT + ct) * NQ + ((s0 + j) & (NQ - 1))) * 64 + lane];
 }
 
 // acc[rt][ct] += W[neuron tile wave*CT + ct][k] . X[16 rt + row][k] over the
-// layer's K = H: the weights are the A operand, taken from the ring (chunk q
-// in slot q % PF), which is refilled PF chunks ahead from pl and then from
-// pl_next (for the last layer of the launch pass pl again: the refill is then
-// unused); the rows X are the B operand, read from LDS (row stride LDW,
-// swizzled chunks) one chunk ahead of the MFMAs that use them.  Every load is
-// issued without a branch around it, so the wait counts stay exact and the
-// ring keeps PF chunks in flight.
+// layer's K = H, chunks in the order s0, s0 + 1, ... (mod NQ): the weights
+// are the A operand, taken from the ring (processing step q in slot q % PF),
+// which is refilled PF steps ahead from pl and then from pl_next (for the
+// last layer of the launch pass pl again: the refill is then unused); the
+// rows X are the B operand, read from LDS (row stride LDW, swizzled chunks)
+// one chunk ahead of the MFMAs that use them.  Every load is issued without
+// a branch around it, so the wait counts stay exact and the ring keeps PF
+// chunks in flight.
 template <class P, int RT, int CT, int NQ, int LDW, int SWM, int PF>
 __device__ __forceinline__ void layer_mma(const typename P::T* X, const uint4* pl,
                                           const uint4* pl_next, WRing<PF, CT>& ring, int wave,
-                                          int lane, int c, int g, floatx4 (&acc)[RT][CT]) {
+                                          int lane, int c, int g, int s0,
+                                          floatx4 (&acc)[RT][CT]) {
   constexpr int ELEMS = Chunk<P>::ELEMS, SPC = Chunk<P>::SPC;
   static_assert(NQ % PF == 0, "chunks must split evenly over the prefetch ring");
   static_assert(PF % 2 == 0 || PF == NQ, "the B double buffer alternates with the chunk parity");
@@ -243,18 +266,18 @@ __device__ __forceinline__ void layer_mma(const typename P::T* X, const uint4* p
   Pack16 x[2][RT];
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt)
-    x[0][rt].u = *(const uint4*)(xr + rt * 16 * LDW + ((g * NQ) ^ sw) * ELEMS);
+    x[0][rt].u = *(const uint4*)(xr + rt * 16 * LDW + ((4 * s0 + g) ^ sw) * ELEMS);
 #pragma unroll 1
   for (int q0 = 0; q0 < NQ; q0 += PF) {
 #pragma unroll
     for (int j = 0; j < PF; ++j) {
       const int q = q0 + j;
       const int b = j & 1;  // q0 is even whenever PF < NQ
-      // next chunk (the last one wraps to chunk 0: an unused read)
-      const int qn = (q + 1) & (NQ - 1);
+      // next chunk (after the last one the first again: an unused read)
+      const int qn = (s0 + q + 1) & (NQ - 1);
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt)
-        x[b ^ 1][rt].u = *(const uint4*)(xr + rt * 16 * LDW + ((g * NQ + qn) ^ sw) * ELEMS);
+        x[b ^ 1][rt].u = *(const uint4*)(xr + rt * 16 * LDW + ((4 * qn + g) ^ sw) * ELEMS);
       __builtin_amdgcn_sched_barrier(0);  // issue them before this chunk's MFMAs
 #pragma unroll
       for (int s = 0; s < SPC; ++s)
@@ -269,7 +292,7 @@ __device__ __forceinline__ void layer_mma(const typename P::T* X, const uint4* p
             }
           }
       const bool here = q + PF < NQ;
-      const uint4* src = (here ? pl : pl_next) + (here ? q + PF : q + PF - NQ) * 64 + lane;
+      const uint4* src = (here ? pl : pl_next) + ((s0 + q + PF) & (NQ - 1)) * 64 + lane;
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) ring.w[j][ct].u = src[(wave * CT + ct) * NQ * 64];
       // keep the refill here, right after the MFMAs that free the slot
@@ -310,7 +333,8 @@ __global__ __launch_bounds__(NW * 64, MINB) void k_mlp(RowSource src, NetView ne
   constexpr size_t LSTRIDE = (size_t)(H / 16) * NQ * 64;  // uint4 per packed layer
   constexpr int PFR = NQ < PF ? NQ : PF;
   WRing<PFR, CT> ring;
-  if (D > 1) ring_prime<NQ, PFR, CT>(ring, packf, wave, lane);
+  const int s0 = chunk_start<P, CT>(wave, NQ);
+  if (D > 1) ring_prime<NQ, PFR, CT>(ring, packf, wave, lane, s0);
   // first-layer and output weights of the wave's neurons, loaded before the
   // row inputs so that both latencies overlap
   float w1[CT][4][6], b1[CT][4], wo[CT][4];
@@ -411,7 +435,7 @@ __global__ __launch_bounds__(NW * 64, MINB) void k_mlp(RowSource src, NetView ne
     }
     const uint4* pl = packf + (size_t)(l - 1) * LSTRIDE;
     const uint4* pn = l < D - 1 ? packf + (size_t)l * LSTRIDE : packb + (size_t)(D - 2) * LSTRIDE;
-    layer_mma<P, RT, CT, NQ, LDW, SWM, PFR>(in, pl, pn, ring, wave, lane, c, g, acc);
+    layer_mma<P, RT, CT, NQ, LDW, SWM, PFR>(in, pl, pn, ring, wave, lane, c, g, s0, acc);
     if constexpr (NBUF == 1) __syncthreads();  // every wave done reading `in`
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
@@ -482,7 +506,7 @@ __global__ __launch_bounds__(NW * 64, MINB) void k_mlp(RowSource src, NetView ne
       for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = floatx4{0, 0, 0, 0};
     const uint4* pl = packb + (size_t)(l - 1) * LSTRIDE;
     const uint4* pn = l > 1 ? packb + (size_t)(l - 2) * LSTRIDE : pl;
-    layer_mma<P, RT, CT, NQ, LDW, SWM, PFR>(eb, pl, pn, ring, wave, lane, c, g, acc);
+    layer_mma<P, RT, CT, NQ, LDW, SWM, PFR>(eb, pl, pn, ring, wave, lane, c, g, s0, acc);
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
@@ -560,14 +584,13 @@ void pack_layer(int H, const float* W, double fscale, unsigned char* fwd, unsign
   using T = typename P::T;
   constexpr int ELEMS = Chunk<P>::ELEMS;
   const int NQ = chunks_per_layer<P>(H);
-  const int KG = H / 4;
   const size_t esz = sizeof(T);
   for (int ct = 0; ct < H / 16; ++ct)
     for (int q = 0; q < NQ; ++q)
       for (int lane = 0; lane < 64; ++lane)
         for (int e = 0; e < ELEMS; ++e) {
           const int n = ct * 16 + (lane & 15);
-          const int k = (lane >> 4) * KG + q * ELEMS + e;
+          const int k = (4 * q + (lane >> 4)) * ELEMS + e;
           const size_t off = ((((size_t)ct * NQ + q) * 64 + lane) * ELEMS + e) * esz;
           // forward: A[n][k] = W[n][k]; backward: A[n][k] = W[k][n]
           const float vf = (float)(fscale * (double)W[(size_t)n * H + k]);

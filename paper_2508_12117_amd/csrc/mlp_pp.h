@@ -50,27 +50,29 @@ struct ShapePP {
 };
 
 // The layer product of row half h (rows 16 (h RH + i) + c) over all NQ chunks
-// of the ring.  With REFILL, chunk q of the ring is replaced after its MFMAs
-// by chunk q of the next layer's stream `refill`.  work(q) runs after the
-// MFMAs of chunk q: the interleaved epilogue of the other half.
+// of the ring, slot q holding chunk s0 + q (mod NQ).  With REFILL, slot q is
+// replaced after its MFMAs by the same chunk of the next layer's stream
+// `refill`.  work(q) runs after the MFMAs of slot q: the interleaved epilogue
+// of the other half.
 template <class P, int h, int RT, int CT, int NQ, int LDW, int SWM, bool REFILL, class F>
 __device__ __forceinline__ void mma_half(const typename P::T* X, WRing<NQ, CT>& ring,
                                          const uint4* refill, int wave, int lane, int c, int g,
-                                         floatx4 (&acc)[RT][CT], F&& work) {
+                                         int s0, floatx4 (&acc)[RT][CT], F&& work) {
   constexpr int RH = RT / 2, ELEMS = Chunk<P>::ELEMS;
   const typename P::T* xr = X + (h * RH * 16 + c) * LDW;
   const int sw = c & SWM;
   Pack16 x[2][RH];
 #pragma unroll
   for (int i = 0; i < RH; ++i)
-    x[0][i].u = *(const uint4*)(xr + i * 16 * LDW + ((g * NQ) ^ sw) * ELEMS);
+    x[0][i].u = *(const uint4*)(xr + i * 16 * LDW + ((4 * s0 + g) ^ sw) * ELEMS);
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     const int b = q & 1;
     if (q + 1 < NQ) {
 #pragma unroll
       for (int i = 0; i < RH; ++i)
-        x[b ^ 1][i].u = *(const uint4*)(xr + i * 16 * LDW + ((g * NQ + q + 1) ^ sw) * ELEMS);
+        x[b ^ 1][i].u =
+            *(const uint4*)(xr + i * 16 * LDW + ((4 * ((s0 + q + 1) & (NQ - 1)) + g) ^ sw) * ELEMS);
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -81,7 +83,7 @@ __device__ __forceinline__ void mma_half(const typename P::T* X, WRing<NQ, CT>& 
     if constexpr (REFILL) {
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct)
-        ring.w[q][ct].u = refill[((wave * CT + ct) * NQ + q) * 64 + lane];
+        ring.w[q][ct].u = refill[((wave * CT + ct) * NQ + ((s0 + q) & (NQ - 1))) * 64 + lane];
     }
     work(q);
     __builtin_amdgcn_sched_barrier(0);
@@ -121,7 +123,8 @@ __global__ __launch_bounds__(NW * 64, 1) void k_mlp_pp(RowSource src, NetView ne
   const uint4* packf = (const uint4*)net.pack_fwd;
   const uint4* packb = (const uint4*)net.pack_bwd;
   WRing<NQ, CT> ring;
-  ring_prime<NQ, NQ, CT>(ring, packf, wave, lane);
+  const int s0 = chunk_start<P, CT>(wave, NQ);
+  ring_prime<NQ, NQ, CT>(ring, packf, wave, lane, s0);
   float w1[CT][4][6], b1[CT][4], wo[CT][4];
 #pragma unroll
   for (int ct = 0; ct < CT; ++ct) {
@@ -258,7 +261,7 @@ __global__ __launch_bounds__(NW * 64, 1) void k_mlp_pp(RowSource src, NetView ne
     const uint4* pn = l < D - 1 ? packf + (size_t)l * LSTRIDE : packb + (size_t)(D - 2) * LSTRIDE;
     // job F(l)A with the epilogue of the previous job (first layer B, or F(l-1)B)
     set_bias(0);
-    mma_half<P, 0, RT, CT, NQ, LDW, SWM, false>(act, ring, pl, wave, lane, c, g, acc, [&](int q) {
+    mma_half<P, 0, RT, CT, NQ, LDW, SWM, false>(act, ring, pl, wave, lane, c, g, s0, acc, [&](int q) {
       spread<NQ, NF>(q, [&](int f) {
         if (l == 1) first_layer(1, f);
         else fwd_epi(l - 1, 1, f);
@@ -268,7 +271,7 @@ __global__ __launch_bounds__(NW * 64, 1) void k_mlp_pp(RowSource src, NetView ne
     // job F(l)B with the epilogue of F(l)A; the ring refills with the next layer
     set_bias(1);
     if (l + 1 < D) load_bias(l + 1);
-    mma_half<P, 1, RT, CT, NQ, LDW, SWM, true>(act, ring, pn, wave, lane, c, g, acc, [&](int q) {
+    mma_half<P, 1, RT, CT, NQ, LDW, SWM, true>(act, ring, pn, wave, lane, c, g, s0, acc, [&](int q) {
       spread<NQ, NF>(q, [&](int f) { fwd_epi(l, 0, f); });
     });
     __syncthreads();
@@ -280,7 +283,7 @@ __global__ __launch_bounds__(NW * 64, 1) void k_mlp_pp(RowSource src, NetView ne
     const uint4* pl = packb + (size_t)(l - 1) * LSTRIDE;
     const uint4* pn = l > 1 ? packb + (size_t)(l - 2) * LSTRIDE : pl;
     set_zero(0);
-    mma_half<P, 0, RT, CT, NQ, LDW, SWM, false>(act, ring, pl, wave, lane, c, g, acc, [&](int q) {
+    mma_half<P, 0, RT, CT, NQ, LDW, SWM, false>(act, ring, pl, wave, lane, c, g, s0, acc, [&](int q) {
       spread<NQ, NF>(q, [&](int f) {
         if (l == D - 1) fwd_epi(D - 1, 1, f);
         else bwd_epi(l + 1, 1, f);
@@ -289,12 +292,12 @@ __global__ __launch_bounds__(NW * 64, 1) void k_mlp_pp(RowSource src, NetView ne
     __syncthreads();
     set_zero(1);
     if (l > 1) {
-      mma_half<P, 1, RT, CT, NQ, LDW, SWM, true>(act, ring, pn, wave, lane, c, g, acc, [&](int q) {
+      mma_half<P, 1, RT, CT, NQ, LDW, SWM, true>(act, ring, pn, wave, lane, c, g, s0, acc, [&](int q) {
         spread<NQ, NF>(q, [&](int f) { bwd_epi(l, 0, f); });
       });
       __syncthreads();
     } else {
-      mma_half<P, 1, RT, CT, NQ, LDW, SWM, false>(act, ring, pn, wave, lane, c, g, acc, [&](int q) {
+      mma_half<P, 1, RT, CT, NQ, LDW, SWM, false>(act, ring, pn, wave, lane, c, g, s0, acc, [&](int q) {
         spread<NQ, NF>(q, [&](int f) { bwd_epi(1, 0, f); });
       });
     }

@@ -981,7 +981,7 @@ hipError_t exact_whiten(const CatView& cat, int C, int64_t n, BatchBufs b, SortB
   a.lambda = (cat.sigma * cat.sigma) / (cat.kappa * cat.kappa);
   a.max_rounds = 64;
   a.max_iter = 200;
-  a.tol2 = 1e-28;
+  a.tol2 = 1e-30;  // relative residual 1e-15: z = (r - U y)/sigma^2 scales y errors by 1/sigma^2
   // nodes: at most one per entry; the kernels stop at the node count on the device
   hipLaunchKernelGGL(k_node_init, dim3(grid_for(E)), dim3(kBlock), 0, s, sb.count, a.node_start,
                      wgt, rv, a.lambda, a.A, a.b, a.state, a.par);
