@@ -23,6 +23,34 @@ sys.path.insert(0, ROOT)
 PEAK = {"bf16": 2500.0, "fp32": 157.3}       # TFLOP/s, MI355X dense
 HBM_PEAK = 8000.0                             # GB/s
 
+# HBM bytes per launch of the BF16 network kernel on the 200k-event workload
+# (16,777,216 rows), from rocprofv3 FETCH_SIZE and WRITE_SIZE passes over the
+# same command, each scaled by what the counter reads for a 1 GiB device copy
+# (FETCH x2.0, WRITE x1.0); profiles/network_bf16_clustered200k_traffic.md.
+# Valid only for the kernel built from the template sources with this digest
+# and the same variant; otherwise the bench reports traffic as null.
+NETWORK_TRAFFIC = {
+    "kernel_sources": ["paper_2508_12117_amd/csrc/mlp_mfma.h", "paper_2508_12117_amd/csrc/mlp_pp.h"],
+    "sha256": "cde6a0defdc0e61ba202d72d79c584fa2c3687ebb119d136264796c824ef234e",
+    "variant": {"waves": 8, "row_tiles": 4, "schedule": 1},
+    "rows": 16777216,
+    "fetch_bytes": 1542885354,
+    "write_bytes": 268435456,
+}
+
+
+def network_traffic(rows, variant):
+    """Measured HBM bytes per network launch, or None if the kernel changed."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in NETWORK_TRAFFIC["kernel_sources"]:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if (h.hexdigest() != NETWORK_TRAFFIC["sha256"] or variant != NETWORK_TRAFFIC["variant"]
+            or rows != NETWORK_TRAFFIC["rows"]):
+        return None
+    return NETWORK_TRAFFIC["fetch_bytes"] + NETWORK_TRAFFIC["write_bytes"]
+
 
 def flops_per_eval(H, D):
     """Matrix flops of one travel-time evaluation, forward + source gradient:
@@ -41,6 +69,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-batch", type=int, default=1 << 20)
     ap.add_argument("--seed", type=int, default=20250817)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="first copy BYTES between two device buffers (one device-to-device "
+                         "copy of known size, to calibrate HBM byte counters in a profile)")
     return ap.parse_args()
 
 
@@ -119,6 +150,14 @@ def main():
     import torch
 
     from paper_2508_12117_amd import spider, synth
+    if args.copy_probe > 0:
+        a = torch.ones(args.copy_probe, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        log(f"copied {args.copy_probe} bytes device to device")
     wl = synth.WORKLOADS[args.workload]
     t = time.perf_counter()
     cat = synth.make_catalog(args.workload)
@@ -147,9 +186,13 @@ def main():
         avg_ms = ms / max(launches, 1)
         achieved = rows / max(launches, 1) * fl / (avg_ms * 1e-3) / 1e12
         waves, tiles = ctx.network_variant(nid, code)
+        sched = ctx.network_schedule(nid, code)
+        traffic = network_traffic(rows // max(launches, 1),
+                                  {"waves": waves, "row_tiles": tiles, "schedule": sched})
         res[p] = dict(value=dd / wall, ms_per_step=wall * 1e3 / args.steps, net_ms=ms,
-                      net_launches=launches, net_avg_ms=avg_ms, achieved=achieved,
-                      variant={"waves_per_workgroup": waves, "rows_per_workgroup": 16 * tiles},
+                      net_launches=launches, net_avg_ms=avg_ms, achieved=achieved, traffic=traffic,
+                      variant={"waves_per_workgroup": waves, "rows_per_workgroup": 16 * tiles,
+                               "schedule": ["barrier per layer", "row-half ping-pong"][sched]},
                       error=sample_error(ctx, spider, cat, net, nid, code))
         log(f"{p}: {dd / wall:.4g} dd-obs/s, {wall * 1e3 / args.steps:.2f} ms/step, network "
             f"{avg_ms:.3f} ms/launch = {achieved:.2f} TFLOP/s, tiles {waves} waves x {16 * tiles} rows")
@@ -166,7 +209,8 @@ def main():
                    "state": "fp64"},
         "roofline": {"bound": "mfma", "kernel": "travel-time network (forward + source "
                      "gradient)", "achieved": r["achieved"], "peak": PEAK[head],
-                     "unit": "TFLOP/s", "frac": r["achieved"] / PEAK[head], "traffic": None},
+                     "unit": "TFLOP/s", "frac": r["achieved"] / PEAK[head],
+                     "traffic": r["traffic"]},
         "paths": {p: {"value": v["value"], "ms_per_step": v["ms_per_step"],
                       "network_ms_per_launch": v["net_avg_ms"],
                       "network_tflops": v["achieved"], "network_tiles": v["variant"],

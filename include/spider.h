@@ -268,12 +268,14 @@ int spider_set_state(spider_ctx* ctx, int32_t cat_id, int32_t chain,
  * (each pointer may be NULL).  Errors: SPIDER_E_INVALID, SPIDER_E_HIP. */
 int spider_profile(spider_ctx* ctx, int enable);
 /* Tile shape of the matrix-core network kernel this context uses for a
- * network and precision: *waves per workgroup and *row_tiles of 16 rows per
- * workgroup (0, 0 when the shape has no matrix-core kernel).  The shape is
- * chosen by timing every compiled variant on the first launch of at least
- * 65,536 rows (all variants give identical results). */
+ * network and precision: *waves per workgroup, *row_tiles of 16 rows per
+ * workgroup and *schedule (0: one workgroup barrier per layer, 1: row halves
+ * in ping-pong); 0, 0, 0 when the shape has no matrix-core kernel.  The
+ * variant is chosen by timing every compiled one on the first launch of at
+ * least 65,536 rows (all variants give identical results).  Any output
+ * pointer may be NULL.  Errors: SPIDER_E_INVALID (unknown network id). */
 int spider_network_variant(spider_ctx* ctx, int32_t net_id, int32_t precision, int32_t* waves,
-                           int32_t* row_tiles);
+                           int32_t* row_tiles, int32_t* schedule);
 int spider_profile_read(spider_ctx* ctx, double* ms, int64_t* launches, int64_t* rows);
 
 #ifdef __cplusplus

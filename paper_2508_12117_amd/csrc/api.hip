@@ -454,13 +454,13 @@ int spider_profile(spider_ctx* ctx, int enable) {
 }
 
 int spider_network_variant(spider_ctx* ctx, int32_t net_id, int32_t precision, int32_t* waves,
-                           int32_t* row_tiles) {
+                           int32_t* row_tiles, int32_t* schedule) {
   if (!ctx) return SPIDER_E_INVALID;
   Net* net = get_net(ctx, net_id);
   if (!net) return fail(ctx, SPIDER_E_INVALID, "unknown network id");
   const MlpVariant* vl = nullptr;
   const int nvar = mlp_variants(precision, net->H, net->D, &vl);
-  int32_t w = 0, r = 0;
+  int32_t w = 0, r = 0, sc = 0;
   if (nvar > 0) {
     auto it = ctx->tuned.find(std::make_tuple((int)precision, net->H, net->D));
     int k = it == ctx->tuned.end() ? 0 : it->second;
@@ -470,9 +470,11 @@ int spider_network_variant(spider_ctx* ctx, int32_t net_id, int32_t precision, i
     }
     w = vl[k].nw;
     r = vl[k].rt;
+    sc = vl[k].schedule;
   }
   if (waves) *waves = w;
   if (row_tiles) *row_tiles = r;
+  if (schedule) *schedule = sc;
   return SPIDER_OK;
 }
 

@@ -149,6 +149,7 @@ hipError_t launch_mlp_tangent(const RowSource& src, const NetView& net, RowOut* 
 // same per-row arithmetic in the same order, so they agree bit for bit.
 struct MlpVariant {
   int nw, rt;
+  int schedule;  // 0: one barrier per layer (k_mlp), 1: row-half ping-pong (k_mlp_pp)
   hipError_t (*launch)(const RowSource&, const NetView&, RowOut*, hipStream_t);
 };
 // Number of variants for (precision, H, D) and the list (0: no kernel).

@@ -9,13 +9,13 @@ using mfma::launch_variant;
 using mfma::PolBF16;
 
 #define SPIDER_V(H, D, NW, RT) \
-  MlpVariant { NW, RT, &launch_variant<PolBF16, H, D, NW, RT> }
+  MlpVariant { NW, RT, 0, &launch_variant<PolBF16, H, D, NW, RT> }
 // shallower weight prefetch ring
 #define SPIDER_VP(H, D, NW, RT, PF) \
-  MlpVariant { NW, RT, &launch_variant<PolBF16, H, D, NW, RT, PF, 1> }
+  MlpVariant { NW, RT, 0, &launch_variant<PolBF16, H, D, NW, RT, PF, 1> }
 // row halves in ping-pong
 #define SPIDER_PP(H, D, NW, RT) \
-  MlpVariant { NW, RT, &mfma::launch_pp<PolBF16, H, D, NW, RT> }
+  MlpVariant { NW, RT, 1, &mfma::launch_pp<PolBF16, H, D, NW, RT> }
 
 int mlp_variants_bf16(int H, int D, const MlpVariant** list) {
   static const MlpVariant h32d2[] = {SPIDER_V(32, 2, 2, 4)};

@@ -8,7 +8,7 @@ using mfma::launch_variant;
 using mfma::PolF32;
 
 #define SPIDER_V(H, D, NW, RT) \
-  MlpVariant { NW, RT, &launch_variant<PolF32, H, D, NW, RT> }
+  MlpVariant { NW, RT, 0, &launch_variant<PolF32, H, D, NW, RT> }
 
 int mlp_variants_f32(int H, int D, const MlpVariant** list) {
   static const MlpVariant h32d2[] = {SPIDER_V(32, 2, 2, 2)};

@@ -89,7 +89,7 @@ _SIGS = {
     "spider_get_state": ([_P, ct.c_int32, ct.c_int32, _P, _P, ct.POINTER(ct.c_int64)], ct.c_int),
     "spider_set_state": ([_P, ct.c_int32, ct.c_int32, _P, _P, ct.c_int64], ct.c_int),
     "spider_profile": ([_P, ct.c_int], ct.c_int),
-    "spider_network_variant": ([_P, ct.c_int32, ct.c_int32, ct.POINTER(ct.c_int32),
+    "spider_network_variant": ([_P, ct.c_int32, ct.c_int32, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32),
                                 ct.POINTER(ct.c_int32)], ct.c_int),
     "spider_profile_read": ([_P, ct.POINTER(ct.c_double), ct.POINTER(ct.c_int64),
                              ct.POINTER(ct.c_int64)], ct.c_int),
@@ -294,8 +294,15 @@ class Context:
         """(waves per workgroup, 16-row tiles per workgroup) of the chosen kernel."""
         w, r = ct.c_int32(), ct.c_int32()
         self._check(lib().spider_network_variant(self._h, net_id, precision, ct.byref(w),
-                                                 ct.byref(r)))
+                                                 ct.byref(r), None))
         return w.value, r.value
+
+    def network_schedule(self, net_id, precision=FP32):
+        """Schedule of the chosen kernel: 0 one barrier per layer, 1 row-half ping-pong."""
+        sc = ct.c_int32()
+        self._check(lib().spider_network_variant(self._h, net_id, precision, None, None,
+                                                 ct.byref(sc)))
+        return sc.value
 
     def profile_read(self):
         """(summed network-kernel ms, launches, rows) since profile(True)."""
