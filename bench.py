@@ -69,6 +69,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-batch", type=int, default=1 << 20)
     ap.add_argument("--seed", type=int, default=20250817)
+    ap.add_argument("--moments-steps", type=int, default=0, metavar="K",
+                    help="also run K sampler steps per precision (second half recorded, thin "
+                         "10) and compare the BF16 and FP32 posterior moments")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="first copy BYTES between two device buffers (one device-to-device "
                          "copy of known size, to calibrate HBM byte counters in a profile)")
@@ -119,6 +122,45 @@ def sample_error(ctx, spider, cat, net, nid, prec, rows=4096, seed=5):
             "gradT_rel_max": float(np.max(np.linalg.norm(g - gw, axis=1)
                                           / np.linalg.norm(gw, axis=1))),
             "rows": rows}
+
+
+def posterior_moments(ctx, spider, cat, cid, nid, wl, steps, seed):
+    """Pooled per-event posterior moments of both paths after the same number
+    of steps from the same start with the same batch and noise streams."""
+    import numpy as np
+    import torch
+    out = {}
+    for name, code in (("bf16", spider.BF16), ("fp32", spider.FP32)):
+        ctx.reset_chains(cid, wl.chains)
+        t = time.perf_counter()
+        done = 0
+        while done < steps:  # in chunks (a split run equals an uninterrupted one)
+            k = min(100, steps - done)
+            ctx.sgld_steps([(cid, nid, wl.chains, wl.batch, code)], k, step=wl.step_size,
+                           seed=seed, burn_in=steps // 2, thin=10)
+            ctx.sync()
+            done += k
+            log(f"moments {name}: {done}/{steps} steps")
+        mean = torch.empty(cat.M, 4, dtype=torch.float64, device="cuda")
+        cov = torch.empty(cat.M, 10, dtype=torch.float64, device="cuda")
+        count = ctx.moments(cid, -1, mean, cov)
+        out[name] = (mean.cpu().numpy(), cov.cpu().numpy(), count)
+        log(f"moments {name}: {steps} steps in {time.perf_counter() - t:.1f}s, {count} samples")
+    mb, cb, n = out["bf16"]
+    mf, cf, _ = out["fp32"]
+    diag = [0, 4, 7, 9]  # xx, yy, zz, tt in the packed upper triangle
+    sdb, sdf = np.sqrt(cb[:, diag]), np.sqrt(cf[:, diag])
+    z = np.abs(mb - mf) / sdf
+    ratio = sdb / sdf
+    true = np.column_stack([cat.hypo_true[:, 0:3], np.zeros(cat.M)])
+    err_b = np.sqrt(np.mean((mb[:, 0:3] - true[:, 0:3]) ** 2))
+    err_f = np.sqrt(np.mean((mf[:, 0:3] - true[:, 0:3]) ** 2))
+    q = lambda a, p: float(np.percentile(a, p))
+    return {"steps": steps, "burn_in": steps // 2, "thin": 10, "samples": int(n),
+            "mean_diff_over_sd": {"median": q(z, 50), "p99": q(z, 99), "max": float(z.max())},
+            "sd_ratio_bf16_fp32": {"p1": q(ratio, 1), "median": q(ratio, 50), "p99": q(ratio, 99)},
+            "location_rms_error_km": {"bf16": float(err_b), "fp32": float(err_f)},
+            "note": "pooled over all chains; same batch and noise streams for both paths"}
 
 
 def cpu_baseline(cat, net, n, seed):
@@ -217,6 +259,9 @@ def main():
                       "error_vs_oracle": v["error"]}
                   for p, v in res.items()},
     }
+    if args.moments_steps > 0:
+        line["posterior_moments"] = posterior_moments(ctx, spider, cat, cid, nid, wl,
+                                                      args.moments_steps, args.seed)
     if not args.no_cpu_baseline:
         t = time.perf_counter()
         line["cpu_baseline"] = cpu_baseline(cat, net, args.cpu_batch, args.seed)
