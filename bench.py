@@ -82,16 +82,19 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def run_precision(ctx, spider, cid, nid, wl, prec, steps, warmup, seed):
+def run_precision(ctx, spider, base_sets, step_size, prec, steps, warmup, seed):
+    """base_sets: (cat_id, net_id, chains, batch) per catalog; several catalogs
+    advance together in the library's fused steps."""
     import torch
-    sets = [(cid, nid, wl.chains, wl.batch, prec)]
-    ctx.reset_chains(cid, wl.chains)
-    ctx.sgld_steps(sets, warmup, step=wl.step_size, seed=seed)
+    sets = [(cid, nid, C, n, prec) for cid, nid, C, n in base_sets]
+    for cid, _, C, _ in base_sets:
+        ctx.reset_chains(cid, C)
+    ctx.sgld_steps(sets, warmup, step=step_size, seed=seed)
     ctx.sync()
     torch.cuda.synchronize()
     ctx.profile(True)
     t0 = time.perf_counter()
-    ctx.sgld_steps(sets, steps, step=wl.step_size, seed=seed)
+    ctx.sgld_steps(sets, steps, step=step_size, seed=seed)
     ctx.sync()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -166,7 +169,7 @@ def posterior_moments(ctx, spider, cat, cid, nid, wl, steps, seed):
 def cpu_baseline(cat, net, n, seed):
     """The FP64 oracle, as it stands, on one chain step with a batch of n."""
     import numpy as np
-    from threadpoolctl import threadpool_info
+    from threadpoolctl import threadpool_info, threadpool_limits
 
     from oracle import likelihood as lk
     from oracle import sampler
@@ -178,16 +181,24 @@ def cpu_baseline(cat, net, n, seed):
     sampler.step(prob, net, ch, cfg, 0, 0, n)
     dt = time.perf_counter() - t0
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    n1 = max(n // 16, 1)  # one core: a smaller batch of the same stream
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        sampler.step(prob, net, ch, cfg, 0, 1, n1)
+        dt1 = time.perf_counter() - t0
     return {"value": n / dt, "unit": "dd-obs/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"one pSGLD step of 1 chain, batch {n} of the same catalog and network, "
-                      f"exact whitening, FP64 numpy ({dt:.1f} s)"}
+            "sample": f"one pSGLD step of 1 chain, batch {n} of the {cat.M}-event catalog and its "
+                      f"network, "
+                      f"exact whitening, FP64 numpy ({dt:.1f} s)",
+            "single_core": {"value": n1 / dt1, "unit": "dd-obs/s", "cores": 1,
+                            "sample": f"one pSGLD step of 1 chain, batch {n1} ({dt1:.1f} s)"}}
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
-              "(the multi-GPU path is a design, see the sharding notes).", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the "
+              "multi-GPU path exists only as a sharding design, not as code).", file=sys.stderr)
         sys.exit(2)
     import torch
 
@@ -200,15 +211,24 @@ def main():
         torch.cuda.synchronize()
         del a, b
         log(f"copied {args.copy_probe} bytes device to device")
-    wl = synth.WORKLOADS[args.workload]
     t = time.perf_counter()
-    cat = synth.make_catalog(args.workload)
-    net = synth.net_for(cat)
-    log(f"generated {args.workload}: M={cat.M} N={cat.N} in {time.perf_counter() - t:.1f}s")
+    if args.workload in synth.MULTI:
+        cats, net = synth.make_multi(
+            args.workload, progress=lambda k, c: log(f"  catalog {k}: M={c.M} N={c.N} "
+                                                     f"({time.perf_counter() - t:.1f}s)"))
+    else:
+        cats = [synth.make_catalog(args.workload)]
+        net = synth.net_for(cats[0])
+    cat, wl = cats[0], cats[0].wl
+    log(f"generated {args.workload}: {len(cats)} catalog(s), M={sum(c.M for c in cats)} "
+        f"N={sum(c.N for c in cats)} in {time.perf_counter() - t:.1f}s")
     ctx = spider.Context(0)
     t = time.perf_counter()
-    cid = ctx.load_catalog(cat, whiten=spider.WHITEN_EXACT)
+    cids = [ctx.load_catalog(c, whiten=spider.WHITEN_EXACT, stream_id=k) for k, c in enumerate(cats)]
+    cid = cids[0]
     nid = ctx.load_net(net)
+    base_sets = [(cid_k, nid, c.wl.chains, c.wl.batch) for cid_k, c in zip(cids, cats)]
+    dd_per_step = sum(C * n for _, _, C, n in base_sets)
     log(f"loaded in {time.perf_counter() - t:.1f}s")
 
     bf16_ok = spider.lib() is not None and _bf16_supported(ctx, nid)
@@ -221,9 +241,9 @@ def main():
     res = {}
     for p in precs:
         code = spider.BF16 if p == "bf16" else spider.FP32
-        wall, ms, launches, rows = run_precision(ctx, spider, cid, nid, wl, code, args.steps,
-                                                 args.warmup, args.seed)
-        dd = wl.chains * wl.batch * args.steps
+        wall, ms, launches, rows = run_precision(ctx, spider, base_sets, wl.step_size, code,
+                                                 args.steps, args.warmup, args.seed)
+        dd = dd_per_step * args.steps
         fl = flops_per_eval(wl.H, wl.D)
         avg_ms = ms / max(launches, 1)
         achieved = rows / max(launches, 1) * fl / (avg_ms * 1e-3) / 1e12
@@ -245,10 +265,16 @@ def main():
         "value": r["value"], "unit": "dd-obs/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": head, "data": "synthetic",
-        "config": {"workload": args.workload, "events": cat.M, "stations": cat.L,
-                   "observations": cat.N, "batch": wl.batch, "chains": wl.chains,
-                   "net": f"6-{wl.H}x{wl.D}-1 tanh", "whiten": "exact", "sampler": "pSGLD",
-                   "state": "fp64"},
+        "config": ({"workload": args.workload, "events": cat.M, "stations": cat.L,
+                    "observations": cat.N, "batch": wl.batch, "chains": wl.chains,
+                    "net": f"6-{wl.H}x{wl.D}-1 tanh", "whiten": "exact", "sampler": "pSGLD",
+                    "state": "fp64"} if len(cats) == 1 else
+                   {"workload": args.workload, "catalogs": len(cats),
+                    "events": sum(c.M for c in cats), "observations": sum(c.N for c in cats),
+                    "chains": sum(c.wl.chains for c in cats), "obs_per_step": dd_per_step,
+                    "per_catalog": [[c.M, c.L, c.N, c.wl.batch, c.wl.chains] for c in cats],
+                    "net": f"6-{wl.H}x{wl.D}-1 tanh", "whiten": "exact", "sampler": "pSGLD",
+                    "state": "fp64", "launch": "all catalogs' network rows in one launch per step"}),
         "roofline": {"bound": "mfma", "kernel": "travel-time network (forward + source "
                      "gradient)", "achieved": r["achieved"], "peak": PEAK[head],
                      "unit": "TFLOP/s", "frac": r["achieved"] / PEAK[head],
@@ -259,12 +285,14 @@ def main():
                       "error_vs_oracle": v["error"]}
                   for p, v in res.items()},
     }
-    if args.moments_steps > 0:
+    if args.moments_steps > 0 and len(cats) == 1:
         line["posterior_moments"] = posterior_moments(ctx, spider, cat, cid, nid, wl,
                                                       args.moments_steps, args.seed)
     if not args.no_cpu_baseline:
         t = time.perf_counter()
-        line["cpu_baseline"] = cpu_baseline(cat, net, args.cpu_batch, args.seed)
+        # several catalogs: the oracle on the one nearest 200k events
+        cb = min(cats, key=lambda c: abs(c.M - 200_000)) if len(cats) > 1 else cat
+        line["cpu_baseline"] = cpu_baseline(cb, net, min(args.cpu_batch, cb.N), args.seed)
         log(f"cpu baseline in {time.perf_counter() - t:.1f}s")
     ctx.close()
     print(json.dumps(line), flush=True)

@@ -376,6 +376,7 @@ int run_batch(spider_ctx* ctx, Catalog& cat, Net& net, int prec, int C, int64_t 
   launch_select(cv, C, n, idx, seed, steps_dev, step_scalar, chain0, b, ws.err.as<int>(),
                 ctx->stream);
   RowSource src;
+  std::memset(&src, 0, sizeof(src));
   src.mode = 0;
   src.rows = 2 * Cn;
   src.ev = b.ev;
@@ -396,6 +397,121 @@ int run_batch(spider_ctx* ctx, Catalog& cat, Net& net, int prec, int C, int64_t 
     HIPCK(reduce_events(cv, C, n, scale, b, ws.sort(), ws.G.as<double>(), ctx->stream),
           "per-event reduction");
   HIPCK(hipGetLastError(), "step kernels");
+  return SPIDER_OK;
+}
+
+// The batch buffers of the observations from obs_off on (rows from 2 obs_off).
+BatchBufs batch_at(const BatchBufs& b, int64_t obs_off) {
+  BatchBufs o = b;
+  o.obs += obs_off;
+  o.ev += 2 * obs_off;
+  o.sta += 2 * obs_off;
+  o.tau += obs_off;
+  o.w += obs_off;
+  o.net_out += 2 * obs_off;
+  o.T += 2 * obs_off;
+  o.gT += 6 * obs_off;
+  o.r += obs_off;
+  o.z += obs_off;
+  return o;
+}
+
+// Chain sets that share one network and precision, advanced together: every
+// set's minibatch is selected into its own slice of the workspace, one
+// network launch evaluates the rows of all sets (row source mode 2), and the
+// residual, whitening, per-event reduction and update of each set follow.
+// The results equal those of advancing each set on its own.
+struct FusedSets {
+  std::vector<int64_t> obs_off;  // first observation of each set in the workspace
+  int64_t total_obs = 0;
+  DevBuf subs, row0;             // device RowSource table and its row offsets
+};
+
+int prepare_fused(spider_ctx* ctx, const spider_chainset* sets, int n_sets, FusedSets& f) {
+  int64_t maxC = 1, maxCn = 1, maxCM = 1, maxCL = 1;
+  f.obs_off.assign(n_sets + 1, 0);
+  for (int k = 0; k < n_sets; ++k) {
+    const Catalog& cat = *get_cat(ctx, sets[k].cat_id);
+    const int64_t C = sets[k].n_chains, Cn = C * sets[k].batch;
+    f.obs_off[k + 1] = f.obs_off[k] + Cn;
+    maxC = std::max(maxC, C);
+    maxCn = std::max(maxCn, Cn);
+    maxCM = std::max(maxCM, C * cat.M);
+    maxCL = std::max(maxCL, C * cat.L);
+  }
+  f.total_obs = f.obs_off[n_sets];
+  Workspace& ws = ctx->ws;
+  // batch buffers for all sets; the sort scratch, sized by the same call,
+  // then holds any single set
+  HIPCK(ws.reserve(maxC, f.total_obs, maxCM, maxCL), "workspace");
+  const BatchBufs b = ws.batch();
+  std::vector<RowSource> subs(n_sets);
+  std::vector<int64_t> row0(n_sets + 1);
+  for (int k = 0; k < n_sets; ++k) {
+    const Catalog& cat = *get_cat(ctx, sets[k].cat_id);
+    const BatchBufs bk = batch_at(b, f.obs_off[k]);
+    RowSource& r = subs[k];
+    std::memset(&r, 0, sizeof(r));
+    r.mode = 0;
+    r.rows = 2 * (f.obs_off[k + 1] - f.obs_off[k]);
+    r.ev = bk.ev;
+    r.sta = bk.sta;
+    r.theta = cat.theta.as<double>();
+    r.rows_per_chain = 2 * sets[k].batch;
+    r.theta_chain_stride = (int64_t)cat.M * 4;
+    r.stations = cat.stations.as<double>();
+    row0[k] = 2 * f.obs_off[k];
+  }
+  row0[n_sets] = 2 * f.total_obs;
+  HIPCK(upload(f.subs, subs.data(), subs.size() * sizeof(RowSource), SPIDER_MEM_HOST, ctx->stream),
+        "row sources");
+  HIPCK(upload(f.row0, row0.data(), row0.size() * 8, SPIDER_MEM_HOST, ctx->stream), "row sources");
+  HIPCK(hipStreamSynchronize(ctx->stream), "row sources");
+  return SPIDER_OK;
+}
+
+int fused_step(spider_ctx* ctx, const spider_chainset* sets, int n_sets, const FusedSets& f,
+               const UpdateArgs& ua) {
+  Workspace& ws = ctx->ws;
+  const BatchBufs b = ws.batch();
+  for (int k = 0; k < n_sets; ++k) {
+    Catalog& cat = *get_cat(ctx, sets[k].cat_id);
+    launch_select(cat.view(), sets[k].n_chains, sets[k].batch, nullptr, ua.seed,
+                  cat.steps.as<int64_t>(), 0, 0, batch_at(b, f.obs_off[k]), ws.err.as<int>(),
+                  ctx->stream);
+  }
+  RowSource src;
+  std::memset(&src, 0, sizeof(src));
+  src.mode = 2;
+  src.nsub = n_sets;
+  src.sub = f.subs.as<RowSource>();
+  src.sub_row0 = f.row0.as<int64_t>();
+  src.rows = 2 * f.total_obs;
+  int rc = run_network(ctx, *get_net(ctx, sets[0].net_id), sets[0].precision, src, b.net_out);
+  if (rc != SPIDER_OK) return rc;
+  for (int k = 0; k < n_sets; ++k) {
+    const spider_chainset& st = sets[k];
+    Catalog& cat = *get_cat(ctx, st.cat_id);
+    Net& net = *get_net(ctx, st.net_id);
+    const int C = st.n_chains;
+    const int64_t n = st.batch;
+    const CatView cv = cat.view();
+    const BatchBufs bk = batch_at(b, f.obs_off[k]);
+    const int whiten = cat.kappa == 0.0 ? SPIDER_WHITEN_NONE : cat.whiten;
+    launch_residual(cv, net.view(st.precision), C, n, cat.theta.as<double>(), (int64_t)cat.M * 4,
+                    whiten, bk, ctx->stream);
+    if (whiten == SPIDER_WHITEN_EXACT)
+      HIPCK(exact_whiten(cv, C, n, bk, ws.sort(), ctx->stream), "exact whitening");
+    HIPCK(reduce_events(cv, C, n, (double)cat.N / (double)n, bk, ws.sort(), ws.G.as<double>(),
+                        ctx->stream),
+          "per-event reduction");
+    launch_centroid(cat.theta.as<double>(), C, cat.M, ws.partial.as<double>(),
+                    ws.thetabar.as<double>(), ctx->stream);
+    launch_update(cv, C, cat.theta.as<double>(), cat.v.as<double>(), ws.G.as<double>(),
+                  ws.thetabar.as<double>(), cat.steps.as<int64_t>(), cat.mcount.as<int64_t>(), ua,
+                  cat.mean.as<double>(), cat.m2.as<double>(), ctx->stream);
+    HIPCK(hipGetLastError(), "update");
+  }
   return SPIDER_OK;
 }
 
@@ -849,7 +965,23 @@ int spider_sgld_steps(spider_ctx* ctx, const spider_chainset* sets, int32_t n_se
   ua.seed = cfg->seed;
   ua.burn = cfg->burn_in;
   ua.thin = cfg->thin;
-  for (int64_t t = 0; t < cfg->n_steps; ++t) {
+  // sets sharing one network and precision (and no catalog twice) advance in
+  // fused steps
+  bool fuse = n_sets > 1;
+  for (int k = 1; k < n_sets && fuse; ++k)
+    fuse = sets[k].net_id == sets[0].net_id && sets[k].precision == sets[0].precision;
+  for (int k = 0; k < n_sets && fuse; ++k)
+    for (int j = 0; j < k && fuse; ++j) fuse = sets[j].cat_id != sets[k].cat_id;
+  if (fuse && cfg->n_steps > 0) {
+    FusedSets f;
+    rc = prepare_fused(ctx, sets, n_sets, f);
+    if (rc) return rc;
+    for (int64_t t = 0; t < cfg->n_steps; ++t) {
+      rc = fused_step(ctx, sets, n_sets, f, ua);
+      if (rc) return rc;
+    }
+  }
+  for (int64_t t = 0; t < (fuse ? 0 : cfg->n_steps); ++t) {
     for (int k = 0; k < n_sets; ++k) {
       const spider_chainset& st = sets[k];
       Catalog& cat = *get_cat(ctx, st.cat_id);

@@ -16,8 +16,14 @@ struct Obs {
 //  mode 0 (minibatch): row r is event ev[r] of chain r / rows_per_chain at
 //          station sta[r]; x = theta[chain][ev][0:3], s = stations[sta].
 //  mode 1 (explicit):  x = x[r][0:3], s = s[r][0:3].
+//  mode 2 (several catalogs in one launch): rows [sub_row0[k], sub_row0[k+1])
+//          are the rows of the mode-0 source sub[k] (device table, nsub
+//          entries, sub_row0[nsub] = rows).
 struct RowSource {
   int mode;
+  int nsub;
+  const RowSource* sub;
+  const int64_t* sub_row0;
   int64_t rows;
   const int32_t* ev;
   const int32_t* sta;
@@ -54,8 +60,20 @@ struct RowOut {
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // Computes the network inputs u of row r.
-__device__ inline void row_inputs(const RowSource& src, const NetView& net, int64_t r, float u[6]) {
+__device__ inline void row_inputs(const RowSource& src_in, const NetView& net, int64_t r, float u[6]) {
   double x[3], s[3];
+  const RowSource* sp = &src_in;
+  if (src_in.mode == 2) {  // the catalog whose rows hold r: the last k with sub_row0[k] <= r
+    int lo = 0, hi = src_in.nsub - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (src_in.sub_row0[mid] <= r) lo = mid;
+      else hi = mid - 1;
+    }
+    r -= src_in.sub_row0[lo];
+    sp = src_in.sub + lo;
+  }
+  const RowSource& src = *sp;
   if (src.mode == 0) {
     const int64_t c = r / src.rows_per_chain;
     const double* th = src.theta + c * src.theta_chain_stride + (int64_t)src.ev[r] * 4;

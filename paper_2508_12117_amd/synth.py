@@ -57,6 +57,7 @@ class Workload:
     centroid_sigma: tuple = (0.01, 0.01, 0.01, 0.01)  # Sec. 4
     v0: float = V_TRUE
     index: int = 0
+    side: float = 200.0    # km, horizontal box side of the clustered generator
 
 
 WORKLOADS = {
@@ -167,16 +168,16 @@ def _events_clustered(rng, wl, side=200.0, depth=30.0):
     return xyz, sta
 
 
-def make_catalog(name: str, seed: int = MASTER_SEED) -> Catalog:
-    """Build workload `name` from `seed`; identical arrays on every machine."""
-    wl = WORKLOADS[name]
+def make_catalog(name, seed: int = MASTER_SEED) -> Catalog:
+    """Build workload `name` (or a Workload) from `seed`; identical arrays on every machine."""
+    wl = name if isinstance(name, Workload) else WORKLOADS[name]
     geo = _rng(wl, seed, 0)
-    if name == "tiny":
+    if wl.name == "tiny":
         xyz, sta = _events_tiny(geo, wl)
-    elif name == "faults10k":
+    elif wl.name == "faults10k":
         xyz, sta = _events_faults(geo, wl)
     else:
-        xyz, sta = _events_clustered(geo, wl)
+        xyz, sta = _events_clustered(geo, wl, side=wl.side)
     M, L = wl.M, wl.L
     hypo_true = np.zeros((M, 4))
     hypo_true[:, 0:3] = xyz
@@ -262,6 +263,54 @@ def net_box(cat: Catalog):
 def net_for(cat: Catalog, seed: int = MASTER_SEED, **kw) -> Net:
     c, h = net_box(cat)
     return make_net(cat.wl.H, cat.wl.D, c, h, seed=seed, v0=cat.wl.v0, **kw)
+
+
+# Several catalogs of uneven size advanced together: one catalog of 10^6
+# events (200 stations, 1/6 of the (pair, station) observations kept,
+# ~400M) and 16 catalogs of M_c events, log-uniform in [1k, 200k] (100
+# stations, 5/6 kept, ~1,000 M_c observations each).  All come from the
+# clustered generator with the box side scaled as 200 sqrt(M_c / 200k) km, so
+# the areal density matches the 200k workload; 4 chains each; the minibatch
+# is clamp(2^ceil(log2(0.01 N_c)), 2^14, 2^20); all share one network
+# 6 -> 256 x 8 -> 1.
+MULTI = {"multi17": dict(big=1_000_000, big_L=200, big_keep=1.0 / 6.0, n_small=16,
+                         small_lo=1_000, small_hi=200_000, small_L=100, small_keep=5.0 / 6.0,
+                         chains=4, H=256, D=8, index=20)}
+
+
+def multi_workloads(name: str, seed: int = MASTER_SEED):
+    """The per-catalog workloads of multi-catalog workload `name` (batch not yet set)."""
+    m = MULTI[name]
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, m["index"], 99])))
+    sizes = [m["big"]] + [int(round(math.exp(rng.uniform(math.log(m["small_lo"]),
+                                                          math.log(m["small_hi"])))))
+                          for _ in range(m["n_small"])]
+    out = []
+    for k, M in enumerate(sizes):
+        big = k == 0
+        out.append(Workload(f"{name}.{k}", M=M, L=m["big_L"] if big else m["small_L"], knn=12,
+                            keep=m["big_keep"] if big else m["small_keep"], H=m["H"], D=m["D"],
+                            batch=0, chains=m["chains"], steps=2000, index=m["index"] + 1 + k,
+                            side=200.0 * math.sqrt(M / 200_000)))
+    return out
+
+
+def multi_batch(N: int) -> int:
+    """Minibatch of a catalog of N observations in a multi-catalog workload."""
+    return int(min(max(1 << math.ceil(math.log2(0.01 * N)), 1 << 14), 1 << 20))
+
+
+def make_multi(name: str, seed: int = MASTER_SEED, progress=None):
+    """The catalogs of multi-catalog workload `name` and their shared network;
+    `progress(k, cat)` is called after each catalog is made."""
+    cats = []
+    for k, wl in enumerate(multi_workloads(name, seed)):
+        cat = make_catalog(wl, seed)
+        cat.wl = dataclasses.replace(wl, batch=min(multi_batch(cat.N), cat.N))
+        cats.append(cat)
+        if progress is not None:
+            progress(k, cat)
+    return cats, net_for(cats[0], seed)
 
 
 def random_theta(cat: Catalog, seed: int, scale=(0.05, 0.05, 0.05, 0.02)) -> np.ndarray:

@@ -331,6 +331,39 @@ def test_sgld_is_deterministic_and_resumable(ctx, tiny_setup):
     assert np.array_equal(outs[0], outs[2])
 
 
+@pytest.mark.parametrize("prec", [spider.FP32, spider.BF16])
+def test_fused_chainsets_equal_separate_runs(ctx, prec):
+    """Catalogs of uneven batch and chain count that share a network advance in
+    fused steps (one network launch for all of them); every chain ends where
+    it ends when its catalog advances alone."""
+    cats = [synth.make_catalog("tiny", seed=s) for s in (101, 102, 103)]
+    net = synth.net_for(cats[0])
+    nid = ctx.load_net(net)
+    shapes = [(1024, 1), (512, 2), (2048, 3)]
+    ids = [ctx.load_catalog(c, whiten=spider.WHITEN_EXACT, stream_id=7 + k)
+           for k, c in enumerate(cats)]
+
+    def states():
+        out = []
+        for cid, cat, (_, C) in zip(ids, cats, shapes):
+            th = torch.empty(C, cat.M, 4, dtype=torch.float64, device="cuda")
+            for c in range(C):
+                ctx.get_state(cid, c, th[c])
+            out.append(host(th))
+        return out
+
+    for cid, (_, C) in zip(ids, shapes):
+        ctx.reset_chains(cid, C)
+    ctx.sgld_steps([(cid, nid, C, n, prec) for cid, (n, C) in zip(ids, shapes)], 6, seed=19)
+    fused = states()
+    for cid, (n, C) in zip(ids, shapes):
+        ctx.reset_chains(cid, C)
+        ctx.sgld_steps([(cid, nid, C, n, prec)], 6, seed=19)
+    alone = states()
+    for a_, b_ in zip(fused, alone):
+        assert np.array_equal(a_, b_)
+
+
 def test_multi_chain_matches_oracle_chains(ctx, tiny_setup):
     """Chains of one launch follow their own batch and noise streams."""
     cat, net, _, nid = tiny_setup
