@@ -127,39 +127,47 @@ def sample_error(ctx, spider, cat, net, nid, prec, rows=4096, seed=5):
             "rows": rows}
 
 
-def posterior_moments(ctx, spider, cat, cid, nid, wl, steps, seed):
+def posterior_moments(ctx, spider, cats, base_sets, step_size, steps, seed):
     """Pooled per-event posterior moments of both paths after the same number
-    of steps from the same start with the same batch and noise streams."""
+    of steps from the same start with the same batch and noise streams (all
+    catalogs of the workload, advanced together)."""
     import numpy as np
     import torch
     out = {}
     for name, code in (("bf16", spider.BF16), ("fp32", spider.FP32)):
-        ctx.reset_chains(cid, wl.chains)
+        sets = [(cid, nid, C, n, code) for cid, nid, C, n in base_sets]
+        for cid, _, C, _ in base_sets:
+            ctx.reset_chains(cid, C)
         t = time.perf_counter()
         done = 0
         while done < steps:  # in chunks (a split run equals an uninterrupted one)
             k = min(100, steps - done)
-            ctx.sgld_steps([(cid, nid, wl.chains, wl.batch, code)], k, step=wl.step_size,
-                           seed=seed, burn_in=steps // 2, thin=10)
+            ctx.sgld_steps(sets, k, step=step_size, seed=seed, burn_in=steps // 2, thin=10)
             ctx.sync()
             done += k
-            log(f"moments {name}: {done}/{steps} steps")
-        mean = torch.empty(cat.M, 4, dtype=torch.float64, device="cuda")
-        cov = torch.empty(cat.M, 10, dtype=torch.float64, device="cuda")
-        count = ctx.moments(cid, -1, mean, cov)
-        out[name] = (mean.cpu().numpy(), cov.cpu().numpy(), count)
-        log(f"moments {name}: {steps} steps in {time.perf_counter() - t:.1f}s, {count} samples")
+            log(f"moments {name}: {done}/{steps} steps ({time.perf_counter() - t:.1f}s)")
+        means, covs, counts = [], [], []
+        for c, (cid, _, _, _) in zip(cats, base_sets):
+            mean = torch.empty(c.M, 4, dtype=torch.float64, device="cuda")
+            cov = torch.empty(c.M, 10, dtype=torch.float64, device="cuda")
+            counts.append(ctx.moments(cid, -1, mean, cov))
+            means.append(mean.cpu().numpy())
+            covs.append(cov.cpu().numpy())
+        out[name] = (np.concatenate(means), np.concatenate(covs), counts)
+        log(f"moments {name}: {steps} steps in {time.perf_counter() - t:.1f}s, {counts[0]} samples")
     mb, cb, n = out["bf16"]
     mf, cf, _ = out["fp32"]
     diag = [0, 4, 7, 9]  # xx, yy, zz, tt in the packed upper triangle
     sdb, sdf = np.sqrt(cb[:, diag]), np.sqrt(cf[:, diag])
     z = np.abs(mb - mf) / sdf
     ratio = sdb / sdf
-    true = np.column_stack([cat.hypo_true[:, 0:3], np.zeros(cat.M)])
-    err_b = np.sqrt(np.mean((mb[:, 0:3] - true[:, 0:3]) ** 2))
-    err_f = np.sqrt(np.mean((mf[:, 0:3] - true[:, 0:3]) ** 2))
+    true = np.concatenate([c.hypo_true[:, 0:3] for c in cats])
+    err_b = np.sqrt(np.mean((mb[:, 0:3] - true) ** 2))
+    err_f = np.sqrt(np.mean((mf[:, 0:3] - true) ** 2))
     q = lambda a, p: float(np.percentile(a, p))
-    return {"steps": steps, "burn_in": steps // 2, "thin": 10, "samples": int(n),
+    return {"steps": steps, "burn_in": steps // 2, "thin": 10,
+            "samples": int(n[0]) if len(n) == 1 else [int(k) for k in n],
+            "events": int(mb.shape[0]),
             "mean_diff_over_sd": {"median": q(z, 50), "p99": q(z, 99), "max": float(z.max())},
             "sd_ratio_bf16_fp32": {"p1": q(ratio, 1), "median": q(ratio, 50), "p99": q(ratio, 99)},
             "location_rms_error_km": {"bf16": float(err_b), "fp32": float(err_f)},
@@ -225,7 +233,6 @@ def main():
     ctx = spider.Context(0)
     t = time.perf_counter()
     cids = [ctx.load_catalog(c, whiten=spider.WHITEN_EXACT, stream_id=k) for k, c in enumerate(cats)]
-    cid = cids[0]
     nid = ctx.load_net(net)
     base_sets = [(cid_k, nid, c.wl.chains, c.wl.batch) for cid_k, c in zip(cids, cats)]
     dd_per_step = sum(C * n for _, _, C, n in base_sets)
@@ -285,8 +292,8 @@ def main():
                       "error_vs_oracle": v["error"]}
                   for p, v in res.items()},
     }
-    if args.moments_steps > 0 and len(cats) == 1:
-        line["posterior_moments"] = posterior_moments(ctx, spider, cat, cid, nid, wl,
+    if args.moments_steps > 0:
+        line["posterior_moments"] = posterior_moments(ctx, spider, cats, base_sets, wl.step_size,
                                                       args.moments_steps, args.seed)
     if not args.no_cpu_baseline:
         t = time.perf_counter()

@@ -235,8 +235,11 @@ typedef struct {
  * over calls equals one uninterrupted run.  Chains are created on first use
  * if the catalog has fewer.  After the last step every state is checked for
  * finite values: SPIDER_E_NUMERIC names the catalog and chain otherwise
- * (this waits for the stream).  Errors: SPIDER_E_INVALID, SPIDER_E_NUMERIC,
- * SPIDER_E_OOM, SPIDER_E_HIP. */
+ * (this waits for the stream).  When there are several sets, all with the
+ * same network and precision and no catalog twice, they advance in fused
+ * steps: one network launch per step evaluates the rows of every set, and
+ * the results equal those of advancing each set on its own.  Errors:
+ * SPIDER_E_INVALID, SPIDER_E_NUMERIC, SPIDER_E_OOM, SPIDER_E_HIP. */
 int spider_sgld_steps(spider_ctx* ctx, const spider_chainset* sets, int32_t n_sets,
                       const spider_sgld_cfg* cfg);
 

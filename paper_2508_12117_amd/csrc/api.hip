@@ -104,6 +104,7 @@ struct Net {
     for (int a = 0; a < 3; ++a) {
       v.center[a] = center[a];
       v.half[a] = half[a];
+      v.inv_half[a] = 1.0 / half[a];
     }
     v.pack_fwd = pack_fwd[prec].p;
     v.pack_bwd = pack_bwd[prec].p;

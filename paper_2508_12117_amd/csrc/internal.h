@@ -48,6 +48,7 @@ struct NetView {
   double v0;
   double center[3];
   double half[3];
+  double inv_half[3];  // 1 / half, rounded once on the host
   const void* pack_fwd;  // matrix-core operand packs (precision dependent)
   const void* pack_bwd;
 };
@@ -89,8 +90,8 @@ __device__ inline void row_inputs(const RowSource& src_in, const NetView& net, i
     }
   }
   for (int a = 0; a < 3; ++a) {
-    u[a] = (float)((x[a] - net.center[a]) / net.half[a]);
-    u[3 + a] = (float)((s[a] - net.center[a]) / net.half[a]);
+    u[a] = (float)((x[a] - net.center[a]) * net.inv_half[a]);
+    u[3 + a] = (float)((s[a] - net.center[a]) * net.inv_half[a]);
   }
 }
 

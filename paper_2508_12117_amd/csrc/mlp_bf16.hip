@@ -32,7 +32,10 @@ int mlp_variants_bf16(int H, int D, const MlpVariant** list) {
   static const MlpVariant h256d6[] = {SPIDER_V(256, 6, 8, 4), SPIDER_PP(256, 6, 8, 4),
                                       SPIDER_V(256, 6, 8, 2), SPIDER_VP(256, 6, 8, 4, 2)};
   static const MlpVariant h256d7[] = {SPIDER_V(256, 7, 8, 4), SPIDER_PP(256, 7, 8, 4)};
-  static const MlpVariant h256d8[] = {SPIDER_V(256, 8, 8, 4), SPIDER_V(256, 8, 8, 2)};
+  // eight layers: the 64-row tiles spill registers (seven stored derivative
+  // layers); the 32-row ping-pong and the shallower ring do not
+  static const MlpVariant h256d8[] = {SPIDER_V(256, 8, 8, 4), SPIDER_PP(256, 8, 8, 2),
+                                      SPIDER_V(256, 8, 8, 2), SPIDER_VP(256, 8, 8, 4, 2)};
 #define SPIDER_L(HH, DD, arr)                \
   if (H == HH && D == DD) {                  \
     *list = arr;                             \

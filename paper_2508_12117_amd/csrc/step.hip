@@ -188,9 +188,9 @@ __device__ inline void assemble_tt(const NetView& net, const double x[3], const 
   T = T0 * f;
   const double a = f / (net.v0 * dist);
   const double bsc = T0 * sg / kLn2;
-  g[0] = a * d0 + bsc * ((double)no.d0 / net.half[0]);
-  g[1] = a * d1 + bsc * ((double)no.d1 / net.half[1]);
-  g[2] = a * d2 + bsc * ((double)no.d2 / net.half[2]);
+  g[0] = a * d0 + bsc * ((double)no.d0 * net.inv_half[0]);
+  g[1] = a * d1 + bsc * ((double)no.d1 * net.inv_half[1]);
+  g[2] = a * d2 + bsc * ((double)no.d2 * net.inv_half[2]);
 }
 
 __global__ void k_residual(CatView cat, NetView net, int C, int64_t n, const double* theta,
