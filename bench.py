@@ -30,7 +30,8 @@ HBM_PEAK = 8000.0                             # GB/s
 # Valid only for the kernel built from the template sources with this digest
 # and the same variant; otherwise the bench reports traffic as null.
 NETWORK_TRAFFIC = {
-    "kernel_sources": ["paper_2508_12117_amd/csrc/mlp_mfma.h", "paper_2508_12117_amd/csrc/mlp_pp.h"],
+    "kernel_sources": ["paper_2508_12117_amd/csrc/mlp_mfma.h", "paper_2508_12117_amd/csrc/mlp_pp.h",
+                       "paper_2508_12117_amd/csrc/internal.h"],
     "sha256": "cde6a0defdc0e61ba202d72d79c584fa2c3687ebb119d136264796c824ef234e",
     "variant": {"waves": 8, "row_tiles": 4, "schedule": 1},
     "rows": 16777216,

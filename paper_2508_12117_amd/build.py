@@ -23,7 +23,7 @@ FLAGS = [
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", CSRC, "-I", os.path.join(ROOT, "include"),
-    "-Wall", "-Wno-unused-function", "-Wno-unused-result",
+    "-Wall", "-Wno-unused-function",
 ]
 
 

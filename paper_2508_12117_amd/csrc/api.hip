@@ -229,17 +229,18 @@ int hip_fail(spider_ctx* ctx, hipError_t e, const char* what) {
     if (_e != hipSuccess) return hip_fail(ctx, _e, what); \
   } while (0)
 
-// Select the context's device for the duration of a call.
+// Select the context's device for the duration of a call.  A failure here
+// surfaces as the error of the call's first HIP operation.
 struct DeviceGuard {
   int prev = -1;
   explicit DeviceGuard(int dev) {
-    hipGetDevice(&prev);
-    if (prev != dev) hipSetDevice(dev);
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
   }
   ~DeviceGuard() {
     int cur = -1;
-    hipGetDevice(&cur);
-    if (prev >= 0 && cur != prev) hipSetDevice(prev);
+    if (hipGetDevice(&cur) != hipSuccess) return;
+    if (prev >= 0 && cur != prev) (void)hipSetDevice(prev);
   }
 };
 

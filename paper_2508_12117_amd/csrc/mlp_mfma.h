@@ -93,18 +93,28 @@ struct Shape {
   static constexpr int NL = D > 1 ? D - 1 : 1;  // stored derivative layers
   // derivative layers kept in registers; the rest go to LDS (BF16 pairs)
   static constexpr size_t LAYER_BYTES = (size_t)R * H * 2;  // one BF16 derivative layer
-  static constexpr int LDS_LAYERS_MAX =
-      (int)((160 * 1024 - (size_t)R * LDW * sizeof(typename P::T) - (size_t)R * 8 * 4 -
-             (size_t)(H / 16) * R * 4 * 4) / LAYER_BYTES);
+  static constexpr size_t ACT_BYTES = (size_t)R * LDW * sizeof(typename P::T);
+  // row inputs [R][8] and per-tile output partials [H/16][R][4]
+  static constexpr size_t UPART_BYTES = (size_t)R * 8 * 4 + (size_t)(H / 16) * R * 4 * 4;
   static constexpr int NLR_PREF = NL < 3 ? NL : 3;
+  static constexpr int LDS_LAYERS_SEP = (int)((160 * 1024 - ACT_BYTES - UPART_BYTES) / LAYER_BYTES);
+  // deep BF16 networks: the row inputs (dead after the first layer) and the
+  // output partials (written after the backward pass) share the LDS slot of
+  // derivative layer D-2 (written by forward layer D-2, last read by backward
+  // layer D-1), so that one more derivative layer fits in LDS
+  static constexpr bool ALIAS = P::kBF16 && D >= 3 && H * RT / NW > 64 &&
+                                NL - LDS_LAYERS_SEP > NLR_PREF && LAYER_BYTES >= UPART_BYTES;
+  static constexpr int LDS_LAYERS_MAX =
+      ALIAS ? (int)((160 * 1024 - ACT_BYTES) / LAYER_BYTES) : LDS_LAYERS_SEP;
   static constexpr int NLR = (P::kBF16 && H * RT / NW > 64)
                                  ? (NLR_PREF > NL - LDS_LAYERS_MAX ? NLR_PREF : NL - LDS_LAYERS_MAX)
                                  : NL;
   static constexpr int NLDS = NL - NLR;
   static constexpr int NT = NW * 64;
-  static constexpr size_t ACT_BYTES = (size_t)R * LDW * sizeof(typename P::T);
   static constexpr size_t DLDS_BYTES = (size_t)NLDS * RT * CT * 2 * NT * 4;
-  static constexpr size_t FIXED_BYTES = (size_t)R * 8 * 4 + (size_t)(H / 16) * R * 4 * 4;
+  static constexpr size_t FIXED_BYTES = ALIAS ? 0 : UPART_BYTES;
+  // derivative layer D-2 = NL-1 sits in LDS slot NLDS-1
+  static_assert(!ALIAS || NLDS >= 1, "the shared slot must be an LDS derivative layer");
   // two activation buffers when they fit in 160 KB of LDS, else one buffer
   // and an extra barrier per layer
   static constexpr int NBUF = 2 * ACT_BYTES + DLDS_BYTES + FIXED_BYTES <= 156 * 1024 ? 2 : 1;
@@ -312,12 +322,15 @@ __global__ __launch_bounds__(NW * 64, MINB) void k_mlp(RowSource src, NetView ne
   constexpr int NL = S::NL, NLR = S::NLR, NT = S::NT, NBUF = S::NBUF;
 
   __shared__ __attribute__((aligned(16))) T act[NBUF][R * LDW];
-  __shared__ uint32_t dlds[S::NLDS > 0 ? S::NLDS * RT * CT * 2 * NT : 1];
-  __shared__ __attribute__((aligned(16))) float u_s[R][8];
-  // per 16-neuron tile partial sums of the output layer and the input
-  // gradient; summed over tiles in a fixed order, so the result does not
-  // depend on how the tiles are split over the waves
-  __shared__ __attribute__((aligned(16))) float part[H / 16][R][4];
+  __shared__ __attribute__((aligned(16))) uint32_t dlds[S::NLDS > 0 ? S::NLDS * RT * CT * 2 * NT : 1];
+  __shared__ __attribute__((aligned(16))) float upart_own[S::ALIAS ? 4 : S::UPART_BYTES / 4];
+  float* upart = S::ALIAS ? (float*)(dlds + (size_t)(S::NLDS - 1) * RT * CT * 2 * NT) : upart_own;
+  // row inputs, then (after the backward pass) the per 16-neuron tile partial
+  // sums of the output layer and the input gradient; summed over tiles in a
+  // fixed order, so the result does not depend on how the tiles are split
+  // over the waves
+  float (*u_s)[8] = (float (*)[8])upart;
+  float (*part)[R][4] = (float (*)[R][4])(upart + R * 8);
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -473,14 +486,6 @@ __global__ __launch_bounds__(NW * 64, MINB) void k_mlp(RowSource src, NetView ne
   // source columns of W_0 for the input gradient, loaded ahead of the
   // backward pass
   float wg[CT][4][3];
-#pragma unroll
-  for (int ct = 0; ct < CT; ++ct) {
-    const int n0 = (wave * CT + ct) * 16 + 4 * g;
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int a = 0; a < 3; ++a) wg[ct][i][a] = net.W0[(n0 + i) * 6 + a];
-  }
 
   // ---- backward l = D-1 .. 1: e_l = (e_{l+1} W_l) * d_l.  With two buffers
   // the first write goes to the one that layer D-2 read, which every wave
@@ -506,6 +511,16 @@ __global__ __launch_bounds__(NW * 64, MINB) void k_mlp(RowSource src, NetView ne
       for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = floatx4{0, 0, 0, 0};
     const uint4* pl = packb + (size_t)(l - 1) * LSTRIDE;
     const uint4* pn = l > 1 ? packb + (size_t)(l - 2) * LSTRIDE : pl;
+    if (l == 1) {
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+        const int n0 = (wave * CT + ct) * 16 + 4 * g;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int a = 0; a < 3; ++a) wg[ct][i][a] = net.W0[(n0 + i) * 6 + a];
+      }
+    }
     layer_mma<P, RT, CT, NQ, LDW, SWM, PFR>(eb, pl, pn, ring, wave, lane, c, g, s0, acc);
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)

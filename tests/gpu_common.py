@@ -39,10 +39,61 @@ def grad_scale(prob, bt, scale, theta):
     return S
 
 
+def sigma_apply(z, w, group, ev_i, ev_j, M, sigma, kappa, mode):
+    """Sigma_B z for the batch covariance of eq:marginal_sigma (matrix-free):
+    sigma^2 z + kappa^2 U (U^T z), U = diag(sqrt w) A_B, where row n of A_B
+    has +1 at node (group_n, ev_i_n) and -1 at node (group_n, ev_j_n)."""
+    s2 = sigma * sigma
+    if mode == lk.WHITEN_NONE or kappa == 0.0:
+        return s2 * z
+    if mode == lk.WHITEN_DIAG:
+        return (s2 + 2.0 * kappa * kappa * w) * z
+    key_i = np.asarray(group, np.int64) * M + ev_i
+    key_j = np.asarray(group, np.int64) * M + ev_j
+    nodes, inv = np.unique(np.concatenate([key_i, key_j]), return_inverse=True)
+    n = z.shape[0]
+    sw = np.sqrt(w)
+    utz = np.bincount(inv[:n], sw * z, nodes.shape[0]) - np.bincount(inv[n:], sw * z,
+                                                                       nodes.shape[0])
+    return s2 * z + kappa * kappa * sw * (utz[inv[:n]] - utz[inv[n:]])
+
+
+def whitening_residual(r, z, bt, prob, mode):
+    """max |Sigma_B z - r| / (|r| + 1e-3 s): how exactly z solves the batch
+    system for the residuals r it was computed from."""
+    Sz = sigma_apply(z, bt.w, bt.group, bt.ev_i, bt.ev_j, prob.M, prob.sigma, prob.kappa, mode)
+    return float(np.max(np.abs(Sz - r) / (np.abs(r) + 1e-3)))
+
+
+def psgld_update_tolerance(theta, v, G, dG, cfg, eta):
+    """How far one pSGLD update (state theta, v) can move when its gradient G
+    is off by up to dG per entry: the drift eps G / (sqrt(v') + eps_p) is
+    monotone in G, v' = beta2 v + (1 - beta2) G^2 and the noise
+    sqrt(2 eps / (sqrt(v') + eps_p)) eta depend on |G| only, so each term's
+    extremes over [G - dG, G + dG] lie at the ends or at G = 0.  Returns
+    (theta tolerance, v tolerance): twice the extreme deviations, plus FP64
+    rounding."""
+    def parts(g):
+        vn = cfg.beta2 * v + (1.0 - cfg.beta2) * g * g
+        q = np.sqrt(vn) + cfg.eps_p
+        return vn, cfg.step * g / q, cfg.noise_scale * np.sqrt(2.0 * cfg.step / q) * eta
+    v0, d0, n0 = parts(G)
+    tv = np.zeros_like(G)
+    td = np.zeros_like(G)
+    tn = np.zeros_like(G)
+    for g in (G - dG, G + dG, np.where(np.abs(G) <= dG, 0.0, G)):
+        vn, d, n = parts(g)
+        tv = np.maximum(tv, np.abs(vn - v0))
+        td = np.maximum(td, np.abs(d - d0))
+        tn = np.maximum(tn, np.abs(n - n0))
+    return (2.0 * (td + tn) + 1e-13 * (np.abs(theta) + np.abs(d0) + np.abs(n0)),
+            2.0 * tv + 1e-13 * np.abs(v0))
+
+
 def scaled_grad_error(G_gpu, G_ref, S, floor):
     err = np.linalg.norm(G_gpu - G_ref, axis=1)
     return float(np.max(err / np.maximum(S, floor)))
 
 
 __all__ = ["torch", "lk", "spider", "synth", "dev", "host", "make_ctx", "grad_scale",
-           "scaled_grad_error"]
+           "scaled_grad_error", "sigma_apply", "whitening_residual", "psgld_update_tolerance"]

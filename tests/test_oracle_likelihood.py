@@ -245,3 +245,24 @@ def test_whole_gradient_central_differences(tiny, prob_tiny, mode):
             fd = (lk.grad_log_post(prob_tiny, net, tp, idx, mode)[1]
                   - lk.grad_log_post(prob_tiny, net, tm, idx, mode)[1]) / (2 * h)
             assert abs(fd - G[m, a]) < 1e-5 * abs(G[m, a]) + 1e-4 * (1 + abs(lp) * 1e-10 / h)
+
+
+@pytest.mark.parametrize("mode", [lk.WHITEN_NONE, lk.WHITEN_DIAG, lk.WHITEN_EXACT])
+def test_whitening_solves_the_batch_system(mode):
+    """The oracle's z (sparse direct solve) satisfies Sigma_B z = r under the
+    matrix-free application of Sigma_B the GPU tests use, on random batches
+    whose event graphs have shared events and cycles."""
+    from gpu_common import sigma_apply
+    rng = np.random.default_rng(5)
+    M, n = 30, 400
+    ei = rng.integers(0, M, n)
+    ej = (ei + rng.integers(1, M, n)) % M
+    g = rng.integers(0, 4, n)
+    w = rng.uniform(0.2, 3.0, n)
+    r = rng.normal(0, 0.05, n)
+    z = _whiten(r, w, g, ei, ej, M, 0.01, 0.03, mode)
+    Sz = sigma_apply(z, w, g, ei, ej, M, 0.01, 0.03, mode)
+    np.testing.assert_allclose(Sz, r, rtol=0, atol=1e-13)
+    # a wrong sign convention or a dropped coupling would not solve it
+    if mode == lk.WHITEN_EXACT:
+        assert np.max(np.abs(sigma_apply(z, w, g, ej, ej, M, 0.01, 0.03, mode) - r)) > 1e-3

@@ -127,3 +127,23 @@ def test_resume_is_exact(tiny):
     half, _ = sampler.run(prob, net, cfg, 1024, 5)
     rest, _ = sampler.run(prob, net, cfg, 1024, 3, chain=half)
     assert np.array_equal(full.theta, rest.theta)
+
+
+def test_psgld_update_tolerance_bounds_gradient_errors():
+    """The GPU tests' bound on how far a gradient error of up to dG moves one
+    pSGLD update holds for sampled errors, including gradients near zero."""
+    from gpu_common import psgld_update_tolerance
+    rng = np.random.default_rng(3)
+    n = 2000
+    theta = rng.normal(0, 5, (n, 4))
+    v = np.where(rng.random((n, 4)) < 0.5, 0.0, rng.uniform(0, 1e4, (n, 4)))
+    G = rng.normal(0, 1, (n, 4)) * 10.0 ** rng.uniform(-6, 4, (n, 4))
+    dG = np.abs(G) * 10.0 ** rng.uniform(-6, 1, (n, 4))
+    eta = rng.normal(0, 1, (n, 4))
+    cfg = sampler.SamplerConfig(step=1e-4)
+    tol_th, tol_v = psgld_update_tolerance(theta, v, G, dG, cfg, eta)
+    th0, v0 = sampler.update(theta, v, G, cfg, eta)
+    for _ in range(20):
+        th1, v1 = sampler.update(theta, v, G + dG * rng.uniform(-1, 1, G.shape), cfg, eta)
+        assert np.all(np.abs(th1 - th0) <= tol_th)
+        assert np.all(np.abs(v1 - v0) <= tol_v)
