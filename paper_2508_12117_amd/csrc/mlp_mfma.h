@@ -143,6 +143,23 @@ __device__ __forceinline__ void tanh_scaled(float y, float& a, float& d) {
 // the BF16 path BF16 pairs (round to nearest even), the first NLR layers in
 // registers and the rest in LDS, where each lane reads back only what it
 // wrote ([layer][pair][thread] uint32, conflict-free).
+// First layer (6 inputs) on the FP32 matrix core, two v_mfma_f32_16x16x4_f32
+// per 16 x 16 tile: k = 0..3, then k = 4..7 with inputs 6 and 7 zero.  The
+// lane supplies the A element (neuron nr = tile + lane % 16, input k = 4 kk +
+// lane / 16) and the B element (row tile + lane % 16, the same k); the result
+// is the accumulator layout of the hidden layers (four consecutive neurons of
+// one row per lane), starting from the bias.
+__device__ __forceinline__ void first_layer_a(const float* W0s, int nr, int g, float w[2]) {
+  w[0] = W0s[nr * 6 + g];
+  w[1] = g < 2 ? W0s[nr * 6 + 4 + g] : 0.0f;
+}
+__device__ __forceinline__ floatx4 first_layer_mma(const float w[2], const float u[2],
+                                                   const float b[4]) {
+  floatx4 z = {b[0], b[1], b[2], b[3]};
+  z = __builtin_amdgcn_mfma_f32_16x16x4f32(w[0], u[0], z, 0, 0, 0);
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(w[1], u[1], z, 0, 0, 0);
+}
+
 template <class P, int NL, int NLR, int RT, int CT, int NT>
 struct DStore {
   float v[NL][RT][CT][4];
@@ -350,7 +367,7 @@ __global__ __launch_bounds__(NW * 64, MINB) void k_mlp(RowSource src, NetView ne
   if (D > 1) ring_prime<NQ, PFR, CT>(ring, packf, wave, lane, s0);
   // first-layer and output weights of the wave's neurons, loaded before the
   // row inputs so that both latencies overlap
-  float w1[CT][4][6], b1[CT][4], wo[CT][4];
+  float w1[CT][2], b1[CT][4], wo[CT][4];
 #pragma unroll
   for (int ct = 0; ct < CT; ++ct) {
     const int n0 = (wave * CT + ct) * 16 + 4 * g;
@@ -364,13 +381,7 @@ __global__ __launch_bounds__(NW * 64, MINB) void k_mlp(RowSource src, NetView ne
     wo[ct][1] = ww.y;
     wo[ct][2] = ww.z;
     wo[ct][3] = ww.w;
-#pragma unroll
-    for (int v = 0; v < 6; ++v) {  // 24 consecutive floats W0s[n0 .. n0+3][0 .. 5]
-      const float4 q = *(const float4*)(net.W0s + n0 * 6 + 4 * v);
-      const float e[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-      for (int t = 0; t < 4; ++t) w1[ct][(4 * v + t) / 6][(4 * v + t) % 6] = e[t];
-    }
+    first_layer_a(net.W0s, (wave * CT + ct) * 16 + c, g, w1[ct]);
   }
 
   for (int r = tid; r < R; r += NW * 64) {
@@ -393,19 +404,13 @@ __global__ __launch_bounds__(NW * 64, MINB) void k_mlp(RowSource src, NetView ne
   floatx4 acc[RT][CT];
   float po[RT][CT];     // output layer over the lane's four neurons of a tile
 
-  // ---- first layer (6 -> H), FP32 vector arithmetic in the C layout
+  // ---- first layer (6 -> H) in FP32 on the matrix core, into the C layout
   {
-    float u[RT][6];
+    float u[RT][2];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
-      const float4 p = *(const float4*)&u_s[rt * 16 + c][0];
-      const float2 q = *(const float2*)&u_s[rt * 16 + c][4];
-      u[rt][0] = p.x;
-      u[rt][1] = p.y;
-      u[rt][2] = p.z;
-      u[rt][3] = p.w;
-      u[rt][4] = q.x;
-      u[rt][5] = q.y;
+      u[rt][0] = u_s[rt * 16 + c][g];
+      u[rt][1] = u_s[rt * 16 + c][4 + g];
     }
     T* out_act = act[0];
 #pragma unroll
@@ -413,13 +418,11 @@ __global__ __launch_bounds__(NW * 64, MINB) void k_mlp(RowSource src, NetView ne
       const int n0 = (wave * CT + ct) * 16 + 4 * g;
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt) {
+        const floatx4 z = first_layer_mma(w1[ct], u[rt], b1[ct]);
         float av[4], dv[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          float z = b1[ct][i];
-#pragma unroll
-          for (int a = 0; a < 6; ++a) z = fmaf(w1[ct][i][a], u[rt][a], z);
-          tanh_scaled(z, av[i], dv[i]);
+          tanh_scaled(z[i], av[i], dv[i]);
           if (D == 1) eD[rt][ct][i] = wo[ct][i] * dv[i];
           acc[rt][ct][i] = av[i];
         }

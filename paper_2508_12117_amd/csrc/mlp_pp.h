@@ -125,7 +125,7 @@ __global__ __launch_bounds__(NW * 64, 1) void k_mlp_pp(RowSource src, NetView ne
   WRing<NQ, CT> ring;
   const int s0 = chunk_start<P, CT>(wave, NQ);
   ring_prime<NQ, NQ, CT>(ring, packf, wave, lane, s0);
-  float w1[CT][4][6], b1[CT][4], wo[CT][4];
+  float w1[CT][2], b1[CT][4], wo[CT][4];
 #pragma unroll
   for (int ct = 0; ct < CT; ++ct) {
     const int n0 = (wave * CT + ct) * 16 + 4 * g;
@@ -139,13 +139,7 @@ __global__ __launch_bounds__(NW * 64, 1) void k_mlp_pp(RowSource src, NetView ne
     wo[ct][1] = ww.y;
     wo[ct][2] = ww.z;
     wo[ct][3] = ww.w;
-#pragma unroll
-    for (int v = 0; v < 6; ++v) {
-      const float4 q = *(const float4*)(net.W0s + n0 * 6 + 4 * v);
-      const float e[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-      for (int t = 0; t < 4; ++t) w1[ct][(4 * v + t) / 6][(4 * v + t) % 6] = e[t];
-    }
+    first_layer_a(net.W0s, (wave * CT + ct) * 16 + c, g, w1[ct]);
   }
 
   for (int r = tid; r < R; r += NT) {
@@ -164,31 +158,21 @@ __global__ __launch_bounds__(NW * 64, 1) void k_mlp_pp(RowSource src, NetView ne
   floatx4 acc[RT][CT];
   float eD[RT][CT][4];  // e_1 at the end
   float po[RT][CT];
-  float u[RT][6];
+  float u[RT][2];
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt) {
-    const float4 p = *(const float4*)&u_s[rt * 16 + c][0];
-    const float2 q = *(const float2*)&u_s[rt * 16 + c][4];
-    u[rt][0] = p.x;
-    u[rt][1] = p.y;
-    u[rt][2] = p.z;
-    u[rt][3] = p.w;
-    u[rt][4] = q.x;
-    u[rt][5] = q.y;
+    u[rt][0] = u_s[rt * 16 + c][g];
+    u[rt][1] = u_s[rt * 16 + c][4 + g];
   }
 
   // fragment f of half h: rows 16 (h RH + f / CT) + c, neurons of tile f % CT
   auto n0_of = [&](int f) __attribute__((always_inline)) { return (wave * CT + f % CT) * 16 + 4 * g; };
   auto first_layer = [&](int h, int f) __attribute__((always_inline)) {
     const int rt = h * RH + f / CT, ct = f % CT;
+    const floatx4 z = first_layer_mma(w1[ct], u[rt], b1[ct]);
     float av[4], dv[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      float z = b1[ct][i];
-#pragma unroll
-      for (int a = 0; a < 6; ++a) z = fmaf(w1[ct][i][a], u[rt][a], z);
-      tanh_scaled(z, av[i], dv[i]);
-    }
+    for (int i = 0; i < 4; ++i) tanh_scaled(z[i], av[i], dv[i]);
     dst.set4(0, rt, ct, dv);
     store_row4<T>(act, LDW, SWM, rt * 16 + c, n0_of(f), av);
   };

@@ -230,23 +230,28 @@ __global__ void k_residual(CatView cat, NetView net, int C, int64_t n, const dou
 // the system is block diagonal over (chain, group); each block is solved by
 // Jacobi-preconditioned CG in FP64 by one workgroup.
 
-__global__ void k_group_keys(int C, int64_t n, int M, int L, const BatchBufs b, uint64_t* keys,
+// Sort keys are 32-bit whenever the key range fits (half the sort traffic),
+// else 64-bit.
+template <class K>
+__global__ void k_group_keys(int C, int64_t n, int M, int L, const BatchBufs b, K* keys,
                              uint32_t* vals) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= 2 * (int64_t)C * n) return;
   const int64_t c = (e >> 1) / n;
-  keys[e] = ((uint64_t)(c * L + b.sta[e]) * (uint64_t)M) + (uint64_t)b.ev[e];
+  keys[e] = (K)(((uint64_t)(c * L + b.sta[e]) * (uint64_t)M) + (uint64_t)b.ev[e]);
   vals[e] = (uint32_t)e;
 }
 
-__global__ void k_heads(const uint64_t* keys, int64_t E, int32_t* flags) {
+template <class K>
+__global__ void k_heads(const K* keys, int64_t E, int32_t* flags) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= E) return;
   flags[p] = (p == 0 || keys[p] != keys[p - 1]) ? 1 : 0;
 }
 
 // After an inclusive scan of the head flags (flags -> node number + 1).
-__global__ void k_nodes(const uint64_t* keys, const uint32_t* vals, const int32_t* scan, int64_t E,
+template <class K>
+__global__ void k_nodes(const K* keys, const uint32_t* vals, const int32_t* scan, int64_t E,
                         int M, int32_t* node_of, int32_t* node_start, int32_t* seg_begin,
                         int32_t* seg_end, int32_t* count) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -256,13 +261,13 @@ __global__ void k_nodes(const uint64_t* keys, const uint32_t* vals, const int32_
   const bool head = p == 0 || keys[p] != keys[p - 1];
   if (head) {
     node_start[node] = (int32_t)p;
-    const uint64_t seg = keys[p] / (uint64_t)M;
-    if (p == 0 || keys[p - 1] / (uint64_t)M != seg) seg_begin[seg] = node;
+    const K seg = keys[p] / (K)M;
+    if (p == 0 || keys[p - 1] / (K)M != seg) seg_begin[seg] = node;
   }
   const bool tail = p == E - 1 || keys[p + 1] != keys[p];
   if (tail) {
-    const uint64_t seg = keys[p] / (uint64_t)M;
-    if (p == E - 1 || keys[p + 1] / (uint64_t)M != seg) seg_end[seg] = node + 1;
+    const K seg = keys[p] / (K)M;
+    if (p == E - 1 || keys[p + 1] / (K)M != seg) seg_end[seg] = node + 1;
   }
   if (p == E - 1) {
     node_start[node + 1] = (int32_t)E;
@@ -583,20 +588,22 @@ __global__ void k_exact_z(int64_t Q, double s2, const double* w, const double* r
 
 // ---- per-event reduction
 
-__global__ void k_event_keys(int C, int64_t n, int M, const BatchBufs b, uint64_t* keys,
+template <class K>
+__global__ void k_event_keys(int C, int64_t n, int M, const BatchBufs b, K* keys,
                              uint32_t* vals) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= 2 * (int64_t)C * n) return;
   const int64_t c = (e >> 1) / n;
-  keys[e] = (uint64_t)c * (uint64_t)M + (uint64_t)b.ev[e];
+  keys[e] = (K)((uint64_t)c * (uint64_t)M + (uint64_t)b.ev[e]);
   vals[e] = (uint32_t)e;
 }
 
-__global__ void k_reduce_runs(const uint64_t* keys, const uint32_t* vals, int64_t E, double scale,
+template <class K>
+__global__ void k_reduce_runs(const K* keys, const uint32_t* vals, int64_t E, double scale,
                               const BatchBufs b, double* G) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= E) return;
-  const uint64_t key = keys[p];
+  const K key = keys[p];
   if (p > 0 && keys[p - 1] == key) return;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   for (int64_t q = p; q < E && keys[q] == key; ++q) {
@@ -607,7 +614,7 @@ __global__ void k_reduce_runs(const uint64_t* keys, const uint32_t* vals, int64_
     s2 += cz * b.gT[e * 3 + 2];
     s3 += cz;
   }
-  double* g = G + key * 4;
+  double* g = G + (uint64_t)key * 4;
   g[0] = s0;
   g[1] = s1;
   g[2] = s2;
@@ -910,10 +917,14 @@ void launch_residual(const CatView& cat, const NetView& net, int C, int64_t n,
 }
 
 size_t sort_temp_bytes(int64_t entries) {
-  size_t bytes = 0;
+  size_t bytes = 0, bytes32 = 0;
   (void)rocprim::radix_sort_pairs(nullptr, bytes, (uint64_t*)nullptr, (uint64_t*)nullptr,
                             (uint32_t*)nullptr, (uint32_t*)nullptr, (size_t)entries, 0, 64,
                             (hipStream_t)0);
+  (void)rocprim::radix_sort_pairs(nullptr, bytes32, (uint32_t*)nullptr, (uint32_t*)nullptr,
+                            (uint32_t*)nullptr, (uint32_t*)nullptr, (size_t)entries, 0, 32,
+                            (hipStream_t)0);
+  if (bytes32 > bytes) bytes = bytes32;
   size_t scan = 0;
   (void)rocprim::inclusive_scan(nullptr, scan, (int32_t*)nullptr, (int32_t*)nullptr, (size_t)entries,
                           rocprim::plus<int32_t>(), (hipStream_t)0);
@@ -926,18 +937,22 @@ static int bits_for(uint64_t maxval) {
   return b;
 }
 
-hipError_t exact_whiten(const CatView& cat, int C, int64_t n, BatchBufs b, SortBufs sb,
-                        hipStream_t s) {
+// Entries sorted by (chain, group, event) with K-bit keys; runs of equal keys
+// become the nodes of the (chain, group) systems: node_of per entry,
+// node_start, the node range of every (chain, group) and the node count.
+template <class K>
+hipError_t group_nodes(int C, int64_t n, const CatView& cat, const BatchBufs& b,
+                       const SortBufs& sb, int end_bit, hipStream_t s) {
   const int64_t E = 2 * (int64_t)C * n;
-  if (E <= 0) return hipSuccess;  // the node kernels read the node count k_nodes writes
-  const int end_bit = bits_for((uint64_t)C * cat.L * (uint64_t)cat.M);
-  hipLaunchKernelGGL(k_group_keys, dim3(grid_for(E)), dim3(kBlock), 0, s, C, n, cat.M, cat.L, b,
-                     sb.key_in, sb.val_in);
+  K* key_in = (K*)sb.key_in;
+  K* key_out = (K*)sb.key_out;
+  hipLaunchKernelGGL(k_group_keys<K>, dim3(grid_for(E)), dim3(kBlock), 0, s, C, n, cat.M, cat.L,
+                     b, key_in, sb.val_in);
   size_t tb = sb.temp_bytes;
-  hipError_t e = rocprim::radix_sort_pairs(sb.temp, tb, sb.key_in, sb.key_out, sb.val_in,
-                                           sb.val_out, (size_t)E, 0, end_bit, s);
+  hipError_t e = rocprim::radix_sort_pairs(sb.temp, tb, key_in, key_out, sb.val_in, sb.val_out,
+                                           (size_t)E, 0, end_bit, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_heads, dim3(grid_for(E)), dim3(kBlock), 0, s, sb.key_out, E, sb.flags);
+  hipLaunchKernelGGL(k_heads<K>, dim3(grid_for(E)), dim3(kBlock), 0, s, key_out, E, sb.flags);
   int32_t* scan = (int32_t*)sb.key_in;  // key_in is free after the sort
   tb = sb.temp_bytes;
   e = rocprim::inclusive_scan(sb.temp, tb, sb.flags, scan, (size_t)E, rocprim::plus<int32_t>(), s);
@@ -946,8 +961,19 @@ hipError_t exact_whiten(const CatView& cat, int C, int64_t n, BatchBufs b, SortB
                      sb.seg_begin, 0, (int64_t)C * cat.L);
   hipLaunchKernelGGL(k_fill_i32, dim3(grid_for((int64_t)C * cat.L)), dim3(kBlock), 0, s,
                      sb.seg_end, 0, (int64_t)C * cat.L);
-  hipLaunchKernelGGL(k_nodes, dim3(grid_for(E)), dim3(kBlock), 0, s, sb.key_out, sb.val_out, scan,
+  hipLaunchKernelGGL(k_nodes<K>, dim3(grid_for(E)), dim3(kBlock), 0, s, key_out, sb.val_out, scan,
                      E, cat.M, sb.node_of, sb.node_start, sb.seg_begin, sb.seg_end, sb.count);
+  return hipGetLastError();
+}
+
+hipError_t exact_whiten(const CatView& cat, int C, int64_t n, BatchBufs b, SortBufs sb,
+                        hipStream_t s) {
+  const int64_t E = 2 * (int64_t)C * n;
+  if (E <= 0) return hipSuccess;  // the node kernels read the node count k_nodes writes
+  const int end_bit = bits_for((uint64_t)C * cat.L * (uint64_t)cat.M - 1);
+  hipError_t e = end_bit <= 32 ? group_nodes<uint32_t>(C, n, cat, b, sb, end_bit, s)
+                               : group_nodes<uint64_t>(C, n, cat, b, sb, end_bit, s);
+  if (e != hipSuccess) return e;
   // key_in and key_out are free after k_nodes; vec slot 7 is unused by the
   // solver, and slot 4 (the CG residual, written only later) holds the
   // right-hand-side terms until k_node_init has summed them
@@ -993,21 +1019,32 @@ hipError_t exact_whiten(const CatView& cat, int C, int64_t n, BatchBufs b, SortB
   return hipGetLastError();
 }
 
-hipError_t reduce_events(const CatView& cat, int C, int64_t n, double scale, BatchBufs b,
-                         SortBufs sb, double* G, hipStream_t s) {
+// Entries sorted by (chain, event) with K-bit keys; the first entry of each
+// run sums the run in entry order into G[chain][event].
+template <class K>
+hipError_t event_runs(int C, int64_t n, const CatView& cat, double scale, const BatchBufs& b,
+                      const SortBufs& sb, double* G, int end_bit, hipStream_t s) {
   const int64_t E = 2 * (int64_t)C * n;
-  const int end_bit = bits_for((uint64_t)C * (uint64_t)cat.M);
-  hipLaunchKernelGGL(k_event_keys, dim3(grid_for(E)), dim3(kBlock), 0, s, C, n, cat.M, b,
-                     sb.key_in, sb.val_in);
+  K* key_in = (K*)sb.key_in;
+  K* key_out = (K*)sb.key_out;
+  hipLaunchKernelGGL(k_event_keys<K>, dim3(grid_for(E)), dim3(kBlock), 0, s, C, n, cat.M, b,
+                     key_in, sb.val_in);
   size_t tb = sb.temp_bytes;
-  hipError_t e = rocprim::radix_sort_pairs(sb.temp, tb, sb.key_in, sb.key_out, sb.val_in,
-                                           sb.val_out, (size_t)E, 0, end_bit, s);
+  hipError_t e = rocprim::radix_sort_pairs(sb.temp, tb, key_in, key_out, sb.val_in, sb.val_out,
+                                           (size_t)E, 0, end_bit, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_fill, dim3(grid_for((int64_t)C * cat.M * 4)), dim3(kBlock), 0, s, G, 0.0,
                      (int64_t)C * cat.M * 4);
-  hipLaunchKernelGGL(k_reduce_runs, dim3(grid_for(E)), dim3(kBlock), 0, s, sb.key_out, sb.val_out,
-                     E, scale, b, G);
+  hipLaunchKernelGGL(k_reduce_runs<K>, dim3(grid_for(E)), dim3(kBlock), 0, s, key_out,
+                     sb.val_out, E, scale, b, G);
   return hipGetLastError();
+}
+
+hipError_t reduce_events(const CatView& cat, int C, int64_t n, double scale, BatchBufs b,
+                         SortBufs sb, double* G, hipStream_t s) {
+  const int end_bit = bits_for((uint64_t)C * (uint64_t)cat.M - 1);
+  return end_bit <= 32 ? event_runs<uint32_t>(C, n, cat, scale, b, sb, G, end_bit, s)
+                       : event_runs<uint64_t>(C, n, cat, scale, b, sb, G, end_bit, s);
 }
 
 void launch_centroid(const double* theta, int C, int M, double* partial, double* thetabar,
