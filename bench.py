@@ -32,10 +32,10 @@ HBM_PEAK = 8000.0                             # GB/s
 NETWORK_TRAFFIC = {
     "kernel_sources": ["paper_2508_12117_amd/csrc/mlp_mfma.h", "paper_2508_12117_amd/csrc/mlp_pp.h",
                        "paper_2508_12117_amd/csrc/internal.h"],
-    "sha256": "cde6a0defdc0e61ba202d72d79c584fa2c3687ebb119d136264796c824ef234e",
+    "sha256": "71474217cc01cb5353db69a3a4c100ed3eef6502dc7371d16d03e8a9322c5118",
     "variant": {"waves": 8, "row_tiles": 4, "schedule": 1},
     "rows": 16777216,
-    "fetch_bytes": 1542885354,
+    "fetch_bytes": 1542890219,
     "write_bytes": 268435456,
 }
 
