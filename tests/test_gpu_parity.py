@@ -485,7 +485,7 @@ def test_bf16_sampler_runs_and_is_deterministic(ctx, tiny_setup):
     assert np.abs(outs[0] - cat.hypo0).max() > 0
 
 
-@pytest.mark.parametrize("H,D", [(256, 6), (128, 4), (256, 8)])
+@pytest.mark.parametrize("H,D", [(256, 6), (128, 4), (256, 8), (256, 4)])
 @pytest.mark.parametrize("prec", [spider.BF16, spider.FP32])
 def test_kernel_variants_agree_bitwise(ctx, monkeypatch, H, D, prec):
     """Every tile variant the autotuner may pick computes the same bits."""
