@@ -216,23 +216,35 @@ typedef struct {
   double beta2;             /* pSGLD second-moment decay, in [0, 1]           */
   double eps_p;             /* pSGLD epsilon in V = 1/(sqrt(v) + eps_p), > 0  */
   double noise_scale;       /* a: multiplies the injected noise (1 sampling,
-                               0 noise off, ramps in between)                 */
+                               0 noise off: the warm-up stage of Sec. 3.2),
+                               >= 0                                           */
   int32_t precond;          /* 0: SGLD  theta += eps g + a sqrt(2 eps) eta
                                1: pSGLD v = b2 v + (1-b2) g*g;
                                   V = 1/(sqrt(v)+eps_p);
                                   theta += eps V g + a sqrt(2 eps V) eta      */
-  int32_t reserved;
+  int32_t noise_ramp;       /* 0: a = noise_scale at every step of the call;
+                               1: a rises linearly over the call (the ramp
+                               stage of Sec. 3.2): step k = 0 .. n_steps-1
+                               of the call uses a = noise_scale +
+                               (noise_scale_end - noise_scale) k / n_steps    */
   int64_t n_steps;          /* steps to run, >= 0                             */
   int64_t burn_in;          /* after the update of global step t, theta enters
                                the moments iff t >= burn_in and
                                (t - burn_in) % thin == 0                      */
   int64_t thin;             /* >= 1                                           */
   uint64_t seed;            /* keys the batch and noise streams               */
+  double noise_scale_end;   /* with noise_ramp = 1: the amplitude the ramp
+                               reaches after the call, >= 0                   */
 } spider_sgld_cfg;
 
 /* Advance every chain of every set by cfg->n_steps steps.  Each step uses
  * the chain's global step counter for its batch and noise, so a run split
- * over calls equals one uninterrupted run.  Chains are created on first use
+ * over calls equals one uninterrupted run (a ramp of the noise amplitude
+ * is defined per call, so a split ramp passes the matching amplitudes to
+ * each part).  The paper's schedule after its first stage is three calls:
+ * warm-up with noise_scale 0, the ramp 0 -> 1, then sampling with
+ * noise_scale 1 and burn_in at the first sampling step.  Chains are created
+ * on first use
  * if the catalog has fewer.  After the last step every state is checked for
  * finite values: SPIDER_E_NUMERIC names the catalog and chain otherwise
  * (this waits for the stream).  When there are several sets, all with the

@@ -9,6 +9,9 @@ Step t of chain c (theta_t -> theta_{t+1}):
              theta += eps V_t * g_t + a sqrt(2 eps V_t) * eta      (eq:pSGLD)
      V is diagonal and used elementwise, v starts at 0, no bias correction.
      a is the noise scale (1 while sampling; 0 turns the noise off).
+Stages after the initial solution (Sec. 3.2): a warm-up with the injected
+noise off, a linear ramp of the noise from zero to full amplitude, then
+sampling at full amplitude; stage_noise_scales gives a per step.
   4. after the update of step t, if t >= burn and (t - burn) % thin == 0,
      theta_{t+1} enters the per-event running mean and covariance (Welford).
 No Metropolis-Hastings correction (Sec. 3.2).
@@ -128,12 +131,22 @@ def step(prob, net, chain: Chain, cfg: SamplerConfig, stream: int, chain_id: int
     return lp
 
 
+def stage_noise_scales(warmup: int, ramp: int, sample: int) -> np.ndarray:
+    """Noise amplitude a of each step of the staged schedule: 0 during the
+    warm-up, k / ramp at step k = 0 .. ramp-1 of the ramp (rising from zero
+    toward full amplitude), 1 while sampling."""
+    return np.concatenate([np.zeros(warmup), np.arange(ramp) / max(ramp, 1), np.ones(sample)])
+
+
 def run(prob, net, cfg: SamplerConfig, n: int, steps: int, stream: int = 0, chain_id: int = 0,
-        chain: Chain | None = None, keep_states=False):
+        chain: Chain | None = None, keep_states=False, noise_scales=None):
+    """`steps` steps of one chain; noise_scales (one per step) overrides
+    cfg.noise_scale step by step."""
     chain = new_chain(prob) if chain is None else chain
     states = []
-    for _ in range(steps):
-        step(prob, net, chain, cfg, stream, chain_id, n)
+    for k in range(steps):
+        c = cfg if noise_scales is None else dataclasses.replace(cfg, noise_scale=float(noise_scales[k]))
+        step(prob, net, chain, c, stream, chain_id, n)
         if keep_states:
             states.append(chain.theta.copy())
     return chain, states

@@ -933,6 +933,12 @@ int spider_reset_chains(spider_ctx* ctx, int32_t cat_id, int32_t n_chains) {
   return SPIDER_OK;
 }
 
+// Noise amplitude of step k of a call (constant, or the linear ramp).
+static double noise_at(const spider_sgld_cfg& cfg, int64_t k) {
+  if (cfg.noise_ramp == 0) return cfg.noise_scale;
+  return cfg.noise_scale + (cfg.noise_scale_end - cfg.noise_scale) * ((double)k / (double)cfg.n_steps);
+}
+
 int spider_sgld_steps(spider_ctx* ctx, const spider_chainset* sets, int32_t n_sets,
                       const spider_sgld_cfg* cfg) {
   if (!ctx) return SPIDER_E_INVALID;
@@ -940,7 +946,9 @@ int spider_sgld_steps(spider_ctx* ctx, const spider_chainset* sets, int32_t n_se
   if (!sets || n_sets < 1 || !cfg) return fail(ctx, SPIDER_E_INVALID, "null or empty arguments");
   if (!(cfg->step > 0) || !(cfg->beta2 >= 0 && cfg->beta2 <= 1) || !(cfg->eps_p > 0) ||
       !std::isfinite(cfg->noise_scale) || cfg->noise_scale < 0 || cfg->n_steps < 0 ||
-      cfg->burn_in < 0 || cfg->thin < 1 || (cfg->precond != 0 && cfg->precond != 1))
+      cfg->burn_in < 0 || cfg->thin < 1 || (cfg->precond != 0 && cfg->precond != 1) ||
+      (cfg->noise_ramp != 0 && cfg->noise_ramp != 1) ||
+      (cfg->noise_ramp == 1 && !(std::isfinite(cfg->noise_scale_end) && cfg->noise_scale_end >= 0)))
     return fail(ctx, SPIDER_E_INVALID, "invalid sampler configuration");
   for (int k = 0; k < n_sets; ++k) {
     const spider_chainset& st = sets[k];
@@ -979,11 +987,13 @@ int spider_sgld_steps(spider_ctx* ctx, const spider_chainset* sets, int32_t n_se
     rc = prepare_fused(ctx, sets, n_sets, f);
     if (rc) return rc;
     for (int64_t t = 0; t < cfg->n_steps; ++t) {
+      ua.noise_scale = noise_at(*cfg, t);
       rc = fused_step(ctx, sets, n_sets, f, ua);
       if (rc) return rc;
     }
   }
   for (int64_t t = 0; t < (fuse ? 0 : cfg->n_steps); ++t) {
+    ua.noise_scale = noise_at(*cfg, t);
     for (int k = 0; k < n_sets; ++k) {
       const spider_chainset& st = sets[k];
       Catalog& cat = *get_cat(ctx, st.cat_id);

@@ -60,9 +60,9 @@ class ChainSet(ct.Structure):
 
 class SgldCfg(ct.Structure):
     _fields_ = [("step", ct.c_double), ("beta2", ct.c_double), ("eps_p", ct.c_double),
-                ("noise_scale", ct.c_double), ("precond", ct.c_int32), ("reserved", ct.c_int32),
+                ("noise_scale", ct.c_double), ("precond", ct.c_int32), ("noise_ramp", ct.c_int32),
                 ("n_steps", ct.c_int64), ("burn_in", ct.c_int64), ("thin", ct.c_int64),
-                ("seed", ct.c_uint64)]
+                ("seed", ct.c_uint64), ("noise_scale_end", ct.c_double)]
 
 
 _P = ct.c_void_p
@@ -264,16 +264,38 @@ class Context:
         self._check(lib().spider_reset_chains(self._h, cat_id, n_chains))
 
     def sgld_steps(self, sets, n_steps, step=1e-4, beta2=0.99, eps_p=1e-5, noise_scale=1.0,
-                   precond=1, burn_in=0, thin=1, seed=0):
-        """sets: list of (cat_id, net_id, n_chains, batch, precision)."""
+                   precond=1, burn_in=0, thin=1, seed=0, noise_scale_end=None):
+        """sets: list of (cat_id, net_id, n_chains, batch, precision).  With
+        noise_scale_end the noise amplitude ramps linearly from noise_scale
+        over the call (step k uses noise_scale + (end - noise_scale) k / n_steps)."""
         arr = (ChainSet * len(sets))()
         for k, (cid, nid, C, n, prec) in enumerate(sets):
             arr[k].cat_id, arr[k].net_id, arr[k].n_chains = cid, nid, C
             arr[k].precision, arr[k].batch = prec, n
+        ramp = noise_scale_end is not None
         cfg = SgldCfg(step=step, beta2=beta2, eps_p=eps_p, noise_scale=noise_scale,
-                      precond=precond, reserved=0, n_steps=n_steps, burn_in=burn_in, thin=thin,
-                      seed=seed)
+                      precond=precond, noise_ramp=1 if ramp else 0, n_steps=n_steps,
+                      burn_in=burn_in, thin=thin, seed=seed,
+                      noise_scale_end=noise_scale_end if ramp else 0.0)
         self._check(lib().spider_sgld_steps(self._h, arr, len(sets), ct.byref(cfg)))
+
+    def sgld_stages(self, sets, warmup, ramp, sample, thin=1, **kw):
+        """The sampler stages that follow the initial solution (Sec. 3.2):
+        `warmup` steps with the injected noise off, `ramp` steps raising it
+        linearly to full amplitude, `sample` steps at full amplitude whose
+        states enter the posterior moments (every `thin`-th)."""
+        try:
+            t0 = self.get_state(sets[0][0], 0)
+        except SpiderError:  # no chains yet: they start at step 0
+            t0 = 0
+        burn = t0 + warmup + ramp  # global step of the first sample
+        if warmup > 0:
+            self.sgld_steps(sets, warmup, noise_scale=0.0, burn_in=burn, thin=thin, **kw)
+        if ramp > 0:
+            self.sgld_steps(sets, ramp, noise_scale=0.0, noise_scale_end=1.0, burn_in=burn,
+                            thin=thin, **kw)
+        if sample > 0:
+            self.sgld_steps(sets, sample, noise_scale=1.0, burn_in=burn, thin=thin, **kw)
 
     def moments(self, cat_id, chain, mean, cov):
         cnt = ct.c_int64()

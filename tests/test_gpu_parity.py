@@ -312,6 +312,50 @@ def test_sgld_one_step_transition(ctx, tiny_setup, t):
     _one_step_check(ctx, cat, net, nid, 0, t, 17)
 
 
+def test_staged_schedule_matches_oracle(ctx, tiny_setup):
+    """Warm-up with the noise off, a linear noise ramp, then sampling (Sec. 3.2):
+    40 + 40 + 120 steps, moments from the first sampling step, against the
+    oracle's run of the same schedule, with the 200-step trajectory test's
+    tolerances."""
+    cat, net, _, nid = tiny_setup
+    cid = ctx.load_catalog(cat, whiten=spider.WHITEN_EXACT, stream_id=3)
+    ctx.reset_chains(cid, 1)
+    ctx.sgld_stages([(cid, nid, 1, 1024, spider.FP32)], 40, 40, 120, thin=1, seed=29)
+    mean = torch.empty(cat.M, 4, dtype=torch.float64, device="cuda")
+    cov = torch.empty(cat.M, 10, dtype=torch.float64, device="cuda")
+    cnt = ctx.moments(cid, 0, mean, cov)
+    assert cnt == 120
+    prob = lk.load(cat)
+    cfg = sampler.SamplerConfig(step=1e-4, seed=29, burn_in=80, thin=1)
+    ch, _ = sampler.run(prob, net, cfg, 1024, 200, stream=3,
+                        noise_scales=sampler.stage_noise_scales(40, 40, 120))
+    assert ch.mom.count == 120
+    sd = np.sqrt(sampler.covariance(ch.mom)[:, [0, 4, 7, 9]])
+    err = np.abs(host(mean) - ch.mom.mean) / sd
+    assert err.max() < 5e-2 and np.median(err) < 1e-4
+
+
+def test_noise_ramp_steps(ctx, tiny_setup):
+    """Step k of a ramp call uses a = a0 + (a1 - a0) k / n_steps: a two-step
+    ramp 0 -> 1 equals a step at a = 0 followed by a step at a = 0.5."""
+    cat, net, _, nid = tiny_setup
+    cid = ctx.load_catalog(cat, stream_id=3)
+    out = []
+    for calls in ([(2, 0.0, 1.0)], [(1, 0.0, None), (1, 0.5, None)]):
+        ctx.reset_chains(cid, 2)
+        for n, a0, a1 in calls:
+            ctx.sgld_steps([(cid, nid, 2, 1024, spider.FP32)], n, seed=13, noise_scale=a0,
+                           noise_scale_end=a1)
+        th = torch.empty(2, cat.M, 4, dtype=torch.float64, device="cuda")
+        ctx.get_state(cid, 0, th[0])
+        ctx.get_state(cid, 1, th[1])
+        out.append(host(th))
+    assert np.array_equal(out[0], out[1])
+    with pytest.raises(spider.SpiderError):
+        ctx.sgld_steps([(cid, nid, 1, 1024, spider.FP32)], 1, noise_scale=0.0,
+                       noise_scale_end=float("nan"))
+
+
 def test_sgld_is_deterministic_and_resumable(ctx, tiny_setup):
     cat, net, _, nid = tiny_setup
     outs = []

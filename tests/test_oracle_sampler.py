@@ -147,3 +147,39 @@ def test_psgld_update_tolerance_bounds_gradient_errors():
         th1, v1 = sampler.update(theta, v, G + dG * rng.uniform(-1, 1, G.shape), cfg, eta)
         assert np.all(np.abs(th1 - th0) <= tol_th)
         assert np.all(np.abs(v1 - v0) <= tol_v)
+
+
+def test_stage_noise_scales():
+    """Warm-up with the noise off, a linear ramp from zero, then full amplitude (Sec. 3.2)."""
+    a = sampler.stage_noise_scales(3, 4, 2)
+    np.testing.assert_array_equal(a, [0, 0, 0, 0, 0.25, 0.5, 0.75, 1, 1])
+    assert sampler.stage_noise_scales(0, 0, 5).tolist() == [1.0] * 5
+
+
+def test_noise_off_finds_the_mode():
+    """With the injected noise off (the warm-up stage) pSGLD is preconditioned
+    gradient ascent: on a Gaussian target it converges to the mean."""
+    lam = np.array([2.0, 10.0, 50.0])
+    P = np.diag(lam)
+    mu = np.array([1.0, -2.0, 0.5])
+    cfg = sampler.SamplerConfig(step=1e-3, precond=1, noise_scale=0.0)
+    theta, v = mu + np.array([3.0, -1.0, 2.0]), np.zeros(3)
+    for _ in range(20000):
+        theta, v = sampler.update(theta, v, -P @ (theta - mu), cfg, np.ones(3))
+    np.testing.assert_allclose(theta, mu, atol=1e-8)
+
+
+def test_noise_scale_scales_the_stationary_covariance():
+    """SGLD with noise amplitude a on N(mu, P^-1): the discrete chain's
+    stationary covariance is a^2 (P (I - eps P / 2))^{-1}."""
+    lam = np.array([1.0, 4.0, 20.0])
+    P = np.diag(lam)
+    mu = np.zeros(3)
+    eps = 0.02
+    cfg = sampler.SamplerConfig(step=eps, precond=0, noise_scale=0.5)
+    x = _gaussian_run(P, mu, cfg, 200_000, seed=7)[1000:]
+    want = 0.25 / (lam * (1 - eps * lam / 2))
+    se = _batch_means_se((x - mu) ** 2)
+    assert np.all(np.abs(x.var(0) - want) < 5 * se + 1e-5)
+    # and not the a = 1 covariance
+    assert np.all(np.abs(x.var(0) - 4 * want) > 10 * se)
