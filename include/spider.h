@@ -62,7 +62,7 @@ enum { SPIDER_WHITEN_NONE = 0, SPIDER_WHITEN_DIAG = 1, SPIDER_WHITEN_EXACT = 2 }
  * assembly, residuals, whitening, gradient and state are FP32/FP64 in both. */
 enum { SPIDER_FP32 = 0, SPIDER_BF16 = 1 };
 /* spider_grad flags */
-enum { SPIDER_GRAD_PRIOR = 1, SPIDER_GRAD_CENTROID = 2 };
+enum { SPIDER_GRAD_PRIOR = 1, SPIDER_GRAD_CENTROID = 2, SPIDER_GRAD_L1 = 4 };
 
 #define SPIDER_MAX_LAYERS 16
 
@@ -162,10 +162,14 @@ int spider_travel_time(spider_ctx* ctx, int32_t net_id, int32_t precision,
  * minibatch `step` of chain `chain` under `seed` (see spider_batch_indices).
  * flags: SPIDER_GRAD_PRIOR adds -(theta - hypo0)/prior_sigma^2,
  * SPIDER_GRAD_CENTROID adds -(mean(theta) - mu_c)/(M centroid_sigma^2) to
- * every event (Sec. 3.1).  grad_out: device [M][4] (events outside the
- * batch get only the prior terms).  logpost_out: device [1] or NULL:
- * -(N/n)/2 r^T z + log priors, up to an additive constant.
- * Errors: SPIDER_E_INVALID (ids, n < 1, n > N without batch_idx). */
+ * every event (Sec. 3.1).  SPIDER_GRAD_L1 replaces the likelihood term by
+ * the negative gradient of the Stage 1 loss (eq:stage1loss with the L1
+ * norm, Sec. 3.2), L = (1/n) sum_{k<n} |r_k|: (1/n) sum_k sign(r_k)
+ * (d tau^_k / d theta), and logpost_out then holds -L + log priors.
+ * grad_out: device [M][4] (events outside the batch get only the prior
+ * terms).  logpost_out: device [1] or NULL: -(N/n)/2 r^T z + log priors, up
+ * to an additive constant.  Errors: SPIDER_E_INVALID (ids, n < 1, n > N
+ * without batch_idx, unknown flags). */
 int spider_grad(spider_ctx* ctx, int32_t cat_id, int32_t net_id, int32_t precision,
                 const double* theta, const int64_t* batch_idx, int64_t n,
                 uint64_t seed, int32_t chain, int64_t step, uint32_t flags,
@@ -254,6 +258,30 @@ typedef struct {
  * SPIDER_E_INVALID, SPIDER_E_NUMERIC, SPIDER_E_OOM, SPIDER_E_HIP. */
 int spider_sgld_steps(spider_ctx* ctx, const spider_chainset* sets, int32_t n_sets,
                       const spider_sgld_cfg* cfg);
+
+/* ---- Stage 1: a robust initial solution (Sec. 3.2, eq:stage1loss) -----
+ * Minimises the L1 loss of the dd residuals, L = (1/n) sum_{k<n} |r_k| over
+ * each chain's minibatch, with Adam and no priors, starting from the chains'
+ * current states.  Step t of chain c uses the sampler's minibatch of (seed,
+ * catalog stream, c, t) and the bias correction of Adam step k = t + 1 (t =
+ * the chain's step counter): with g = -(1/n) sum_k sign(r_k) dtau^_k/dtheta,
+ * m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ * theta -= lr (m / (1 - b1^k)) / (sqrt(v / (1 - b2^k)) + eps).
+ * m and v start at zero after spider_reset_chains; the step counters
+ * advance (the sampler stages continue the same minibatch stream) and no
+ * moments are recorded.  Non-finite states are reported as by
+ * spider_sgld_steps.  Errors: SPIDER_E_INVALID, SPIDER_E_NUMERIC,
+ * SPIDER_E_OOM, SPIDER_E_HIP. */
+typedef struct {
+  double lr;                /* Adam learning rate (Table 1: 1e-3, 1e-4), > 0  */
+  double beta1;             /* first-moment decay, in [0, 1) (0.9)            */
+  double beta2;             /* second-moment decay, in [0, 1) (0.999)         */
+  double eps;               /* > 0 (1e-8)                                     */
+  int64_t n_steps;          /* steps to run, >= 0                             */
+  uint64_t seed;            /* keys the batch stream                          */
+} spider_map_cfg;
+int spider_map_steps(spider_ctx* ctx, const spider_chainset* sets, int32_t n_sets,
+                     const spider_map_cfg* cfg);
 
 /* Posterior moments (Sec. 3.4) of a catalog: chain >= 0 for one chain, -1
  * for all chains pooled (pairwise combination of Chan, Golub and LeVeque).

@@ -36,6 +36,7 @@ import scipy.sparse.linalg as spla
 from .travel_time import travel_time
 
 WHITEN_NONE, WHITEN_DIAG, WHITEN_EXACT = 0, 1, 2
+L1 = 3  # not a whitening: z = sign(r), the derivative of |r| (Stage 1 loss)
 
 
 @dataclasses.dataclass
@@ -140,6 +141,8 @@ def residuals(T_i, T_j, t_i, t_j, tau):
 def whiten(r, w, group, ev_i, ev_j, M, sigma, kappa, mode):
     """z = Sigma_B^{-1} r for the minibatch's observations."""
     s2 = sigma * sigma
+    if mode == L1:
+        return np.sign(r)
     if mode == WHITEN_NONE or kappa == 0.0:
         return r / s2
     if mode == WHITEN_DIAG:

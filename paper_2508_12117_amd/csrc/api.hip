@@ -58,6 +58,8 @@ struct Catalog {
   DevBuf hypo0, stations, pairs, w_pair, obs, inv_mean, mu_c;
   int C = 0;  // chains allocated
   DevBuf theta, v, mean, m2, steps, mcount;
+  DevBuf adam_m, adam_v;      // Stage 1 optimiser moments, allocated on first use
+  bool adam_zeroed = false;   // cleared by spider_reset_chains
 
   CatView view() const {
     CatView c;
@@ -366,10 +368,12 @@ void clear_profile(spider_ctx* ctx) {
 }
 
 // One minibatch for C chains: selection, network, residuals, whitening and
-// (if G) the scaled per-event likelihood gradient into ws.G.
+// (if G) the scaled per-event likelihood gradient into ws.G.  With l1, z is
+// sign(r) instead of the whitened residual (the Stage 1 loss).
 int run_batch(spider_ctx* ctx, Catalog& cat, Net& net, int prec, int C, int64_t n,
               const double* theta, int64_t theta_stride, const int64_t* idx, uint64_t seed,
-              const int64_t* steps_dev, int64_t step_scalar, int chain0, bool grad, double scale) {
+              const int64_t* steps_dev, int64_t step_scalar, int chain0, bool grad, double scale,
+              bool l1 = false) {
   Workspace& ws = ctx->ws;
   const int64_t Cn = (int64_t)C * n;
   HIPCK(ws.reserve(C, Cn, (int64_t)C * cat.M, (int64_t)C * cat.L), "workspace");
@@ -391,7 +395,7 @@ int run_batch(spider_ctx* ctx, Catalog& cat, Net& net, int prec, int C, int64_t 
   src.s = nullptr;
   int rc = run_network(ctx, net, prec, src, b.net_out);
   if (rc != SPIDER_OK) return rc;
-  const int whiten = cat.kappa == 0.0 ? SPIDER_WHITEN_NONE : cat.whiten;
+  const int whiten = l1 ? kWhitenL1 : cat.kappa == 0.0 ? SPIDER_WHITEN_NONE : cat.whiten;
   launch_residual(cv, net.view(prec), C, n, theta, theta_stride, whiten, b, ctx->stream);
   if (whiten == SPIDER_WHITEN_EXACT)
     HIPCK(exact_whiten(cv, C, n, b, ws.sort(), ctx->stream), "exact whitening");
@@ -811,7 +815,8 @@ int spider_travel_time(spider_ctx* ctx, int32_t net_id, int32_t precision, const
 
 static int grad_common(spider_ctx* ctx, int32_t cat_id, int32_t net_id, int32_t precision,
                        const double* theta, const int64_t* batch_idx, int64_t n, uint64_t seed,
-                       int32_t chain, int64_t step, bool grad, Catalog** cat_out, Net** net_out) {
+                       int32_t chain, int64_t step, bool grad, Catalog** cat_out, Net** net_out,
+                       bool l1 = false) {
   Catalog* cat = get_cat(ctx, cat_id);
   Net* net = get_net(ctx, net_id);
   if (!cat) return fail(ctx, SPIDER_E_INVALID, "unknown catalog id");
@@ -825,7 +830,7 @@ static int grad_common(spider_ctx* ctx, int32_t cat_id, int32_t net_id, int32_t 
   int rc = reset_err_flag(ctx);
   if (rc) return rc;
   rc = run_batch(ctx, *cat, *net, precision, 1, n, theta, (int64_t)cat->M * 4, batch_idx, seed,
-                 nullptr, step, chain, grad, (double)cat->N / (double)n);
+                 nullptr, step, chain, grad, l1 ? 1.0 / (double)n : (double)cat->N / (double)n, l1);
   if (rc) return rc;
   *cat_out = cat;
   *net_out = net;
@@ -841,18 +846,22 @@ int spider_grad(spider_ctx* ctx, int32_t cat_id, int32_t net_id, int32_t precisi
   if (!grad_out) return fail(ctx, SPIDER_E_INVALID, "null grad_out");
   Catalog* cat;
   Net* net;
+  if (flags & ~(uint32_t)(SPIDER_GRAD_PRIOR | SPIDER_GRAD_CENTROID | SPIDER_GRAD_L1))
+    return fail(ctx, SPIDER_E_INVALID, "unknown gradient flags");
+  const bool l1 = (flags & SPIDER_GRAD_L1) != 0;
   int rc = grad_common(ctx, cat_id, net_id, precision, theta, batch_idx, n, seed, chain, step,
-                       true, &cat, &net);
+                       true, &cat, &net, l1);
   if (rc) return rc;
   Workspace& ws = ctx->ws;
   const CatView cv = cat->view();
   launch_centroid(theta, 1, cat->M, ws.partial.as<double>(), ws.thetabar.as<double>(), ctx->stream);
   launch_grad_finish(cv, theta, ws.G.as<double>(), ws.thetabar.as<double>(), flags, grad_out,
                      ctx->stream);
+  // L1: -(1/n) sum |r| = -(scale/2) r.z with z = sign(r) and scale = 2/n
   if (logpost_out)
-    launch_logpost(cv, n, (double)cat->N / (double)n, ws.r.as<double>(), ws.z.as<double>(), theta,
-                   ws.thetabar.as<double>(), flags, ws.lp_tmp.as<double>(), logpost_out,
-                   ctx->stream);
+    launch_logpost(cv, n, l1 ? 2.0 / (double)n : (double)cat->N / (double)n, ws.r.as<double>(),
+                   ws.z.as<double>(), theta, ws.thetabar.as<double>(), flags,
+                   ws.lp_tmp.as<double>(), logpost_out, ctx->stream);
   HIPCK(hipGetLastError(), "gradient kernels");
   return check_select_flag(ctx);
 }
@@ -930,6 +939,30 @@ int spider_reset_chains(spider_ctx* ctx, int32_t cat_id, int32_t n_chains) {
   HIPCK(hipMemsetAsync(cat->mcount.p, 0, (size_t)C * 8, ctx->stream), "init chains");
   HIPCK(hipGetLastError(), "init chains");
   cat->C = C;
+  cat->adam_zeroed = false;
+  return SPIDER_OK;
+}
+
+// Numeric check of every chain state of the sets (waits for the stream).
+static int check_finite_states(spider_ctx* ctx, const spider_chainset* sets, int n_sets) {
+  for (int k = 0; k < n_sets; ++k) {
+    const spider_chainset& st = sets[k];
+    Catalog& cat = *get_cat(ctx, st.cat_id);
+    DevBuf bad;
+    HIPCK(bad.alloc(16), "alloc");
+    const int big = INT_MAX;
+    HIPCK(hipMemcpyAsync(bad.p, &big, sizeof(int), hipMemcpyHostToDevice, ctx->stream), "flag");
+    launch_finite(cat.theta.as<double>(), (int64_t)cat.M * 4 * st.n_chains, (int64_t)cat.M * 4,
+                  bad.as<int>(), ctx->stream);
+    int first = INT_MAX;
+    HIPCK(hipMemcpyAsync(&first, bad.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream), "flag");
+    HIPCK(hipStreamSynchronize(ctx->stream), "sync");
+    if (first != INT_MAX) {
+      char msg[160];
+      std::snprintf(msg, sizeof msg, "non-finite state in catalog %d chain %d", st.cat_id, first);
+      return fail(ctx, SPIDER_E_NUMERIC, msg);
+    }
+  }
   return SPIDER_OK;
 }
 
@@ -1012,25 +1045,71 @@ int spider_sgld_steps(spider_ctx* ctx, const spider_chainset* sets, int32_t n_se
       HIPCK(hipGetLastError(), "update");
     }
   }
-  // numeric check of every chain state
+  rc = check_finite_states(ctx, sets, n_sets);
+  if (rc) return rc;
+  return check_select_flag(ctx);
+}
+
+int spider_map_steps(spider_ctx* ctx, const spider_chainset* sets, int32_t n_sets,
+                     const spider_map_cfg* cfg) {
+  if (!ctx) return SPIDER_E_INVALID;
+  DeviceGuard g(ctx->device);
+  if (!sets || n_sets < 1 || !cfg) return fail(ctx, SPIDER_E_INVALID, "null or empty arguments");
+  if (!(cfg->lr > 0) || !std::isfinite(cfg->lr) || !(cfg->beta1 >= 0 && cfg->beta1 < 1) ||
+      !(cfg->beta2 >= 0 && cfg->beta2 < 1) || !(cfg->eps > 0) || cfg->n_steps < 0)
+    return fail(ctx, SPIDER_E_INVALID, "invalid optimiser configuration");
   for (int k = 0; k < n_sets; ++k) {
     const spider_chainset& st = sets[k];
-    Catalog& cat = *get_cat(ctx, st.cat_id);
-    DevBuf bad;
-    HIPCK(bad.alloc(16), "alloc");
-    const int big = INT_MAX;
-    HIPCK(hipMemcpyAsync(bad.p, &big, sizeof(int), hipMemcpyHostToDevice, ctx->stream), "flag");
-    launch_finite(cat.theta.as<double>(), (int64_t)cat.M * 4 * st.n_chains, (int64_t)cat.M * 4,
-                  bad.as<int>(), ctx->stream);
-    int first = INT_MAX;
-    HIPCK(hipMemcpyAsync(&first, bad.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream), "flag");
-    HIPCK(hipStreamSynchronize(ctx->stream), "sync");
-    if (first != INT_MAX) {
-      char msg[160];
-      std::snprintf(msg, sizeof msg, "non-finite state in catalog %d chain %d", st.cat_id, first);
-      return fail(ctx, SPIDER_E_NUMERIC, msg);
+    Catalog* cat = get_cat(ctx, st.cat_id);
+    Net* net = get_net(ctx, st.net_id);
+    if (!cat || !net) return fail(ctx, SPIDER_E_INVALID, "unknown catalog or network id");
+    if (st.n_chains < 1 || st.batch < 1 || st.batch > cat->N)
+      return fail(ctx, SPIDER_E_INVALID, "need n_chains >= 1 and 1 <= batch <= N");
+    if (st.precision != SPIDER_FP32 && st.precision != SPIDER_BF16)
+      return fail(ctx, SPIDER_E_INVALID, "unknown precision");
+    if (cat->C < st.n_chains) {
+      int rc = spider_reset_chains(ctx, st.cat_id, st.n_chains);
+      if (rc) return rc;
+    }
+    const size_t bytes = (size_t)cat->M * 4 * cat->C * 8;
+    if (!cat->adam_m.p || cat->adam_m.bytes < bytes || cat->adam_v.bytes < bytes) {
+      HIPCK(hipStreamSynchronize(ctx->stream), "sync");
+      HIPCK(cat->adam_m.alloc(bytes), "alloc optimiser state");
+      HIPCK(cat->adam_v.alloc(bytes), "alloc optimiser state");
+      cat->adam_zeroed = false;
+    }
+    if (!cat->adam_zeroed) {
+      launch_fill(cat->adam_m.as<double>(), 0.0, (int64_t)cat->M * 4 * cat->C, ctx->stream);
+      launch_fill(cat->adam_v.as<double>(), 0.0, (int64_t)cat->M * 4 * cat->C, ctx->stream);
+      cat->adam_zeroed = true;
     }
   }
+  int rc = reset_err_flag(ctx);
+  if (rc) return rc;
+  AdamArgs aa;
+  aa.lr = cfg->lr;
+  aa.beta1 = cfg->beta1;
+  aa.beta2 = cfg->beta2;
+  aa.eps = cfg->eps;
+  for (int64_t t = 0; t < cfg->n_steps; ++t) {
+    for (int k = 0; k < n_sets; ++k) {
+      const spider_chainset& st = sets[k];
+      Catalog& cat = *get_cat(ctx, st.cat_id);
+      Net& net = *get_net(ctx, st.net_id);
+      const int C = st.n_chains;
+      // G = (1/n) sum_batch sign(r) dtau^/dtheta = -grad of the batch L1 loss
+      rc = run_batch(ctx, cat, net, st.precision, C, st.batch, cat.theta.as<double>(),
+                     (int64_t)cat.M * 4, nullptr, cfg->seed, cat.steps.as<int64_t>(), 0, 0, true,
+                     1.0 / (double)st.batch, true);
+      if (rc) return rc;
+      launch_adam(C, cat.M, cat.theta.as<double>(), cat.adam_m.as<double>(),
+                  cat.adam_v.as<double>(), ctx->ws.G.as<double>(), cat.steps.as<int64_t>(), aa,
+                  ctx->stream);
+      HIPCK(hipGetLastError(), "optimiser step");
+    }
+  }
+  rc = check_finite_states(ctx, sets, n_sets);
+  if (rc) return rc;
   return check_select_flag(ctx);
 }
 

@@ -214,6 +214,18 @@ size_t sort_temp_bytes(int64_t entries);
 // thetabar[c] = mean over events of theta[c] (4 values per chain).
 void launch_centroid(const double* theta, int C, int M, double* partial, double* thetabar,
                      hipStream_t s);
+// Residual mode of k_residual beside SPIDER_WHITEN_*: z = sign(r), the
+// derivative of |r| (the L1 loss of Stage 1).
+constexpr int kWhitenL1 = 3;
+
+struct AdamArgs {
+  double lr, beta1, beta2, eps;
+};
+// Adam step of chains 0..C-1 on the loss whose negative gradient is G, with
+// bias correction at the chains' step counters + 1; then steps[c] += 1.
+void launch_adam(int C, int M, double* theta, double* m, double* v, const double* G,
+                 int64_t* steps, const AdamArgs& a, hipStream_t s);
+
 struct UpdateArgs {
   double step, beta2, eps_p, noise_scale;
   int precond;

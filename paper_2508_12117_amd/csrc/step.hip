@@ -11,6 +11,7 @@
 //             one thread, no floating-point atomics (deterministic)
 //   centroid  per-chain mean of theta (fixed-order two-level reduction)
 //   update    priors + SGLD / pSGLD (eq:pSGLD) + Philox noise + Welford
+#include <climits>
 #include <cstring>
 
 #include <rocprim/rocprim.hpp>
@@ -217,7 +218,9 @@ __global__ void k_residual(CatView cat, NetView net, int C, int64_t n, const dou
   const double r = b.tau[q] - ((T[0] - T[1]) + (tt[0] - tt[1]));
   b.r[q] = r;
   const double s2 = cat.sigma * cat.sigma;
-  if (whiten == 0 || cat.kappa == 0.0) {
+  if (whiten == kWhitenL1) {
+    b.z[q] = r > 0.0 ? 1.0 : (r < 0.0 ? -1.0 : 0.0);  // d|r|/dr, 0 at 0
+  } else if (whiten == 0 || cat.kappa == 0.0) {
     b.z[q] = r / s2;
   } else if (whiten == 1) {
     b.z[q] = r / (s2 + 2.0 * cat.kappa * cat.kappa * b.w[q]);
@@ -704,6 +707,25 @@ __global__ void k_update(CatView cat, int C, double* theta, double* v, const dou
   }
 }
 
+// Adam on the loss whose negative gradient is G (Stage 1, Sec. 3.2): with
+// g = -G, m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2, and k = the chain's
+// step counter + 1, theta -= lr (m / (1 - b1^k)) / (sqrt(v / (1 - b2^k)) + eps).
+__global__ void k_adam(int C, int M, double* theta, double* m, double* v, const double* G,
+                       const int64_t* steps, AdamArgs a) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= (int64_t)C * M * 4) return;
+  const int c = (int)(q / ((int64_t)M * 4));
+  const double k = (double)(steps[c] + 1);
+  const double g = -G[q];
+  const double mq = a.beta1 * m[q] + (1.0 - a.beta1) * g;
+  const double vq = a.beta2 * v[q] + (1.0 - a.beta2) * g * g;
+  m[q] = mq;
+  v[q] = vq;
+  const double mh = mq / (1.0 - pow(a.beta1, k));
+  const double vh = vq / (1.0 - pow(a.beta2, k));
+  theta[q] -= a.lr * mh / (sqrt(vh) + a.eps);
+}
+
 __global__ void k_advance(int C, int64_t* steps, int64_t* mcount, int64_t burn, int64_t thin) {
   const int c = threadIdx.x + blockIdx.x * blockDim.x;
   if (c >= C) return;
@@ -1072,6 +1094,15 @@ void launch_update(const CatView& cat, int C, double* theta, double* v, const do
                      theta, v, G, thetabar, steps, mcount, k, mean, m2);
   hipLaunchKernelGGL(k_advance, dim3(grid_for(C, 64)), dim3(64), 0, s, C, steps, mcount, a.burn,
                      a.thin);
+}
+
+void launch_adam(int C, int M, double* theta, double* m, double* v, const double* G,
+                 int64_t* steps, const AdamArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_adam, dim3(grid_for((int64_t)C * M * 4)), dim3(kBlock), 0, s, C, M, theta,
+                     m, v, G, steps, a);
+  // the step counters advance; no step of this stage records moments
+  hipLaunchKernelGGL(k_advance, dim3(grid_for(C, 64)), dim3(64), 0, s, C, steps, (int64_t*)nullptr,
+                     INT64_MAX, (int64_t)1);
 }
 
 void launch_grad_finish(const CatView& cat, const double* theta, const double* G,

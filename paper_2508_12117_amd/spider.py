@@ -21,7 +21,7 @@ OK, E_INVALID, E_OOM, E_HIP, E_STATE, E_UNSUPPORTED, E_NUMERIC = 0, -1, -2, -3, 
 MEM_HOST, MEM_DEVICE = 0, 1
 WHITEN_NONE, WHITEN_DIAG, WHITEN_EXACT = 0, 1, 2
 FP32, BF16 = 0, 1
-GRAD_PRIOR, GRAD_CENTROID = 1, 2
+GRAD_PRIOR, GRAD_CENTROID, GRAD_L1 = 1, 2, 4
 MAX_LAYERS = 16
 
 _ERRNAMES = {E_INVALID: "invalid", E_OOM: "out of memory", E_HIP: "HIP error",
@@ -65,6 +65,11 @@ class SgldCfg(ct.Structure):
                 ("seed", ct.c_uint64), ("noise_scale_end", ct.c_double)]
 
 
+class MapCfg(ct.Structure):
+    _fields_ = [("lr", ct.c_double), ("beta1", ct.c_double), ("beta2", ct.c_double),
+                ("eps", ct.c_double), ("n_steps", ct.c_int64), ("seed", ct.c_uint64)]
+
+
 _P = ct.c_void_p
 _SIGS = {
     "spider_version": ([], ct.c_int),
@@ -85,6 +90,7 @@ _SIGS = {
     "spider_noise": ([_P, ct.c_int32, ct.c_uint64, ct.c_int32, ct.c_int64, _P], ct.c_int),
     "spider_reset_chains": ([_P, ct.c_int32, ct.c_int32], ct.c_int),
     "spider_sgld_steps": ([_P, ct.POINTER(ChainSet), ct.c_int32, ct.POINTER(SgldCfg)], ct.c_int),
+    "spider_map_steps": ([_P, ct.POINTER(ChainSet), ct.c_int32, ct.POINTER(MapCfg)], ct.c_int),
     "spider_moments": ([_P, ct.c_int32, ct.c_int32, _P, _P, ct.POINTER(ct.c_int64)], ct.c_int),
     "spider_get_state": ([_P, ct.c_int32, ct.c_int32, _P, _P, ct.POINTER(ct.c_int64)], ct.c_int),
     "spider_set_state": ([_P, ct.c_int32, ct.c_int32, _P, _P, ct.c_int64], ct.c_int),
@@ -278,6 +284,16 @@ class Context:
                       burn_in=burn_in, thin=thin, seed=seed,
                       noise_scale_end=noise_scale_end if ramp else 0.0)
         self._check(lib().spider_sgld_steps(self._h, arr, len(sets), ct.byref(cfg)))
+
+    def map_steps(self, sets, n_steps, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, seed=0):
+        """Stage 1: Adam on the minibatch L1 loss of the dd residuals, no priors.
+        sets: list of (cat_id, net_id, n_chains, batch, precision)."""
+        arr = (ChainSet * len(sets))()
+        for k, (cid, nid, C, n, prec) in enumerate(sets):
+            arr[k].cat_id, arr[k].net_id, arr[k].n_chains = cid, nid, C
+            arr[k].precision, arr[k].batch = prec, n
+        cfg = MapCfg(lr=lr, beta1=beta1, beta2=beta2, eps=eps, n_steps=n_steps, seed=seed)
+        self._check(lib().spider_map_steps(self._h, arr, len(sets), ct.byref(cfg)))
 
     def sgld_stages(self, sets, warmup, ramp, sample, thin=1, **kw):
         """The sampler stages that follow the initial solution (Sec. 3.2):

@@ -13,7 +13,7 @@ import pytest
 from gpu_common import (dev, grad_scale, host, lk, make_ctx, psgld_update_tolerance,
                         scaled_grad_error, spider, synth, torch, whitening_residual)
 from oracle import batch as obatch
-from oracle import philox, sampler
+from oracle import philox, sampler, stage1
 from oracle import travel_time as ott
 
 pytestmark = pytest.mark.gpu
@@ -226,6 +226,85 @@ def test_grad_sampler_batch_matches_explicit(ctx, tiny_setup):
     idx = obatch.batch_indices(8, 3, 2, 40, cat.N, 1024)
     ctx.grad(cid, nid, theta, G2, batch_idx=dev(idx))
     assert torch.equal(G1, G2)
+
+
+# ----------------------------------------------------------------- stage 1
+
+def _l1_tolerance(bt, n, M, delta=1e-4, rel=1e-5):
+    """Per-event bound on |G_gpu - G_oracle| for the L1 gradient
+    (1/n) sum sign(r) dtau^/dtheta: an observation whose oracle residual lies
+    within delta of zero may take the other sign under FP32 rounding of the
+    network (up to 2/n of its derivative), and the rest carry rel of theirs."""
+    gi = np.abs(np.column_stack([bt.gT_i, np.ones(len(bt.r))]))
+    gj = np.abs(np.column_stack([bt.gT_j, np.ones(len(bt.r))]))
+    w = np.where(np.abs(bt.r) < delta, 2.0 / n, rel / n)[:, None]
+    tol = np.zeros((M, 4))
+    np.add.at(tol, bt.ev_i, w * gi)
+    np.add.at(tol, bt.ev_j, w * gj)
+    return tol + 1e-12
+
+
+def test_l1_gradient_parity(ctx, tiny_setup):
+    cat, net, cid, nid = tiny_setup
+    prob = lk.load(cat)
+    theta = synth.random_theta(cat, 51)
+    idx = synth.random_batch(cat.N, 1024, 52)
+    G = torch.empty(cat.M, 4, dtype=torch.float64, device="cuda")
+    lp = torch.empty(1, dtype=torch.float64, device="cuda")
+    ctx.grad(cid, nid, dev(theta), G, batch_idx=dev(idx), flags=spider.GRAD_L1, logpost=lp)
+    loss, Gw, bt = stage1.l1_loss_gradient(prob, net, theta, idx)
+    tol = _l1_tolerance(bt, 1024, cat.M)
+    assert np.all(np.abs(host(G) - Gw) <= tol)
+    assert abs(-float(host(lp)[0]) - loss) < 1e-5 * loss + 2e-4
+    with pytest.raises(spider.SpiderError):
+        ctx.grad(cid, nid, dev(theta), G, batch_idx=dev(idx), flags=8)
+
+
+def test_stage1_first_step_matches_oracle(ctx, tiny_setup):
+    """One Adam step from theta_0 on the sampler's first minibatch: each
+    coordinate moves by lr G / (|G| + eps), so the state is held to what the
+    L1 gradient tolerance can change in that expression."""
+    cat, net, _, nid = tiny_setup
+    cid = ctx.load_catalog(cat, stream_id=3)
+    ctx.reset_chains(cid, 2)
+    ctx.map_steps([(cid, nid, 2, 1024, spider.FP32)], 1, lr=1e-3, seed=31)
+    th = torch.empty(cat.M, 4, dtype=torch.float64, device="cuda")
+    assert ctx.get_state(cid, 1, th) == 1
+    prob = lk.load(cat)
+    cfg = stage1.AdamConfig(lr=1e-3, seed=31)
+    st = stage1.new_state(prob)
+    idx = obatch.batch_indices(31, 3, 1, 0, cat.N, 1024)
+    _, Gw, bt = stage1.l1_loss_gradient(prob, net, st.theta, idx)
+    stage1.step(prob, net, st, cfg, 3, 1, 1024)
+    dG = _l1_tolerance(bt, 1024, cat.M)
+    g_lo = np.abs(Gw) - dG
+    tol = np.where(g_lo > 0, dG * 1e-3 * 1e-8 / (np.maximum(g_lo, 0) + 1e-8) ** 2, 2e-3) + 1e-15
+    assert np.all(np.abs(host(th) - st.theta) <= tol)
+
+
+def test_stage1_run_is_deterministic_and_lowers_the_loss(ctx, tiny_setup):
+    cat, net, _, nid = tiny_setup
+    cid = ctx.load_catalog(cat, stream_id=3)
+    allobs = dev(np.arange(cat.N))
+    lp = torch.empty(1, dtype=torch.float64, device="cuda")
+    G = torch.empty(cat.M, 4, dtype=torch.float64, device="cuda")
+    for prec in (spider.FP32, spider.BF16):
+        outs = []
+        for _ in range(2):
+            ctx.reset_chains(cid, 1)
+            ctx.map_steps([(cid, nid, 1, 1024, prec)], 60, lr=1e-3, seed=9)
+            th = torch.empty(cat.M, 4, dtype=torch.float64, device="cuda")
+            assert ctx.get_state(cid, 0, th) == 60
+            outs.append(host(th))
+        assert np.array_equal(outs[0], outs[1])
+        ctx.grad(cid, nid, dev(cat.hypo0), G, batch_idx=allobs, flags=spider.GRAD_L1, logpost=lp,
+                 precision=prec)
+        before = -float(host(lp)[0])
+        ctx.grad(cid, nid, dev(outs[0]), G, batch_idx=allobs, flags=spider.GRAD_L1, logpost=lp,
+                 precision=prec)
+        assert -float(host(lp)[0]) < 0.9 * before
+    with pytest.raises(spider.SpiderError):
+        ctx.map_steps([(cid, nid, 1, 1024, spider.FP32)], 1, lr=0.0)
 
 
 # ----------------------------------------------------------------- sampler

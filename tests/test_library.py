@@ -62,3 +62,27 @@ def test_header_is_plain_c():
                                        ("spider_moments", 6), ("spider_load_catalog", 3)])
 def test_binding_arities(name, argc):
     assert len(spider._SIGS[name][0]) == argc
+
+
+def test_struct_layouts_match_the_header():
+    """The binding's ctypes structures have the header's sizes and offsets."""
+    import tempfile
+    structs = {"spider_sgld_cfg": spider.SgldCfg, "spider_map_cfg": spider.MapCfg,
+               "spider_chainset": spider.ChainSet}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "spider.h"', "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    with tempfile.TemporaryDirectory() as d:
+        src, exe = os.path.join(d, "l.c"), os.path.join(d, "l")
+        open(src, "w").write("\n".join(lines))
+        subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), src, "-o", exe],
+                       check=True)
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out.splitlines()}
+    for cname, cls in structs.items():
+        assert got[(cname, "size")] == ct.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
