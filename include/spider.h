@@ -283,6 +283,20 @@ typedef struct {
 int spider_map_steps(spider_ctx* ctx, const spider_chainset* sets, int32_t n_sets,
                      const spider_map_cfg* cfg);
 
+/* Outlier screening after Stage 1 (Sec. 3.2): the residuals r of all N
+ * observations at chain `chain`'s state (the network in `precision`), their
+ * median and median absolute deviation MAD = median |r - median(r)| (the
+ * mean of the middle two values for an even count), and keep[i] = 1 iff
+ * |r_i - median(r)| <= k_mad MAD (the paper uses k_mad = 4), else 0.  The
+ * caller loads the kept observations as a new catalog (its edge weights are
+ * then normalised over them).  keep: device [N] uint8, caller-allocated;
+ * n_keep, median, mad: host, each may be NULL.  Synchronous; allocates
+ * scratch for three N-double arrays.  Errors: SPIDER_E_INVALID (ids,
+ * chain, k_mad <= 0, NULL keep), SPIDER_E_OOM, SPIDER_E_HIP. */
+int spider_outliers(spider_ctx* ctx, int32_t cat_id, int32_t net_id, int32_t precision,
+                    int32_t chain, double k_mad, uint8_t* keep, int64_t* n_keep, double* median,
+                    double* mad);
+
 /* Posterior moments (Sec. 3.4) of a catalog: chain >= 0 for one chain, -1
  * for all chains pooled (pairwise combination of Chan, Golub and LeVeque).
  * mean: device [M][4]; cov: device [M][10] upper triangle xx xy xz xt yy yz

@@ -9,6 +9,8 @@ The loss is the L1 norm of the dd residuals over a minibatch,
 minimised with Adam (eta from Table 1) and no priors.  Its gradient is
   dL/dtheta = -(1/n) sum_k sign(r_k) dtau^_k/dtheta,
 i.e. the likelihood gradient's assembly with z = sign(r) and scale 1/n.
+After Stage 1, observations whose residual lies more than 4 median absolute
+deviations from the median residual are discarded (outlier_mask).
 Minibatch t of chain c is the sampler's (batch.batch_indices), and Adam's
 bias correction uses step k = t + 1:
   m = b1 m + (1 - b1) g,  v = b2 v + (1 - b2) g^2,
@@ -78,3 +80,13 @@ def run(prob, net, cfg: AdamConfig, n: int, steps: int, stream: int = 0, chain_i
     st = new_state(prob) if st is None else st
     losses = [step(prob, net, st, cfg, stream, chain_id, n) for _ in range(steps)]
     return st, losses
+
+
+def outlier_mask(prob: lk.Problem, net, theta, k_mad: float = 4.0):
+    """Residuals of all observations at theta, their median and median
+    absolute deviation MAD = median |r - median(r)|, and the mask of the
+    observations with |r - median(r)| <= k_mad MAD."""
+    r = lk.batch_terms(prob, net, theta, np.arange(prob.N), lk.L1).r
+    med = float(np.median(r))
+    mad = float(np.median(np.abs(r - med)))
+    return np.abs(r - med) <= k_mad * mad, med, mad, r

@@ -1113,6 +1113,74 @@ int spider_map_steps(spider_ctx* ctx, const spider_chainset* sets, int32_t n_set
   return check_select_flag(ctx);
 }
 
+// Median of n ascending doubles on the device (mean of the middle two when n is even).
+static hipError_t device_median(const double* sorted, int64_t n, hipStream_t s, double* med) {
+  double mid[2] = {0, 0};
+  const int64_t lo = (n - 1) / 2;
+  hipError_t e = hipMemcpyAsync(mid, sorted + lo, (n % 2 ? 1 : 2) * sizeof(double),
+                                hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  *med = n % 2 ? mid[0] : 0.5 * (mid[0] + mid[1]);
+  return e;
+}
+
+int spider_outliers(spider_ctx* ctx, int32_t cat_id, int32_t net_id, int32_t precision,
+                    int32_t chain, double k_mad, uint8_t* keep, int64_t* n_keep, double* median,
+                    double* mad) {
+  if (!ctx) return SPIDER_E_INVALID;
+  DeviceGuard g(ctx->device);
+  Catalog* cat = get_cat(ctx, cat_id);
+  Net* net = get_net(ctx, net_id);
+  if (!cat || !net) return fail(ctx, SPIDER_E_INVALID, "unknown catalog or network id");
+  if (precision != SPIDER_FP32 && precision != SPIDER_BF16)
+    return fail(ctx, SPIDER_E_INVALID, "unknown precision");
+  if (chain < 0 || chain >= cat->C) return fail(ctx, SPIDER_E_INVALID, "bad chain index");
+  if (!(k_mad > 0) || !std::isfinite(k_mad) || !keep)
+    return fail(ctx, SPIDER_E_INVALID, "need k_mad > 0 and a keep array");
+  const int64_t N = cat->N;
+  const int64_t CH = std::min<int64_t>(N, (int64_t)1 << 22);
+  DevBuf r, d, srt, idx, temp, cnt;
+  HIPCK(hipStreamSynchronize(ctx->stream), "sync");
+  HIPCK(r.alloc((size_t)N * 8), "alloc residuals");
+  HIPCK(d.alloc((size_t)N * 8), "alloc residuals");
+  HIPCK(srt.alloc((size_t)N * 8), "alloc residuals");
+  HIPCK(idx.alloc((size_t)CH * 8), "alloc residuals");
+  HIPCK(cnt.alloc(16), "alloc residuals");
+  int rc = reset_err_flag(ctx);
+  if (rc) return rc;
+  const double* theta = cat->theta.as<double>() + (size_t)cat->M * 4 * chain;
+  // residuals of every observation at the chain's state, in chunks
+  for (int64_t start = 0; start < N; start += CH) {
+    const int64_t len = std::min(CH, N - start);
+    launch_iota(idx.as<int64_t>(), start, len, ctx->stream);
+    rc = run_batch(ctx, *cat, *net, precision, 1, len, theta, (int64_t)cat->M * 4,
+                   idx.as<int64_t>(), 0, nullptr, 0, 0, false, 1.0, true);
+    if (rc) return rc;
+    HIPCK(hipMemcpyAsync(r.as<double>() + start, ctx->ws.r.p, (size_t)len * 8,
+                         hipMemcpyDeviceToDevice, ctx->stream),
+          "copy residuals");
+  }
+  size_t tb = 0;
+  HIPCK(sort_doubles(nullptr, nullptr, N, nullptr, &tb, ctx->stream), "sort size");
+  HIPCK(temp.alloc(tb), "alloc sort scratch");
+  double med = 0, md = 0;
+  HIPCK(sort_doubles(r.as<double>(), srt.as<double>(), N, temp.p, &tb, ctx->stream), "sort");
+  HIPCK(device_median(srt.as<double>(), N, ctx->stream, &med), "median");
+  launch_absdev(r.as<double>(), N, med, d.as<double>(), ctx->stream);
+  HIPCK(sort_doubles(d.as<double>(), srt.as<double>(), N, temp.p, &tb, ctx->stream), "sort");
+  HIPCK(device_median(srt.as<double>(), N, ctx->stream, &md), "median");
+  HIPCK(hipMemsetAsync(cnt.p, 0, 8, ctx->stream), "count");
+  launch_keep(r.as<double>(), N, med, k_mad * md, keep, (unsigned long long*)cnt.p, ctx->stream);
+  HIPCK(hipGetLastError(), "screening kernels");
+  unsigned long long kept = 0;
+  HIPCK(hipMemcpyAsync(&kept, cnt.p, 8, hipMemcpyDeviceToHost, ctx->stream), "count");
+  HIPCK(hipStreamSynchronize(ctx->stream), "sync");
+  if (n_keep) *n_keep = (int64_t)kept;
+  if (median) *median = med;
+  if (mad) *mad = md;
+  return check_select_flag(ctx);
+}
+
 int spider_moments(spider_ctx* ctx, int32_t cat_id, int32_t chain, double* mean, double* cov,
                    int64_t* count) {
   if (!ctx) return SPIDER_E_INVALID;

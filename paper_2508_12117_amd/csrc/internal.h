@@ -255,5 +255,14 @@ void launch_finite(const double* a, int64_t count, int64_t per_chain, int* bad_c
 void launch_pool_moments(int C, int M, const double* mean, const double* m2, const int64_t* cnt,
                          double* out_mean, double* out_cov, hipStream_t s);
 void launch_fill(double* p, double v, int64_t count, hipStream_t s);
+// Outlier screening: idx[t] = start + t; d = |r - med|; keep = |r - med| <=
+// thr with the kept count added to *count; ascending sort of N doubles
+// (temp = nullptr queries *temp_bytes).
+void launch_iota(int64_t* idx, int64_t start, int64_t len, hipStream_t s);
+void launch_absdev(const double* r, int64_t N, double med, double* d, hipStream_t s);
+void launch_keep(const double* r, int64_t N, double med, double thr, uint8_t* keep,
+                 unsigned long long* count, hipStream_t s);
+hipError_t sort_doubles(const double* in, double* out, int64_t N, void* temp, size_t* temp_bytes,
+                        hipStream_t s);
 
 }  // namespace spider

@@ -866,6 +866,37 @@ __global__ void k_fill(double* p, double v, int64_t count) {
   if (t < count) p[t] = v;
 }
 
+// ---- outlier screening after Stage 1
+
+__global__ void k_iota(int64_t* idx, int64_t start, int64_t len) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < len) idx[t] = start + t;
+}
+
+__global__ void k_absdev(const double* r, int64_t N, double med, double* d) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < N) d[t] = fabs(r[t] - med);
+}
+
+// keep[i] = |r_i - med| <= thr; the kept count is added to *count.
+__global__ void k_keep(const double* r, int64_t N, double med, double thr, uint8_t* keep,
+                       unsigned long long* count) {
+  __shared__ unsigned int sh[kBlock];
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned int k = 0;
+  if (t < N) {
+    k = fabs(r[t] - med) <= thr ? 1u : 0u;
+    keep[t] = (uint8_t)k;
+  }
+  sh[threadIdx.x] = k;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && sh[0]) atomicAdd(count, (unsigned long long)sh[0]);
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
@@ -1149,6 +1180,27 @@ void launch_pool_moments(int C, int M, const double* mean, const double* m2, con
                          double* out_mean, double* out_cov, hipStream_t s) {
   hipLaunchKernelGGL(k_pool_moments, dim3(grid_for(M)), dim3(kBlock), 0, s, C, M, mean, m2, cnt,
                      out_mean, out_cov);
+}
+
+void launch_iota(int64_t* idx, int64_t start, int64_t len, hipStream_t s) {
+  if (len == 0) return;
+  hipLaunchKernelGGL(k_iota, dim3(grid_for(len)), dim3(kBlock), 0, s, idx, start, len);
+}
+
+void launch_absdev(const double* r, int64_t N, double med, double* d, hipStream_t s) {
+  if (N == 0) return;
+  hipLaunchKernelGGL(k_absdev, dim3(grid_for(N)), dim3(kBlock), 0, s, r, N, med, d);
+}
+
+void launch_keep(const double* r, int64_t N, double med, double thr, uint8_t* keep,
+                 unsigned long long* count, hipStream_t s) {
+  if (N == 0) return;
+  hipLaunchKernelGGL(k_keep, dim3(grid_for(N)), dim3(kBlock), 0, s, r, N, med, thr, keep, count);
+}
+
+hipError_t sort_doubles(const double* in, double* out, int64_t N, void* temp, size_t* temp_bytes,
+                        hipStream_t s) {
+  return rocprim::radix_sort_keys(temp, *temp_bytes, in, out, (size_t)N, 0, 64, s);
 }
 
 void launch_fill(double* p, double v, int64_t count, hipStream_t s) {

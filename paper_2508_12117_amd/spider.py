@@ -91,6 +91,9 @@ _SIGS = {
     "spider_reset_chains": ([_P, ct.c_int32, ct.c_int32], ct.c_int),
     "spider_sgld_steps": ([_P, ct.POINTER(ChainSet), ct.c_int32, ct.POINTER(SgldCfg)], ct.c_int),
     "spider_map_steps": ([_P, ct.POINTER(ChainSet), ct.c_int32, ct.POINTER(MapCfg)], ct.c_int),
+    "spider_outliers": ([_P, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_double, _P,
+                         ct.POINTER(ct.c_int64), ct.POINTER(ct.c_double), ct.POINTER(ct.c_double)],
+                        ct.c_int),
     "spider_moments": ([_P, ct.c_int32, ct.c_int32, _P, _P, ct.POINTER(ct.c_int64)], ct.c_int),
     "spider_get_state": ([_P, ct.c_int32, ct.c_int32, _P, _P, ct.POINTER(ct.c_int64)], ct.c_int),
     "spider_set_state": ([_P, ct.c_int32, ct.c_int32, _P, _P, ct.c_int64], ct.c_int),
@@ -159,6 +162,7 @@ class Context:
             raise SpiderError(rc, f"spider_create(device={device}) failed")
         self._h = h
         self._keep = []
+        self._n_obs = {}  # observations of each loaded catalog
 
     def close(self):
         if getattr(self, "_h", None):
@@ -212,6 +216,7 @@ class Context:
         d.whiten = whiten
         cid = ct.c_int32()
         self._check(lib().spider_load_catalog(self._h, ct.byref(d), ct.byref(cid)))
+        self._n_obs[cid.value] = cat.N
         return cid.value
 
     def load_net(self, net) -> int:
@@ -294,6 +299,17 @@ class Context:
             arr[k].precision, arr[k].batch = prec, n
         cfg = MapCfg(lr=lr, beta1=beta1, beta2=beta2, eps=eps, n_steps=n_steps, seed=seed)
         self._check(lib().spider_map_steps(self._h, arr, len(sets), ct.byref(cfg)))
+
+    def outliers(self, cat_id, net_id, chain=0, k_mad=4.0, precision=FP32):
+        """Outlier screening at a chain's state: (keep [N] uint8 device
+        tensor, kept count, median, MAD) of the residuals of all observations."""
+        torch = self._torch
+        keep = torch.empty(self._n_obs.get(cat_id, 0), dtype=torch.uint8,
+                           device=f"cuda:{self.device}")
+        n, med, mad = ct.c_int64(), ct.c_double(), ct.c_double()
+        self._check(lib().spider_outliers(self._h, cat_id, net_id, precision, chain, k_mad,
+                                          _ptr(keep), ct.byref(n), ct.byref(med), ct.byref(mad)))
+        return keep, n.value, med.value, mad.value
 
     def sgld_stages(self, sets, warmup, ramp, sample, thin=1, **kw):
         """The sampler stages that follow the initial solution (Sec. 3.2):

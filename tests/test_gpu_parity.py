@@ -307,6 +307,94 @@ def test_stage1_run_is_deterministic_and_lowers_the_loss(ctx, tiny_setup):
         ctx.map_steps([(cid, nid, 1, 1024, spider.FP32)], 1, lr=0.0)
 
 
+
+def _planted(cat, n_bad=200, seed=8):
+    """The catalog with n_bad observed times shifted by +-5 s."""
+    import dataclasses
+    rng = np.random.default_rng(seed)
+    bad = rng.choice(cat.N, n_bad, replace=False)
+    dt = cat.obs_dt.copy()
+    dt[bad] += np.where(rng.random(n_bad) < 0.5, 5.0, -5.0).astype(dt.dtype)
+    return dataclasses.replace(cat, obs_dt=dt), bad
+
+
+def _filtered(cat, keep):
+    import dataclasses
+    return dataclasses.replace(cat, obs_pair=cat.obs_pair[keep], obs_sta=cat.obs_sta[keep],
+                               obs_dt=cat.obs_dt[keep])
+
+
+@pytest.mark.parametrize("prec", [spider.FP32, spider.BF16])
+def test_outlier_screening_matches_oracle(ctx, tiny_setup, prec):
+    """Median, MAD and keep mask of the residuals of every observation at a
+    chain's state.  (a) They are the median, MAD and 4-MAD mask of the GPU's
+    own residuals of the same precision.  (b) Each of those residuals is
+    within delta of the oracle's (1e-5 of its magnitudes for FP32, the BF16
+    travel-time bound for BF16), so the median and the MAD are within delta
+    and 2 delta of the oracle's, and an observation's verdict can differ only
+    where | |r - med| - 4 MAD | <= 10 delta (for FP32 that leaves all but a
+    handful of observations to compare)."""
+    base, net, _, nid = tiny_setup
+    cat, bad = _planted(base)
+    cid = ctx.load_catalog(cat, stream_id=3)
+    ctx.reset_chains(cid, 2)
+    theta = synth.random_theta(cat, 61)
+    ctx.set_state(cid, 1, dev(theta))
+    keep, n_keep, med, mad = ctx.outliers(cid, nid, chain=1, k_mad=4.0, precision=prec)
+    keep = host(keep).astype(bool)
+    assert n_keep == keep.sum()
+    assert not keep[bad].any()
+    # (a)
+    r = host(ctx.batch_terms(cid, nid, dev(theta), dev(np.arange(cat.N)), precision=prec)["r"])
+    assert med == np.median(r) and mad == np.median(np.abs(r - med))
+    d = np.abs(r - med)
+    sure = np.abs(d - 4 * mad) > 1e-12
+    np.testing.assert_array_equal(keep[sure], (d <= 4 * mad)[sure])
+    # (b)
+    prob = lk.load(cat)
+    keep_o, med_o, mad_o, r_o = stage1.outlier_mask(prob, net, theta, 4.0)
+    bt = lk.batch_terms(prob, net, theta, np.arange(cat.N), lk.L1)
+    if prec == spider.FP32:
+        mag = (np.abs(bt.T_i) + np.abs(bt.T_j) + np.abs(bt.tau)
+               + np.abs(theta[bt.ev_i, 3] - theta[bt.ev_j, 3]))
+        delta = 1e-5 * mag.max()
+    else:
+        delta = BF16_T_REL * (bt.T_i + bt.T_j).max()
+    assert np.max(np.abs(r - r_o)) <= delta
+    assert abs(med - med_o) <= delta and abs(mad - mad_o) <= 2 * delta
+    clear = np.abs(np.abs(r_o - med_o) - 4 * mad_o) > 10 * delta
+    if prec == spider.FP32:
+        assert clear.mean() > 0.99
+    np.testing.assert_array_equal(keep[clear], keep_o[clear])
+
+
+def test_screened_catalog_reloads(ctx, tiny_setup):
+    """The FP32 screen of the planted catalog at theta_0 drops exactly the
+    oracle's observations; the filtered catalog loads and its L1 gradient
+    matches the oracle's on the oracle's filtered catalog."""
+    base, net, _, nid = tiny_setup
+    cat, bad = _planted(base)
+    cid = ctx.load_catalog(cat, stream_id=3)
+    ctx.reset_chains(cid, 1)
+    keep, n_keep, _, _ = ctx.outliers(cid, nid)
+    keep_o, _, _, _ = stage1.outlier_mask(lk.load(cat), net, cat.hypo0)
+    assert np.array_equal(host(keep).astype(bool), keep_o)
+    sub = _filtered(cat, keep_o)
+    assert sub.N == n_keep
+    fid = ctx.load_catalog(sub, stream_id=3)
+    prob = lk.load(sub)
+    theta = synth.random_theta(sub, 62)
+    idx = synth.random_batch(sub.N, 1024, 63)
+    G = torch.empty(sub.M, 4, dtype=torch.float64, device="cuda")
+    ctx.grad(fid, nid, dev(theta), G, batch_idx=dev(idx), flags=spider.GRAD_L1)
+    _, Gw, bt = stage1.l1_loss_gradient(prob, net, theta, idx)
+    assert np.all(np.abs(host(G) - Gw) <= _l1_tolerance(bt, 1024, sub.M))
+    ctx.reset_chains(fid, 1)
+    ctx.sgld_steps([(fid, nid, 1, 1024, spider.FP32)], 5, seed=4)
+    th = torch.empty(sub.M, 4, dtype=torch.float64, device="cuda")
+    assert ctx.get_state(fid, 0, th) == 5 and np.all(np.isfinite(host(th)))
+
+
 # ----------------------------------------------------------------- sampler
 
 def _oracle_run(cat, net, steps, seed, stream, chain_id=0, burn=0, thin=1, n=1024):

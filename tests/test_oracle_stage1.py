@@ -1,4 +1,6 @@
 """Pins for the oracle's Stage 1 (L1 loss, Adam; Sec. 3.2, eq:stage1loss)."""
+import dataclasses
+
 import numpy as np
 
 from oracle import batch as obatch
@@ -74,3 +76,56 @@ def test_stage1_reduces_the_l1_loss():
     # the first minibatch is the sampler's
     idx0 = obatch.batch_indices(9, 3, 0, 0, cat.N, 1024)
     assert abs(losses[0] - stage1.l1_loss_gradient(prob, net, prob.hypo0, idx0)[0]) < 1e-15
+
+
+def _screen(cat, shift=None):
+    cat = dataclasses.replace(cat, obs_dt=cat.obs_dt.copy())
+    if shift is not None:
+        cat.obs_dt += shift.astype(cat.obs_dt.dtype)
+    prob = lk.load(cat)
+    return stage1.outlier_mask(prob, synth.net_for(cat), prob.hypo0)
+
+
+def test_outlier_mask_removes_planted_outliers():
+    """Observed times shifted by 5 s (beyond every genuine residual, which
+    stay within 0.9 s at the start) are all screened out; the median and MAD
+    hardly move with 0.6% of the data corrupted."""
+    cat = synth.make_catalog("tiny")
+    keep0, med0, mad0, r0 = _screen(cat)
+    rng = np.random.default_rng(8)
+    bad = rng.choice(cat.N, 200, replace=False)
+    shift = np.zeros(cat.N)
+    shift[bad] = np.where(rng.random(200) < 0.5, 5.0, -5.0)
+    keep, med, mad, r = _screen(cat, shift)
+    assert not keep[bad].any()
+    np.testing.assert_allclose(r[bad], r0[bad] + shift[bad], atol=1e-5)  # r = observed - predicted
+    assert abs(med - med0) < 0.02 * mad0 and abs(mad - mad0) < 0.02 * mad0
+    good = np.setdiff1d(np.arange(cat.N), bad)
+    # genuine observations well inside (or outside) the threshold keep their fate
+    clear = np.abs(np.abs(r0[good] - med0) - 4 * mad0) > 0.05 * mad0
+    np.testing.assert_array_equal(keep[good][clear], keep0[good][clear])
+
+
+def test_median_and_mad_by_counting():
+    """The median splits the residuals in halves and the MAD is the median
+    distance from it (counted, for the even N of this catalog)."""
+    cat = synth.make_catalog("tiny")
+    assert cat.N % 2 == 0
+    keep, med, mad, r = _screen(cat)
+    n = cat.N
+    assert np.sum(r < med) == n // 2 and np.sum(r > med) == n // 2
+    d = np.abs(r - med)
+    assert np.sum(d < mad) <= n // 2 <= np.sum(d <= mad)
+    assert 0 < keep.sum() < n
+
+
+def test_outlier_mask_is_shift_invariant():
+    """A constant added to every observed time moves the median by it and
+    leaves the MAD and the mask unchanged (centering at the median)."""
+    cat = synth.make_catalog("tiny")
+    keep0, med0, mad0, _ = _screen(cat)
+    keep1, med1, mad1, _ = _screen(cat, np.full(cat.N, 0.25))
+    assert abs(med1 - med0 - 0.25) < 1e-5 and abs(mad1 - mad0) < 1e-5
+    d = np.abs(_screen(cat)[3] - med0)
+    near = np.abs(d - 4 * mad0) < 1e-4
+    np.testing.assert_array_equal(keep0[~near], keep1[~near])
