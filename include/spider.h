@@ -297,6 +297,19 @@ int spider_outliers(spider_ctx* ctx, int32_t cat_id, int32_t net_id, int32_t pre
                     int32_t chain, double k_mad, uint8_t* keep, int64_t* n_keep, double* median,
                     double* mad);
 
+/* Linear-regime data filter (Sec. 2.1, eq:dd_linearization; 5% in Sec. 4):
+ * for every observation of pair (i, j) at station s, at chain `chain`'s state
+ * and with the network in `precision`, dT = T(x_j; s) - T(x_i; s) and its
+ * first-order expansion lin = grad_x T(x_i; s) . (x_j - x_i); keep[q] = 1
+ * iff |dT - lin| <= max_rel_err |dT| (the paper uses 0.05), else 0.  Run it
+ * at the initial locations (after spider_reset_chains) to filter the data
+ * before inversion; the caller loads the kept observations as a new catalog.
+ * keep: device [N] uint8, caller-allocated; n_keep: host, may be NULL.
+ * Synchronous.  Errors: SPIDER_E_INVALID (ids, chain, max_rel_err < 0,
+ * NULL keep), SPIDER_E_OOM, SPIDER_E_HIP. */
+int spider_linearity(spider_ctx* ctx, int32_t cat_id, int32_t net_id, int32_t precision,
+                     int32_t chain, double max_rel_err, uint8_t* keep, int64_t* n_keep);
+
 /* Posterior moments (Sec. 3.4) of a catalog: chain >= 0 for one chain, -1
  * for all chains pooled (pairwise combination of Chan, Golub and LeVeque).
  * mean: device [M][4]; cov: device [M][10] upper triangle xx xy xz xt yy yz

@@ -1124,42 +1124,72 @@ static hipError_t device_median(const double* sorted, int64_t n, hipStream_t s, 
   return e;
 }
 
+extern "C++" {
+// Runs the network and residual kernels over all N observations of a
+// catalog at one chain's state, in chunks of at most 2^22 observations, and
+// calls chunk(start, len) after each (the batch buffers then hold the chunk).
+template <class F>
+static int over_all_observations(spider_ctx* ctx, Catalog& cat, Net& net, int prec, int chain,
+                                 DevBuf& idx, F chunk) {
+  const int64_t N = cat.N;
+  const int64_t CH = std::min<int64_t>(N, (int64_t)1 << 22);
+  HIPCK(idx.alloc((size_t)std::max<int64_t>(CH, 1) * 8), "alloc indices");
+  const double* theta = cat.theta.as<double>() + (size_t)cat.M * 4 * chain;
+  for (int64_t start = 0; start < N; start += CH) {
+    const int64_t len = std::min(CH, N - start);
+    launch_iota(idx.as<int64_t>(), start, len, ctx->stream);
+    int rc = run_batch(ctx, cat, net, prec, 1, len, theta, (int64_t)cat.M * 4,
+                       idx.as<int64_t>(), 0, nullptr, 0, 0, false, 1.0, true);
+    if (rc) return rc;
+    rc = chunk(start, len, theta);
+    if (rc) return rc;
+  }
+  return SPIDER_OK;
+}
+
+}  // extern "C++"
+
+static int screening_args(spider_ctx* ctx, int32_t cat_id, int32_t net_id, int32_t precision,
+                          int32_t chain, Catalog*& cat, Net*& net) {
+  cat = get_cat(ctx, cat_id);
+  net = get_net(ctx, net_id);
+  if (!cat || !net) return fail(ctx, SPIDER_E_INVALID, "unknown catalog or network id");
+  if (precision != SPIDER_FP32 && precision != SPIDER_BF16)
+    return fail(ctx, SPIDER_E_INVALID, "unknown precision");
+  if (chain < 0 || chain >= cat->C) return fail(ctx, SPIDER_E_INVALID, "bad chain index");
+  return SPIDER_OK;
+}
+
 int spider_outliers(spider_ctx* ctx, int32_t cat_id, int32_t net_id, int32_t precision,
                     int32_t chain, double k_mad, uint8_t* keep, int64_t* n_keep, double* median,
                     double* mad) {
   if (!ctx) return SPIDER_E_INVALID;
   DeviceGuard g(ctx->device);
-  Catalog* cat = get_cat(ctx, cat_id);
-  Net* net = get_net(ctx, net_id);
-  if (!cat || !net) return fail(ctx, SPIDER_E_INVALID, "unknown catalog or network id");
-  if (precision != SPIDER_FP32 && precision != SPIDER_BF16)
-    return fail(ctx, SPIDER_E_INVALID, "unknown precision");
-  if (chain < 0 || chain >= cat->C) return fail(ctx, SPIDER_E_INVALID, "bad chain index");
+  Catalog* cat;
+  Net* net;
+  int rc = screening_args(ctx, cat_id, net_id, precision, chain, cat, net);
+  if (rc) return rc;
   if (!(k_mad > 0) || !std::isfinite(k_mad) || !keep)
     return fail(ctx, SPIDER_E_INVALID, "need k_mad > 0 and a keep array");
   const int64_t N = cat->N;
-  const int64_t CH = std::min<int64_t>(N, (int64_t)1 << 22);
   DevBuf r, d, srt, idx, temp, cnt;
   HIPCK(hipStreamSynchronize(ctx->stream), "sync");
   HIPCK(r.alloc((size_t)N * 8), "alloc residuals");
   HIPCK(d.alloc((size_t)N * 8), "alloc residuals");
   HIPCK(srt.alloc((size_t)N * 8), "alloc residuals");
-  HIPCK(idx.alloc((size_t)CH * 8), "alloc residuals");
-  HIPCK(cnt.alloc(16), "alloc residuals");
-  int rc = reset_err_flag(ctx);
+  HIPCK(cnt.alloc(16), "alloc count");
+  rc = reset_err_flag(ctx);
   if (rc) return rc;
-  const double* theta = cat->theta.as<double>() + (size_t)cat->M * 4 * chain;
-  // residuals of every observation at the chain's state, in chunks
-  for (int64_t start = 0; start < N; start += CH) {
-    const int64_t len = std::min(CH, N - start);
-    launch_iota(idx.as<int64_t>(), start, len, ctx->stream);
-    rc = run_batch(ctx, *cat, *net, precision, 1, len, theta, (int64_t)cat->M * 4,
-                   idx.as<int64_t>(), 0, nullptr, 0, 0, false, 1.0, true);
-    if (rc) return rc;
-    HIPCK(hipMemcpyAsync(r.as<double>() + start, ctx->ws.r.p, (size_t)len * 8,
-                         hipMemcpyDeviceToDevice, ctx->stream),
-          "copy residuals");
-  }
+  // residuals of every observation at the chain's state
+  rc = over_all_observations(ctx, *cat, *net, precision, chain, idx,
+                             [&](int64_t start, int64_t len, const double*) -> int {
+                               HIPCK(hipMemcpyAsync(r.as<double>() + start, ctx->ws.r.p,
+                                                    (size_t)len * 8, hipMemcpyDeviceToDevice,
+                                                    ctx->stream),
+                                     "copy residuals");
+                               return SPIDER_OK;
+                             });
+  if (rc) return rc;
   size_t tb = 0;
   HIPCK(sort_doubles(nullptr, nullptr, N, nullptr, &tb, ctx->stream), "sort size");
   HIPCK(temp.alloc(tb), "alloc sort scratch");
@@ -1178,6 +1208,38 @@ int spider_outliers(spider_ctx* ctx, int32_t cat_id, int32_t net_id, int32_t pre
   if (n_keep) *n_keep = (int64_t)kept;
   if (median) *median = med;
   if (mad) *mad = md;
+  return check_select_flag(ctx);
+}
+
+int spider_linearity(spider_ctx* ctx, int32_t cat_id, int32_t net_id, int32_t precision,
+                     int32_t chain, double max_rel_err, uint8_t* keep, int64_t* n_keep) {
+  if (!ctx) return SPIDER_E_INVALID;
+  DeviceGuard g(ctx->device);
+  Catalog* cat;
+  Net* net;
+  int rc = screening_args(ctx, cat_id, net_id, precision, chain, cat, net);
+  if (rc) return rc;
+  if (!(max_rel_err >= 0) || !std::isfinite(max_rel_err) || !keep)
+    return fail(ctx, SPIDER_E_INVALID, "need max_rel_err >= 0 and a keep array");
+  DevBuf idx, cnt;
+  HIPCK(hipStreamSynchronize(ctx->stream), "sync");
+  HIPCK(cnt.alloc(16), "alloc count");
+  rc = reset_err_flag(ctx);
+  if (rc) return rc;
+  HIPCK(hipMemsetAsync(cnt.p, 0, 8, ctx->stream), "count");
+  rc = over_all_observations(ctx, *cat, *net, precision, chain, idx,
+                             [&](int64_t start, int64_t len, const double* theta) -> int {
+                               launch_linear_keep(ctx->ws.batch(), theta, len, max_rel_err,
+                                                  keep + start, (unsigned long long*)cnt.p,
+                                                  ctx->stream);
+                               HIPCK(hipGetLastError(), "linearity kernel");
+                               return SPIDER_OK;
+                             });
+  if (rc) return rc;
+  unsigned long long kept = 0;
+  HIPCK(hipMemcpyAsync(&kept, cnt.p, 8, hipMemcpyDeviceToHost, ctx->stream), "count");
+  HIPCK(hipStreamSynchronize(ctx->stream), "sync");
+  if (n_keep) *n_keep = (int64_t)kept;
   return check_select_flag(ctx);
 }
 

@@ -262,6 +262,10 @@ void launch_iota(int64_t* idx, int64_t start, int64_t len, hipStream_t s);
 void launch_absdev(const double* r, int64_t N, double med, double* d, hipStream_t s);
 void launch_keep(const double* r, int64_t N, double med, double thr, uint8_t* keep,
                  unsigned long long* count, hipStream_t s);
+// Linear-regime screening of one chain's batch: keep[q] = |dT - lin| <= e_max
+// |dT| with dT = T_j - T_i and lin = grad T(x_i) . (x_j - x_i).
+void launch_linear_keep(const BatchBufs& b, const double* theta, int64_t n, double e_max,
+                        uint8_t* keep, unsigned long long* count, hipStream_t s);
 hipError_t sort_doubles(const double* in, double* out, int64_t N, void* temp, size_t* temp_bytes,
                         hipStream_t s);
 

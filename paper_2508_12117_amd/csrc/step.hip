@@ -878,16 +878,9 @@ __global__ void k_absdev(const double* r, int64_t N, double med, double* d) {
   if (t < N) d[t] = fabs(r[t] - med);
 }
 
-// keep[i] = |r_i - med| <= thr; the kept count is added to *count.
-__global__ void k_keep(const double* r, int64_t N, double med, double thr, uint8_t* keep,
-                       unsigned long long* count) {
+// Adds the block's sum of k (one value per thread) to *count.
+__device__ void block_count_add(unsigned int k, unsigned long long* count) {
   __shared__ unsigned int sh[kBlock];
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  unsigned int k = 0;
-  if (t < N) {
-    k = fabs(r[t] - med) <= thr ? 1u : 0u;
-    keep[t] = (uint8_t)k;
-  }
   sh[threadIdx.x] = k;
   __syncthreads();
   for (int w = kBlock / 2; w > 0; w >>= 1) {
@@ -895,6 +888,37 @@ __global__ void k_keep(const double* r, int64_t N, double med, double thr, uint8
     __syncthreads();
   }
   if (threadIdx.x == 0 && sh[0]) atomicAdd(count, (unsigned long long)sh[0]);
+}
+
+// keep[i] = |r_i - med| <= thr; the kept count is added to *count.
+__global__ void k_keep(const double* r, int64_t N, double med, double thr, uint8_t* keep,
+                       unsigned long long* count) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned int k = 0;
+  if (t < N) {
+    k = fabs(r[t] - med) <= thr ? 1u : 0u;
+    keep[t] = (uint8_t)k;
+  }
+  block_count_add(k, count);
+}
+
+// Linear-regime test of the n slots of one chain's batch (rows 2q, 2q + 1 =
+// events i, j): dT = T_j - T_i, lin = grad T(x_i) . (x_j - x_i), keep[q] =
+// |dT - lin| <= e_max |dT|; the kept count is added to *count.
+__global__ void k_linear_keep(const BatchBufs b, const double* theta, int64_t n, double e_max,
+                              uint8_t* keep, unsigned long long* count) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned int k = 0;
+  if (q < n) {
+    const double* xi = theta + (int64_t)b.ev[2 * q] * 4;
+    const double* xj = theta + (int64_t)b.ev[2 * q + 1] * 4;
+    const double* g = b.gT + 6 * q;
+    const double dT = b.T[2 * q + 1] - b.T[2 * q];
+    const double lin = g[0] * (xj[0] - xi[0]) + g[1] * (xj[1] - xi[1]) + g[2] * (xj[2] - xi[2]);
+    k = fabs(dT - lin) <= e_max * fabs(dT) ? 1u : 0u;
+    keep[q] = (uint8_t)k;
+  }
+  block_count_add(k, count);
 }
 
 }  // namespace
@@ -1196,6 +1220,13 @@ void launch_keep(const double* r, int64_t N, double med, double thr, uint8_t* ke
                  unsigned long long* count, hipStream_t s) {
   if (N == 0) return;
   hipLaunchKernelGGL(k_keep, dim3(grid_for(N)), dim3(kBlock), 0, s, r, N, med, thr, keep, count);
+}
+
+void launch_linear_keep(const BatchBufs& b, const double* theta, int64_t n, double e_max,
+                        uint8_t* keep, unsigned long long* count, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_linear_keep, dim3(grid_for(n)), dim3(kBlock), 0, s, b, theta, n, e_max,
+                     keep, count);
 }
 
 hipError_t sort_doubles(const double* in, double* out, int64_t N, void* temp, size_t* temp_bytes,

@@ -94,6 +94,8 @@ _SIGS = {
     "spider_outliers": ([_P, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_double, _P,
                          ct.POINTER(ct.c_int64), ct.POINTER(ct.c_double), ct.POINTER(ct.c_double)],
                         ct.c_int),
+    "spider_linearity": ([_P, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_double, _P,
+                          ct.POINTER(ct.c_int64)], ct.c_int),
     "spider_moments": ([_P, ct.c_int32, ct.c_int32, _P, _P, ct.POINTER(ct.c_int64)], ct.c_int),
     "spider_get_state": ([_P, ct.c_int32, ct.c_int32, _P, _P, ct.POINTER(ct.c_int64)], ct.c_int),
     "spider_set_state": ([_P, ct.c_int32, ct.c_int32, _P, _P, ct.c_int64], ct.c_int),
@@ -310,6 +312,17 @@ class Context:
         self._check(lib().spider_outliers(self._h, cat_id, net_id, precision, chain, k_mad,
                                           _ptr(keep), ct.byref(n), ct.byref(med), ct.byref(mad)))
         return keep, n.value, med.value, mad.value
+
+    def linearity(self, cat_id, net_id, chain=0, max_rel_err=0.05, precision=FP32):
+        """Linear-regime data filter at a chain's state: (keep [N] uint8
+        device tensor, kept count)."""
+        torch = self._torch
+        keep = torch.empty(self._n_obs.get(cat_id, 0), dtype=torch.uint8,
+                           device=f"cuda:{self.device}")
+        n = ct.c_int64()
+        self._check(lib().spider_linearity(self._h, cat_id, net_id, precision, chain,
+                                           max_rel_err, _ptr(keep), ct.byref(n)))
+        return keep, n.value
 
     def sgld_stages(self, sets, warmup, ramp, sample, thin=1, **kw):
         """The sampler stages that follow the initial solution (Sec. 3.2):

@@ -13,7 +13,7 @@ import pytest
 from gpu_common import (dev, grad_scale, host, lk, make_ctx, psgld_update_tolerance,
                         scaled_grad_error, spider, synth, torch, whitening_residual)
 from oracle import batch as obatch
-from oracle import philox, sampler, stage1
+from oracle import linearity, philox, sampler, stage1
 from oracle import travel_time as ott
 
 pytestmark = pytest.mark.gpu
@@ -393,6 +393,69 @@ def test_screened_catalog_reloads(ctx, tiny_setup):
     ctx.sgld_steps([(fid, nid, 1, 1024, spider.FP32)], 5, seed=4)
     th = torch.empty(sub.M, 4, dtype=torch.float64, device="cuda")
     assert ctx.get_state(fid, 0, th) == 5 and np.all(np.isfinite(host(th)))
+
+
+
+@pytest.mark.parametrize("prec", [spider.FP32, spider.BF16])
+def test_linearity_filter_matches_oracle(ctx, tiny_setup, prec):
+    """Keep mask of the linear-regime filter (|dT - lin| <= 5% |dT|) at a
+    chain's state.  (a) It is the mask of the GPU's own T_i, T_j and grad
+    T(x_i) of the same precision.  (b) With T within 1e-5 relative and grad T
+    within 1e-5 of its norm (FP32; the BF16 bounds for BF16), the margin
+    |dT - lin| - 0.05 |dT| moves by at most 1.05 dT_err + lin_err, so
+    verdicts agree with the oracle's wherever its margin exceeds that."""
+    cat, net, cid, nid = tiny_setup
+    ctx.reset_chains(cid, 2)
+    theta = synth.random_theta(cat, 71)
+    ctx.set_state(cid, 1, dev(theta))
+    keep, n_keep = ctx.linearity(cid, nid, chain=1, max_rel_err=0.05, precision=prec)
+    keep = host(keep).astype(bool)
+    assert n_keep == keep.sum() and 0 < n_keep < cat.N
+    # (a)
+    out = ctx.batch_terms(cid, nid, dev(theta), dev(np.arange(cat.N)), precision=prec)
+    Ti, Tj, gi = host(out["T_i"]), host(out["T_j"]), host(out["gT_i"])
+    pr = cat.obs_pair
+    dx = theta[cat.pair_j[pr], 0:3] - theta[cat.pair_i[pr], 0:3]
+    dT = Tj - Ti
+    lin = np.sum(gi * dx, axis=1)
+    m = np.abs(dT - lin) - 0.05 * np.abs(dT)
+    sure = np.abs(m) > 1e-12 * (np.abs(dT) + np.abs(lin) + 1e-12)
+    np.testing.assert_array_equal(keep[sure], (m <= 0)[sure])
+    # (b)
+    prob = lk.load(cat)
+    keep_o, _ = linearity.linearity_mask(prob, net, theta, 0.05)
+    dT_o, lin_o = linearity.linearisation_terms(prob, net, theta)
+    bt = lk.batch_terms(prob, net, theta, np.arange(cat.N), lk.L1)
+    t_rel, g_rel = (1e-5, 1e-5) if prec == spider.FP32 else (BF16_T_REL, BF16_G_REL)
+    err = 1.05 * t_rel * (bt.T_i + bt.T_j) + g_rel * np.linalg.norm(bt.gT_i, axis=1) * \
+        np.linalg.norm(dx, axis=1)
+    m_o = np.abs(dT_o - lin_o) - 0.05 * np.abs(dT_o)
+    clear = np.abs(m_o) > 2 * err
+    if prec == spider.FP32:
+        assert clear.mean() > 0.95
+    np.testing.assert_array_equal(keep[clear], keep_o[clear])
+
+
+def test_linearity_filter_homogeneous_medium(ctx):
+    """With a zero-output network (T = |x - s| / 6) the GPU's verdicts are
+    the oracle's except within 1e-9 of the threshold."""
+    cat = synth.make_catalog("tiny")
+    net = synth.make_net(128, 4, center=[5.0, 5.0, 4.0], half_extent=[10.0, 10.0, 6.0],
+                         zero_output=True)
+    cid = ctx.load_catalog(cat, stream_id=3)
+    nid = ctx.load_net(net)
+    ctx.reset_chains(cid, 1)
+    keep, n_keep = ctx.linearity(cid, nid)
+    prob = lk.load(cat)
+    keep_o, _ = linearity.linearity_mask(prob, net, prob.hypo0)
+    dT, lin = linearity.linearisation_terms(prob, net, prob.hypo0)
+    clear = np.abs(np.abs(dT - lin) - 0.05 * np.abs(dT)) > 1e-9
+    assert clear.mean() > 0.999
+    np.testing.assert_array_equal(host(keep).astype(bool)[clear], keep_o[clear])
+    with pytest.raises(spider.SpiderError):
+        ctx.linearity(cid, nid, max_rel_err=-1.0)
+    with pytest.raises(spider.SpiderError):
+        ctx.linearity(cid, nid, chain=3)
 
 
 # ----------------------------------------------------------------- sampler
