@@ -90,8 +90,8 @@ int spider_sync(spider_ctx* ctx);
 /* ---- catalog (Sec. 3.1: M events, L stations, dd observations) --------- */
 typedef struct {
   int32_t M;                /* events, >= 2                                    */
-  int32_t L;                /* stations, >= 1; group g of an observation is its
-                               station (one phase)                            */
+  int32_t L;                /* stations, >= 1; the group g of an observation is
+                               its station + L * phase (Sec. 3.1)            */
   int32_t P;                /* event pairs, >= 1                              */
   int64_t N;                /* observations, >= 1                             */
   int32_t mem;              /* SPIDER_MEM_HOST or _DEVICE for every array     */
@@ -103,8 +103,8 @@ typedef struct {
   const int32_t* obs_pair;  /* [N] pair of each observation, in [0, P)        */
   const int16_t* obs_sta;   /* [N] station of each observation, in [0, L)     */
   const float* obs_dt;      /* [N] observed differential time tau_n (s)       */
-  double sigma;             /* IID noise s.d. sigma_phi (s), > 0              */
-  double kappa;             /* shared-event s.d. kappa_phi (s), >= 0          */
+  double sigma;             /* IID noise s.d. sigma_P (s), > 0                */
+  double kappa;             /* shared-event s.d. kappa_P (s), >= 0            */
   double p;                 /* weight decay exponent p (eq:correlation_decay) */
   double ell;               /* weight length scale ell (km), > 0              */
   double eps_w;             /* weight floor epsilon, > 0                      */
@@ -112,6 +112,13 @@ typedef struct {
   double centroid_sigma[4]; /* centroid prior s.d., > 0                       */
   uint32_t stream;          /* random-stream id of this catalog, < 2^24       */
   int32_t whiten;           /* SPIDER_WHITEN_*                                */
+  const int8_t* obs_phase;  /* [N] phase of each observation, 0 = P, 1 = S, or
+                               NULL for all P.  A catalog with S observations
+                               has 2L groups and needs an S network
+                               (spider_set_phase_net)                          */
+  double sigma_s;           /* S-phase sigma_S (s), > 0 (two phases only)      */
+  double kappa_s;           /* S-phase kappa_S (s), >= 0, and > 0 exactly when
+                               kappa > 0 (two phases only)                     */
 } spider_catalog_desc;
 
 /* Load a catalog (Sec. 3.1).  Copies every array to the device, then on the
@@ -123,6 +130,16 @@ typedef struct {
  * source lies within 1e-3 km of its station; SPIDER_E_OOM; SPIDER_E_HIP.
  * Synchronous (the arrays may be reused when it returns). */
 int spider_load_catalog(spider_ctx* ctx, const spider_catalog_desc* desc, int32_t* cat_id);
+
+/* The S-phase travel-time network of a two-phase catalog (Sec. 3.1: one
+ * forward model per phase): every later call that evaluates the catalog's
+ * observations runs its S rows through `net_id` and its P rows through the
+ * network the call names, in the call's precision.  Two-phase catalogs are
+ * stepped one chain set at a time (never fused with other catalogs), and
+ * each minibatch waits once for the count of its P rows.  Calls on a
+ * two-phase catalog without one fail with SPIDER_E_STATE.
+ * Errors: SPIDER_E_INVALID (ids). */
+int spider_set_phase_net(spider_ctx* ctx, int32_t cat_id, int32_t net_id);
 
 /* ---- travel-time network (Sec. 3.2: EikoNet; Sec. 5: any differentiable T)
  * u = ((x - center)/half_extent, (s - center)/half_extent)   (6 inputs)

@@ -18,17 +18,20 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import travel_time as tt
+from . import likelihood as lk
 
 
 def linearisation_terms(prob, net, theta):
-    """dT and lin of every observation at the state theta [M,4]."""
+    """dT and lin of every observation at the state theta [M,4] (net: the
+    network, or the (P, S) pair of a two-phase catalog)."""
     pr = prob.obs_pair
     xi = theta[prob.pair_i[pr], 0:3]
     xj = theta[prob.pair_j[pr], 0:3]
     s = prob.stations[prob.obs_sta]
-    Ti, gi = tt.travel_time(net, xi, s)
-    Tj, _ = tt.travel_time(net, xj, s)
+    ph = getattr(prob, "obs_phase", None)
+    ph = np.zeros(len(pr), np.int64) if ph is None else ph
+    Ti, gi = lk.travel_times(net, ph, xi, s)
+    Tj, _ = lk.travel_times(net, ph, xj, s)
     dT = Tj - Ti
     lin = np.sum(gi * (xj - xi), axis=1)
     return dT, lin

@@ -55,6 +55,10 @@ struct Catalog {
   uint32_t stream = 0;
   int whiten = SPIDER_WHITEN_EXACT;
   double sigma = 0, kappa = 0, prior_sigma[4] = {}, centroid_sigma[4] = {};
+  // two phases: L = 2 L_p groups (station + L_p phase), stations duplicated
+  int32_t L_p = 0;
+  double zscale_s = 1.0;  // sigma_P^2 / sigma_S^2
+  int net_s = -1;         // S-phase network (spider_set_phase_net)
   DevBuf hypo0, stations, pairs, w_pair, obs, inv_mean, mu_c;
   int C = 0;  // chains allocated
   DevBuf theta, v, mean, m2, steps, mcount;
@@ -76,6 +80,8 @@ struct Catalog {
     c.stream = stream;
     c.sigma = sigma;
     c.kappa = kappa;
+    c.L_p = L_p;
+    c.zscale_s = zscale_s;
     for (int k = 0; k < 4; ++k) {
       c.prior_sigma[k] = prior_sigma[k];
       c.centroid_sigma[k] = centroid_sigma[k];
@@ -120,6 +126,7 @@ struct Workspace {
   DevBuf key_in, key_out, val_in, val_out, temp, node_of, node_start, seg_begin, seg_end, flags,
       vec, ivec, count;
   DevBuf G, partial, thetabar, lp_tmp, err;
+  DevBuf ptemp;  // scratch of the two-phase row partition
   size_t temp_bytes = 0;
 
   hipError_t reserve(int64_t C, int64_t Cn, int64_t CM, int64_t CL) {
@@ -393,10 +400,45 @@ int run_batch(spider_ctx* ctx, Catalog& cat, Net& net, int prec, int C, int64_t 
   src.stations = cv.stations;
   src.x = nullptr;
   src.s = nullptr;
-  int rc = run_network(ctx, net, prec, src, b.net_out);
-  if (rc != SPIDER_OK) return rc;
+  Net* net_s = &net;
+  int rc;
+  if (cat.L_p < cat.L) {
+    // two phases: the P rows through net and the S rows through the
+    // catalog's S network, each launch over a list of rows
+    net_s = get_net(ctx, cat.net_s);
+    if (!net_s)
+      return fail(ctx, SPIDER_E_STATE, "two-phase catalog without an S network "
+                                       "(spider_set_phase_net)");
+    const int64_t E = 2 * Cn;
+    int32_t* list = ws.flags.as<int32_t>();
+    RowOut* compact = (RowOut*)ws.vec.p;
+    uint64_t* cnt = (uint64_t*)ws.count.p;
+    size_t tb = 0;
+    HIPCK(partition_rows_by_phase(b.sta, cat.L_p, E, list, cnt, nullptr, &tb, ctx->stream),
+          "phase partition size");
+    HIPCK(ws.ptemp.reserve(tb), "phase partition scratch");
+    HIPCK(partition_rows_by_phase(b.sta, cat.L_p, E, list, cnt, ws.ptemp.p, &tb, ctx->stream),
+          "phase partition");
+    uint64_t n_p = 0;
+    HIPCK(hipMemcpyAsync(&n_p, cnt, 8, hipMemcpyDeviceToHost, ctx->stream), "phase count");
+    HIPCK(hipStreamSynchronize(ctx->stream), "phase count");
+    src.mode = 3;
+    src.list = list;
+    src.rows = (int64_t)n_p;
+    rc = run_network(ctx, net, prec, src, compact);
+    if (rc != SPIDER_OK) return rc;
+    src.list = list + n_p;
+    src.rows = E - (int64_t)n_p;
+    rc = run_network(ctx, *net_s, prec, src, compact + n_p);
+    if (rc != SPIDER_OK) return rc;
+    launch_scatter_rows(compact, list, E, b.net_out, ctx->stream);
+  } else {
+    rc = run_network(ctx, net, prec, src, b.net_out);
+    if (rc != SPIDER_OK) return rc;
+  }
   const int whiten = l1 ? kWhitenL1 : cat.kappa == 0.0 ? SPIDER_WHITEN_NONE : cat.whiten;
-  launch_residual(cv, net.view(prec), C, n, theta, theta_stride, whiten, b, ctx->stream);
+  launch_residual(cv, net.view(prec), net_s->view(prec), C, n, theta, theta_stride, whiten, b,
+                  ctx->stream);
   if (whiten == SPIDER_WHITEN_EXACT)
     HIPCK(exact_whiten(cv, C, n, b, ws.sort(), ctx->stream), "exact whitening");
   if (grad)
@@ -504,8 +546,9 @@ int fused_step(spider_ctx* ctx, const spider_chainset* sets, int n_sets, const F
     const CatView cv = cat.view();
     const BatchBufs bk = batch_at(b, f.obs_off[k]);
     const int whiten = cat.kappa == 0.0 ? SPIDER_WHITEN_NONE : cat.whiten;
-    launch_residual(cv, net.view(st.precision), C, n, cat.theta.as<double>(), (int64_t)cat.M * 4,
-                    whiten, bk, ctx->stream);
+    const NetView nv = net.view(st.precision);
+    launch_residual(cv, nv, nv, C, n, cat.theta.as<double>(), (int64_t)cat.M * 4, whiten, bk,
+                    ctx->stream);
     if (whiten == SPIDER_WHITEN_EXACT)
       HIPCK(exact_whiten(cv, C, n, bk, ws.sort(), ctx->stream), "exact whitening");
     HIPCK(reduce_events(cv, C, n, (double)cat.N / (double)n, bk, ws.sort(), ws.G.as<double>(),
@@ -653,10 +696,26 @@ int spider_load_catalog(spider_ctx* ctx, const spider_catalog_desc* d, int32_t* 
   if (d->stream >= (1u << 24)) return fail(ctx, SPIDER_E_INVALID, "stream id must be < 2^24");
   if (d->whiten < SPIDER_WHITEN_NONE || d->whiten > SPIDER_WHITEN_EXACT)
     return fail(ctx, SPIDER_E_INVALID, "unknown whitening mode");
+  std::vector<int8_t> phase;
+  bool two_phase = false;
+  if (d->obs_phase) {
+    HIPCK(fetch(phase, d->obs_phase, d->N, d->mem, ctx->stream), "read obs_phase");
+    for (int8_t ph : phase) {
+      if (ph != 0 && ph != 1) return fail(ctx, SPIDER_E_INVALID, "phase must be 0 (P) or 1 (S)");
+      two_phase |= ph == 1;
+    }
+  }
+  if (two_phase && (!(d->sigma_s > 0) || !(d->kappa_s >= 0) || !std::isfinite(d->sigma_s) ||
+                    !std::isfinite(d->kappa_s) || (d->kappa_s > 0) != (d->kappa > 0)))
+    return fail(ctx, SPIDER_E_INVALID,
+                "need sigma_s > 0, kappa_s >= 0, and kappa_s > 0 exactly when kappa > 0");
+  const int32_t Lg = two_phase ? 2 * d->L : d->L;  // station-phase groups
 
   auto cat = std::make_unique<Catalog>();
   cat->M = d->M;
-  cat->L = d->L;
+  cat->L = Lg;
+  cat->L_p = d->L;
+  if (two_phase) cat->zscale_s = (d->sigma * d->sigma) / (d->sigma_s * d->sigma_s);
   cat->P = d->P;
   cat->N = d->N;
   cat->stream = d->stream;
@@ -669,7 +728,15 @@ int spider_load_catalog(spider_ctx* ctx, const spider_catalog_desc* d, int32_t* 
   }
   hipStream_t s = ctx->stream;
   HIPCK(upload(cat->hypo0, d->hypo0, (size_t)d->M * 32, d->mem, s), "upload hypo0");
-  HIPCK(upload(cat->stations, d->stations, (size_t)d->L * 24, d->mem, s), "upload stations");
+  if (two_phase) {  // the S groups' rows of the station table repeat the P ones
+    std::vector<double> st;
+    HIPCK(fetch(st, d->stations, (size_t)d->L * 3, d->mem, s), "read stations");
+    st.insert(st.end(), st.begin(), st.end());
+    HIPCK(upload(cat->stations, st.data(), st.size() * 8, SPIDER_MEM_HOST, s), "upload stations");
+    HIPCK(hipStreamSynchronize(s), "sync");
+  } else {
+    HIPCK(upload(cat->stations, d->stations, (size_t)d->L * 24, d->mem, s), "upload stations");
+  }
 
   // pairs and observations are re-packed on the host (12-byte records)
   {
@@ -691,6 +758,12 @@ int spider_load_catalog(spider_ctx* ctx, const spider_catalog_desc* d, int32_t* 
     HIPCK(fetch(od, d->obs_dt, d->N, d->mem, s), "read obs_dt");
     std::vector<Obs> obs(d->N);
     for (int64_t q = 0; q < d->N; ++q) obs[q] = Obs{op[q], od[q], (int32_t)os[q]};
+    if (two_phase)
+      for (int64_t q = 0; q < d->N; ++q) {
+        if (os[q] < 0 || os[q] >= d->L)
+          return fail(ctx, SPIDER_E_INVALID, "event, pair or station id out of range, or i == j");
+        obs[q].sta += d->L * phase[q];
+      }
     HIPCK(upload(cat->obs, obs.data(), obs.size() * sizeof(Obs), SPIDER_MEM_HOST, s),
           "upload observations");
     HIPCK(hipStreamSynchronize(s), "sync");
@@ -699,7 +772,7 @@ int spider_load_catalog(spider_ctx* ctx, const spider_catalog_desc* d, int32_t* 
   DevBuf bad;
   HIPCK(bad.alloc(16), "alloc");
   HIPCK(hipMemsetAsync(bad.p, 0, 16, s), "memset");
-  launch_validate(cat->hypo0.as<double>(), d->M, cat->stations.as<double>(), d->L,
+  launch_validate(cat->hypo0.as<double>(), d->M, cat->stations.as<double>(), Lg,
                   cat->pairs.as<int2>(), d->P, cat->obs.as<Obs>(), d->N, bad.as<int>(), s);
   int flag = 0;
   HIPCK(hipMemcpyAsync(&flag, bad.p, sizeof(int), hipMemcpyDeviceToHost, s), "read flag");
@@ -709,18 +782,42 @@ int spider_load_catalog(spider_ctx* ctx, const spider_catalog_desc* d, int32_t* 
   if (flag & 4) return fail(ctx, SPIDER_E_INVALID, "an initial source lies within 1e-3 km of its station");
 
   HIPCK(cat->w_pair.alloc((size_t)d->P * 8), "alloc w_pair");
-  HIPCK(cat->inv_mean.alloc((size_t)d->L * 8), "alloc inv_mean");
+  HIPCK(cat->inv_mean.alloc((size_t)Lg * 8), "alloc inv_mean");
   HIPCK(cat->mu_c.alloc(32), "alloc mu_c");
   launch_pair_weights(cat->hypo0.as<double>(), cat->pairs.as<int2>(), d->P, d->ell, d->p, d->eps_w,
                       cat->w_pair.as<double>(), s);
-  HIPCK(group_inverse_mean(cat->obs.as<Obs>(), d->N, d->L, cat->w_pair.as<double>(),
+  HIPCK(group_inverse_mean(cat->obs.as<Obs>(), d->N, Lg, cat->w_pair.as<double>(),
                            cat->inv_mean.as<double>(), s),
         "group means");
+  if (two_phase && d->kappa > 0) {
+    // Sigma_g of an S group = (sigma_S^2 / sigma_P^2) times the P-phase form
+    // sigma_P^2 I + kappa_P^2 W'^1/2 A A^T W'^1/2 with W' = rho W: the S
+    // weights carry rho, and z of an S row is scaled by sigma_P^2 / sigma_S^2
+    const double rho = (d->kappa_s * d->kappa_s * d->sigma * d->sigma) /
+                       (d->sigma_s * d->sigma_s * d->kappa * d->kappa);
+    std::vector<double> im(Lg);
+    HIPCK(hipMemcpyAsync(im.data(), cat->inv_mean.p, (size_t)Lg * 8, hipMemcpyDeviceToHost, s),
+          "read group means");
+    HIPCK(hipStreamSynchronize(s), "sync");
+    for (int32_t g2 = d->L; g2 < Lg; ++g2) im[g2] *= rho;
+    HIPCK(hipMemcpyAsync(cat->inv_mean.p, im.data(), (size_t)Lg * 8, hipMemcpyHostToDevice, s),
+          "write group means");
+    HIPCK(hipStreamSynchronize(s), "sync");
+  }
   launch_mean4(cat->hypo0.as<double>(), d->M, cat->mu_c.as<double>(), s);
   HIPCK(hipGetLastError(), "load kernels");
   HIPCK(hipStreamSynchronize(s), "load");
   ctx->cats.push_back(std::move(cat));
   *cat_id = (int32_t)ctx->cats.size() - 1;
+  return SPIDER_OK;
+}
+
+int spider_set_phase_net(spider_ctx* ctx, int32_t cat_id, int32_t net_id) {
+  if (!ctx) return SPIDER_E_INVALID;
+  Catalog* cat = get_cat(ctx, cat_id);
+  if (!cat || !get_net(ctx, net_id))
+    return fail(ctx, SPIDER_E_INVALID, "unknown catalog or network id");
+  cat->net_s = net_id;
   return SPIDER_OK;
 }
 
@@ -1008,11 +1105,15 @@ int spider_sgld_steps(spider_ctx* ctx, const spider_chainset* sets, int32_t n_se
   ua.seed = cfg->seed;
   ua.burn = cfg->burn_in;
   ua.thin = cfg->thin;
-  // sets sharing one network and precision (and no catalog twice) advance in
-  // fused steps
+  // sets sharing one network and precision (and no catalog twice, no
+  // two-phase catalog) advance in fused steps
   bool fuse = n_sets > 1;
   for (int k = 1; k < n_sets && fuse; ++k)
     fuse = sets[k].net_id == sets[0].net_id && sets[k].precision == sets[0].precision;
+  for (int k = 0; k < n_sets && fuse; ++k) {
+    const Catalog* c = get_cat(ctx, sets[k].cat_id);
+    fuse = c && c->L_p == c->L;
+  }
   for (int k = 0; k < n_sets && fuse; ++k)
     for (int j = 0; j < k && fuse; ++j) fuse = sets[j].cat_id != sets[k].cat_id;
   if (fuse && cfg->n_steps > 0) {

@@ -20,7 +20,7 @@ struct Obs {
 //          are the rows of the mode-0 source sub[k] (device table, nsub
 //          entries, sub_row0[nsub] = rows).
 struct RowSource {
-  int mode;
+  int mode;  // 0 catalog rows, 1 explicit x/s, 2 several mode-0 sources, 3 listed catalog rows
   int nsub;
   const RowSource* sub;
   const int64_t* sub_row0;
@@ -33,6 +33,7 @@ struct RowSource {
   const double* stations;
   const double* x;
   const double* s;
+  const int32_t* list;  // mode 3: row r of the launch is catalog row list[r]
 };
 
 // Network as the kernels see it (device pointers).
@@ -75,7 +76,8 @@ __device__ inline void row_inputs(const RowSource& src_in, const NetView& net, i
     sp = src_in.sub + lo;
   }
   const RowSource& src = *sp;
-  if (src.mode == 0) {
+  if (src.mode == 0 || src.mode == 3) {
+    if (src.mode == 3) r = src.list[r];
     const int64_t c = r / src.rows_per_chain;
     const double* th = src.theta + c * src.theta_chain_stride + (int64_t)src.ev[r] * 4;
     const double* st = src.stations + (int64_t)src.sta[r] * 3;
@@ -123,6 +125,11 @@ struct CatView {
   const double* mu_c;      // [4] centroid prior mean
   uint32_t stream;
   double sigma, kappa;
+  // Two-phase catalogs: groups g >= L_p are S groups (L_p = L otherwise);
+  // their edge weights carry the factor that maps Sigma_g onto the P
+  // phase's sigma and kappa, and their z is multiplied by zscale_s.
+  int32_t L_p;
+  double zscale_s;
   double prior_sigma[4], centroid_sigma[4];
 };
 
@@ -200,7 +207,7 @@ void launch_mean4(const double* a, int64_t rows, double* out, hipStream_t s);
 void launch_select(const CatView& cat, int C, int64_t n, const int64_t* idx, uint64_t seed,
                    const int64_t* steps, int64_t step_scalar, int chain0, BatchBufs b,
                    int* err_flag, hipStream_t s);
-void launch_residual(const CatView& cat, const NetView& net, int C, int64_t n,
+void launch_residual(const CatView& cat, const NetView& net, const NetView& net_s, int C, int64_t n,
                      const double* theta, int64_t theta_stride, int whiten, BatchBufs b,
                      hipStream_t s);
 // Exact whitening z = Sigma_B^{-1} r by Woodbury + a per-(chain, group)
@@ -266,6 +273,13 @@ void launch_keep(const double* r, int64_t N, double med, double thr, uint8_t* ke
 // |dT| with dT = T_j - T_i and lin = grad T(x_i) . (x_j - x_i).
 void launch_linear_keep(const BatchBufs& b, const double* theta, int64_t n, double e_max,
                         uint8_t* keep, unsigned long long* count, hipStream_t s);
+// Two-phase catalogs: list = the E rows with group < L_p (P) in order, then
+// the others (S) in reverse order; *count = the number of P rows.
+hipError_t partition_rows_by_phase(const int32_t* sta, int32_t L_p, int64_t E, int32_t* list,
+                                   uint64_t* count, void* temp, size_t* temp_bytes, hipStream_t s);
+// out[list[v]] = compact[v] for v < E.
+void launch_scatter_rows(const RowOut* compact, const int32_t* list, int64_t E, RowOut* out,
+                         hipStream_t s);
 hipError_t sort_doubles(const double* in, double* out, int64_t N, void* temp, size_t* temp_bytes,
                         hipStream_t s);
 

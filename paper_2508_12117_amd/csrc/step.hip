@@ -194,13 +194,14 @@ __device__ inline void assemble_tt(const NetView& net, const double x[3], const 
   g[2] = a * d2 + bsc * ((double)no.d2 * net.inv_half[2]);
 }
 
-__global__ void k_residual(CatView cat, NetView net, int C, int64_t n, const double* theta,
-                           int64_t theta_stride, int whiten, BatchBufs b) {
+__global__ void k_residual(CatView cat, NetView net, NetView net_s, int C, int64_t n,
+                           const double* theta, int64_t theta_stride, int whiten, BatchBufs b) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= (int64_t)C * n) return;
   const int c = (int)(q / n);
   const double* th = theta + (int64_t)c * theta_stride;
   double T[2], tt[2];
+  const bool s_phase = b.sta[2 * q] >= cat.L_p;
   for (int side = 0; side < 2; ++side) {
     const int64_t row = 2 * q + side;
     const double* xe = th + (int64_t)b.ev[row] * 4;
@@ -208,7 +209,7 @@ __global__ void k_residual(CatView cat, NetView net, int C, int64_t n, const dou
     const double x[3] = {xe[0], xe[1], xe[2]};
     const double s[3] = {st[0], st[1], st[2]};
     double g[3];
-    assemble_tt(net, x, s, b.net_out[row], T[side], g);
+    assemble_tt(s_phase ? net_s : net, x, s, b.net_out[row], T[side], g);
     b.T[row] = T[side];
     b.gT[row * 3 + 0] = g[0];
     b.gT[row * 3 + 1] = g[1];
@@ -221,9 +222,9 @@ __global__ void k_residual(CatView cat, NetView net, int C, int64_t n, const dou
   if (whiten == kWhitenL1) {
     b.z[q] = r > 0.0 ? 1.0 : (r < 0.0 ? -1.0 : 0.0);  // d|r|/dr, 0 at 0
   } else if (whiten == 0 || cat.kappa == 0.0) {
-    b.z[q] = r / s2;
+    b.z[q] = r / s2 * (s_phase ? cat.zscale_s : 1.0);
   } else if (whiten == 1) {
-    b.z[q] = r / (s2 + 2.0 * cat.kappa * cat.kappa * b.w[q]);
+    b.z[q] = r / (s2 + 2.0 * cat.kappa * cat.kappa * b.w[q]) * (s_phase ? cat.zscale_s : 1.0);
   }
 }
 
@@ -581,12 +582,13 @@ __global__ __launch_bounds__(TB) void k_tree_solve(SolveArgs a) {
 }
 
 __global__ void k_exact_z(int64_t Q, double s2, const double* w, const double* r,
-                          const int32_t* node_of, const double* y, double* z) {
+                          const int32_t* node_of, const double* y, const int32_t* sta,
+                          int32_t L_p, double zscale_s, double* z) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= Q) return;
   const double yi = y[node_of[2 * q]];
   const double yj = y[node_of[2 * q + 1]];
-  z[q] = (r[q] - sqrt(w[q]) * (yi - yj)) / s2;
+  z[q] = (r[q] - sqrt(w[q]) * (yi - yj)) / s2 * (sta[2 * q] >= L_p ? zscale_s : 1.0);
 }
 
 // ---- per-event reduction
@@ -986,11 +988,39 @@ void launch_select(const CatView& cat, int C, int64_t n, const int64_t* idx, uin
                      err_flag);
 }
 
-void launch_residual(const CatView& cat, const NetView& net, int C, int64_t n,
+void launch_residual(const CatView& cat, const NetView& net, const NetView& net_s, int C, int64_t n,
                      const double* theta, int64_t theta_stride, int whiten, BatchBufs b,
                      hipStream_t s) {
-  hipLaunchKernelGGL(k_residual, dim3(grid_for((int64_t)C * n)), dim3(kBlock), 0, s, cat, net, C,
-                     n, theta, theta_stride, whiten, b);
+  hipLaunchKernelGGL(k_residual, dim3(grid_for((int64_t)C * n)), dim3(kBlock), 0, s, cat, net,
+                     net_s, C, n, theta, theta_stride, whiten, b);
+}
+
+namespace {
+struct PhaseIsP {
+  const int32_t* sta;
+  int32_t L_p;
+  __device__ bool operator()(int32_t row) const { return sta[row] < L_p; }
+};
+
+__global__ void k_scatter_rows(const RowOut* compact, const int32_t* list, int64_t E,
+                               RowOut* out) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < E) out[list[v]] = compact[v];
+}
+}  // namespace
+
+hipError_t partition_rows_by_phase(const int32_t* sta, int32_t L_p, int64_t E, int32_t* list,
+                                   uint64_t* count, void* temp, size_t* temp_bytes,
+                                   hipStream_t s) {
+  return rocprim::partition(temp, *temp_bytes, rocprim::counting_iterator<int32_t>(0), list,
+                            count, (size_t)E, PhaseIsP{sta, L_p}, s);
+}
+
+void launch_scatter_rows(const RowOut* compact, const int32_t* list, int64_t E, RowOut* out,
+                         hipStream_t s) {
+  if (E == 0) return;
+  hipLaunchKernelGGL(k_scatter_rows, dim3(grid_for(E)), dim3(kBlock), 0, s, compact, list, E,
+                     out);
 }
 
 size_t sort_temp_bytes(int64_t entries) {
@@ -1092,7 +1122,8 @@ hipError_t exact_whiten(const CatView& cat, int C, int64_t n, BatchBufs b, SortB
                      a.wgt, a.A, a.b, a.y, a.state);
   hipLaunchKernelGGL(k_tree_solve<kTreeBlock>, dim3((unsigned)(C * cat.L)), dim3(kTreeBlock), 0, s, a);
   hipLaunchKernelGGL(k_exact_z, dim3(grid_for((int64_t)C * n)), dim3(kBlock), 0, s,
-                     (int64_t)C * n, cat.sigma * cat.sigma, b.w, b.r, sb.node_of, a.y, b.z);
+                     (int64_t)C * n, cat.sigma * cat.sigma, b.w, b.r, sb.node_of, a.y, b.sta,
+                     cat.L_p, cat.zscale_s, b.z);
   return hipGetLastError();
 }
 

@@ -43,7 +43,8 @@ class CatalogDesc(ct.Structure):
                 ("sigma", ct.c_double), ("kappa", ct.c_double), ("p", ct.c_double),
                 ("ell", ct.c_double), ("eps_w", ct.c_double),
                 ("prior_sigma", ct.c_double * 4), ("centroid_sigma", ct.c_double * 4),
-                ("stream", ct.c_uint32), ("whiten", ct.c_int32)]
+                ("stream", ct.c_uint32), ("whiten", ct.c_int32),
+                ("obs_phase", ct.c_void_p), ("sigma_s", ct.c_double), ("kappa_s", ct.c_double)]
 
 
 class NetDesc(ct.Structure):
@@ -94,6 +95,7 @@ _SIGS = {
     "spider_outliers": ([_P, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_double, _P,
                          ct.POINTER(ct.c_int64), ct.POINTER(ct.c_double), ct.POINTER(ct.c_double)],
                         ct.c_int),
+    "spider_set_phase_net": ([_P, ct.c_int32, ct.c_int32], ct.c_int),
     "spider_linearity": ([_P, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_double, _P,
                           ct.POINTER(ct.c_int64)], ct.c_int),
     "spider_moments": ([_P, ct.c_int32, ct.c_int32, _P, _P, ct.POINTER(ct.c_int64)], ct.c_int),
@@ -192,7 +194,9 @@ class Context:
 
     # ---- loading
     def load_catalog(self, cat, whiten=WHITEN_EXACT, stream_id=0, sigma=None, kappa=None,
-                     p=None, ell=None, eps_w=None) -> int:
+                     p=None, ell=None, eps_w=None, sigma_s=None, kappa_s=None) -> int:
+        """Load a catalog; one with S observations (cat.obs_phase) also needs
+        set_phase_net before it is evaluated."""
         wl = cat.wl
         arrays = dict(
             hypo0=np.ascontiguousarray(cat.hypo0, np.float64),
@@ -202,6 +206,9 @@ class Context:
             obs_pair=np.ascontiguousarray(cat.obs_pair, np.int32),
             obs_sta=np.ascontiguousarray(cat.obs_sta, np.int16),
             obs_dt=np.ascontiguousarray(cat.obs_dt, np.float32))
+        phase = getattr(cat, "obs_phase", None)
+        if phase is not None:
+            arrays["obs_phase"] = np.ascontiguousarray(phase, np.int8)
         d = CatalogDesc()
         d.M, d.L, d.P, d.N = cat.M, cat.L, cat.P, cat.N
         d.mem = MEM_HOST
@@ -216,10 +223,16 @@ class Context:
         d.centroid_sigma[:] = list(wl.centroid_sigma)
         d.stream = stream_id
         d.whiten = whiten
+        d.sigma_s = getattr(wl, "sigma_s", d.sigma) if sigma_s is None else sigma_s
+        d.kappa_s = getattr(wl, "kappa_s", d.kappa) if kappa_s is None else kappa_s
         cid = ct.c_int32()
         self._check(lib().spider_load_catalog(self._h, ct.byref(d), ct.byref(cid)))
         self._n_obs[cid.value] = cat.N
         return cid.value
+
+    def set_phase_net(self, cat_id, net_id):
+        """The S-phase network of a two-phase catalog."""
+        self._check(lib().spider_set_phase_net(self._h, cat_id, net_id))
 
     def load_net(self, net) -> int:
         W = [np.ascontiguousarray(w, np.float32) for w in net.W]

@@ -16,6 +16,10 @@ that the method inverts with is a seeded random MLP (weights N(0, 1/fan_in),
 biases 0), so the inverting forward model is deliberately not the truth, as
 in the paper's synthetic test where a 1D model inverts 3D synthetics.
 
+Two-phase workloads add S observations for a random subset of the P ones:
+the same truth at speed 6/1.73 km/s with noise N(0, 0.02^2), inverted with
+their own seeded network (scale speed v0/1.73) and their own sigma, kappa.
+
 Units: km and s, z is depth (positive down), stations at z = 0.
 """
 from __future__ import annotations
@@ -30,6 +34,7 @@ MASTER_SEED = 20250817
 V_TRUE = 6.0          # km/s, homogeneous truth and network scale speed
 NOISE_SIGMA = 0.01    # s, observation noise on differential times
 THETA0_SIGMA = (0.2, 0.2, 0.2, 0.1)
+VP_VS = 1.73          # P to S speed ratio of the S-phase observations
 
 
 @dataclasses.dataclass
@@ -58,12 +63,18 @@ class Workload:
     v0: float = V_TRUE
     index: int = 0
     side: float = 200.0    # km, horizontal box side of the clustered generator
+    s_frac: float = 0.0    # probability that a P observation also has an S observation
+    sigma_s: float = 0.02  # s, IID term of the S-phase groups
+    kappa_s: float = 0.05  # s, shared-event term of the S-phase groups
 
 
 WORKLOADS = {
     # 200 events in a 10 km box, 20 stations, 8-NN pairs x all stations (32k obs)
     "tiny": Workload("tiny", M=200, L=20, knn=8, keep=1.0, H=32, D=3,
                      batch=1024, chains=1, steps=200, index=0),
+    # tiny plus S observations for about half of the (pair, station) P ones
+    "tiny2ph": Workload("tiny2ph", M=200, L=20, knn=8, keep=1.0, H=32, D=3,
+                        batch=1024, chains=1, steps=200, index=5, s_frac=0.5),
     # 10k events (three planar faults + 20% background), 50 stations, 10-NN (5M obs)
     "faults10k": Workload("faults10k", M=10_000, L=50, knn=10, keep=1.0,
                           H=128, D=4, batch=65_536, chains=1, steps=5000, index=1),
@@ -86,6 +97,7 @@ class Catalog:
     obs_pair: np.ndarray    # [N] i32
     obs_sta: np.ndarray     # [N] i16
     obs_dt: np.ndarray      # [N] f32
+    obs_phase: np.ndarray = None  # [N] i8, 0 = P, 1 = S (None: all P)
 
     @property
     def M(self):
@@ -172,7 +184,7 @@ def make_catalog(name, seed: int = MASTER_SEED) -> Catalog:
     """Build workload `name` (or a Workload) from `seed`; identical arrays on every machine."""
     wl = name if isinstance(name, Workload) else WORKLOADS[name]
     geo = _rng(wl, seed, 0)
-    if wl.name == "tiny":
+    if wl.name in ("tiny", "tiny2ph"):
         xyz, sta = _events_tiny(geo, wl)
     elif wl.name == "faults10k":
         xyz, sta = _events_faults(geo, wl)
@@ -216,7 +228,20 @@ def make_catalog(name, seed: int = MASTER_SEED) -> Catalog:
         obs_sta[o:o + k] = s
         obs_dt[o:o + k] = dt
         o += k
-    return Catalog(wl, hypo_true, hypo0, sta, pair_i, pair_j, obs_pair, obs_sta, obs_dt)
+    if wl.s_frac <= 0.0:
+        return Catalog(wl, hypo_true, hypo0, sta, pair_i, pair_j, obs_pair, obs_sta, obs_dt)
+    # S observations: a random subset of the P ones, times of the same
+    # homogeneous truth at the S speed V_TRUE / VP_VS
+    pick = _rng(wl, seed, 4).random(N) < wl.s_frac
+    ns = int(pick.sum())
+    sp, ss = obs_pair[pick], obs_sta[pick].astype(np.int64)
+    pi, pj = pair_i[sp], pair_j[sp]
+    dt_s = VP_VS * (t_true[pi, ss] - t_true[pj, ss]) + (hypo_true[pi, 3] - hypo_true[pj, 3])
+    dt_s += _rng(wl, seed, 5).normal(0.0, 2 * NOISE_SIGMA, ns)
+    return Catalog(wl, hypo_true, hypo0, sta, pair_i, pair_j,
+                   np.concatenate([obs_pair, sp]), np.concatenate([obs_sta, obs_sta[pick]]),
+                   np.concatenate([obs_dt, dt_s.astype(np.float32)]),
+                   np.concatenate([np.zeros(N, np.int8), np.ones(ns, np.int8)]))
 
 
 @dataclasses.dataclass
@@ -260,8 +285,12 @@ def net_box(cat: Catalog):
     return (lo + hi) / 2, np.maximum((hi - lo) / 2, 1e-3)
 
 
-def net_for(cat: Catalog, seed: int = MASTER_SEED, **kw) -> Net:
+def net_for(cat: Catalog, seed: int = MASTER_SEED, phase: int = 0, **kw) -> Net:
+    """The catalog's network for phase 0 (P) or 1 (S: scale speed v0 / VP_VS,
+    its own weights)."""
     c, h = net_box(cat)
+    if phase == 1:
+        return make_net(cat.wl.H, cat.wl.D, c, h, seed=seed + 1, v0=cat.wl.v0 / VP_VS, **kw)
     return make_net(cat.wl.H, cat.wl.D, c, h, seed=seed, v0=cat.wl.v0, **kw)
 
 

@@ -30,7 +30,8 @@ def grad_scale(prob, bt, scale, theta):
     """S_m: per-event sum over the batch of the magnitudes that enter G_m,
     c (|T_i| + |T_j| + |tau| + |t_i - t_j|) / sigma_eff^2 * |d tau^/d theta_m|.
     FP32 rounding of the network perturbs G_m by a small multiple of S_m."""
-    s_eff = prob.sigma ** 2 + 2 * prob.kappa ** 2 * bt.w
+    sig, kap = prob.row_sigma_kappa(bt.phase)
+    s_eff = sig ** 2 + 2 * kap ** 2 * bt.w
     dt = np.abs(theta[bt.ev_i, 3] - theta[bt.ev_j, 3])
     mag = scale * (np.abs(bt.T_i) + np.abs(bt.T_j) + np.abs(bt.tau) + dt) / s_eff
     S = np.zeros(prob.M)
@@ -42,26 +43,29 @@ def grad_scale(prob, bt, scale, theta):
 def sigma_apply(z, w, group, ev_i, ev_j, M, sigma, kappa, mode):
     """Sigma_B z for the batch covariance of eq:marginal_sigma (matrix-free):
     sigma^2 z + kappa^2 U (U^T z), U = diag(sqrt w) A_B, where row n of A_B
-    has +1 at node (group_n, ev_i_n) and -1 at node (group_n, ev_j_n)."""
-    s2 = sigma * sigma
-    if mode == lk.WHITEN_NONE or kappa == 0.0:
+    has +1 at node (group_n, ev_i_n) and -1 at node (group_n, ev_j_n).  sigma
+    and kappa are scalars or per-row values (a row's group's phase)."""
+    s2 = np.asarray(sigma, np.float64) ** 2
+    k2 = np.asarray(kappa, np.float64) ** 2
+    if mode == lk.WHITEN_NONE or np.all(k2 == 0.0):
         return s2 * z
     if mode == lk.WHITEN_DIAG:
-        return (s2 + 2.0 * kappa * kappa * w) * z
+        return (s2 + 2.0 * k2 * w) * z
     key_i = np.asarray(group, np.int64) * M + ev_i
     key_j = np.asarray(group, np.int64) * M + ev_j
     nodes, inv = np.unique(np.concatenate([key_i, key_j]), return_inverse=True)
     n = z.shape[0]
-    sw = np.sqrt(w)
+    sw = np.sqrt(k2 * w) * np.ones(n)  # kappa_n sqrt(w_n): groups never mix phases
     utz = np.bincount(inv[:n], sw * z, nodes.shape[0]) - np.bincount(inv[n:], sw * z,
                                                                        nodes.shape[0])
-    return s2 * z + kappa * kappa * sw * (utz[inv[:n]] - utz[inv[n:]])
+    return s2 * z + sw * (utz[inv[:n]] - utz[inv[n:]])
 
 
 def whitening_residual(r, z, bt, prob, mode):
     """max |Sigma_B z - r| / (|r| + 1e-3 s): how exactly z solves the batch
     system for the residuals r it was computed from."""
-    Sz = sigma_apply(z, bt.w, bt.group, bt.ev_i, bt.ev_j, prob.M, prob.sigma, prob.kappa, mode)
+    sig, kap = prob.row_sigma_kappa(bt.phase)
+    Sz = sigma_apply(z, bt.w, bt.group, bt.ev_i, bt.ev_j, prob.M, sig, kap, mode)
     return float(np.max(np.abs(Sz - r) / (np.abs(r) + 1e-3)))
 
 

@@ -169,7 +169,12 @@ def test_batch_terms_tiny(ctx, tiny_setup, whiten):
 
 def test_exact_whitening_with_cycles(ctx, tiny_setup):
     """The whole catalog as one batch: every group is the full k-NN graph, so
-    leaf peeling leaves large cyclic cores for the CG stage."""
+    leaf peeling leaves large cyclic cores for the CG stage.  Here z = (r -
+    U y) / sigma^2 carries the rounding of U y (~eps |r| / sigma^2 ~ 1e-12),
+    which Sigma_B multiplies by kappa^2 ||U U^T|| ~ 0.05 for groups of 1,600
+    rows: about 1e-13 s absolute, 1e-10 of the 1e-3 s floor of the measure
+    (a converged FP64 solve of the same form on the host lands at 9e-11), so
+    the bound here is 1e-9."""
     cat, net, cid, nid = tiny_setup
     prob = lk.load(cat)
     theta = synth.random_theta(cat, 23)
@@ -177,7 +182,7 @@ def test_exact_whitening_with_cycles(ctx, tiny_setup):
     out = ctx.batch_terms(cid, nid, dev(theta), dev(idx))
     bt = lk.batch_terms(prob, net, theta, idx, lk.WHITEN_EXACT)
     r, z = host(out["r"]), host(out["z"])
-    assert whitening_residual(r, z, bt, prob, lk.WHITEN_EXACT) < 1e-10
+    assert whitening_residual(r, z, bt, prob, lk.WHITEN_EXACT) < 1e-9
 
 
 def test_batch_terms_faults_full_batch(ctx, faults_setup):

@@ -68,6 +68,7 @@ def test_struct_layouts_match_the_header():
     """The binding's ctypes structures have the header's sizes and offsets."""
     import tempfile
     structs = {"spider_sgld_cfg": spider.SgldCfg, "spider_map_cfg": spider.MapCfg,
+               "spider_catalog_desc": spider.CatalogDesc, "spider_net_desc": spider.NetDesc,
                "spider_chainset": spider.ChainSet}
     lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "spider.h"', "int main(void) {"]
     for cname, cls in structs.items():

@@ -266,3 +266,83 @@ def test_whitening_solves_the_batch_system(mode):
     # a wrong sign convention or a dropped coupling would not solve it
     if mode == lk.WHITEN_EXACT:
         assert np.max(np.abs(sigma_apply(z, w, g, ej, ej, M, 0.01, 0.03, mode) - r)) > 1e-3
+
+
+# ------------------------------------------------------------------ two phases
+
+@pytest.fixture(scope="module")
+def two_phase():
+    cat = synth.make_catalog("tiny2ph")
+    return cat, (synth.net_for(cat), synth.net_for(cat, phase=1)), lk.load(cat)
+
+
+def _subset(cat, keep):
+    import dataclasses
+    return dataclasses.replace(cat, obs_pair=cat.obs_pair[keep], obs_sta=cat.obs_sta[keep],
+                               obs_dt=cat.obs_dt[keep], obs_phase=None)
+
+
+def test_two_phase_groups_and_weights(two_phase):
+    """Groups are (station, phase) pairs; the edge weights are normalised to
+    mean 1 over each of them (Sec. 3.1)."""
+    cat, _, prob = two_phase
+    assert prob.two_phase and prob.G == 2 * cat.L
+    np.testing.assert_array_equal(prob.obs_group, cat.obs_sta + cat.L * cat.obs_phase)
+    w = prob.w_pair[prob.obs_pair] * prob.inv_mean[prob.obs_group]
+    for g in range(prob.G):
+        np.testing.assert_allclose(w[prob.obs_group == g].mean(), 1.0, rtol=1e-13)
+
+
+def test_two_phase_batch_splits_by_phase(two_phase):
+    """Groups of different phases share no covariance, so a mixed minibatch's
+    z and gradient are those of its P rows in the P-only catalog (P network,
+    sigma_P, kappa_P) plus those of its S rows in the S-only catalog (S
+    network, sigma_S, kappa_S) with the same weight normalisation."""
+    cat, nets, prob = two_phase
+    ph = cat.obs_phase.astype(bool)
+    pos_p, pos_s = np.flatnonzero(~ph), np.flatnonzero(ph)
+    prob_p = lk.load(_subset(cat, ~ph))
+    prob_s = lk.load(_subset(cat, ph), sigma=cat.wl.sigma_s, kappa=cat.wl.kappa_s)
+    theta = synth.random_theta(cat, 5)
+    idx = np.sort(synth.random_batch(cat.N, 2048, 6))
+    bt = lk.batch_terms(prob, nets, theta, idx)
+    in_s = ph[idx]
+    assert 0 < in_s.sum() < len(idx)
+    bp = lk.batch_terms(prob_p, nets[0], theta, np.searchsorted(pos_p, idx[~in_s]))
+    bs = lk.batch_terms(prob_s, nets[1], theta, np.searchsorted(pos_s, idx[in_s]))
+    np.testing.assert_allclose(bt.r[~in_s], bp.r, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(bt.r[in_s], bs.r, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(bt.w[~in_s], bp.w, rtol=1e-14)
+    np.testing.assert_allclose(bt.w[in_s], bs.w, rtol=1e-14)
+    np.testing.assert_allclose(bt.z[~in_s], bp.z, rtol=1e-9, atol=1e-9 * np.abs(bp.z).max())
+    np.testing.assert_allclose(bt.z[in_s], bs.z, rtol=1e-9, atol=1e-9 * np.abs(bs.z).max())
+    G, _ = lk.likelihood_gradient(prob, bt, 3.0)
+    Gp, _ = lk.likelihood_gradient(prob_p, bp, 3.0)
+    Gs, _ = lk.likelihood_gradient(prob_s, bs, 3.0)
+    np.testing.assert_allclose(G, Gp + Gs, rtol=1e-8, atol=1e-8 * np.abs(G).max())
+
+
+def test_two_phase_whitening_dense():
+    """z against a dense Sigma_B built entry by entry from eq:marginal_sigma
+    with each group's own sigma_phi, kappa_phi: Sigma[n, m] = [n = m]
+    sigma_n^2 + [g_n = g_m] kappa_n^2 sqrt(w_n w_m) (A_n . A_m)."""
+    rng = np.random.default_rng(9)
+    M, n = 6, 14
+    ei = rng.integers(0, M, n)
+    ej = (ei + rng.integers(1, M, n)) % M
+    g = rng.integers(0, 4, n)           # groups 0, 1: P; 2, 3: S
+    w = rng.uniform(0.3, 2.0, n)
+    sig = np.where(g >= 2, 0.02, 0.01)
+    kap = np.where(g >= 2, 0.05, 0.03)
+    S = np.zeros((n, n))
+    for a in range(n):
+        for b in range(n):
+            dot = (int(ei[a] == ei[b]) - int(ei[a] == ej[b]) - int(ej[a] == ei[b])
+                   + int(ej[a] == ej[b]))
+            S[a, b] = (a == b) * sig[a] ** 2 + (g[a] == g[b]) * kap[a] ** 2 * \
+                math.sqrt(w[a] * w[b]) * dot
+    r = rng.normal(0.0, 0.05, n)
+    z = lk.whiten(r, w, g, ei, ej, M, sig, kap, lk.WHITEN_EXACT)
+    np.testing.assert_allclose(z, np.linalg.solve(S, r), rtol=1e-10)
+    zd = lk.whiten(r, w, g, ei, ej, M, sig, kap, lk.WHITEN_DIAG)
+    np.testing.assert_allclose(zd, r / (sig ** 2 + 2 * kap ** 2 * w), rtol=1e-14)
