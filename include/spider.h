@@ -327,6 +327,60 @@ int spider_outliers(spider_ctx* ctx, int32_t cat_id, int32_t net_id, int32_t pre
 int spider_linearity(spider_ctx* ctx, int32_t cat_id, int32_t net_id, int32_t precision,
                      int32_t chain, double max_rel_err, uint8_t* keep, int64_t* n_keep);
 
+/* ---- samples and sampler diagnostics (Sec. 3.4, Sec. 3.6, Sec. 5) -------
+ * Thinned samples: while a buffer is attached, every recorded state (the
+ * steps that enter the moments) of chain c is also written to
+ * samples[slot][C][M][4], slot = the chain's number of recorded states
+ * before it (0 after spider_reset_chains), C = the catalog's chain count, as
+ * long as slot < capacity.  samples: device, caller-owned and kept alive
+ * while attached; NULL detaches.  Errors: SPIDER_E_INVALID. */
+int spider_set_sample_buffer(spider_ctx* ctx, int32_t cat_id, double* samples,
+                             int64_t capacity);
+
+/* Percentiles of each parameter over stored samples (Sec. 3.4 credibility
+ * intervals, e.g. probs 0.005 and 0.995): samples device [n_samples][n_params]
+ * (a sample buffer holding K recorded states of C chains is [K * C][M * 4]);
+ * out device [n_probs][n_params] receives, for each probability p, the
+ * linear interpolation between the order statistics around (n_samples - 1)
+ * p.  probs: host [n_probs], each in [0, 1].  n_samples <= 8192.
+ * Synchronous.  Errors: SPIDER_E_INVALID, SPIDER_E_UNSUPPORTED. */
+int spider_quantiles(spider_ctx* ctx, const double* samples, int64_t n_samples, int64_t n_params,
+                     const double* probs, int32_t n_probs, double* out);
+
+/* Calibration against a known truth (Sec. 4 synthetic test): frac[p] =
+ * (#{samples < values[p]} + #{samples == values[p]} / 2) / n_samples, the
+ * position of values[p] among parameter p's samples.  samples device
+ * [n_samples][n_params]; values, frac device [n_params].  Enqueued.
+ * Errors: SPIDER_E_INVALID. */
+int spider_sample_ranks(spider_ctx* ctx, const double* samples, int64_t n_samples,
+                        int64_t n_params, const double* values, double* frac);
+
+/* Effective sample size (Sec. 5) of each parameter over draws
+ * samples[n_draws][n_chains][n_params] (a sample buffer's layout): within-
+ * chain variance W (divisor n_draws - 1), between-chain variance of the
+ * chain means, var+ = (K - 1)/K W + B/K, lag-t autocorrelations
+ * rho_t = 1 - (W - mean over chains of the lag-t autocovariance, divisor K)
+ * / var+, rho_0 = 1, Geyer's initial positive and monotone sequence over
+ * the pair sums rho_2k + rho_2k+1, tau = -1 + 2 sum, ESS = n_chains K / tau
+ * (NaN for constant draws).  ess: device [n_params].  n_draws >= 4,
+ * n_chains <= 64.  Enqueued.  Errors: SPIDER_E_INVALID, SPIDER_E_UNSUPPORTED. */
+int spider_ess(spider_ctx* ctx, const double* samples, int64_t n_draws, int32_t n_chains,
+               int64_t n_params, double* ess);
+
+/* Step-size diagnostic (Sec. 3.6, Sec. 5): at chain `chain`'s current state,
+ * the likelihood gradients of its next n_batches sampler minibatches (steps
+ * t, t+1, ... of its counter, cfg->seed, `batch` observations each), their
+ * per-coordinate variance Var(g) (divisor n_batches - 1), and ratio[m][k] =
+ * step V Var(g) / (2 noise_scale^2): the variance of the drift step V g over
+ * that of the injected noise, with V = 1/(sqrt(v) + eps_p) from the chain's
+ * preconditioner (cfg->precond = 1) or 1.  The paper targets 0.1-1.0.
+ * ratio: device [M][4]; *mean_ratio (host, may be NULL) their mean.  Uses
+ * step, eps_p, noise_scale, precond and seed of cfg; the chain is not
+ * advanced.  Synchronous.  Errors: SPIDER_E_INVALID, SPIDER_E_HIP. */
+int spider_noise_ratio(spider_ctx* ctx, int32_t cat_id, int32_t net_id, int32_t precision,
+                       int32_t chain, int64_t batch, int32_t n_batches, const spider_sgld_cfg* cfg,
+                       double* ratio, double* mean_ratio);
+
 /* Posterior moments (Sec. 3.4) of a catalog: chain >= 0 for one chain, -1
  * for all chains pooled (pairwise combination of Chan, Golub and LeVeque).
  * mean: device [M][4]; cov: device [M][10] upper triangle xx xy xz xt yy yz

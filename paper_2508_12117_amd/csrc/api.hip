@@ -59,6 +59,8 @@ struct Catalog {
   int32_t L_p = 0;
   double zscale_s = 1.0;  // sigma_P^2 / sigma_S^2
   int net_s = -1;         // S-phase network (spider_set_phase_net)
+  double* samples = nullptr;  // caller's sample buffer (spider_set_sample_buffer)
+  int64_t sample_cap = 0;
   DevBuf hypo0, stations, pairs, w_pair, obs, inv_mean, mu_c;
   int C = 0;  // chains allocated
   DevBuf theta, v, mean, m2, steps, mcount;
@@ -448,6 +450,14 @@ int run_batch(spider_ctx* ctx, Catalog& cat, Net& net, int prec, int C, int64_t 
   return SPIDER_OK;
 }
 
+// The update arguments with the catalog's sample buffer.
+UpdateArgs with_samples(UpdateArgs a, const Catalog& cat) {
+  a.samples = cat.samples;
+  a.sample_cap = cat.samples ? cat.sample_cap : 0;
+  a.sample_C = cat.C;
+  return a;
+}
+
 // The batch buffers of the observations from obs_off on (rows from 2 obs_off).
 BatchBufs batch_at(const BatchBufs& b, int64_t obs_off) {
   BatchBufs o = b;
@@ -557,8 +567,8 @@ int fused_step(spider_ctx* ctx, const spider_chainset* sets, int n_sets, const F
     launch_centroid(cat.theta.as<double>(), C, cat.M, ws.partial.as<double>(),
                     ws.thetabar.as<double>(), ctx->stream);
     launch_update(cv, C, cat.theta.as<double>(), cat.v.as<double>(), ws.G.as<double>(),
-                  ws.thetabar.as<double>(), cat.steps.as<int64_t>(), cat.mcount.as<int64_t>(), ua,
-                  cat.mean.as<double>(), cat.m2.as<double>(), ctx->stream);
+                  ws.thetabar.as<double>(), cat.steps.as<int64_t>(), cat.mcount.as<int64_t>(),
+                  with_samples(ua, cat), cat.mean.as<double>(), cat.m2.as<double>(), ctx->stream);
     HIPCK(hipGetLastError(), "update");
   }
   return SPIDER_OK;
@@ -1096,7 +1106,7 @@ int spider_sgld_steps(spider_ctx* ctx, const spider_chainset* sets, int32_t n_se
   }
   int rc = reset_err_flag(ctx);
   if (rc) return rc;
-  UpdateArgs ua;
+  UpdateArgs ua{};
   ua.step = cfg->step;
   ua.beta2 = cfg->beta2;
   ua.eps_p = cfg->eps_p;
@@ -1141,8 +1151,9 @@ int spider_sgld_steps(spider_ctx* ctx, const spider_chainset* sets, int32_t n_se
       launch_centroid(cat.theta.as<double>(), C, cat.M, ws.partial.as<double>(),
                       ws.thetabar.as<double>(), ctx->stream);
       launch_update(cat.view(), C, cat.theta.as<double>(), cat.v.as<double>(), ws.G.as<double>(),
-                    ws.thetabar.as<double>(), cat.steps.as<int64_t>(), cat.mcount.as<int64_t>(), ua,
-                    cat.mean.as<double>(), cat.m2.as<double>(), ctx->stream);
+                    ws.thetabar.as<double>(), cat.steps.as<int64_t>(), cat.mcount.as<int64_t>(),
+                    with_samples(ua, cat), cat.mean.as<double>(), cat.m2.as<double>(),
+                    ctx->stream);
       HIPCK(hipGetLastError(), "update");
     }
   }
@@ -1341,6 +1352,112 @@ int spider_linearity(spider_ctx* ctx, int32_t cat_id, int32_t net_id, int32_t pr
   HIPCK(hipMemcpyAsync(&kept, cnt.p, 8, hipMemcpyDeviceToHost, ctx->stream), "count");
   HIPCK(hipStreamSynchronize(ctx->stream), "sync");
   if (n_keep) *n_keep = (int64_t)kept;
+  return check_select_flag(ctx);
+}
+
+int spider_set_sample_buffer(spider_ctx* ctx, int32_t cat_id, double* samples,
+                             int64_t capacity) {
+  if (!ctx) return SPIDER_E_INVALID;
+  Catalog* cat = get_cat(ctx, cat_id);
+  if (!cat) return fail(ctx, SPIDER_E_INVALID, "unknown catalog id");
+  if (samples && capacity < 1) return fail(ctx, SPIDER_E_INVALID, "need capacity >= 1");
+  cat->samples = samples;
+  cat->sample_cap = samples ? capacity : 0;
+  return SPIDER_OK;
+}
+
+int spider_quantiles(spider_ctx* ctx, const double* samples, int64_t n_samples, int64_t n_params,
+                     const double* probs, int32_t n_probs, double* out) {
+  if (!ctx) return SPIDER_E_INVALID;
+  DeviceGuard g(ctx->device);
+  if (!samples || !probs || !out) return fail(ctx, SPIDER_E_INVALID, "null argument");
+  if (n_samples < 1 || n_params < 1 || n_params > INT32_MAX || n_probs < 1)
+    return fail(ctx, SPIDER_E_INVALID, "need n_samples, n_params, n_probs >= 1");
+  if (n_samples > kMaxQuantileSamples)
+    return fail(ctx, SPIDER_E_UNSUPPORTED, "at most 8192 samples per parameter");
+  for (int32_t q = 0; q < n_probs; ++q)
+    if (!(probs[q] >= 0.0 && probs[q] <= 1.0))
+      return fail(ctx, SPIDER_E_INVALID, "probabilities must lie in [0, 1]");
+  DevBuf pd;
+  HIPCK(upload(pd, probs, (size_t)n_probs * 8, SPIDER_MEM_HOST, ctx->stream), "upload probs");
+  HIPCK(launch_quantiles(samples, n_samples, n_params, pd.as<double>(), n_probs, out,
+                         ctx->stream),
+        "quantile kernel");
+  HIPCK(hipStreamSynchronize(ctx->stream), "sync");
+  return SPIDER_OK;
+}
+
+int spider_sample_ranks(spider_ctx* ctx, const double* samples, int64_t n_samples,
+                        int64_t n_params, const double* values, double* frac) {
+  if (!ctx) return SPIDER_E_INVALID;
+  DeviceGuard g(ctx->device);
+  if (!samples || !values || !frac) return fail(ctx, SPIDER_E_INVALID, "null argument");
+  if (n_samples < 1 || n_params < 1)
+    return fail(ctx, SPIDER_E_INVALID, "need n_samples, n_params >= 1");
+  HIPCK(launch_ranks(samples, n_samples, n_params, values, frac, ctx->stream), "rank kernel");
+  return SPIDER_OK;
+}
+
+int spider_ess(spider_ctx* ctx, const double* samples, int64_t n_draws, int32_t n_chains,
+               int64_t n_params, double* ess) {
+  if (!ctx) return SPIDER_E_INVALID;
+  DeviceGuard g(ctx->device);
+  if (!samples || !ess) return fail(ctx, SPIDER_E_INVALID, "null argument");
+  if (n_draws < 4 || n_chains < 1 || n_params < 1)
+    return fail(ctx, SPIDER_E_INVALID, "need n_draws >= 4, n_chains >= 1, n_params >= 1");
+  if (n_chains > kMaxEssChains) return fail(ctx, SPIDER_E_UNSUPPORTED, "at most 64 chains");
+  HIPCK(launch_ess(samples, n_draws, n_chains, n_params, ess, ctx->stream), "ess kernel");
+  return SPIDER_OK;
+}
+
+int spider_noise_ratio(spider_ctx* ctx, int32_t cat_id, int32_t net_id, int32_t precision,
+                       int32_t chain, int64_t batch, int32_t n_batches, const spider_sgld_cfg* cfg,
+                       double* ratio, double* mean_ratio) {
+  if (!ctx) return SPIDER_E_INVALID;
+  DeviceGuard g(ctx->device);
+  Catalog* cat;
+  Net* net;
+  int rc = screening_args(ctx, cat_id, net_id, precision, chain, cat, net);
+  if (rc) return rc;
+  if (!cfg || !ratio) return fail(ctx, SPIDER_E_INVALID, "null argument");
+  if (batch < 1 || batch > cat->N || n_batches < 2)
+    return fail(ctx, SPIDER_E_INVALID, "need 1 <= batch <= N and n_batches >= 2");
+  if (!(cfg->step > 0) || !(cfg->noise_scale > 0) || !(cfg->eps_p > 0))
+    return fail(ctx, SPIDER_E_INVALID, "need step, noise_scale, eps_p > 0");
+  const int64_t n4 = (int64_t)cat->M * 4;
+  int64_t t0 = 0;
+  HIPCK(hipMemcpyAsync(&t0, cat->steps.as<int64_t>() + chain, 8, hipMemcpyDeviceToHost,
+                       ctx->stream),
+        "read step");
+  HIPCK(hipStreamSynchronize(ctx->stream), "sync");
+  DevBuf mean, m2, part;
+  const int64_t nb = noise_ratio_blocks(n4);
+  HIPCK(mean.alloc((size_t)n4 * 8), "alloc");
+  HIPCK(m2.alloc((size_t)n4 * 8), "alloc");
+  HIPCK(part.alloc((size_t)nb * 8), "alloc");
+  rc = reset_err_flag(ctx);
+  if (rc) return rc;
+  const double* theta = cat->theta.as<double>() + (size_t)n4 * chain;
+  // the likelihood gradients of the chain's next n_batches minibatches at its
+  // current state (the priors add the same vector to each)
+  for (int32_t k = 0; k < n_batches; ++k) {
+    rc = run_batch(ctx, *cat, *net, precision, 1, batch, theta, n4, nullptr, cfg->seed, nullptr,
+                   t0 + k, chain, true, (double)cat->N / (double)batch);
+    if (rc) return rc;
+    launch_welford(ctx->ws.G.as<double>(), n4, k, mean.as<double>(), m2.as<double>(),
+                   ctx->stream);
+  }
+  launch_noise_ratio(m2.as<double>(), n4, n_batches, cat->v.as<double>() + (size_t)n4 * chain,
+                     cfg->precond, cfg->eps_p, cfg->step, cfg->noise_scale, ratio, part.as<double>(),
+                     ctx->stream);
+  HIPCK(hipGetLastError(), "noise ratio kernels");
+  std::vector<double> ps(nb);
+  HIPCK(hipMemcpyAsync(ps.data(), part.p, (size_t)nb * 8, hipMemcpyDeviceToHost, ctx->stream),
+        "read partial sums");
+  HIPCK(hipStreamSynchronize(ctx->stream), "sync");
+  double tot = 0.0;
+  for (double x : ps) tot += x;
+  if (mean_ratio) *mean_ratio = tot / (double)n4;
   return check_select_flag(ctx);
 }
 

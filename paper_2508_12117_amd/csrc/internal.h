@@ -238,6 +238,11 @@ struct UpdateArgs {
   int precond;
   uint64_t seed;
   int64_t burn, thin;
+  // recorded states also go to samples[slot][sample_C][M][4], slot = the
+  // chain's sample count before the step, while slot < sample_cap
+  double* samples;
+  int64_t sample_cap;
+  int sample_C;
 };
 // Priors + Langevin update of chains 0..C-1 at their device step counters,
 // Welford moments on recording steps, then steps[c] += 1 (and mcount[c] on
@@ -280,6 +285,20 @@ hipError_t partition_rows_by_phase(const int32_t* sta, int32_t L_p, int64_t E, i
 // out[list[v]] = compact[v] for v < E.
 void launch_scatter_rows(const RowOut* compact, const int32_t* list, int64_t E, RowOut* out,
                          hipStream_t s);
+// Diagnostics over stored samples [S][P] (sample-major).
+constexpr int kMaxEssChains = 64;
+constexpr int64_t kMaxQuantileSamples = 8192;
+hipError_t launch_quantiles(const double* samples, int64_t S, int64_t P, const double* probs,
+                            int n_probs, double* out, hipStream_t s);
+hipError_t launch_ranks(const double* samples, int64_t S, int64_t P, const double* values,
+                        double* frac, hipStream_t s);
+hipError_t launch_ess(const double* x, int64_t K, int C, int64_t P, double* ess, hipStream_t s);
+void launch_welford(const double* g, int64_t n, int64_t k, double* mean, double* m2,
+                    hipStream_t s);
+int64_t noise_ratio_blocks(int64_t n);
+void launch_noise_ratio(const double* m2, int64_t n, int64_t K, const double* v, int precond,
+                        double eps_p, double step, double amp, double* ratio, double* part,
+                        hipStream_t s);
 hipError_t sort_doubles(const double* in, double* out, int64_t N, void* temp, size_t* temp_bytes,
                         hipStream_t s);
 

@@ -659,6 +659,9 @@ struct UpdateKArgs {
   int precond;
   uint32_t k0, k1;
   int64_t burn, thin;
+  double* samples;
+  int64_t sample_cap;
+  int sample_C;
 };
 
 __device__ inline bool records(int64_t t, int64_t burn, int64_t thin) {
@@ -706,6 +709,11 @@ __global__ void k_update(CatView cat, int C, double* theta, double* v, const dou
     int u = 0;
     for (int i = 0; i < 4; ++i)
       for (int j = i; j < 4; ++j, ++u) m2[q * 10 + u] += d[i] * after[j];
+    const int64_t slot = mcount[c];
+    if (a.samples && slot < a.sample_cap) {
+      double* o = a.samples + ((slot * a.sample_C + c) * (int64_t)cat.M + m) * 4;
+      for (int k = 0; k < 4; ++k) o[k] = x[k];
+    }
   }
 }
 
@@ -1176,6 +1184,9 @@ void launch_update(const CatView& cat, int C, double* theta, double* v, const do
   k.k1 = (uint32_t)(a.seed >> 32);
   k.burn = a.burn;
   k.thin = a.thin;
+  k.samples = a.samples;
+  k.sample_cap = a.sample_cap;
+  k.sample_C = a.sample_C;
   hipLaunchKernelGGL(k_update, dim3(grid_for((int64_t)C * cat.M)), dim3(kBlock), 0, s, cat, C,
                      theta, v, G, thetabar, steps, mcount, k, mean, m2);
   hipLaunchKernelGGL(k_advance, dim3(grid_for(C, 64)), dim3(64), 0, s, C, steps, mcount, a.burn,

@@ -98,6 +98,12 @@ _SIGS = {
     "spider_set_phase_net": ([_P, ct.c_int32, ct.c_int32], ct.c_int),
     "spider_linearity": ([_P, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_double, _P,
                           ct.POINTER(ct.c_int64)], ct.c_int),
+    "spider_set_sample_buffer": ([_P, ct.c_int32, _P, ct.c_int64], ct.c_int),
+    "spider_quantiles": ([_P, _P, ct.c_int64, ct.c_int64, _P, ct.c_int32, _P], ct.c_int),
+    "spider_sample_ranks": ([_P, _P, ct.c_int64, ct.c_int64, _P, _P], ct.c_int),
+    "spider_ess": ([_P, _P, ct.c_int64, ct.c_int32, ct.c_int64, _P], ct.c_int),
+    "spider_noise_ratio": ([_P, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int64,
+                            ct.c_int32, _P, _P, ct.POINTER(ct.c_double)], ct.c_int),
     "spider_moments": ([_P, ct.c_int32, ct.c_int32, _P, _P, ct.POINTER(ct.c_int64)], ct.c_int),
     "spider_get_state": ([_P, ct.c_int32, ct.c_int32, _P, _P, ct.POINTER(ct.c_int64)], ct.c_int),
     "spider_set_state": ([_P, ct.c_int32, ct.c_int32, _P, _P, ct.c_int64], ct.c_int),
@@ -167,6 +173,7 @@ class Context:
         self._h = h
         self._keep = []
         self._n_obs = {}  # observations of each loaded catalog
+        self._n_ev = {}   # and its events
 
     def close(self):
         if getattr(self, "_h", None):
@@ -228,6 +235,7 @@ class Context:
         cid = ct.c_int32()
         self._check(lib().spider_load_catalog(self._h, ct.byref(d), ct.byref(cid)))
         self._n_obs[cid.value] = cat.N
+        self._n_ev[cid.value] = cat.M
         return cid.value
 
     def set_phase_net(self, cat_id, net_id):
@@ -336,6 +344,64 @@ class Context:
         self._check(lib().spider_linearity(self._h, cat_id, net_id, precision, chain,
                                            max_rel_err, _ptr(keep), ct.byref(n)))
         return keep, n.value
+
+    def set_sample_buffer(self, cat_id, samples):
+        """Attach a device tensor [K, C, M, 4] (float64) that receives the
+        recorded states of the catalog's C chains; None detaches."""
+        if samples is None:
+            self._check(lib().spider_set_sample_buffer(self._h, cat_id, None, 0))
+            return
+        self._keep.append(samples)
+        self._check(lib().spider_set_sample_buffer(self._h, cat_id, _ptr(samples),
+                                                   samples.shape[0]))
+
+    def quantiles(self, samples, probs):
+        """Percentiles over the first axis of a device tensor [S, ...]:
+        returns [len(probs), ...]."""
+        torch = self._torch
+        S = samples.shape[0]
+        P = samples.numel() // S
+        pr = np.ascontiguousarray(probs, np.float64)
+        out = torch.empty((len(pr),) + tuple(samples.shape[1:]), dtype=torch.float64,
+                          device=samples.device)
+        self._check(lib().spider_quantiles(self._h, _ptr(samples), S, P, _np_ptr(pr), len(pr),
+                                           _ptr(out)))
+        return out
+
+    def sample_ranks(self, samples, values):
+        """Position of values [...] among samples [S, ...] (fractions)."""
+        torch = self._torch
+        S = samples.shape[0]
+        out = torch.empty(values.shape, dtype=torch.float64, device=samples.device)
+        self._check(lib().spider_sample_ranks(self._h, _ptr(samples), S, values.numel(),
+                                              _ptr(values), _ptr(out)))
+        self.sync()
+        return out
+
+    def ess(self, samples):
+        """Effective sample size of draws [K, C, ...]: returns [...]."""
+        torch = self._torch
+        K, C = samples.shape[0], samples.shape[1]
+        out = torch.empty(tuple(samples.shape[2:]), dtype=torch.float64, device=samples.device)
+        self._check(lib().spider_ess(self._h, _ptr(samples), K, C, out.numel(), _ptr(out)))
+        self.sync()
+        return out
+
+    def noise_ratio(self, cat_id, net_id, chain, batch, n_batches, step=1e-4, eps_p=1e-5,
+                    noise_scale=1.0, precond=1, seed=0, precision=FP32):
+        """Gradient-noise to injected-noise variance ratio [M, 4] at a
+        chain's state, and its mean."""
+        torch = self._torch
+        cfg = SgldCfg(step=step, beta2=0.99, eps_p=eps_p, noise_scale=noise_scale,
+                      precond=precond, noise_ramp=0, n_steps=0, burn_in=0, thin=1, seed=seed,
+                      noise_scale_end=noise_scale)
+        out = torch.empty(self._n_ev.get(cat_id, 0), 4, dtype=torch.float64,
+                          device=f"cuda:{self.device}")
+        mean = ct.c_double()
+        self._check(lib().spider_noise_ratio(self._h, cat_id, net_id, precision, chain, batch,
+                                             n_batches, ct.byref(cfg), _ptr(out),
+                                             ct.byref(mean)))
+        return out, mean.value
 
     def sgld_stages(self, sets, warmup, ramp, sample, thin=1, **kw):
         """The sampler stages that follow the initial solution (Sec. 3.2):
