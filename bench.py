@@ -31,11 +31,11 @@ HBM_PEAK = 8000.0                             # GB/s
 # and the same variant; otherwise the bench reports traffic as null.
 NETWORK_TRAFFIC = {
     "kernel_sources": ["paper_2508_12117_amd/csrc/mlp_mfma.h", "paper_2508_12117_amd/csrc/mlp_pp.h",
-                       "paper_2508_12117_amd/csrc/internal.h"],
-    "sha256": "71474217cc01cb5353db69a3a4c100ed3eef6502dc7371d16d03e8a9322c5118",
+                       "paper_2508_12117_amd/csrc/net_rows.h"],
+    "sha256": "1e2e192253e6d9a798baa4b9ebaa680b5a2c345875dec2cfc74e7ea29102209a",
     "variant": {"waves": 8, "row_tiles": 4, "schedule": 1},
     "rows": 16777216,
-    "fetch_bytes": 1542890219,
+    "fetch_bytes": 1542910763,
     "write_bytes": 268435456,
 }
 
