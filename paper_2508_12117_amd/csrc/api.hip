@@ -62,6 +62,7 @@ struct Catalog {
   double* samples = nullptr;  // caller's sample buffer (spider_set_sample_buffer)
   int64_t sample_cap = 0;
   DevBuf hypo0, stations, pairs, w_pair, obs, inv_mean, mu_c;
+  DevBuf rec;  // packed observation records (the 12-byte ones are freed after load)
   int C = 0;  // chains allocated
   DevBuf theta, v, mean, m2, steps, mcount;
   DevBuf adam_m, adam_v;      // Stage 1 optimiser moments, allocated on first use
@@ -76,7 +77,7 @@ struct Catalog {
     c.stations = stations.as<double>();
     c.pairs = pairs.as<int2>();
     c.w_pair = w_pair.as<double>();
-    c.obs = obs.as<Obs>();
+    c.rec = rec.as<ObsRec>();
     c.inv_mean = inv_mean.as<double>();
     c.mu_c = mu_c.as<double>();
     c.stream = stream;
@@ -815,8 +816,12 @@ int spider_load_catalog(spider_ctx* ctx, const spider_catalog_desc* d, int32_t* 
     HIPCK(hipStreamSynchronize(s), "sync");
   }
   launch_mean4(cat->hypo0.as<double>(), d->M, cat->mu_c.as<double>(), s);
+  HIPCK(cat->rec.alloc((size_t)d->N * sizeof(ObsRec)), "alloc observation records");
+  launch_pack_obs(cat->obs.as<Obs>(), d->N, cat->pairs.as<int2>(), cat->w_pair.as<double>(),
+                  cat->inv_mean.as<double>(), cat->rec.as<ObsRec>(), s);
   HIPCK(hipGetLastError(), "load kernels");
   HIPCK(hipStreamSynchronize(s), "load");
+  cat->obs.release();
   ctx->cats.push_back(std::move(cat));
   *cat_id = (int32_t)ctx->cats.size() - 1;
   return SPIDER_OK;

@@ -7,11 +7,22 @@
 
 namespace spider {
 
-// One observation record in HBM: 12 bytes, loaded as three dwords.
+// One observation record as loaded: 12 bytes, loaded as three dwords.
 struct Obs {
   int32_t pair;
   float dt;
   int32_t sta;
+};
+
+// What the minibatch gather reads of an observation, packed once at load
+// into one aligned 32-byte record (a single cache line per random read):
+// the pair's events, the group, tau and the normalised edge weight
+// w = w~_pair * inv_mean[group].
+struct __attribute__((aligned(32))) ObsRec {
+  int32_t i, j, g;
+  float dt;
+  double w;
+  double pad;
 };
 
 // Catalog as the step kernels see it.
@@ -22,7 +33,7 @@ struct CatView {
   const double* stations;  // [L][3]
   const int2* pairs;       // [P] (i, j)
   const double* w_pair;    // [P] unnormalised edge weight
-  const Obs* obs;          // [N]
+  const ObsRec* rec;       // [N] packed observation records
   const double* inv_mean;  // [L] 1 / group mean of the edge weights
   const double* mu_c;      // [4] centroid prior mean
   uint32_t stream;
@@ -94,6 +105,9 @@ void mfma_pack_layer(int precision, int H, const float* W, void* fwd, void* bwd)
 // Load-time kernels (step.hip).
 void launch_pair_weights(const double* hypo0, const int2* pairs, int64_t P, double ell, double p,
                          double eps_w, double* w_pair, hipStream_t s);
+// rec[t] = the packed record of observation t.
+void launch_pack_obs(const Obs* obs, int64_t N, const int2* pairs, const double* w_pair,
+                     const double* inv_mean, ObsRec* rec, hipStream_t s);
 void launch_validate(const double* hypo0, int M, const double* stations, int L, const int2* pairs,
                      int64_t P, const Obs* obs, int64_t N, int* bad, hipStream_t s);
 // inv_mean[g] = count_g / sum of w~ over group g; deterministic.

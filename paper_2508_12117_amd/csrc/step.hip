@@ -165,15 +165,30 @@ __global__ void k_select(CatView cat, int C, int64_t n, const int64_t* idx, uint
     atomicOr(err, 1);
     o = 0;
   }
-  const Obs ob = cat.obs[o];
-  const int2 ij = cat.pairs[ob.pair];
+  const ObsRec rc = cat.rec[o];
   b.obs[q] = o;
-  b.ev[2 * q] = ij.x;
-  b.ev[2 * q + 1] = ij.y;
-  b.sta[2 * q] = ob.sta;
-  b.sta[2 * q + 1] = ob.sta;
-  b.tau[q] = (double)ob.dt;
-  b.w[q] = cat.w_pair[ob.pair] * cat.inv_mean[ob.sta];
+  b.ev[2 * q] = rc.i;
+  b.ev[2 * q + 1] = rc.j;
+  b.sta[2 * q] = rc.g;
+  b.sta[2 * q + 1] = rc.g;
+  b.tau[q] = (double)rc.dt;
+  b.w[q] = rc.w;
+}
+
+__global__ void k_pack_obs(const Obs* obs, int64_t N, const int2* pairs, const double* w_pair,
+                           const double* inv_mean, ObsRec* rec) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N) return;
+  const Obs ob = obs[t];
+  const int2 ij = pairs[ob.pair];
+  ObsRec r;
+  r.i = ij.x;
+  r.j = ij.y;
+  r.g = ob.sta;
+  r.dt = ob.dt;
+  r.w = w_pair[ob.pair] * inv_mean[ob.sta];
+  r.pad = 0.0;
+  rec[t] = r;
 }
 
 // Travel time and source gradient of one row from the network output.
@@ -934,6 +949,12 @@ __global__ void k_linear_keep(const BatchBufs b, const double* theta, int64_t n,
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
+
+void launch_pack_obs(const Obs* obs, int64_t N, const int2* pairs, const double* w_pair,
+                     const double* inv_mean, ObsRec* rec, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack_obs, dim3(grid_for(N)), dim3(kBlock), 0, s, obs, N, pairs, w_pair,
+                     inv_mean, rec);
+}
 
 void launch_pair_weights(const double* hypo0, const int2* pairs, int64_t P, double ell, double p,
                          double eps_w, double* w_pair, hipStream_t s) {
