@@ -782,3 +782,38 @@ def test_kernel_variants_agree_bitwise(ctx, monkeypatch, H, D, prec):
     for T, g in outs[1:]:
         assert np.array_equal(T, outs[0][0]) and np.array_equal(g, outs[0][1])
     assert all(w > 0 and r > 0 for w, r in shapes)
+
+
+def test_screens_span_several_chunks(ctx, faults_setup):
+    """faults10k (5,000,000 observations): the screens evaluate the catalog
+    in chunks of 2^22 observations.  Both masks equal the ones computed from
+    the GPU's own whole-catalog residuals and travel times, and sampled
+    observations on both sides of the chunk boundary match the oracle."""
+    cat, net, cid, nid = faults_setup
+    ctx.reset_chains(cid, 1)
+    keep, n_keep, med, mad = ctx.outliers(cid, nid)
+    lin_keep, n_lin = ctx.linearity(cid, nid)
+    out = ctx.batch_terms(cid, nid, dev(cat.hypo0), dev(np.arange(cat.N)))
+    r = host(out["r"])
+    assert med == np.median(r) and mad == np.median(np.abs(r - med))
+    keep = host(keep).astype(bool)
+    d = np.abs(r - med)
+    sure = np.abs(d - 4 * mad) > 1e-12
+    np.testing.assert_array_equal(keep[sure], (d <= 4 * mad)[sure])
+    assert n_keep == keep.sum()
+    Ti, Tj, gi = host(out["T_i"]), host(out["T_j"]), host(out["gT_i"])
+    pr = cat.obs_pair
+    dx = cat.hypo0[cat.pair_j[pr], 0:3] - cat.hypo0[cat.pair_i[pr], 0:3]
+    m = np.abs((Tj - Ti) - np.sum(gi * dx, axis=1)) - 0.05 * np.abs(Tj - Ti)
+    lin_keep = host(lin_keep).astype(bool)
+    sure = np.abs(m) > 1e-12 * (np.abs(Tj - Ti) + 1e-12)
+    np.testing.assert_array_equal(lin_keep[sure], (m <= 0)[sure])
+    assert n_lin == lin_keep.sum()
+    # the oracle on observations around the chunk boundary and spread over the catalog
+    rng = np.random.default_rng(3)
+    b = 1 << 22
+    idx = np.unique(np.concatenate([np.arange(b - 500, b + 500), rng.choice(cat.N, 2000, replace=False)]))
+    prob = lk.load(cat)
+    bt = lk.batch_terms(prob, net, cat.hypo0, idx, lk.L1)
+    mag = np.abs(bt.T_i) + np.abs(bt.T_j) + np.abs(bt.tau)
+    assert np.all(np.abs(r[idx] - bt.r) <= 1e-5 * mag)
