@@ -319,8 +319,10 @@ struct SolveArgs {
   int32_t* state;   // kActive, or the round in which the node was removed
   int32_t* nstate;
   int32_t* par;     // parent of an eliminated node (-1: solved on its own)
-  int32_t* core;    // scratch list of the nodes that need the rounds
-  int32_t* core2;   // scratch list of the nodes left on cycles
+  int32_t* core;    // scratch: active-node list (room for one entry per node)
+  int32_t* core2;   // scratch: second active-node list, then the elimination order
+                    // (room for 2 n_entries)
+  int32_t n_entries;
   double lambda;
   int max_rounds;
   int max_iter;
@@ -328,6 +330,7 @@ struct SolveArgs {
 };
 
 constexpr int32_t kActive = -1;
+constexpr int kMaxRounds = 64;
 constexpr int kTreeBlock = 1024;  // threads per (chain, group) system
 
 // Neighbour node, weight and right-hand-side term (+-sqrt(w) r, the entry's
@@ -377,7 +380,11 @@ __device__ int32_t block_compact(int32_t n, Keep&& keep, Item&& item, int32_t* o
     if (on) out[warp_base[w] + before] = item(k);
     __syncthreads();
   }
-  return *total;
+  // every thread reads the count before any thread can start another call
+  // (which resets it)
+  const int32_t count = *total;
+  __syncthreads();
+  return count;
 }
 
 // Diagonal lambda + sum w and right-hand side (U^T r)_q of every node, one
@@ -438,26 +445,29 @@ __global__ __launch_bounds__(TB) void k_tree_solve(SolveArgs a) {
   __shared__ double sh[TB];
   __shared__ int32_t warp_base[TB / 64];
   __shared__ int32_t total_sh;
+  __shared__ int32_t elim_start[kMaxRounds + 2];  // elimination order: round r's nodes
   const int32_t nb = a.seg_begin[blockIdx.x];
   const int32_t ne = a.seg_end[blockIdx.x];
   if (ne <= nb) return;
   const int t = threadIdx.x;
-  int32_t* list = a.core + nb;
-  const int32_t nl = block_compact<TB>(
+  // the nodes still active at the start of each round (two buffers in turn),
+  // and every eliminated node in round order; all lists keep node order
+  int32_t* act = a.core + nb;
+  int32_t* act_next = a.core2 + nb;
+  int32_t* elim = a.core2 + a.n_entries + nb;
+  int32_t nl = block_compact<TB>(
       ne - nb, [&](int32_t k) { return a.state[nb + k] != kPair; }, [&](int32_t k) { return nb + k; },
-      list, warp_base, &total_sh);
+      act, warp_base, &total_sh);
+  int32_t n_elim = 0;
 
-  // ---- 1. peeling rounds over the listed nodes
+  // ---- 1. peeling rounds over the active nodes
   int rounds = 0;
   for (; rounds < a.max_rounds && nl > 0; ++rounds) {
+    if (t == 0) elim_start[rounds] = n_elim;
     // phase 1: classify active nodes
     int changed = 0;
     for (int32_t k = t; k < nl; k += TB) {
-      const int32_t q = list[k];
-      if (a.state[q] != kActive) {
-        a.nstate[q] = a.state[q];
-        continue;
-      }
+      const int32_t q = act[k];
       int32_t p0 = -1;
       double W = 0.0;
       bool multi = false;
@@ -500,7 +510,7 @@ __global__ __launch_bounds__(TB) void k_tree_solve(SolveArgs a) {
     if (!changed) break;
     // phase 2: parents gather the Schur updates of this round's leaves
     for (int32_t k = t; k < nl; k += TB) {
-      const int32_t q = list[k];
+      const int32_t q = act[k];
       if (a.nstate[q] == kActive) {
         const int32_t e0 = a.node_start[q], e1 = a.node_start[q + 1];
         double dA = 0.0, db = 0.0;
@@ -521,18 +531,32 @@ __global__ __launch_bounds__(TB) void k_tree_solve(SolveArgs a) {
         a.A[q] -= dA;
         a.b[q] += db;
       }
+    }
+    __syncthreads();
+    for (int32_t k = t; k < nl; k += TB) {
+      const int32_t q = act[k];
       a.state[q] = a.nstate[q];
     }
     __syncthreads();
+    // this round's eliminated nodes join the elimination order; the rest
+    // form the next round's active list
+    n_elim += block_compact<TB>(
+        nl, [&](int32_t k) { return a.state[act[k]] != kActive; }, [&](int32_t k) { return act[k]; },
+        elim + n_elim, warp_base, &total_sh);
+    nl = block_compact<TB>(
+        nl, [&](int32_t k) { return a.state[act[k]] == kActive; }, [&](int32_t k) { return act[k]; },
+        act_next, warp_base, &total_sh);
+    int32_t* tmp = act;
+    act = act_next;
+    act_next = tmp;
   }
+  if (t == 0) elim_start[rounds] = n_elim;
+  __syncthreads();
 
   // ---- 2. nodes still active sit on cycles (or on paths longer than the
   // round cap): CG on them only
-  int32_t* core = a.core2 + nb;
-  const int32_t ncore = nl == 0 ? 0
-                                : block_compact<TB>(
-                                      nl, [&](int32_t k) { return a.state[list[k]] == kActive; },
-                                      [&](int32_t k) { return list[k]; }, core, warp_base, &total_sh);
+  const int32_t* core = act;
+  const int32_t ncore = nl;
   if (ncore > 0) {
     double bb = 0.0, rz = 0.0;
     for (int32_t k = t; k < ncore; k += TB) {
@@ -584,11 +608,10 @@ __global__ __launch_bounds__(TB) void k_tree_solve(SolveArgs a) {
     __syncthreads();
   }
 
-  // ---- 3. back substitution over the listed nodes, last round first
-  for (int rnd = rounds; rnd >= 0 && nl > 0; --rnd) {
-    for (int32_t k = t; k < nl; k += TB) {
-      const int32_t q = list[k];
-      if (a.state[q] != rnd) continue;
+  // ---- 3. back substitution in reverse elimination order, one round at a time
+  for (int rnd = rounds - 1; rnd >= 0; --rnd) {
+    for (int32_t k = elim_start[rnd] + t; k < elim_start[rnd + 1]; k += TB) {
+      const int32_t q = elim[k];
       const int32_t pn = a.par[q];
       a.y[q] = pn < 0 ? a.b[q] / a.A[q] : (a.b[q] + a.Wp[q] * a.y[pn]) / a.A[q];
     }
@@ -1141,7 +1164,8 @@ hipError_t exact_whiten(const CatView& cat, int C, int64_t n, BatchBufs b, SortB
   a.core = sb.ivec + 3 * E;
   a.core2 = (int32_t*)sb.key_in;  // free after k_nodes (room for 2E entries)
   a.lambda = (cat.sigma * cat.sigma) / (cat.kappa * cat.kappa);
-  a.max_rounds = 64;
+  a.max_rounds = kMaxRounds;
+  a.n_entries = (int32_t)E;
   a.max_iter = 200;
   a.tol2 = 1e-30;  // relative residual 1e-15: z = (r - U y)/sigma^2 scales y errors by 1/sigma^2
   // nodes: at most one per entry; the kernels stop at the node count on the device

@@ -11,7 +11,8 @@ import numpy as np
 import pytest
 
 from gpu_common import (dev, grad_scale, host, lk, make_ctx, psgld_update_tolerance,
-                        scaled_grad_error, spider, synth, torch, whitening_residual)
+                        scaled_grad_error, sigma_apply, spider, synth, torch,
+                        whitening_residual)
 from oracle import batch as obatch
 from oracle import linearity, philox, sampler, stage1
 from oracle import travel_time as ott
@@ -196,6 +197,23 @@ def test_batch_terms_faults_full_batch(ctx, faults_setup):
     mag = np.abs(bt.T_i) + np.abs(bt.T_j) + np.abs(bt.tau) + np.abs(theta[bt.ev_i, 3] - theta[bt.ev_j, 3])
     assert np.max(np.abs(r - bt.r) / mag) < 1e-5
     assert whitening_residual(r, z, bt, prob, lk.WHITEN_EXACT) < 1e-10
+
+
+@pytest.mark.parametrize("n,C", [(1 << 19, 1), (1 << 20, 2)])
+def test_exact_whitening_large_batches(ctx, faults_setup, n, C):
+    """Batches of 2^19 and 2^20 observations (up to 4,096 nodes per group
+    block, several peeling rounds with the block-wide list compactions in
+    between): z solves the batch system of every chain's minibatch."""
+    cat, _, cid, nid = faults_setup
+    prob = lk.load(cat)
+    theta = synth.random_theta(cat, 32)
+    for chain in range(C):
+        out = ctx.batch_terms(cid, nid, dev(theta), None, n=n, seed=9, chain=chain, step=1)
+        idx = obatch.batch_indices(9, 5, chain, 1, cat.N, n)
+        ev_i, ev_j, g, _, w = lk.gather(prob, idx)
+        r, z = host(out["r"]), host(out["z"])
+        Sz = sigma_apply(z, w, g, ev_i, ev_j, prob.M, prob.sigma, prob.kappa, lk.WHITEN_EXACT)
+        assert np.max(np.abs(Sz - r) / (np.abs(r) + 1e-3)) < 1e-10
 
 
 # ----------------------------------------------------------------- gradient
