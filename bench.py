@@ -32,10 +32,10 @@ HBM_PEAK = 8000.0                             # GB/s
 NETWORK_TRAFFIC = {
     "kernel_sources": ["paper_2508_12117_amd/csrc/mlp_mfma.h", "paper_2508_12117_amd/csrc/mlp_pp.h",
                        "paper_2508_12117_amd/csrc/net_rows.h"],
-    "sha256": "1e2e192253e6d9a798baa4b9ebaa680b5a2c345875dec2cfc74e7ea29102209a",
+    "sha256": "c3a980ef6d6249f401676f4c58c0dd6eec182965a02fbe65c4ca2b95e9e797ac",
     "variant": {"waves": 8, "row_tiles": 4, "schedule": 1},
     "rows": 16777216,
-    "fetch_bytes": 1542910763,
+    "fetch_bytes": 1545127936,
     "write_bytes": 268435456,
 }
 

@@ -85,11 +85,12 @@ struct Shape {
   static constexpr int KG = H / 4;             // k per lane group
   static constexpr int NQ = chunks_per_layer<P>(H);
   // LDS rows of H elements, unpadded; the 16-byte chunks of row r sit at
-  // chunk index ^ (r & SWM), which spreads the B-operand reads (16 rows, one
-  // chunk column) and the fragment stores over all banks
+  // chunk index ^ (r & SWM): the 16 rows that one B-operand read or fragment
+  // store touches then land on 16 different chunk slots, which covers the
+  // 64 banks of gfx950's LDS (with 8 slots, rows r and r + 8 collide)
   static constexpr int LDW = H;
   static constexpr int CPR = H / Chunk<P>::ELEMS;  // chunks per row
-  static constexpr int SWM = CPR >= 8 ? 7 : CPR - 1;
+  static constexpr int SWM = CPR >= 16 ? 15 : CPR - 1;
   static constexpr int NL = D > 1 ? D - 1 : 1;  // stored derivative layers
   // derivative layers kept in registers; the rest go to LDS (BF16 pairs)
   static constexpr size_t LAYER_BYTES = (size_t)R * H * 2;  // one BF16 derivative layer

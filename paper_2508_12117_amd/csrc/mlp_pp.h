@@ -33,7 +33,7 @@ struct ShapePP {
   static constexpr int NQ = chunks_per_layer<P>(H);
   static constexpr int LDW = H;
   static constexpr int CPR = H / Chunk<P>::ELEMS;
-  static constexpr int SWM = CPR >= 8 ? 7 : CPR - 1;
+  static constexpr int SWM = CPR >= 16 ? 15 : CPR - 1;
   static constexpr int NL = D - 1;  // stored derivative layers
   static constexpr int NT = NW * 64;
   static constexpr size_t ACT_BYTES = (size_t)R * LDW * sizeof(typename P::T);
