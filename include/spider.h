@@ -333,7 +333,9 @@ int spider_linearity(spider_ctx* ctx, int32_t cat_id, int32_t net_id, int32_t pr
  * samples[slot][C][M][4], slot = the chain's number of recorded states
  * before it (0 after spider_reset_chains), C = the catalog's chain count, as
  * long as slot < capacity.  samples: device, caller-owned and kept alive
- * while attached; NULL detaches.  Errors: SPIDER_E_INVALID. */
+ * while attached, room for capacity * C * M * 4 doubles; NULL detaches.
+ * spider_reset_chains detaches it (attach after resetting).
+ * Errors: SPIDER_E_INVALID, SPIDER_E_STATE (no chains yet). */
 int spider_set_sample_buffer(spider_ctx* ctx, int32_t cat_id, double* samples,
                              int64_t capacity);
 

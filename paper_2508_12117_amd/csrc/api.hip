@@ -1052,6 +1052,8 @@ int spider_reset_chains(spider_ctx* ctx, int32_t cat_id, int32_t n_chains) {
   HIPCK(hipGetLastError(), "init chains");
   cat->C = C;
   cat->adam_zeroed = false;
+  cat->samples = nullptr;  // its layout was sized for the previous chains
+  cat->sample_cap = 0;
   return SPIDER_OK;
 }
 
@@ -1366,6 +1368,8 @@ int spider_set_sample_buffer(spider_ctx* ctx, int32_t cat_id, double* samples,
   Catalog* cat = get_cat(ctx, cat_id);
   if (!cat) return fail(ctx, SPIDER_E_INVALID, "unknown catalog id");
   if (samples && capacity < 1) return fail(ctx, SPIDER_E_INVALID, "need capacity >= 1");
+  if (samples && cat->C < 1)
+    return fail(ctx, SPIDER_E_STATE, "reset the chains before attaching a sample buffer");
   cat->samples = samples;
   cat->sample_cap = samples ? capacity : 0;
   return SPIDER_OK;

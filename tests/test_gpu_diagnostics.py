@@ -215,3 +215,20 @@ def test_four_stage_pipeline(ctx):
         return np.sqrt(np.mean(((th[:, 0:3] - th[:, 0:3].mean(0)) - truth) ** 2))
     e0, e1, e2 = rel_err(cat.hypo0), np.mean([rel_err(s) for s in s1]), rel_err(host(mean))
     assert e1 < 0.3 * e0 and e2 < 0.3 * e0, (e0, e1, e2)
+
+
+def test_sample_buffer_detaches_on_reset(ctx):
+    """A buffer sized for C chains is detached when the chains are reset (to
+    another count), so later steps never write past it; attaching needs
+    chains."""
+    cat = synth.make_catalog("tiny")
+    net = synth.net_for(cat)
+    cid, nid = ctx.load_catalog(cat, stream_id=4), ctx.load_net(net)
+    buf = torch.full((4, 1, cat.M, 4), np.nan, dtype=torch.float64, device="cuda")
+    with pytest.raises(spider.SpiderError):
+        ctx.set_sample_buffer(cid, buf)
+    ctx.reset_chains(cid, 1)
+    ctx.set_sample_buffer(cid, buf)
+    ctx.reset_chains(cid, 3)
+    ctx.sgld_steps([(cid, nid, 3, 1024, spider.FP32)], 5, seed=1)
+    assert np.all(np.isnan(host(buf)))
