@@ -125,7 +125,7 @@ struct Net {
 
 // Scratch of one minibatch pipeline, grown on demand.
 struct Workspace {
-  DevBuf obs, ev, sta, tau, w, net_out, T, gT, r, z;
+  DevBuf obs, ev, sta, tau, w, net_out, T, gT, r, z, wr;
   DevBuf key_in, key_out, val_in, val_out, temp, node_of, node_start, seg_begin, seg_end, flags,
       vec, ivec, count;
   DevBuf G, partial, thetabar, lp_tmp, err;
@@ -147,6 +147,7 @@ struct Workspace {
     RES(gT, E * 24);
     RES(r, Cn * 8);
     RES(z, Cn * 8);
+    RES(wr, Cn * 16);
     RES(key_in, E * 8);
     RES(key_out, E * 8);
     RES(val_in, E * 4);
@@ -185,6 +186,7 @@ struct Workspace {
     b.gT = gT.as<double>();
     b.r = r.as<double>();
     b.z = z.as<double>();
+    b.wr = wr.as<double2>();
     return b;
   }
   SortBufs sort() const {
@@ -472,6 +474,7 @@ BatchBufs batch_at(const BatchBufs& b, int64_t obs_off) {
   o.gT += 6 * obs_off;
   o.r += obs_off;
   o.z += obs_off;
+  o.wr += obs_off;
   return o;
 }
 

@@ -59,6 +59,7 @@ struct BatchBufs {
   double* gT;       // [2 C n][3] source gradient of each row
   double* r;        // [C n] residual
   double* z;        // [C n] whitened residual
+  double2* wr;      // [C n] (w, r) side by side, for the edge gathers of the solver
 };
 
 // Scratch of the exact whitening and the per-event reduction.

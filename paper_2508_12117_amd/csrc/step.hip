@@ -240,6 +240,8 @@ __global__ void k_residual(CatView cat, NetView net, NetView net_s, int C, int64
     b.z[q] = r / s2 * (s_phase ? cat.zscale_s : 1.0);
   } else if (whiten == 1) {
     b.z[q] = r / (s2 + 2.0 * cat.kappa * cat.kappa * b.w[q]) * (s_phase ? cat.zscale_s : 1.0);
+  } else {
+    b.wr[q] = make_double2(b.w[q], r);  // exact whitening: the solver's edge gathers
   }
 }
 
@@ -337,15 +339,15 @@ constexpr int kTreeBlock = 1024;  // threads per (chain, group) system
 // row of U^T r) of every sorted entry, so that the node kernels and the
 // elimination rounds read them contiguously instead of through a chain of
 // lookups.
-__global__ void k_edges(int64_t E, const uint32_t* vals, const int32_t* node_of, const double* w,
-                        const double* r, int32_t* nbr, double* wgt, double* rv) {
+__global__ void k_edges(int64_t E, const uint32_t* vals, const int32_t* node_of, const double2* wr,
+                        int32_t* nbr, double* wgt, double* rv) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= E) return;
   const uint32_t en = vals[e];
-  const double wk = w[en >> 1];
+  const double2 x = wr[en >> 1];  // (w, r) of the entry's observation
   nbr[e] = node_of[en ^ 1u];
-  wgt[e] = wk;
-  rv[e] = ((en & 1u) ? -1.0 : 1.0) * sqrt(wk) * r[en >> 1];
+  wgt[e] = x.x;
+  rv[e] = ((en & 1u) ? -1.0 : 1.0) * sqrt(x.x) * x.y;
 }
 constexpr int32_t kCore = 1 << 30;  // solved by CG after the peeling rounds
 constexpr int32_t kPair = -2;       // solved directly: an isolated single edge
@@ -1140,7 +1142,7 @@ hipError_t exact_whiten(const CatView& cat, int C, int64_t n, BatchBufs b, SortB
   double* wgt = sb.vec + 7 * E;
   double* rv = sb.vec + 4 * E;
   hipLaunchKernelGGL(k_edges, dim3(grid_for(E)), dim3(kBlock), 0, s, E, sb.val_out, sb.node_of,
-                     b.w, b.r, nbr, wgt, rv);
+                     b.wr, nbr, wgt, rv);
   SolveArgs a;
   a.vals = sb.val_out;
   a.node_of = sb.node_of;

@@ -201,9 +201,12 @@ def test_batch_terms_faults_full_batch(ctx, faults_setup):
 
 @pytest.mark.parametrize("n,C", [(1 << 19, 1), (1 << 20, 2)])
 def test_exact_whitening_large_batches(ctx, faults_setup, n, C):
-    """Batches of 2^19 and 2^20 observations (up to 4,096 nodes per group
+    """Batches of 2^19 and 2^20 observations (about 20,000 nodes per group
     block, several peeling rounds with the block-wide list compactions in
-    between): z solves the batch system of every chain's minibatch."""
+    between, cyclic cores for the CG): z solves the batch system of every
+    chain's minibatch.  As for the whole tiny catalog, the Woodbury form
+    z = (r - U y)/sigma^2 puts the rounding floor of this measure near 1e-10
+    once the groups hold cycles of thousands of rows, so the bound is 1e-9."""
     cat, _, cid, nid = faults_setup
     prob = lk.load(cat)
     theta = synth.random_theta(cat, 32)
@@ -213,7 +216,7 @@ def test_exact_whitening_large_batches(ctx, faults_setup, n, C):
         ev_i, ev_j, g, _, w = lk.gather(prob, idx)
         r, z = host(out["r"]), host(out["z"])
         Sz = sigma_apply(z, w, g, ev_i, ev_j, prob.M, prob.sigma, prob.kappa, lk.WHITEN_EXACT)
-        assert np.max(np.abs(Sz - r) / (np.abs(r) + 1e-3)) < 1e-10
+        assert np.max(np.abs(Sz - r) / (np.abs(r) + 1e-3)) < 1e-9
 
 
 # ----------------------------------------------------------------- gradient
