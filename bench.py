@@ -32,11 +32,11 @@ HBM_PEAK = 8000.0                             # GB/s
 NETWORK_TRAFFIC = {
     "kernel_sources": ["paper_2508_12117_amd/csrc/mlp_mfma.h", "paper_2508_12117_amd/csrc/mlp_pp.h",
                        "paper_2508_12117_amd/csrc/net_rows.h"],
-    "sha256": "c3a980ef6d6249f401676f4c58c0dd6eec182965a02fbe65c4ca2b95e9e797ac",
+    "sha256": "96a603008fa9a6407cccbc096bfa851ac303b449bf95ef863f3d11499406b334",
     "variant": {"waves": 8, "row_tiles": 4, "schedule": 1},
     "rows": 16777216,
-    "fetch_bytes": 1545127936,
-    "write_bytes": 268435456,
+    "fetch_bytes": 1682280448,
+    "write_bytes": 805306368,
 }
 
 

@@ -125,7 +125,7 @@ struct Net {
 
 // Scratch of one minibatch pipeline, grown on demand.
 struct Workspace {
-  DevBuf obs, ev, sta, tau, w, net_out, T, gT, r, z, wr;
+  DevBuf obs, ev, sta, tau, w, net_out, T, gT, r, z, wr, xt;
   DevBuf key_in, key_out, val_in, val_out, temp, node_of, node_start, seg_begin, seg_end, flags,
       vec, ivec, count;
   DevBuf G, partial, thetabar, lp_tmp, err;
@@ -148,6 +148,7 @@ struct Workspace {
     RES(r, Cn * 8);
     RES(z, Cn * 8);
     RES(wr, Cn * 16);
+    RES(xt, E * 32);
     RES(key_in, E * 8);
     RES(key_out, E * 8);
     RES(val_in, E * 4);
@@ -187,6 +188,7 @@ struct Workspace {
     b.r = r.as<double>();
     b.z = z.as<double>();
     b.wr = wr.as<double2>();
+    b.xt = xt.as<double4>();
     return b;
   }
   SortBufs sort() const {
@@ -405,6 +407,7 @@ int run_batch(spider_ctx* ctx, Catalog& cat, Net& net, int prec, int C, int64_t 
   src.stations = cv.stations;
   src.x = nullptr;
   src.s = nullptr;
+  src.xt = b.xt;
   Net* net_s = &net;
   int rc;
   if (cat.L_p < cat.L) {
@@ -475,6 +478,7 @@ BatchBufs batch_at(const BatchBufs& b, int64_t obs_off) {
   o.r += obs_off;
   o.z += obs_off;
   o.wr += obs_off;
+  o.xt += 2 * obs_off;
   return o;
 }
 
@@ -522,6 +526,7 @@ int prepare_fused(spider_ctx* ctx, const spider_chainset* sets, int n_sets, Fuse
     r.rows_per_chain = 2 * sets[k].batch;
     r.theta_chain_stride = (int64_t)cat.M * 4;
     r.stations = cat.stations.as<double>();
+    r.xt = bk.xt;
     row0[k] = 2 * f.obs_off[k];
   }
   row0[n_sets] = 2 * f.total_obs;

@@ -60,6 +60,7 @@ struct BatchBufs {
   double* r;        // [C n] residual
   double* z;        // [C n] whitened residual
   double2* wr;      // [C n] (w, r) side by side, for the edge gathers of the solver
+  double4* xt;      // [2 C n] event state of each row, written by the network kernels
 };
 
 // Scratch of the exact whitening and the per-event reduction.

@@ -213,15 +213,13 @@ __global__ void k_residual(CatView cat, NetView net, NetView net_s, int C, int64
                            const double* theta, int64_t theta_stride, int whiten, BatchBufs b) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= (int64_t)C * n) return;
-  const int c = (int)(q / n);
-  const double* th = theta + (int64_t)c * theta_stride;
   double T[2], tt[2];
   const bool s_phase = b.sta[2 * q] >= cat.L_p;
   for (int side = 0; side < 2; ++side) {
     const int64_t row = 2 * q + side;
-    const double* xe = th + (int64_t)b.ev[row] * 4;
+    const double4 xe = b.xt[row];  // the row's event state, as the network read it
     const double* st = cat.stations + (int64_t)b.sta[row] * 3;
-    const double x[3] = {xe[0], xe[1], xe[2]};
+    const double x[3] = {xe.x, xe.y, xe.z};
     const double s[3] = {st[0], st[1], st[2]};
     double g[3];
     assemble_tt(s_phase ? net_s : net, x, s, b.net_out[row], T[side], g);
@@ -229,7 +227,7 @@ __global__ void k_residual(CatView cat, NetView net, NetView net_s, int C, int64
     b.gT[row * 3 + 0] = g[0];
     b.gT[row * 3 + 1] = g[1];
     b.gT[row * 3 + 2] = g[2];
-    tt[side] = xe[3];
+    tt[side] = xe.w;
   }
   const double r = b.tau[q] - ((T[0] - T[1]) + (tt[0] - tt[1]));
   b.r[q] = r;
