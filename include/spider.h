@@ -164,13 +164,30 @@ typedef struct {
 int spider_load_net(spider_ctx* ctx, const spider_net_desc* desc, int32_t* net_id);
 
 /* T(x; s) and dT/dx for `rows` source/receiver pairs.  x_src, s: device
- * [rows][3]; T: device [rows]; gradT: device [rows][3] or NULL.  Forward
- * pass then reverse-mode source gradient (Sec. 3.2) with activations
- * recomputed on chip, never stored to memory.  rows may be 0.
+ * [rows][3]; T: device [rows]; gradT: device [rows][3] or NULL.  One kernel
+ * runs the forward pass and then the reverse-mode source gradient (Sec. 3.2):
+ * the derivative factors 1 - a^2 of the hidden layers stay in registers and
+ * LDS between the two passes, so no activation is written to memory and
+ * nothing is recomputed.  rows may be 0.
  * Errors: SPIDER_E_INVALID (ids, rows < 0, NULL required pointers). */
 int spider_travel_time(spider_ctx* ctx, int32_t net_id, int32_t precision,
                        const double* x_src, const double* s, int64_t rows,
                        double* T, double* gradT);
+
+/* The two halves of a differentiable T (Sec. 3.2 and Sec. 5: any
+ * differentiable travel-time model), for a reverse-mode caller such as an
+ * autograd engine.  spider_tt_forward writes T only (device [rows]).
+ * spider_tt_backward evaluates the network again at the same points (the
+ * activations of the forward call are not kept anywhere) and writes the
+ * vector-Jacobian product grad_x[r] = grad_T[r] dT/dx(x_src[r]; s[r])
+ * (device [rows][3]) for the source only; grad_T is device [rows].
+ * x_src, s: device [rows][3].  rows may be 0.
+ * Errors: SPIDER_E_INVALID (ids, rows < 0, NULL pointers). */
+int spider_tt_forward(spider_ctx* ctx, int32_t net_id, int32_t precision,
+                      const double* x_src, const double* s, int64_t rows, double* T);
+int spider_tt_backward(spider_ctx* ctx, int32_t net_id, int32_t precision,
+                       const double* x_src, const double* s, const double* grad_T,
+                       int64_t rows, double* grad_x);
 
 /* ---- one stochastic gradient (eq:sgd) ----------------------------------
  * g = [prior terms] + (N/n) * sum_{k<n} (d tau^_k / d theta)^T z_k

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "index_limits.h"
 #include "spider.h"
 
 using namespace spider;
@@ -346,19 +347,38 @@ int pick_variant(spider_ctx* ctx, const NetView& nv, int prec, const RowSource& 
   return SPIDER_OK;
 }
 
-// Network forward/backward over the rows of src.
-int run_network(spider_ctx* ctx, const Net& net, int prec, const RowSource& src, RowOut* out) {
+// The variant a launch uses without tuning: SPIDER_MLP_VARIANT, else the
+// context's tuned choice, else the first one (all give identical results).
+int untuned_variant(const spider_ctx* ctx, int prec, const Net& net, int nvar) {
+  if (const char* env = std::getenv("SPIDER_MLP_VARIANT")) {
+    const int k = std::atoi(env);
+    return (k >= 0 && k < nvar) ? k : 0;
+  }
+  auto it = ctx->tuned.find(std::make_tuple(prec, net.H, net.D));
+  return it == ctx->tuned.end() ? 0 : it->second;
+}
+
+// Network forward/backward over the rows of src.  With may_allocate false
+// the launch is never tuned or profiled (both create HIP events), so it
+// enqueues the kernel and nothing else.
+int run_network(spider_ctx* ctx, const Net& net, int prec, const RowSource& src, RowOut* out,
+                bool may_allocate = true) {
   const NetView nv = net.view(prec);
   hipError_t e;
   const MlpVariant* vl = nullptr;
   const int nvar = mlp_variants(prec, net.H, net.D, &vl);
   int vi = 0;
   if (nvar > 0 && src.rows > 0) {
-    int rc = pick_variant(ctx, nv, prec, src, out, vl, nvar, &vi);
-    if (rc != SPIDER_OK) return rc;
+    if (may_allocate) {
+      int rc = pick_variant(ctx, nv, prec, src, out, vl, nvar, &vi);
+      if (rc != SPIDER_OK) return rc;
+    } else {
+      vi = untuned_variant(ctx, prec, net, nvar);
+    }
   }
+  const bool prof = ctx->profiling && may_allocate;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  if (ctx->profiling) {
+  if (prof) {
     HIPCK(hipEventCreate(&ev0), "event");
     HIPCK(hipEventCreate(&ev1), "event");
     HIPCK(hipEventRecord(ev0, ctx->stream), "event");
@@ -371,7 +391,7 @@ int run_network(spider_ctx* ctx, const Net& net, int prec, const RowSource& src,
     return fail(ctx, SPIDER_E_UNSUPPORTED, "no BF16 matrix-core kernel for this network shape");
   }
   if (e != hipSuccess) return hip_fail(ctx, e, "network kernel");
-  if (ctx->profiling) {
+  if (prof) {
     HIPCK(hipEventRecord(ev1, ctx->stream), "event");
     ctx->prof_events.emplace_back(ev0, ev1);
     ctx->prof_rows.push_back(src.rows);
@@ -455,7 +475,7 @@ int run_batch(spider_ctx* ctx, Catalog& cat, Net& net, int prec, int C, int64_t 
   launch_residual(cv, net.view(prec), net_s->view(prec), C, n, theta, theta_stride, whiten, b,
                   ctx->stream);
   if (whiten == SPIDER_WHITEN_EXACT)
-    HIPCK(exact_whiten(cv, C, n, b, ws.sort(), ctx->stream), "exact whitening");
+    HIPCK(exact_whiten(cv, C, n, b, ws.sort(), ws.err.as<int>(), ctx->stream), "exact whitening");
   if (grad)
     HIPCK(reduce_events(cv, C, n, scale, b, ws.sort(), ws.G.as<double>(), ctx->stream),
           "per-event reduction");
@@ -576,7 +596,7 @@ int fused_step(spider_ctx* ctx, const spider_chainset* sets, int n_sets, const F
     launch_residual(cv, nv, nv, C, n, cat.theta.as<double>(), (int64_t)cat.M * 4, whiten, bk,
                     ctx->stream);
     if (whiten == SPIDER_WHITEN_EXACT)
-      HIPCK(exact_whiten(cv, C, n, bk, ws.sort(), ctx->stream), "exact whitening");
+      HIPCK(exact_whiten(cv, C, n, bk, ws.sort(), ws.err.as<int>(), ctx->stream), "exact whitening");
     HIPCK(reduce_events(cv, C, n, (double)cat.N / (double)n, bk, ws.sort(), ws.G.as<double>(),
                         ctx->stream),
           "per-event reduction");
@@ -596,15 +616,50 @@ int check_select_flag(spider_ctx* ctx) {
                        ctx->stream),
         "read flag");
   HIPCK(hipStreamSynchronize(ctx->stream), "sync");
-  if (flag)
+  if (flag & kErrSelect)
     return fail(ctx, SPIDER_E_INVALID,
                 "observation index out of range (or the minibatch permutation walk failed)");
+  if (flag & kErrSolve)
+    return fail(ctx, SPIDER_E_NUMERIC,
+                "exact whitening: the CG solve of a cyclic core stayed above 1e-8 relative "
+                "residual after 200 iterations");
   return SPIDER_OK;
 }
 
 int reset_err_flag(spider_ctx* ctx) {
   HIPCK(ctx->ws.err.reserve(64), "workspace");
   HIPCK(hipMemsetAsync(ctx->ws.err.p, 0, sizeof(int), ctx->stream), "flag reset");
+  return SPIDER_OK;
+}
+
+// T and dT/dx (or vjp_w dT/dx) of explicit rows: the network kernel into
+// the RowOut buffer `net_out`, then the FP64 assembly.
+int travel_time_rows(spider_ctx* ctx, Net& net, int32_t precision, const double* x_src,
+                     const double* s, int64_t rows, RowOut* net_out, bool may_allocate,
+                     double* T, double* gradT, const double* vjp_w) {
+  RowSource src;
+  std::memset(&src, 0, sizeof(src));
+  src.mode = 1;
+  src.rows = rows;
+  src.x = x_src;
+  src.s = s;
+  int rc = run_network(ctx, net, precision, src, net_out, may_allocate);
+  if (rc != SPIDER_OK) return rc;
+  launch_tt_assemble(net.view(precision), rows, x_src, s, net_out, T, gradT, vjp_w, ctx->stream);
+  HIPCK(hipGetLastError(), "travel time");
+  return SPIDER_OK;
+}
+
+// Common checks of the travel-time calls; *skip is set when rows == 0.
+int travel_time_args(spider_ctx* ctx, int32_t net_id, int32_t precision, int64_t rows,
+                     Net** net, bool* skip) {
+  *net = get_net(ctx, net_id);
+  *skip = false;
+  if (!*net) return fail(ctx, SPIDER_E_INVALID, "unknown network id");
+  if (precision != SPIDER_FP32 && precision != SPIDER_BF16)
+    return fail(ctx, SPIDER_E_INVALID, "unknown precision");
+  if (rows < 0) return fail(ctx, SPIDER_E_INVALID, "rows < 0");
+  *skip = rows == 0;
   return SPIDER_OK;
 }
 
@@ -918,26 +973,42 @@ int spider_travel_time(spider_ctx* ctx, int32_t net_id, int32_t precision, const
                        const double* s, int64_t rows, double* T, double* gradT) {
   if (!ctx) return SPIDER_E_INVALID;
   DeviceGuard g(ctx->device);
-  Net* net = get_net(ctx, net_id);
-  if (!net) return fail(ctx, SPIDER_E_INVALID, "unknown network id");
-  if (precision != SPIDER_FP32 && precision != SPIDER_BF16)
-    return fail(ctx, SPIDER_E_INVALID, "unknown precision");
-  if (rows < 0) return fail(ctx, SPIDER_E_INVALID, "rows < 0");
-  if (rows == 0) return SPIDER_OK;
+  Net* net;
+  bool skip;
+  int rc = travel_time_args(ctx, net_id, precision, rows, &net, &skip);
+  if (rc != SPIDER_OK || skip) return rc;
   if (!x_src || !s || !T) return fail(ctx, SPIDER_E_INVALID, "null array");
   HIPCK(ctx->ws.net_out.reserve((size_t)rows * sizeof(RowOut)), "workspace");
-  RowSource src;
-  std::memset(&src, 0, sizeof(src));
-  src.mode = 1;
-  src.rows = rows;
-  src.x = x_src;
-  src.s = s;
-  int rc = run_network(ctx, *net, precision, src, ctx->ws.net_out.as<RowOut>());
-  if (rc != SPIDER_OK) return rc;
-  launch_tt_assemble(net->view(precision), rows, x_src, s, ctx->ws.net_out.as<RowOut>(), T, gradT,
-                     ctx->stream);
-  HIPCK(hipGetLastError(), "travel time");
-  return SPIDER_OK;
+  return travel_time_rows(ctx, *net, precision, x_src, s, rows, ctx->ws.net_out.as<RowOut>(), true,
+                          T, gradT, nullptr);
+}
+
+int spider_tt_forward(spider_ctx* ctx, int32_t net_id, int32_t precision, const double* x_src,
+                      const double* s, int64_t rows, double* T) {
+  if (!ctx) return SPIDER_E_INVALID;
+  DeviceGuard g(ctx->device);
+  Net* net;
+  bool skip;
+  int rc = travel_time_args(ctx, net_id, precision, rows, &net, &skip);
+  if (rc != SPIDER_OK || skip) return rc;
+  if (!x_src || !s || !T) return fail(ctx, SPIDER_E_INVALID, "null array");
+  HIPCK(ctx->ws.net_out.reserve((size_t)rows * sizeof(RowOut)), "workspace");
+  return travel_time_rows(ctx, *net, precision, x_src, s, rows, ctx->ws.net_out.as<RowOut>(), true,
+                          T, nullptr, nullptr);
+}
+
+int spider_tt_backward(spider_ctx* ctx, int32_t net_id, int32_t precision, const double* x_src,
+                       const double* s, const double* grad_T, int64_t rows, double* grad_x) {
+  if (!ctx) return SPIDER_E_INVALID;
+  DeviceGuard g(ctx->device);
+  Net* net;
+  bool skip;
+  int rc = travel_time_args(ctx, net_id, precision, rows, &net, &skip);
+  if (rc != SPIDER_OK || skip) return rc;
+  if (!x_src || !s || !grad_T || !grad_x) return fail(ctx, SPIDER_E_INVALID, "null array");
+  HIPCK(ctx->ws.net_out.reserve((size_t)rows * sizeof(RowOut)), "workspace");
+  return travel_time_rows(ctx, *net, precision, x_src, s, rows, ctx->ws.net_out.as<RowOut>(), true,
+                          nullptr, grad_x, grad_T);
 }
 
 static int grad_common(spider_ctx* ctx, int32_t cat_id, int32_t net_id, int32_t precision,
@@ -953,6 +1024,8 @@ static int grad_common(spider_ctx* ctx, int32_t cat_id, int32_t net_id, int32_t 
   if (!theta) return fail(ctx, SPIDER_E_INVALID, "null theta");
   if (n < 1) return fail(ctx, SPIDER_E_INVALID, "n must be >= 1");
   if (!batch_idx && n > cat->N) return fail(ctx, SPIDER_E_INVALID, "n > N");
+  if (!entries_fit(1, n))
+    return fail(ctx, SPIDER_E_UNSUPPORTED, "minibatch above 2^30 - 1 observations");
   if (chain < 0 || step < 0) return fail(ctx, SPIDER_E_INVALID, "chain and step must be >= 0");
   int rc = reset_err_flag(ctx);
   if (rc) return rc;
@@ -1017,6 +1090,8 @@ int spider_batch_indices(spider_ctx* ctx, int32_t cat_id, uint64_t seed, int32_t
   if (!cat) return fail(ctx, SPIDER_E_INVALID, "unknown catalog id");
   if (n < 1 || n > cat->N) return fail(ctx, SPIDER_E_INVALID, "need 1 <= n <= N");
   if (!idx_out || chain < 0 || step < 0) return fail(ctx, SPIDER_E_INVALID, "bad argument");
+  if (!entries_fit(1, n))
+    return fail(ctx, SPIDER_E_UNSUPPORTED, "minibatch above 2^30 - 1 observations");
   int rc = reset_err_flag(ctx);
   if (rc) return rc;
   HIPCK(ctx->ws.reserve(1, n, cat->M, cat->L), "workspace");
@@ -1121,9 +1196,21 @@ int spider_sgld_steps(spider_ctx* ctx, const spider_chainset* sets, int32_t n_se
       return fail(ctx, SPIDER_E_INVALID, "need n_chains >= 1 and 1 <= batch <= N");
     if (st.precision != SPIDER_FP32 && st.precision != SPIDER_BF16)
       return fail(ctx, SPIDER_E_INVALID, "unknown precision");
+    if (!entries_fit(st.n_chains, st.batch))
+      return fail(ctx, SPIDER_E_UNSUPPORTED,
+                  "a chain set holds more than 2^31 - 1 minibatch entries (2 n_chains batch)");
     if (cat->C < st.n_chains) {
       int rc = spider_reset_chains(ctx, st.cat_id, st.n_chains);
       if (rc) return rc;
+    }
+  }
+  {
+    int64_t total = 0;  // entries of all sets (one fused step holds them all)
+    for (int k = 0; k < n_sets; ++k) {
+      total += 2 * (int64_t)sets[k].n_chains * sets[k].batch;
+      if (total > kMaxEntries)
+        return fail(ctx, SPIDER_E_UNSUPPORTED,
+                    "the chain sets hold more than 2^31 - 1 minibatch entries in total");
     }
   }
   int rc = reset_err_flag(ctx);
@@ -1201,6 +1288,9 @@ int spider_map_steps(spider_ctx* ctx, const spider_chainset* sets, int32_t n_set
       return fail(ctx, SPIDER_E_INVALID, "need n_chains >= 1 and 1 <= batch <= N");
     if (st.precision != SPIDER_FP32 && st.precision != SPIDER_BF16)
       return fail(ctx, SPIDER_E_INVALID, "unknown precision");
+    if (!entries_fit(st.n_chains, st.batch))
+      return fail(ctx, SPIDER_E_UNSUPPORTED,
+                  "a chain set holds more than 2^31 - 1 minibatch entries (2 n_chains batch)");
     if (cat->C < st.n_chains) {
       int rc = spider_reset_chains(ctx, st.cat_id, st.n_chains);
       if (rc) return rc;
@@ -1446,6 +1536,8 @@ int spider_noise_ratio(spider_ctx* ctx, int32_t cat_id, int32_t net_id, int32_t 
   if (!cfg || !ratio) return fail(ctx, SPIDER_E_INVALID, "null argument");
   if (batch < 1 || batch > cat->N || n_batches < 2)
     return fail(ctx, SPIDER_E_INVALID, "need 1 <= batch <= N and n_batches >= 2");
+  if (!entries_fit(1, batch))
+    return fail(ctx, SPIDER_E_UNSUPPORTED, "minibatch above 2^30 - 1 observations");
   if (!(cfg->step > 0) || !(cfg->noise_scale > 0) || !(cfg->eps_p > 0))
     return fail(ctx, SPIDER_E_INVALID, "need step, noise_scale, eps_p > 0");
   const int64_t n4 = (int64_t)cat->M * 4;

@@ -128,9 +128,15 @@ void launch_select(const CatView& cat, int C, int64_t n, const int64_t* idx, uin
 void launch_residual(const CatView& cat, const NetView& net, const NetView& net_s, int C, int64_t n,
                      const double* theta, int64_t theta_stride, int whiten, BatchBufs b,
                      hipStream_t s);
+// Error bits a step sets in its device flag (read back by the host after
+// the call): a minibatch index outside [0, N) or a failed permutation walk,
+// and a CG solve of a cyclic core that did not converge.
+constexpr int kErrSelect = 1;
+constexpr int kErrSolve = 2;
 // Exact whitening z = Sigma_B^{-1} r by Woodbury + a per-(chain, group)
-// elimination solve of the batch graph system.
-hipError_t exact_whiten(const CatView& cat, int C, int64_t n, BatchBufs b, SortBufs sb,
+// elimination solve of the batch graph system; err |= kErrSolve when a CG
+// core does not converge.
+hipError_t exact_whiten(const CatView& cat, int C, int64_t n, BatchBufs b, SortBufs sb, int* err,
                         hipStream_t s);
 // G_lik[c][m] = scale * sum over the chain's batch of the event's terms.
 hipError_t reduce_events(const CatView& cat, int C, int64_t n, double scale, BatchBufs b,
@@ -174,8 +180,11 @@ void launch_grad_finish(const CatView& cat, const double* theta, const double* G
 void launch_logpost(const CatView& cat, int64_t n, double scale, const double* r, const double* z,
                     const double* theta, const double* thetabar, unsigned flags, double* tmp,
                     double* out, hipStream_t s);
+// T (may be null) and dT/dx (may be null; scaled by vjp_w[r] when vjp_w is
+// not null) of explicit rows from the network outputs.
 void launch_tt_assemble(const NetView& net, int64_t rows, const double* x, const double* s,
-                        const RowOut* out, double* T, double* gradT, hipStream_t st);
+                        const RowOut* out, double* T, double* gradT, const double* vjp_w,
+                        hipStream_t st);
 void launch_batch_terms_out(int64_t n, const BatchBufs& b, double* T_i, double* T_j, double* gT_i,
                             double* gT_j, double* r, double* z, hipStream_t s);
 void launch_noise(const CatView& cat, uint64_t seed, int chain, int64_t step, double* eta,

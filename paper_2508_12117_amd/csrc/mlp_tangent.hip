@@ -5,8 +5,8 @@
 // the source inputs (c = 0, 1, 2):  da_1/du_c = (1 - a_1^2) W_0[:, c],
 // da_{l+1}/du_c = (1 - a_{l+1}^2) (W_l da_l/du_c), do/du_c = w_out . da_D/du_c.
 // This is the same derivative as the paper's reverse-mode AD (Sec. 3.2) with
-// no stored activations at all; it serves shapes the matrix-core kernels do
-// not instantiate and is the reference the faster kernels are tested against.
+// no stored activations at all; it serves the FP32 path of shapes the
+// matrix-core kernels do not instantiate.
 //
 // Block: 256 threads, TR rows.  Thread t owns neuron t % H for rows
 // t / H, t / H + 256 / H, ...  LDS holds the current layer as

@@ -162,7 +162,7 @@ __global__ void k_select(CatView cat, int C, int64_t n, const int64_t* idx, uint
                         (uint32_t)epoch);
   }
   if (o < 0 || o >= cat.N) {
-    atomicOr(err, 1);
+    atomicOr(err, kErrSelect);
     o = 0;
   }
   const ObsRec rc = cat.rec[o];
@@ -326,7 +326,9 @@ struct SolveArgs {
   double lambda;
   int max_rounds;
   int max_iter;
-  double tol2;
+  double tol2;     // CG stops once |res|^2 <= tol2 |rhs|^2
+  double accept2;  // after max_iter, |res|^2 > accept2 |rhs|^2 raises kErrSolve
+  int* err;        // error bits of the step
 };
 
 constexpr int32_t kActive = -1;
@@ -554,56 +556,76 @@ __global__ __launch_bounds__(TB) void k_tree_solve(SolveArgs a) {
   __syncthreads();
 
   // ---- 2. nodes still active sit on cycles (or on paths longer than the
-  // round cap): CG on them only
+  // round cap): Jacobi-preconditioned CG on them only.  Each pass starts from
+  // the true residual b - A y of the current y (the first from y = 0), so a
+  // second pass corrects the drift of CG's recursively updated residual.
   const int32_t* core = act;
   const int32_t ncore = nl;
   if (ncore > 0) {
-    double bb = 0.0, rz = 0.0;
+    double bb = 0.0;
     for (int32_t k = t; k < ncore; k += TB) {
       const int32_t q = core[k];
-      const double rhs = a.b[q];
       a.y[q] = 0.0;
-      a.rr[q] = rhs;
-      a.p[q] = rhs / a.A[q];
-      bb += rhs * rhs;
-      rz += rhs * rhs / a.A[q];
+      bb += a.b[q] * a.b[q];
     }
     bb = block_sum<TB>(bb, sh);
-    rz = block_sum<TB>(rz, sh);
-    for (int it = 0; it < a.max_iter && bb > 0.0; ++it) {
-      double pap = 0.0;
+    double rn = bb;
+    for (int pass = 0; pass < 2 && bb > 0.0; ++pass) {
+      double rz = 0.0;
+      rn = 0.0;
       for (int32_t k = t; k < ncore; k += TB) {
         const int32_t q = core[k];
-        double v = a.A[q] * a.p[q];
+        double v = a.b[q] - a.A[q] * a.y[q];
         for (int32_t e = a.node_start[q]; e < a.node_start[q + 1]; ++e) {
           const int32_t pn = a.nbr[e];
-          if (a.state[pn] == kActive) v -= a.wgt[e] * a.p[pn];
+          if (a.state[pn] == kActive) v += a.wgt[e] * a.y[pn];
         }
-        a.ap[q] = v;
-        pap += a.p[q] * v;
-      }
-      pap = block_sum<TB>(pap, sh);
-      const double alpha = rz / pap;
-      double rn = 0.0, rz_new = 0.0;
-      for (int32_t k = t; k < ncore; k += TB) {
-        const int32_t q = core[k];
-        a.y[q] += alpha * a.p[q];
-        const double rq = a.rr[q] - alpha * a.ap[q];
-        a.rr[q] = rq;
-        rn += rq * rq;
-        rz_new += rq * rq / a.A[q];
+        a.rr[q] = v;
+        a.p[q] = v / a.A[q];
+        rn += v * v;
+        rz += v * v / a.A[q];
       }
       rn = block_sum<TB>(rn, sh);
-      rz_new = block_sum<TB>(rz_new, sh);
+      rz = block_sum<TB>(rz, sh);
       if (rn <= a.tol2 * bb) break;
-      const double beta = rz_new / rz;
-      rz = rz_new;
-      for (int32_t k = t; k < ncore; k += TB) {
-        const int32_t q = core[k];
-        a.p[q] = a.rr[q] / a.A[q] + beta * a.p[q];
+      for (int it = 0; it < a.max_iter; ++it) {
+        double pap = 0.0;
+        for (int32_t k = t; k < ncore; k += TB) {
+          const int32_t q = core[k];
+          double v = a.A[q] * a.p[q];
+          for (int32_t e = a.node_start[q]; e < a.node_start[q + 1]; ++e) {
+            const int32_t pn = a.nbr[e];
+            if (a.state[pn] == kActive) v -= a.wgt[e] * a.p[pn];
+          }
+          a.ap[q] = v;
+          pap += a.p[q] * v;
+        }
+        pap = block_sum<TB>(pap, sh);
+        const double alpha = rz / pap;
+        double rz_new = 0.0;
+        rn = 0.0;
+        for (int32_t k = t; k < ncore; k += TB) {
+          const int32_t q = core[k];
+          a.y[q] += alpha * a.p[q];
+          const double rq = a.rr[q] - alpha * a.ap[q];
+          a.rr[q] = rq;
+          rn += rq * rq;
+          rz_new += rq * rq / a.A[q];
+        }
+        rn = block_sum<TB>(rn, sh);
+        rz_new = block_sum<TB>(rz_new, sh);
+        if (rn <= a.tol2 * bb) break;
+        const double beta = rz_new / rz;
+        rz = rz_new;
+        for (int32_t k = t; k < ncore; k += TB) {
+          const int32_t q = core[k];
+          a.p[q] = a.rr[q] / a.A[q] + beta * a.p[q];
+        }
+        __syncthreads();
       }
-      __syncthreads();
     }
+    // not converged to the acceptance level: the step reports an error
+    if (t == 0 && bb > 0.0 && !(rn <= a.accept2 * bb)) atomicOr(a.err, kErrSolve);
     for (int32_t k = t; k < ncore; k += TB) a.state[core[k]] = kCore;
     __syncthreads();
   }
@@ -835,19 +857,23 @@ __global__ void k_logpost_final(CatView cat, const double* tmp, int nb, const do
   *out = s;
 }
 
+// T and dT/dx of explicit rows from the network outputs; with vjp_w the
+// source gradient is written scaled by the row's weight, w dT/dx (the
+// vector-Jacobian product of a reverse sweep through T).  T may be null.
 __global__ void k_tt_assemble(NetView net, int64_t rows, const double* x, const double* s,
-                              const RowOut* out, double* T, double* gradT) {
+                              const RowOut* out, double* T, double* gradT, const double* vjp_w) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= rows) return;
   const double xx[3] = {x[r * 3], x[r * 3 + 1], x[r * 3 + 2]};
   const double ss[3] = {s[r * 3], s[r * 3 + 1], s[r * 3 + 2]};
   double tt, g[3];
   assemble_tt(net, xx, ss, out[r], tt, g);
-  T[r] = tt;
+  if (T) T[r] = tt;
   if (gradT) {
-    gradT[r * 3] = g[0];
-    gradT[r * 3 + 1] = g[1];
-    gradT[r * 3 + 2] = g[2];
+    const double w = vjp_w ? vjp_w[r] : 1.0;
+    gradT[r * 3] = w * g[0];
+    gradT[r * 3 + 1] = w * g[1];
+    gradT[r * 3 + 2] = w * g[2];
   }
 }
 
@@ -1125,7 +1151,7 @@ hipError_t group_nodes(int C, int64_t n, const CatView& cat, const BatchBufs& b,
   return hipGetLastError();
 }
 
-hipError_t exact_whiten(const CatView& cat, int C, int64_t n, BatchBufs b, SortBufs sb,
+hipError_t exact_whiten(const CatView& cat, int C, int64_t n, BatchBufs b, SortBufs sb, int* err,
                         hipStream_t s) {
   const int64_t E = 2 * (int64_t)C * n;
   if (E <= 0) return hipSuccess;  // the node kernels read the node count k_nodes writes
@@ -1167,7 +1193,11 @@ hipError_t exact_whiten(const CatView& cat, int C, int64_t n, BatchBufs b, SortB
   a.max_rounds = kMaxRounds;
   a.n_entries = (int32_t)E;
   a.max_iter = 200;
-  a.tol2 = 1e-30;  // relative residual 1e-15: z = (r - U y)/sigma^2 scales y errors by 1/sigma^2
+  // relative residual 1e-14 (z = (r - U y)/sigma^2 scales y errors by
+  // 1/sigma^2); a core still above 1e-8 after max_iter is an error
+  a.tol2 = 1e-28;
+  a.accept2 = 1e-16;
+  a.err = err;
   // nodes: at most one per entry; the kernels stop at the node count on the device
   hipLaunchKernelGGL(k_node_init, dim3(grid_for(E)), dim3(kBlock), 0, s, sb.count, a.node_start,
                      wgt, rv, a.lambda, a.A, a.b, a.state, a.par);
@@ -1263,10 +1293,11 @@ void launch_logpost(const CatView& cat, int64_t n, double scale, const double* r
 }
 
 void launch_tt_assemble(const NetView& net, int64_t rows, const double* x, const double* s,
-                        const RowOut* out, double* T, double* gradT, hipStream_t st) {
+                        const RowOut* out, double* T, double* gradT, const double* vjp_w,
+                        hipStream_t st) {
   if (rows == 0) return;
   hipLaunchKernelGGL(k_tt_assemble, dim3(grid_for(rows)), dim3(kBlock), 0, st, net, rows, x, s,
-                     out, T, gradT);
+                     out, T, gradT, vjp_w);
 }
 
 void launch_batch_terms_out(int64_t n, const BatchBufs& b, double* T_i, double* T_j, double* gT_i,

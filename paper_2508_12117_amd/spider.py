@@ -81,6 +81,8 @@ _SIGS = {
     "spider_load_catalog": ([_P, ct.POINTER(CatalogDesc), ct.POINTER(ct.c_int32)], ct.c_int),
     "spider_load_net": ([_P, ct.POINTER(NetDesc), ct.POINTER(ct.c_int32)], ct.c_int),
     "spider_travel_time": ([_P, ct.c_int32, ct.c_int32, _P, _P, ct.c_int64, _P, _P], ct.c_int),
+    "spider_tt_forward": ([_P, ct.c_int32, ct.c_int32, _P, _P, ct.c_int64, _P], ct.c_int),
+    "spider_tt_backward": ([_P, ct.c_int32, ct.c_int32, _P, _P, _P, ct.c_int64, _P], ct.c_int),
     "spider_grad": ([_P, ct.c_int32, ct.c_int32, ct.c_int32, _P, _P, ct.c_int64, ct.c_uint64,
                      ct.c_int32, ct.c_int64, ct.c_uint32, _P, _P], ct.c_int),
     "spider_batch_terms": ([_P, ct.c_int32, ct.c_int32, ct.c_int32, _P, _P, ct.c_int64,
@@ -261,6 +263,14 @@ class Context:
     def travel_time(self, net_id, x_src, s, T, gradT=None, precision=FP32):
         self._check(lib().spider_travel_time(self._h, net_id, precision, _ptr(x_src), _ptr(s),
                                              x_src.shape[0], _ptr(T), _ptr(gradT)))
+
+    def tt_forward(self, net_id, x_src, s, T, precision=FP32):
+        self._check(lib().spider_tt_forward(self._h, net_id, precision, _ptr(x_src), _ptr(s),
+                                            x_src.shape[0], _ptr(T)))
+
+    def tt_backward(self, net_id, x_src, s, grad_T, grad_x, precision=FP32):
+        self._check(lib().spider_tt_backward(self._h, net_id, precision, _ptr(x_src), _ptr(s),
+                                             _ptr(grad_T), x_src.shape[0], _ptr(grad_x)))
 
     def grad(self, cat_id, net_id, theta, grad_out, batch_idx=None, n=None, seed=0, chain=0,
              step=0, flags=GRAD_PRIOR | GRAD_CENTROID, logpost=None, precision=FP32):

@@ -69,6 +69,30 @@ def whitening_residual(r, z, bt, prob, mode):
     return float(np.max(np.abs(Sz - r) / (np.abs(r) + 1e-3)))
 
 
+def woodbury_floor(r, w, group, ev_i, ev_j, M, sigma, kappa):
+    """The rounding floor of the Woodbury form the GPU uses, for the same r:
+    y from a direct sparse FP64 solve of (lambda I + U^T U) y = U^T r
+    (lambda = sigma^2/kappa^2, U = W^1/2 A_B), then z = (r - U y)/sigma^2;
+    returns whitening_residual's measure of that z.  The subtraction r - U y
+    cancels most of r where groups are dense, so this floor sits well above
+    that of a direct solve of Sigma_B z = r."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    key_i = np.asarray(group, np.int64) * M + ev_i
+    key_j = np.asarray(group, np.int64) * M + ev_j
+    nodes, inv = np.unique(np.concatenate([key_i, key_j]), return_inverse=True)
+    n = r.shape[0]
+    sw = np.sqrt(w)
+    rows = np.concatenate([np.arange(n), np.arange(n)])
+    U = sp.csr_matrix((np.concatenate([sw, -sw]), (rows, inv)), shape=(n, nodes.shape[0]))
+    lam = sigma ** 2 / kappa ** 2
+    K = (sp.identity(nodes.shape[0]) * lam + U.T @ U).tocsc()
+    y = spla.spsolve(K, U.T @ r)
+    z = (r - U @ y) / sigma ** 2
+    Sz = sigma_apply(z, w, group, ev_i, ev_j, M, sigma, kappa, lk.WHITEN_EXACT)
+    return float(np.max(np.abs(Sz - r) / (np.abs(r) + 1e-3)))
+
+
 def psgld_update_tolerance(theta, v, G, dG, cfg, eta):
     """How far one pSGLD update (state theta, v) can move when its gradient G
     is off by up to dG per entry: the drift eps G / (sqrt(v') + eps_p) is
@@ -100,4 +124,5 @@ def scaled_grad_error(G_gpu, G_ref, S, floor):
 
 
 __all__ = ["torch", "lk", "spider", "synth", "dev", "host", "make_ctx", "grad_scale",
-           "scaled_grad_error", "sigma_apply", "whitening_residual", "psgld_update_tolerance"]
+           "scaled_grad_error", "sigma_apply", "whitening_residual", "psgld_update_tolerance",
+           "woodbury_floor"]
