@@ -189,6 +189,25 @@ int spider_tt_backward(spider_ctx* ctx, int32_t net_id, int32_t precision,
                        const double* x_src, const double* s, const double* grad_T,
                        int64_t rows, double* grad_x);
 
+/* ---- allocation-free travel time ----------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * spider_travel_time with the same arguments, results and errors, whose
+ * scratch (the network kernel's per-row outputs) is a fixed array compiled
+ * into the library instead of the context's workspace.  Each device the
+ * library runs on holds its own copy of that array (16 MiB) until the
+ * process ends.  The call allocates nothing (no hipMalloc, hipFree or
+ * allocating library routine) and never tunes or profiles the network launch:
+ * it uses the context's tuned tile variant if there is one (every variant
+ * gives the same bits).  rows <= SPIDER_NOALLOC_MAX_ROWS, else
+ * SPIDER_E_INVALID.  All calls on one device share its array: calls that
+ * overlap on one GPU (several streams or contexts) race, and the caller
+ * must order them. */
+#define SPIDER_NOALLOC_MAX_ROWS 1048576
+int spider_travel_time_noalloc(spider_ctx* ctx, int32_t net_id, int32_t precision,
+                               const double* x_src, const double* s, int64_t rows,
+                               double* T, double* gradT);
+
 /* ---- one stochastic gradient (eq:sgd) ----------------------------------
  * g = [prior terms] + (N/n) * sum_{k<n} (d tau^_k / d theta)^T z_k
  * at state theta (device [M][4]).  The batch is batch_idx (device [n]

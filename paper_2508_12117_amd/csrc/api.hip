@@ -7,6 +7,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -226,6 +227,7 @@ struct spider_ctx {
   std::vector<std::unique_ptr<Catalog>> cats;
   std::vector<std::unique_ptr<Net>> nets;
   Workspace ws;
+  RowOut* noalloc_scratch = nullptr;  // this device's copy of the static scratch array
 };
 
 namespace {
@@ -632,6 +634,35 @@ int reset_err_flag(spider_ctx* ctx) {
   return SPIDER_OK;
 }
 
+// ---- scratch of the allocation-free travel-time call
+// The network kernel's per-row outputs for spider_travel_time_noalloc, at
+// most SPIDER_NOALLOC_MAX_ROWS rows (16 MiB).  Every device the library runs
+// on holds its own copy of this array until the process ends.  In host code
+// the name `scratch` is only a host-side stand-in: kernels are given the
+// device address that hipGetSymbolAddress returns for the current device
+// (kept per device in g_scratch by noalloc_setup), never the name itself.
+static __device__ __align__(256) RowOut scratch[SPIDER_NOALLOC_MAX_ROWS];
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+RowOut* g_scratch[kMaxScratchDevices] = {};
+
+// Resolves this device's copy of `scratch` once per device; the device must
+// be current.
+hipError_t noalloc_setup(int device, RowOut** out) {
+  if (device < 0 || device >= kMaxScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch[device] = (RowOut*)p;
+  }
+  *out = g_scratch[device];
+  return hipSuccess;
+}
+
 // T and dT/dx (or vjp_w dT/dx) of explicit rows: the network kernel into
 // the RowOut buffer `net_out`, then the FP64 assembly.
 int travel_time_rows(spider_ctx* ctx, Net& net, int32_t precision, const double* x_src,
@@ -674,10 +705,16 @@ int spider_create(spider_ctx** out, int device, void* hip_stream) {
   *out = nullptr;
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return SPIDER_E_INVALID;
+  RowOut* scr = nullptr;
+  {
+    DeviceGuard g(device);
+    if (noalloc_setup(device, &scr) != hipSuccess) return SPIDER_E_HIP;
+  }
   auto* ctx = new (std::nothrow) spider_ctx();
   if (!ctx) return SPIDER_E_OOM;
   ctx->device = device;
   ctx->stream = (hipStream_t)hip_stream;
+  ctx->noalloc_scratch = scr;
   *out = ctx;
   return SPIDER_OK;
 }
@@ -1009,6 +1046,26 @@ int spider_tt_backward(spider_ctx* ctx, int32_t net_id, int32_t precision, const
   HIPCK(ctx->ws.net_out.reserve((size_t)rows * sizeof(RowOut)), "workspace");
   return travel_time_rows(ctx, *net, precision, x_src, s, rows, ctx->ws.net_out.as<RowOut>(), true,
                           nullptr, grad_x, grad_T);
+}
+
+int spider_travel_time_noalloc(spider_ctx* ctx, int32_t net_id, int32_t precision,
+                               const double* x_src, const double* s, int64_t rows, double* T,
+                               double* gradT) {
+  if (!ctx) return SPIDER_E_INVALID;
+  DeviceGuard g(ctx->device);
+  Net* net;
+  bool skip;
+  int rc = travel_time_args(ctx, net_id, precision, rows, &net, &skip);
+  if (rc != SPIDER_OK || skip) return rc;
+  if (rows > SPIDER_NOALLOC_MAX_ROWS)
+    return fail(ctx, SPIDER_E_INVALID,
+                "rows exceeds SPIDER_NOALLOC_MAX_ROWS (1048576), the allocation-free scratch");
+  if (!x_src || !s || !T) return fail(ctx, SPIDER_E_INVALID, "null array");
+  if (!ctx->noalloc_scratch) return fail(ctx, SPIDER_E_STATE, "no scratch array on this device");
+  // every row of the scratch that the assembly reads is written by the
+  // network kernel first: nothing has to start at zero
+  return travel_time_rows(ctx, *net, precision, x_src, s, rows, ctx->noalloc_scratch, false, T,
+                          gradT, nullptr);
 }
 
 static int grad_common(spider_ctx* ctx, int32_t cat_id, int32_t net_id, int32_t precision,

@@ -83,6 +83,8 @@ _SIGS = {
     "spider_travel_time": ([_P, ct.c_int32, ct.c_int32, _P, _P, ct.c_int64, _P, _P], ct.c_int),
     "spider_tt_forward": ([_P, ct.c_int32, ct.c_int32, _P, _P, ct.c_int64, _P], ct.c_int),
     "spider_tt_backward": ([_P, ct.c_int32, ct.c_int32, _P, _P, _P, ct.c_int64, _P], ct.c_int),
+    "spider_travel_time_noalloc": ([_P, ct.c_int32, ct.c_int32, _P, _P, ct.c_int64, _P, _P],
+                                   ct.c_int),
     "spider_grad": ([_P, ct.c_int32, ct.c_int32, ct.c_int32, _P, _P, ct.c_int64, ct.c_uint64,
                      ct.c_int32, ct.c_int64, ct.c_uint32, _P, _P], ct.c_int),
     "spider_batch_terms": ([_P, ct.c_int32, ct.c_int32, ct.c_int32, _P, _P, ct.c_int64,
@@ -263,6 +265,11 @@ class Context:
     def travel_time(self, net_id, x_src, s, T, gradT=None, precision=FP32):
         self._check(lib().spider_travel_time(self._h, net_id, precision, _ptr(x_src), _ptr(s),
                                              x_src.shape[0], _ptr(T), _ptr(gradT)))
+
+    def travel_time_noalloc(self, net_id, x_src, s, T, gradT=None, precision=FP32):
+        self._check(lib().spider_travel_time_noalloc(self._h, net_id, precision, _ptr(x_src),
+                                                     _ptr(s), x_src.shape[0], _ptr(T),
+                                                     _ptr(gradT)))
 
     def tt_forward(self, net_id, x_src, s, T, precision=FP32):
         self._check(lib().spider_tt_forward(self._h, net_id, precision, _ptr(x_src), _ptr(s),
