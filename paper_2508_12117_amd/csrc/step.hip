@@ -557,8 +557,8 @@ __global__ __launch_bounds__(TB) void k_tree_solve(SolveArgs a) {
 
   // ---- 2. nodes still active sit on cycles (or on paths longer than the
   // round cap): Jacobi-preconditioned CG on them only.  Each pass starts from
-  // the true residual b - A y of the current y (the first from y = 0), so a
-  // second pass corrects the drift of CG's recursively updated residual.
+  // the true residual b - A y of the current y (the first from y = 0), so
+  // later passes correct the drift of CG's recursively updated residual.
   const int32_t* core = act;
   const int32_t ncore = nl;
   if (ncore > 0) {
@@ -570,7 +570,7 @@ __global__ __launch_bounds__(TB) void k_tree_solve(SolveArgs a) {
     }
     bb = block_sum<TB>(bb, sh);
     double rn = bb;
-    for (int pass = 0; pass < 2 && bb > 0.0; ++pass) {
+    for (int pass = 0; pass < 3 && bb > 0.0; ++pass) {
       double rz = 0.0;
       rn = 0.0;
       for (int32_t k = t; k < ncore; k += TB) {
@@ -1192,10 +1192,12 @@ hipError_t exact_whiten(const CatView& cat, int C, int64_t n, BatchBufs b, SortB
   a.lambda = (cat.sigma * cat.sigma) / (cat.kappa * cat.kappa);
   a.max_rounds = kMaxRounds;
   a.n_entries = (int32_t)E;
-  a.max_iter = 200;
-  // relative residual 1e-14 (z = (r - U y)/sigma^2 scales y errors by
-  // 1/sigma^2); a core still above 1e-8 after max_iter is an error
-  a.tol2 = 1e-28;
+  // CG to a relative residual of 1e-16 (z = (r - U y)/sigma^2 scales y
+  // errors by 1/sigma^2, so y is solved to FP64 rounding), at most 1,000
+  // iterations per pass and three passes; a core still above 1e-8 after them
+  // is an error
+  a.max_iter = 1000;
+  a.tol2 = 1e-32;
   a.accept2 = 1e-16;
   a.err = err;
   // nodes: at most one per entry; the kernels stop at the node count on the device

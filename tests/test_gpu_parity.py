@@ -172,9 +172,11 @@ def test_exact_whitening_with_cycles(ctx, tiny_setup):
     """The whole catalog as one batch: every group is the full k-NN graph, so
     leaf peeling leaves large cyclic cores for the CG stage.  In the Woodbury
     form z = (r - U y)/sigma^2 the product U y nearly cancels r in such dense
-    groups, so even an exact FP64 solve for y leaves a floor near 1e-10 in
+    groups, so even an exact FP64 solve for y leaves a floor of ~5e-11 in
     this measure (woodbury_floor: a direct sparse solve on the host for the
-    GPU's own r).  The bound: within 3e-10, and within 4x that host floor."""
+    GPU's own r).  With CG run to FP64 convergence (true-residual restarts)
+    the GPU lands at 6.4e-11 on an MI355X: held to T4's 1e-10 and to within
+    2x that host floor."""
     cat, net, cid, nid = tiny_setup
     prob = lk.load(cat)
     theta = synth.random_theta(cat, 23)
@@ -185,7 +187,7 @@ def test_exact_whitening_with_cycles(ctx, tiny_setup):
     err = whitening_residual(r, z, bt, prob, lk.WHITEN_EXACT)
     floor = woodbury_floor(r, bt.w, bt.group, bt.ev_i, bt.ev_j, prob.M, prob.sigma, prob.kappa)
     print(f"whitening with cycles: GPU {err:.3e}, host Woodbury floor {floor:.3e}")
-    assert err < 3e-10 and err < 4 * floor + 1e-11
+    assert err < 1e-10 and err < 2 * floor + 1e-11
 
 
 def test_batch_terms_faults_full_batch(ctx, faults_setup):
@@ -206,8 +208,9 @@ def test_exact_whitening_large_batches(ctx, faults_setup, n, C):
     """Batches of 2^19 and 2^20 observations (about 20,000 nodes per group
     block, several peeling rounds with the block-wide list compactions in
     between, cyclic cores for the CG): z solves the batch system of every
-    chain's minibatch, within 3e-10 and within 4x the host floor of the same
-    Woodbury form for the same r (see test_exact_whitening_with_cycles)."""
+    chain's minibatch within T4's 1e-10 and within 2x the host floor of the
+    same Woodbury form for the same r (measured 3.5e-12 - 9.7e-12 against
+    floors of 5.6e-12 - 2.9e-11; see test_exact_whitening_with_cycles)."""
     cat, _, cid, nid = faults_setup
     prob = lk.load(cat)
     theta = synth.random_theta(cat, 32)
@@ -220,7 +223,7 @@ def test_exact_whitening_large_batches(ctx, faults_setup, n, C):
         err = float(np.max(np.abs(Sz - r) / (np.abs(r) + 1e-3)))
         floor = woodbury_floor(r, w, g, ev_i, ev_j, prob.M, prob.sigma, prob.kappa)
         print(f"whitening n={n} chain {chain}: GPU {err:.3e}, host Woodbury floor {floor:.3e}")
-        assert err < 3e-10 and err < 4 * floor + 1e-11
+        assert err < 1e-10 and err < 2 * floor + 1e-11
 
 
 # ----------------------------------------------------------------- gradient
