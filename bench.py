@@ -32,11 +32,11 @@ HBM_PEAK = 8000.0                             # GB/s
 NETWORK_TRAFFIC = {
     "kernel_sources": ["paper_2508_12117_amd/csrc/mlp_mfma.h", "paper_2508_12117_amd/csrc/mlp_pp.h",
                        "paper_2508_12117_amd/csrc/net_rows.h"],
-    "sha256": "96a603008fa9a6407cccbc096bfa851ac303b449bf95ef863f3d11499406b334",
+    "sha256": "1c88f808c37dd726b298b5fab521402efaa847f077beb951117d4de7ea615ad3",
     "variant": {"waves": 8, "row_tiles": 4, "schedule": 1},
     "rows": 16777216,
-    "fetch_bytes": 1682280448,
-    "write_bytes": 805306368,
+    "fetch_bytes": 229275776,
+    "write_bytes": 268435456,
 }
 
 
@@ -70,9 +70,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-batch", type=int, default=1 << 20)
     ap.add_argument("--seed", type=int, default=20250817)
-    ap.add_argument("--moments-steps", type=int, default=0, metavar="K",
+    ap.add_argument("--moments-steps", type=int, default=300, metavar="K",
                     help="also run K sampler steps per precision (second half recorded, thin "
-                         "10) and compare the BF16 and FP32 posterior moments")
+                         "10) and compare the BF16 and FP32 posterior moments (0: skip)")
+    ap.add_argument("--no-graph-compare", action="store_true",
+                    help="skip the graph-against-stream rates of the tiny catalog")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="first copy BYTES between two device buffers (one device-to-device "
                          "copy of known size, to calibrate HBM byte counters in a profile)")
@@ -85,23 +87,68 @@ def log(msg):
 
 def run_precision(ctx, spider, base_sets, step_size, prec, steps, warmup, seed):
     """base_sets: (cat_id, net_id, chains, batch) per catalog; several catalogs
-    advance together in the library's fused steps."""
+    advance together in the library's fused steps.  Two timed passes of
+    `steps` steps from the same warmed-up start: the step as the library runs
+    it (one eager step, then replays of a HIP graph of one step) for the
+    throughput, then with the network launches bracketed by HIP events on the
+    library's stream (profiling launches every step on the stream) for the
+    network kernel's time.  Returns (graph wall s, stream wall s, network ms,
+    launches, rows)."""
     import torch
     sets = [(cid, nid, C, n, prec) for cid, nid, C, n in base_sets]
-    for cid, _, C, _ in base_sets:
-        ctx.reset_chains(cid, C)
-    ctx.sgld_steps(sets, warmup, step=step_size, seed=seed)
+
+    def fresh():
+        for cid, _, C, _ in base_sets:
+            ctx.reset_chains(cid, C)
+        ctx.sgld_steps(sets, warmup, step=step_size, seed=seed)
+        ctx.sync()
+        torch.cuda.synchronize()
+
+    fresh()
+    t0 = time.perf_counter()
+    ctx.sgld_steps(sets, steps, step=step_size, seed=seed)
     ctx.sync()
     torch.cuda.synchronize()
+    wall_graph = time.perf_counter() - t0
+    fresh()
     ctx.profile(True)
     t0 = time.perf_counter()
     ctx.sgld_steps(sets, steps, step=step_size, seed=seed)
     ctx.sync()
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    wall_stream = time.perf_counter() - t0
     ms, launches, rows = ctx.profile_read()
     ctx.profile(False)
-    return t1 - t0, ms, launches, rows
+    return wall_graph, wall_stream, ms, launches, rows
+
+
+def small_catalog_rates(spider, seed, steps=2000):
+    """Steps per second of the tiny catalog (200 events, 32,000 observations,
+    one chain, minibatch 1,024, FP32 network), where the step is launch-bound:
+    HIP-graph replay against launching every kernel of every step."""
+    import torch
+
+    from paper_2508_12117_amd import synth
+    cat = synth.make_catalog("tiny")
+    out = {}
+    with spider.Context(0) as ctx:
+        cid = ctx.load_catalog(cat, whiten=spider.WHITEN_EXACT)
+        nid = ctx.load_net(synth.net_for(cat))
+        sets = [(cid, nid, 1, cat.wl.batch, spider.FP32)]
+        for name, graphs in (("graph", True), ("stream", False)):
+            ctx.set_graphs(graphs)
+            ctx.reset_chains(cid, 1)
+            ctx.sgld_steps(sets, 50, seed=seed)
+            ctx.sync()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.sgld_steps(sets, steps, seed=seed)
+            ctx.sync()
+            torch.cuda.synchronize()
+            out[name] = steps / (time.perf_counter() - t0)
+    return {"workload": "tiny", "steps": steps, "steps_per_s_graph": out["graph"],
+            "steps_per_s_stream": out["stream"],
+            "dd_obs_per_s_graph": out["graph"] * cat.wl.batch}
 
 
 def sample_error(ctx, spider, cat, net, nid, prec, rows=4096, seed=5):
@@ -166,13 +213,54 @@ def posterior_moments(ctx, spider, cats, base_sets, step_size, steps, seed):
     err_b = np.sqrt(np.mean((mb[:, 0:3] - true) ** 2))
     err_f = np.sqrt(np.mean((mf[:, 0:3] - true) ** 2))
     q = lambda a, p: float(np.percentile(a, p))
+    # the coordinates where the paths differ most, with the number of
+    # observations of their event (the best-constrained events have the
+    # smallest posterior s.d., so a smooth BF16 travel-time bias is the most
+    # standard deviations there)
+    nobs = np.concatenate([np.bincount(c.pair_i[c.obs_pair], minlength=c.M)
+                           + np.bincount(c.pair_j[c.obs_pair], minlength=c.M) for c in cats])
+    flat = np.argsort(z, axis=None)[::-1][:5]
+    worst = []
+    for f in flat:
+        ev, comp = np.unravel_index(f, z.shape)
+        worst.append({"event": int(ev), "component": "xyzt"[comp], "observations": int(nobs[ev]),
+                      "sd_fp32": float(sdf[ev, comp]), "abs_mean_diff": float(abs(mb - mf)[ev, comp]),
+                      "diff_over_sd": float(z[ev, comp])})
+    dec = np.argsort(nobs)
+    top = dec[-max(1, len(dec) // 10):]
+    low = dec[:max(1, len(dec) // 10)]
     return {"steps": steps, "burn_in": steps // 2, "thin": 10,
+            "worst": worst,
+            "median_diff_over_sd_by_observations": {
+                "fewest_10pct": float(np.median(z[low])), "most_10pct": float(np.median(z[top]))},
             "samples": int(n[0]) if len(n) == 1 else [int(k) for k in n],
             "events": int(mb.shape[0]),
             "mean_diff_over_sd": {"median": q(z, 50), "p99": q(z, 99), "max": float(z.max())},
             "sd_ratio_bf16_fp32": {"p1": q(ratio, 1), "median": q(ratio, 50), "p99": q(ratio, 99)},
             "location_rms_error_km": {"bf16": float(err_b), "fp32": float(err_f)},
             "note": "pooled over all chains; same batch and noise streams for both paths"}
+
+
+def host_description():
+    """CPU model, logical CPUs and the BLAS library numpy calls."""
+    from threadpoolctl import threadpool_info
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    blas = [f"{i.get('internal_api')} {i.get('version')} ({i.get('threading_layer', '')})"
+            for i in threadpool_info() if i.get("user_api") == "blas"]
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable,
+            "blas": "; ".join(blas) or "none"}
 
 
 def cpu_baseline(cat, net, n, seed):
@@ -199,6 +287,7 @@ def cpu_baseline(cat, net, n, seed):
             "sample": f"one pSGLD step of 1 chain, batch {n} of the {cat.M}-event catalog and its "
                       f"network, "
                       f"exact whitening, FP64 numpy ({dt:.1f} s)",
+            "host": host_description(),
             "single_core": {"value": n1 / dt1, "unit": "dd-obs/s", "cores": 1,
                             "sample": f"one pSGLD step of 1 chain, batch {n1} ({dt1:.1f} s)"}}
 
@@ -249,8 +338,9 @@ def main():
     res = {}
     for p in precs:
         code = spider.BF16 if p == "bf16" else spider.FP32
-        wall, ms, launches, rows = run_precision(ctx, spider, base_sets, wl.step_size, code,
-                                                 args.steps, args.warmup, args.seed)
+        wall, wall_stream, ms, launches, rows = run_precision(ctx, spider, base_sets, wl.step_size,
+                                                              code, args.steps, args.warmup,
+                                                              args.seed)
         dd = dd_per_step * args.steps
         fl = flops_per_eval(wl.H, wl.D)
         avg_ms = ms / max(launches, 1)
@@ -259,7 +349,8 @@ def main():
         sched = ctx.network_schedule(nid, code)
         traffic = network_traffic(rows // max(launches, 1),
                                   {"waves": waves, "row_tiles": tiles, "schedule": sched})
-        res[p] = dict(value=dd / wall, ms_per_step=wall * 1e3 / args.steps, net_ms=ms,
+        res[p] = dict(value=dd / wall, ms_per_step=wall * 1e3 / args.steps,
+                      ms_per_step_stream=wall_stream * 1e3 / args.steps, net_ms=ms,
                       net_launches=launches, net_avg_ms=avg_ms, achieved=achieved, traffic=traffic,
                       variant={"waves_per_workgroup": waves, "rows_per_workgroup": 16 * tiles,
                                "schedule": ["barrier per layer", "row-half ping-pong"][sched]},
@@ -288,14 +379,19 @@ def main():
                      "unit": "TFLOP/s", "frac": r["achieved"] / PEAK[head],
                      "traffic": r["traffic"]},
         "paths": {p: {"value": v["value"], "ms_per_step": v["ms_per_step"],
+                      "ms_per_step_stream_launches": v["ms_per_step_stream"],
                       "network_ms_per_launch": v["net_avg_ms"],
                       "network_tflops": v["achieved"], "network_tiles": v["variant"],
                       "error_vs_oracle": v["error"]}
                   for p, v in res.items()},
     }
-    if args.moments_steps > 0:
+    if "bf16" in res and "fp32" in res:
+        line["bf16_over_fp32"] = res["bf16"]["value"] / res["fp32"]["value"]
+    if args.moments_steps > 0 and bf16_ok:
         line["posterior_moments"] = posterior_moments(ctx, spider, cats, base_sets, wl.step_size,
                                                       args.moments_steps, args.seed)
+    if not args.no_graph_compare:
+        line["small_catalog"] = small_catalog_rates(spider, args.seed)
     if not args.no_cpu_baseline:
         t = time.perf_counter()
         # several catalogs: the oracle on the one nearest 200k events

@@ -127,7 +127,8 @@ typedef struct {
  * each group's observations; the centroid prior mean mu_c = mean of hypo0.
  * Errors: SPIDER_E_INVALID for out-of-range ids, i == j, non-finite values,
  * non-positive sigma/ell/eps_w/prior s.d., an observation whose initial
- * source lies within 1e-3 km of its station; SPIDER_E_OOM; SPIDER_E_HIP.
+ * source lies within 1e-3 km of its station; SPIDER_E_UNSUPPORTED for more
+ * than 40,960 station-phase groups; SPIDER_E_OOM; SPIDER_E_HIP.
  * Synchronous (the arrays may be reused when it returns). */
 int spider_load_catalog(spider_ctx* ctx, const spider_catalog_desc* desc, int32_t* cat_id);
 
@@ -311,6 +312,16 @@ typedef struct {
  * SPIDER_E_INVALID, SPIDER_E_NUMERIC, SPIDER_E_OOM, SPIDER_E_HIP. */
 int spider_sgld_steps(spider_ctx* ctx, const spider_chainset* sets, int32_t n_sets,
                       const spider_sgld_cfg* cfg);
+
+/* HIP graphs for spider_sgld_steps (default on).  When a call's sets advance
+ * in fused steps, the noise amplitude is constant over the call and
+ * profiling is off, the first step runs eagerly and the others are replayed
+ * from a HIP graph of one step captured on a private stream of the context
+ * (every kernel reads the chains' step counters on the device, so each
+ * replay is the next step; the results equal those of launching every step,
+ * bit for bit).  enable = 0 launches every step on the stream.
+ * Errors: SPIDER_E_INVALID (null context). */
+int spider_set_graphs(spider_ctx* ctx, int enable);
 
 /* ---- Stage 1: a robust initial solution (Sec. 3.2, eq:stage1loss) -----
  * Minimises the L1 loss of the dd residuals, L = (1/n) sum_{k<n} |r_k| over

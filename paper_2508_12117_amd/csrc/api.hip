@@ -125,17 +125,22 @@ struct Net {
   }
 };
 
-// Scratch of one minibatch pipeline, grown on demand.
+// Scratch of one minibatch pipeline, grown on demand.  Entry- and
+// slot-indexed arrays hold every chain set of a fused step side by side
+// (obs_total slots); the count and system arrays hold each set's keys and
+// systems side by side; the solver scratch holds one set at a time.
 struct Workspace {
-  DevBuf obs, ev, sta, tau, w, net_out, T, gT, r, z, wr, xt;
-  DevBuf key_in, key_out, val_in, val_out, temp, node_of, node_start, seg_begin, seg_end, flags,
-      vec, ivec, count;
+  DevBuf obs, ev, sta, tau, w, rank, start, csr, ckey, pos, pev, pgr, head, nend, rows, net_out,
+      T, gT, r, z, zp, wr;
+  DevBuf act, sys, list, nbr, wgt, vec, ivec, scan_part, long_list, phase_flags, n_p;
   DevBuf G, partial, thetabar, lp_tmp, err;
-  DevBuf ptemp;  // scratch of the two-phase row partition
-  size_t temp_bytes = 0;
 
-  hipError_t reserve(int64_t C, int64_t Cn, int64_t CM, int64_t CL) {
-    const int64_t E = 2 * Cn;
+  // obs_total: slots of all sets; keys_total: sum of (C M + 1); sys_total:
+  // the largest set's system-list counts (C L nb + 1); C, CM: the largest
+  // set's chains and C M
+  hipError_t reserve(int64_t C, int64_t obs_total, int64_t keys_total, int64_t sys_total,
+                     int64_t CM) {
+    const int64_t Cn = obs_total, E = 2 * obs_total;
     hipError_t e;
 #define RES(buf, bytes)                                     \
   if ((e = buf.reserve((size_t)(bytes))) != hipSuccess) return e;
@@ -144,36 +149,43 @@ struct Workspace {
     RES(sta, E * 4);
     RES(tau, Cn * 8);
     RES(w, Cn * 8);
+    RES(rank, E * 4);
+    RES(start, keys_total * 4);
+    RES(csr, E * 4);
+    RES(ckey, E * 8);
+    RES(pos, E * 4);
+    RES(pev, E * 4);
+    RES(pgr, E * 4);
+    RES(head, E * 4);
+    RES(nend, E * 4);
+    RES(rows, E * 4);
     RES(net_out, E * sizeof(RowOut));
     RES(T, E * 8);
     RES(gT, E * 24);
     RES(r, Cn * 8);
     RES(z, Cn * 8);
+    RES(zp, E * 8);
     RES(wr, Cn * 16);
-    RES(xt, E * 32);
-    RES(key_in, E * 8);
-    RES(key_out, E * 8);
-    RES(val_in, E * 4);
-    RES(val_out, E * 4);
-    RES(node_of, E * 4);
-    RES(node_start, (E + 1) * 4);
-    RES(seg_begin, CL * 4);
-    RES(seg_end, CL * 4);
-    RES(flags, E * 4);
-    RES(vec, E * 8 * 8);
-    RES(ivec, E * 4 * 4);
-    RES(count, 16);
+    RES(act, E * 4);
+    RES(sys, sys_total * 4);
+    RES(list, E * 4);
+    RES(nbr, E * 4);
+    RES(wgt, E * 8);
+    RES(vec, E * 8 * 7);
+    RES(ivec, E * 4 * 5);
+    int64_t sp = scan_part_size(E + 1);
+    if (scan_part_size(keys_total) > sp) sp = scan_part_size(keys_total);
+    if (scan_part_size(sys_total) > sp) sp = scan_part_size(sys_total);
+    RES(scan_part, sp * 4);
+    RES(long_list, (keys_total + 1) * 4);
+    RES(phase_flags, (E + 1) * 4);
+    RES(n_p, 16);
     RES(G, CM * 32);
     RES(partial, (CM / 4096 + C + 1) * 32);
     RES(thetabar, C * 32);
     RES(lp_tmp, 4096 * 8);
     RES(err, 64);
 #undef RES
-    const size_t tb = sort_temp_bytes(E);
-    if (tb > temp_bytes || !temp.p) {
-      if ((e = temp.alloc(tb)) != hipSuccess) return e;
-      temp_bytes = tb;
-    }
     return hipSuccess;
   }
 
@@ -184,32 +196,36 @@ struct Workspace {
     b.sta = sta.as<int32_t>();
     b.tau = tau.as<double>();
     b.w = w.as<double>();
+    b.rank = rank.as<int32_t>();
+    b.start = start.as<int32_t>();
+    b.csr = csr.as<int32_t>();
+    b.ckey = ckey.as<uint64_t>();
+    b.pos = pos.as<int32_t>();
+    b.pev = pev.as<int32_t>();
+    b.pgr = pgr.as<int32_t>();
+    b.head = head.as<int32_t>();
+    b.nend = nend.as<int32_t>();
+    b.rows = rows.as<int32_t>();
     b.net_out = net_out.as<RowOut>();
     b.T = T.as<double>();
     b.gT = gT.as<double>();
     b.r = r.as<double>();
     b.z = z.as<double>();
+    b.zp = zp.as<double>();
     b.wr = wr.as<double2>();
-    b.xt = xt.as<double4>();
     return b;
   }
-  SortBufs sort() const {
-    SortBufs s;
-    s.key_in = key_in.as<uint64_t>();
-    s.key_out = key_out.as<uint64_t>();
-    s.val_in = val_in.as<uint32_t>();
-    s.val_out = val_out.as<uint32_t>();
-    s.temp = temp.p;
-    s.temp_bytes = temp_bytes;
-    s.node_of = node_of.as<int32_t>();
-    s.node_start = node_start.as<int32_t>();
-    s.seg_begin = seg_begin.as<int32_t>();
-    s.seg_end = seg_end.as<int32_t>();
-    s.flags = flags.as<int32_t>();
-    s.vec = vec.as<double>();
-    s.ivec = ivec.as<int32_t>();
-    s.count = count.as<int32_t>();
-    return s;
+  SolveBufs solve(int64_t sys_off) const {
+    SolveBufs v;
+    v.act = act.as<int32_t>();
+    v.sys = sys.as<int32_t>() + sys_off;
+    v.list = list.as<int32_t>();
+    v.nbr = nbr.as<int32_t>();
+    v.wgt = wgt.as<double>();
+    v.vec = vec.as<double>();
+    v.ivec = ivec.as<int32_t>();
+    v.scan_part = scan_part.as<int32_t>();
+    return v;
   }
 };
 
@@ -228,6 +244,8 @@ struct spider_ctx {
   std::vector<std::unique_ptr<Net>> nets;
   Workspace ws;
   RowOut* noalloc_scratch = nullptr;  // this device's copy of the static scratch array
+  bool graphs = true;                 // replay sampler steps from a captured HIP graph
+  hipStream_t cap_stream = nullptr;   // the stream graphs are captured on
 };
 
 namespace {
@@ -410,79 +428,131 @@ void clear_profile(spider_ctx* ctx) {
   ctx->prof_rows.clear();
 }
 
+// The batch buffers of a chain set whose slots start at obs_off (entries and
+// network rows at 2 obs_off) and whose (chain, event) counts start at key_off.
+BatchBufs batch_at(const BatchBufs& b, int64_t obs_off, int64_t key_off) {
+  BatchBufs o = b;
+  o.obs += obs_off;
+  o.tau += obs_off;
+  o.w += obs_off;
+  o.r += obs_off;
+  o.z += obs_off;
+  o.wr += obs_off;
+  o.ev += 2 * obs_off;
+  o.sta += 2 * obs_off;
+  o.rank += 2 * obs_off;
+  o.csr += 2 * obs_off;
+  o.ckey += 2 * obs_off;
+  o.pos += 2 * obs_off;
+  o.pev += 2 * obs_off;
+  o.pgr += 2 * obs_off;
+  o.zp += 2 * obs_off;
+  o.head += 2 * obs_off;
+  o.nend += 2 * obs_off;
+  o.rows += 2 * obs_off;
+  o.net_out += 2 * obs_off;
+  o.T += 2 * obs_off;
+  o.gT += 6 * obs_off;
+  o.start += key_off;
+  return o;
+}
+
+// Before the network: the minibatch of each chain and its CSR order.
+void pre_network(spider_ctx* ctx, const Catalog& cat, int C, int64_t n, const int64_t* idx,
+                 uint64_t seed, const int64_t* steps_dev, int64_t step_scalar, int chain0,
+                 const BatchBufs& b) {
+  Workspace& ws = ctx->ws;
+  const CatView cv = cat.view();
+  launch_clear_counts(b, (int64_t)C * cat.M, ctx->stream);
+  launch_select(cv, C, n, idx, seed, steps_dev, step_scalar, chain0, b, ws.err.as<int>(),
+                ctx->stream);
+  launch_build_csr(cv, C, n, b, ws.scan_part.as<int32_t>(), ws.long_list.as<int32_t>(),
+                   ctx->stream);
+}
+
+// The network's row source of a chain set: its entries in CSR order (row p
+// is CSR position p: event pev[p], group pgr[p], chain p / 2n).
+RowSource csr_rows(const Catalog& cat, int64_t n, int64_t E, const double* theta,
+                   int64_t theta_stride, const BatchBufs& b) {
+  RowSource src;
+  std::memset(&src, 0, sizeof(src));
+  src.mode = 0;
+  src.rows = E;
+  src.ev = b.pev;
+  src.sta = b.pgr;
+  src.theta = theta;
+  src.rows_per_chain = 2 * n;
+  src.theta_chain_stride = theta_stride;
+  src.stations = cat.stations.as<double>();
+  return src;
+}
+
+// After the network: travel times, residuals, whitening and (if grad) the
+// scaled per-event likelihood gradient into ws.G.  rows: the network's row
+// order when it is not the CSR order (two-phase catalogs), else null.
+int post_network(spider_ctx* ctx, const Catalog& cat, const Net& net, const Net& net_s, int prec,
+                 int C, int64_t n, const double* theta, int64_t theta_stride, const int32_t* rows,
+                 const BatchBufs& b, bool grad, double scale, bool l1) {
+  Workspace& ws = ctx->ws;
+  const CatView cv = cat.view();
+  launch_assemble(cv, net.view(prec), net_s.view(prec), C, n, theta, theta_stride, rows, b,
+                  ctx->stream);
+  const int whiten = l1 ? kWhitenL1 : cat.kappa == 0.0 ? SPIDER_WHITEN_NONE : cat.whiten;
+  const SolveBufs sv = ws.solve(0);
+  launch_residual(cv, C, n, theta, theta_stride, whiten, b, sv, ctx->stream);
+  if (whiten == SPIDER_WHITEN_EXACT)
+    HIPCK(exact_whiten(cv, C, n, b, sv, ws.err.as<int>(), ctx->stream), "exact whitening");
+  if (grad) launch_reduce(cv, C, n, scale, b, ws.G.as<double>(), ctx->stream);
+  HIPCK(hipGetLastError(), "step kernels");
+  return SPIDER_OK;
+}
+
 // One minibatch for C chains: selection, network, residuals, whitening and
-// (if G) the scaled per-event likelihood gradient into ws.G.  With l1, z is
-// sign(r) instead of the whitened residual (the Stage 1 loss).
+// (if grad) the scaled per-event likelihood gradient into ws.G.  With l1, z
+// is sign(r) instead of the whitened residual (the Stage 1 loss).
 int run_batch(spider_ctx* ctx, Catalog& cat, Net& net, int prec, int C, int64_t n,
               const double* theta, int64_t theta_stride, const int64_t* idx, uint64_t seed,
               const int64_t* steps_dev, int64_t step_scalar, int chain0, bool grad, double scale,
               bool l1 = false) {
   Workspace& ws = ctx->ws;
-  const int64_t Cn = (int64_t)C * n;
-  HIPCK(ws.reserve(C, Cn, (int64_t)C * cat.M, (int64_t)C * cat.L), "workspace");
-  const CatView cv = cat.view();
+  const int64_t Cn = (int64_t)C * n, E = 2 * Cn;
+  HIPCK(ws.reserve(C, Cn, (int64_t)C * cat.M + 1,
+                   (int64_t)C * cat.L * list_blocks(C, n, cat.L) + 1, (int64_t)C * cat.M),
+        "workspace");
   const BatchBufs b = ws.batch();
-  launch_select(cv, C, n, idx, seed, steps_dev, step_scalar, chain0, b, ws.err.as<int>(),
-                ctx->stream);
-  RowSource src;
-  std::memset(&src, 0, sizeof(src));
-  src.mode = 0;
-  src.rows = 2 * Cn;
-  src.ev = b.ev;
-  src.sta = b.sta;
-  src.theta = theta;
-  src.rows_per_chain = 2 * n;
-  src.theta_chain_stride = theta_stride;
-  src.stations = cv.stations;
-  src.x = nullptr;
-  src.s = nullptr;
-  src.xt = b.xt;
+  pre_network(ctx, cat, C, n, idx, seed, steps_dev, step_scalar, chain0, b);
+  RowSource src = csr_rows(cat, n, E, theta, theta_stride, b);
   Net* net_s = &net;
+  const int32_t* rows = nullptr;
   int rc;
   if (cat.L_p < cat.L) {
     // two phases: the P rows through net and the S rows through the
-    // catalog's S network, each launch over a list of rows
+    // catalog's S network, each launch over its part of the row list
     net_s = get_net(ctx, cat.net_s);
     if (!net_s)
       return fail(ctx, SPIDER_E_STATE, "two-phase catalog without an S network "
                                        "(spider_set_phase_net)");
-    const int64_t E = 2 * Cn;
-    int32_t* list = ws.flags.as<int32_t>();
-    RowOut* compact = (RowOut*)ws.vec.p;
-    uint64_t* cnt = (uint64_t*)ws.count.p;
-    size_t tb = 0;
-    HIPCK(partition_rows_by_phase(b.sta, cat.L_p, E, list, cnt, nullptr, &tb, ctx->stream),
-          "phase partition size");
-    HIPCK(ws.ptemp.reserve(tb), "phase partition scratch");
-    HIPCK(partition_rows_by_phase(b.sta, cat.L_p, E, list, cnt, ws.ptemp.p, &tb, ctx->stream),
-          "phase partition");
-    uint64_t n_p = 0;
-    HIPCK(hipMemcpyAsync(&n_p, cnt, 8, hipMemcpyDeviceToHost, ctx->stream), "phase count");
+    launch_phase_rows(cat.view(), E, b, ws.phase_flags.as<int32_t>(), ws.scan_part.as<int32_t>(),
+                      ws.n_p.as<int64_t>(), ctx->stream);
+    int64_t n_p = 0;
+    HIPCK(hipMemcpyAsync(&n_p, ws.n_p.p, 8, hipMemcpyDeviceToHost, ctx->stream), "phase count");
     HIPCK(hipStreamSynchronize(ctx->stream), "phase count");
-    src.mode = 3;
-    src.list = list;
-    src.rows = (int64_t)n_p;
-    rc = run_network(ctx, net, prec, src, compact);
+    rows = b.rows;
+    src.mode = 3;  // rows listed by CSR position, P first
+    src.list = b.rows;
+    src.rows = n_p;
+    rc = run_network(ctx, net, prec, src, b.net_out);
     if (rc != SPIDER_OK) return rc;
-    src.list = list + n_p;
-    src.rows = E - (int64_t)n_p;
-    rc = run_network(ctx, *net_s, prec, src, compact + n_p);
+    src.list = b.rows + n_p;
+    src.rows = E - n_p;
+    rc = run_network(ctx, *net_s, prec, src, b.net_out + n_p);
     if (rc != SPIDER_OK) return rc;
-    launch_scatter_rows(compact, list, E, b.net_out, ctx->stream);
   } else {
     rc = run_network(ctx, net, prec, src, b.net_out);
     if (rc != SPIDER_OK) return rc;
   }
-  const int whiten = l1 ? kWhitenL1 : cat.kappa == 0.0 ? SPIDER_WHITEN_NONE : cat.whiten;
-  launch_residual(cv, net.view(prec), net_s->view(prec), C, n, theta, theta_stride, whiten, b,
-                  ctx->stream);
-  if (whiten == SPIDER_WHITEN_EXACT)
-    HIPCK(exact_whiten(cv, C, n, b, ws.sort(), ws.err.as<int>(), ctx->stream), "exact whitening");
-  if (grad)
-    HIPCK(reduce_events(cv, C, n, scale, b, ws.sort(), ws.G.as<double>(), ctx->stream),
-          "per-event reduction");
-  HIPCK(hipGetLastError(), "step kernels");
-  return SPIDER_OK;
+  return post_network(ctx, cat, net, *net_s, prec, C, n, theta, theta_stride, rows, b, grad, scale,
+                      l1);
 }
 
 // The update arguments with the catalog's sample buffer.
@@ -493,69 +563,42 @@ UpdateArgs with_samples(UpdateArgs a, const Catalog& cat) {
   return a;
 }
 
-// The batch buffers of the observations from obs_off on (rows from 2 obs_off).
-BatchBufs batch_at(const BatchBufs& b, int64_t obs_off) {
-  BatchBufs o = b;
-  o.obs += obs_off;
-  o.ev += 2 * obs_off;
-  o.sta += 2 * obs_off;
-  o.tau += obs_off;
-  o.w += obs_off;
-  o.net_out += 2 * obs_off;
-  o.T += 2 * obs_off;
-  o.gT += 6 * obs_off;
-  o.r += obs_off;
-  o.z += obs_off;
-  o.wr += obs_off;
-  o.xt += 2 * obs_off;
-  return o;
-}
-
 // Chain sets that share one network and precision, advanced together: every
-// set's minibatch is selected into its own slice of the workspace, one
-// network launch evaluates the rows of all sets (row source mode 2), and the
-// residual, whitening, per-event reduction and update of each set follow.
+// set's minibatch and CSR order are built in its own slice of the workspace,
+// one network launch evaluates the rows of all sets (row source mode 2), and
+// the residual, whitening, per-event reduction and update of each set follow.
 // The results equal those of advancing each set on its own.
 struct FusedSets {
-  std::vector<int64_t> obs_off;  // first observation of each set in the workspace
+  std::vector<int64_t> obs_off;  // first slot of each set in the workspace
+  std::vector<int64_t> key_off;  // first (chain, event) count of each set
   int64_t total_obs = 0;
   DevBuf subs, row0;             // device RowSource table and its row offsets
 };
 
 int prepare_fused(spider_ctx* ctx, const spider_chainset* sets, int n_sets, FusedSets& f) {
-  int64_t maxC = 1, maxCn = 1, maxCM = 1, maxCL = 1;
+  int64_t maxC = 1, maxCM = 1, maxS = 1;
   f.obs_off.assign(n_sets + 1, 0);
+  f.key_off.assign(n_sets + 1, 0);
   for (int k = 0; k < n_sets; ++k) {
     const Catalog& cat = *get_cat(ctx, sets[k].cat_id);
     const int64_t C = sets[k].n_chains, Cn = C * sets[k].batch;
     f.obs_off[k + 1] = f.obs_off[k] + Cn;
+    f.key_off[k + 1] = f.key_off[k] + C * cat.M + 1;
     maxC = std::max(maxC, C);
-    maxCn = std::max(maxCn, Cn);
     maxCM = std::max(maxCM, C * cat.M);
-    maxCL = std::max(maxCL, C * cat.L);
+    maxS = std::max(maxS, C * cat.L * list_blocks(C, sets[k].batch, cat.L) + 1);
   }
   f.total_obs = f.obs_off[n_sets];
   Workspace& ws = ctx->ws;
-  // batch buffers for all sets; the sort scratch, sized by the same call,
-  // then holds any single set
-  HIPCK(ws.reserve(maxC, f.total_obs, maxCM, maxCL), "workspace");
+  HIPCK(ws.reserve(maxC, f.total_obs, f.key_off[n_sets], maxS, maxCM), "workspace");
   const BatchBufs b = ws.batch();
   std::vector<RowSource> subs(n_sets);
   std::vector<int64_t> row0(n_sets + 1);
   for (int k = 0; k < n_sets; ++k) {
     const Catalog& cat = *get_cat(ctx, sets[k].cat_id);
-    const BatchBufs bk = batch_at(b, f.obs_off[k]);
-    RowSource& r = subs[k];
-    std::memset(&r, 0, sizeof(r));
-    r.mode = 0;
-    r.rows = 2 * (f.obs_off[k + 1] - f.obs_off[k]);
-    r.ev = bk.ev;
-    r.sta = bk.sta;
-    r.theta = cat.theta.as<double>();
-    r.rows_per_chain = 2 * sets[k].batch;
-    r.theta_chain_stride = (int64_t)cat.M * 4;
-    r.stations = cat.stations.as<double>();
-    r.xt = bk.xt;
+    const BatchBufs bk = batch_at(b, f.obs_off[k], f.key_off[k]);
+    subs[k] = csr_rows(cat, sets[k].batch, 2 * (f.obs_off[k + 1] - f.obs_off[k]),
+                       cat.theta.as<double>(), (int64_t)cat.M * 4, bk);
     row0[k] = 2 * f.obs_off[k];
   }
   row0[n_sets] = 2 * f.total_obs;
@@ -571,10 +614,9 @@ int fused_step(spider_ctx* ctx, const spider_chainset* sets, int n_sets, const F
   Workspace& ws = ctx->ws;
   const BatchBufs b = ws.batch();
   for (int k = 0; k < n_sets; ++k) {
-    Catalog& cat = *get_cat(ctx, sets[k].cat_id);
-    launch_select(cat.view(), sets[k].n_chains, sets[k].batch, nullptr, ua.seed,
-                  cat.steps.as<int64_t>(), 0, 0, batch_at(b, f.obs_off[k]), ws.err.as<int>(),
-                  ctx->stream);
+    const Catalog& cat = *get_cat(ctx, sets[k].cat_id);
+    pre_network(ctx, cat, sets[k].n_chains, sets[k].batch, nullptr, ua.seed,
+                cat.steps.as<int64_t>(), 0, 0, batch_at(b, f.obs_off[k], f.key_off[k]));
   }
   RowSource src;
   std::memset(&src, 0, sizeof(src));
@@ -588,27 +630,59 @@ int fused_step(spider_ctx* ctx, const spider_chainset* sets, int n_sets, const F
   for (int k = 0; k < n_sets; ++k) {
     const spider_chainset& st = sets[k];
     Catalog& cat = *get_cat(ctx, st.cat_id);
-    Net& net = *get_net(ctx, st.net_id);
+    const Net& net = *get_net(ctx, st.net_id);
     const int C = st.n_chains;
     const int64_t n = st.batch;
-    const CatView cv = cat.view();
-    const BatchBufs bk = batch_at(b, f.obs_off[k]);
-    const int whiten = cat.kappa == 0.0 ? SPIDER_WHITEN_NONE : cat.whiten;
-    const NetView nv = net.view(st.precision);
-    launch_residual(cv, nv, nv, C, n, cat.theta.as<double>(), (int64_t)cat.M * 4, whiten, bk,
-                    ctx->stream);
-    if (whiten == SPIDER_WHITEN_EXACT)
-      HIPCK(exact_whiten(cv, C, n, bk, ws.sort(), ws.err.as<int>(), ctx->stream), "exact whitening");
-    HIPCK(reduce_events(cv, C, n, (double)cat.N / (double)n, bk, ws.sort(), ws.G.as<double>(),
-                        ctx->stream),
-          "per-event reduction");
+    rc = post_network(ctx, cat, net, net, st.precision, C, n, cat.theta.as<double>(),
+                      (int64_t)cat.M * 4, nullptr, batch_at(b, f.obs_off[k], f.key_off[k]), true,
+                      (double)cat.N / (double)n, false);
+    if (rc != SPIDER_OK) return rc;
     launch_centroid(cat.theta.as<double>(), C, cat.M, ws.partial.as<double>(),
                     ws.thetabar.as<double>(), ctx->stream);
-    launch_update(cv, C, cat.theta.as<double>(), cat.v.as<double>(), ws.G.as<double>(),
+    launch_update(cat.view(), C, cat.theta.as<double>(), cat.v.as<double>(), ws.G.as<double>(),
                   ws.thetabar.as<double>(), cat.steps.as<int64_t>(), cat.mcount.as<int64_t>(),
                   with_samples(ua, cat), cat.mean.as<double>(), cat.m2.as<double>(), ctx->stream);
     HIPCK(hipGetLastError(), "update");
   }
+  return SPIDER_OK;
+}
+
+// n fused steps replayed from one HIP graph of a step, captured on the
+// context's capture stream and launched on its stream.  Every kernel of a
+// step reads the chains' step counters on the device, so each replay is the
+// next step; the step holds no host synchronisation, allocation or memset.
+int graph_steps(spider_ctx* ctx, const spider_chainset* sets, int n_sets, const FusedSets& f,
+                const UpdateArgs& ua, int64_t n) {
+  if (n <= 0) return SPIDER_OK;
+  if (!ctx->cap_stream)
+    HIPCK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking), "capture stream");
+  const hipStream_t main = ctx->stream;
+  ctx->stream = ctx->cap_stream;
+  hipError_t e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    ctx->stream = main;
+    return hip_fail(ctx, e, "graph capture");
+  }
+  const int rc = fused_step(ctx, sets, n_sets, f, ua);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(ctx->cap_stream, &g);
+  ctx->stream = main;
+  if (rc != SPIDER_OK || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc != SPIDER_OK ? rc : hip_fail(ctx, e, "graph capture");
+  }
+  hipGraphExec_t x = nullptr;
+  e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return hip_fail(ctx, e, "graph instantiate");
+  }
+  for (int64_t t = 0; t < n && e == hipSuccess; ++t) e = hipGraphLaunch(x, main);
+  const hipError_t es = hipStreamSynchronize(main);
+  (void)hipGraphExecDestroy(x);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return hip_fail(ctx, e, "graph launch");
+  if (es != hipSuccess) return hip_fail(ctx, es, "graph steps");
   return SPIDER_OK;
 }
 
@@ -724,7 +798,14 @@ void spider_destroy(spider_ctx* ctx) {
   DeviceGuard g(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   clear_profile(ctx);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   delete ctx;
+}
+
+int spider_set_graphs(spider_ctx* ctx, int enable) {
+  if (!ctx) return SPIDER_E_INVALID;
+  ctx->graphs = enable != 0;
+  return SPIDER_OK;
 }
 
 int spider_profile(spider_ctx* ctx, int enable) {
@@ -828,6 +909,8 @@ int spider_load_catalog(spider_ctx* ctx, const spider_catalog_desc* d, int32_t* 
     return fail(ctx, SPIDER_E_INVALID,
                 "need sigma_s > 0, kappa_s >= 0, and kappa_s > 0 exactly when kappa > 0");
   const int32_t Lg = two_phase ? 2 * d->L : d->L;  // station-phase groups
+  if (Lg > kMaxGroups)
+    return fail(ctx, SPIDER_E_UNSUPPORTED, "more than 40,960 station-phase groups");
 
   auto cat = std::make_unique<Catalog>();
   cat->M = d->M;
@@ -1134,7 +1217,7 @@ int spider_batch_terms(spider_ctx* ctx, int32_t cat_id, int32_t net_id, int32_t 
   int rc = grad_common(ctx, cat_id, net_id, precision, theta, batch_idx, n, seed, chain, step,
                        false, &cat, &net);
   if (rc) return rc;
-  launch_batch_terms_out(n, ctx->ws.batch(), T_i, T_j, gT_i, gT_j, r, z, ctx->stream);
+  launch_batch_terms_out(n, ctx->ws.batch(), theta, T_i, T_j, gT_i, gT_j, r, z, ctx->stream);
   HIPCK(hipGetLastError(), "batch terms");
   return check_select_flag(ctx);
 }
@@ -1151,8 +1234,9 @@ int spider_batch_indices(spider_ctx* ctx, int32_t cat_id, uint64_t seed, int32_t
     return fail(ctx, SPIDER_E_UNSUPPORTED, "minibatch above 2^30 - 1 observations");
   int rc = reset_err_flag(ctx);
   if (rc) return rc;
-  HIPCK(ctx->ws.reserve(1, n, cat->M, cat->L), "workspace");
+  HIPCK(ctx->ws.reserve(1, n, (int64_t)cat->M + 1, 1, cat->M), "workspace");
   BatchBufs b = ctx->ws.batch();
+  b.start = nullptr;  // indices only: no (chain, event) counts
   launch_select(cat->view(), 1, n, nullptr, seed, nullptr, step, chain, b, ctx->ws.err.as<int>(),
                 ctx->stream);
   HIPCK(hipMemcpyAsync(idx_out, b.obs, (size_t)n * 8, hipMemcpyDeviceToDevice, ctx->stream),
@@ -1283,7 +1367,7 @@ int spider_sgld_steps(spider_ctx* ctx, const spider_chainset* sets, int32_t n_se
   ua.thin = cfg->thin;
   // sets sharing one network and precision (and no catalog twice, no
   // two-phase catalog) advance in fused steps
-  bool fuse = n_sets > 1;
+  bool fuse = true;
   for (int k = 1; k < n_sets && fuse; ++k)
     fuse = sets[k].net_id == sets[0].net_id && sets[k].precision == sets[0].precision;
   for (int k = 0; k < n_sets && fuse; ++k) {
@@ -1296,9 +1380,17 @@ int spider_sgld_steps(spider_ctx* ctx, const spider_chainset* sets, int32_t n_se
     FusedSets f;
     rc = prepare_fused(ctx, sets, n_sets, f);
     if (rc) return rc;
-    for (int64_t t = 0; t < cfg->n_steps; ++t) {
+    // a constant noise amplitude makes every step the same launches: the
+    // first runs eagerly (it tunes the network kernel), the rest replay a
+    // graph of one step
+    const bool graph = ctx->graphs && !ctx->profiling && cfg->noise_ramp == 0 && cfg->n_steps > 1;
+    for (int64_t t = 0; t < (graph ? 1 : cfg->n_steps); ++t) {
       ua.noise_scale = noise_at(*cfg, t);
       rc = fused_step(ctx, sets, n_sets, f, ua);
+      if (rc) return rc;
+    }
+    if (graph) {
+      rc = graph_steps(ctx, sets, n_sets, f, ua, cfg->n_steps - 1);
       if (rc) return rc;
     }
   }

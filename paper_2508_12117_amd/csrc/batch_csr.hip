@@ -1,0 +1,974 @@
+// Per-step kernels of the minibatch pipeline around the travel-time network.
+//
+//   select    minibatch without replacement (Sec. 3.2) and its gathers; each
+//             entry (events i and j of an observation) is counted under its
+//             (chain, event) key with an arrival rank
+//   csr       exclusive scan of the counts, scatter of the entries to their
+//             key's segment, and each segment sorted by (group, entry): a
+//             fixed order whatever the ranks were, in which the entries of a
+//             (chain, group, event) node of the whitening are contiguous
+//   assemble  T and dT/dx in FP64 from the network outputs; the network runs
+//             over the rows in CSR order, so dT/dx lands in CSR order
+//   residual  r = tau - [T_i - T_j + t_i - t_j] (Eq. 1); whitening in closed
+//             form where it applies: z = r / sigma^2 (none), r / (sigma^2 +
+//             2 kappa^2 w) (diagonal, and exact for an observation whose two
+//             nodes hold only it), sign(r) (the L1 loss of Stage 1)
+//   whitening exact Sigma_B^{-1} r (Sec. 3.1, eq:marginal_sigma) for the
+//             other observations: by Woodbury, z = (r - U y)/sigma^2 with
+//             (lambda I + U^T U) y = U^T r per (chain, group) system, solved
+//             by leaf elimination and CG on the cyclic core
+//   reduce    per-event gradient (eq:sgd): the sum over one CSR segment per
+//             (chain, event), in CSR order
+// No floating-point atomics anywhere: every sum runs in a fixed order, so a
+// step is bitwise reproducible.
+#include "device_rng.h"
+#include "internal.h"
+#include "tt_assemble.h"
+
+namespace spider {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWhitenExact = 2;  // SPIDER_WHITEN_EXACT
+constexpr int32_t kSingle = (int32_t)0x80000000;  // pos bit: the node holds one entry
+constexpr int32_t kPosMask = 0x7fffffff;
+
+inline unsigned grid_for(int64_t n, int block = kBlock) {
+  int64_t g = ceil_div(n, block);
+  if (g < 1) g = 1;
+  return (unsigned)g;
+}
+
+// Sum of one double per thread over the block, the same fixed tree every
+// time: butterfly within each wave, then the wave sums in wave order (every
+// thread returns the sum).  sh holds TB / 64 doubles.
+template <int TB>
+__device__ inline double block_sum(double v, double* sh) {
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = sh[0];
+#pragma unroll
+  for (int w = 1; w < TB / 64; ++w) r += sh[w];
+  __syncthreads();
+  return r;
+}
+
+__global__ void k_fill_i32(int32_t* p, int32_t v, int64_t count) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < count) p[t] = v;
+}
+
+// ---------------------------------------------------------------- scan
+
+constexpr int kScanTB = 256;
+constexpr int kScanIPT = 16;                     // items per thread
+constexpr int kScanChunk = kScanTB * kScanIPT;  // items per block
+
+// Inclusive block scan of one value per thread (fixed order).
+__device__ inline int32_t block_scan_incl(int32_t v, int32_t* sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int d = 1; d < kScanTB; d <<= 1) {
+    const int32_t x = t >= d ? sh[t - d] : 0;
+    __syncthreads();
+    sh[t] += x;
+    __syncthreads();
+  }
+  const int32_t r = sh[t];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(kScanTB) void k_scan_reduce(const int32_t* a, int64_t len,
+                                                         int32_t* part) {
+  __shared__ int32_t sh[kScanTB];
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanIPT;
+  int32_t s = 0;
+#pragma unroll
+  for (int i = 0; i < kScanIPT; ++i)
+    if (base + i < len) s += a[base + i];
+  s = block_scan_incl(s, sh);
+  if (threadIdx.x == kScanTB - 1) part[blockIdx.x] = s;
+}
+
+// Exclusive scan of the block sums by one block.
+__global__ __launch_bounds__(kScanTB) void k_scan_top(int32_t* part, int64_t nb) {
+  __shared__ int32_t sh[kScanTB];
+  int32_t carry = 0;
+  for (int64_t b0 = 0; b0 < nb; b0 += kScanTB) {
+    const int64_t k = b0 + threadIdx.x;
+    const int32_t v = k < nb ? part[k] : 0;
+    const int32_t incl = block_scan_incl(v, sh);
+    if (k < nb) part[k] = carry + incl - v;
+    carry += sh[kScanTB - 1];  // this chunk's total (sh still holds the scan)
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kScanTB) void k_scan_apply(int32_t* a, int64_t len,
+                                                        const int32_t* part) {
+  __shared__ int32_t sh[kScanTB];
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanIPT;
+  int32_t v[kScanIPT];
+  int32_t s = 0;
+#pragma unroll
+  for (int i = 0; i < kScanIPT; ++i) {
+    v[i] = base + i < len ? a[base + i] : 0;
+    s += v[i];
+  }
+  const int32_t incl = block_scan_incl(s, sh);
+  int32_t run = part[blockIdx.x] + incl - s;
+#pragma unroll
+  for (int i = 0; i < kScanIPT; ++i) {
+    if (base + i < len) a[base + i] = run;
+    run += v[i];
+  }
+}
+
+// ---------------------------------------------------------------- select
+
+__global__ void k_select(CatView cat, int C, int64_t n, const int64_t* idx, uint32_t k0,
+                         uint32_t k1, const int64_t* steps, int64_t step_scalar, int chain0,
+                         BatchBufs b, int* err) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= (int64_t)C * n) return;
+  const int c = (int)(q / n);
+  const int64_t k = q - (int64_t)c * n;
+  int64_t o;
+  if (idx) {
+    o = idx[k];
+  } else {
+    const int64_t t = steps ? steps[c] : step_scalar;
+    const int64_t B = cat.N / n;
+    const int64_t epoch = t / B;
+    const int64_t j = t - epoch * B;
+    const FeistelShape sh = feistel_shape(cat.N);
+    o = feistel_permute(j * n + k, cat.N, sh, k0, k1, cat.stream, (uint32_t)(chain0 + c),
+                        (uint32_t)epoch);
+  }
+  if (o < 0 || o >= cat.N) {
+    atomicOr(err, kErrSelect);
+    o = 0;
+  }
+  const ObsRec rc = cat.rec[o];
+  b.obs[q] = o;
+  b.ev[2 * q] = rc.i;
+  b.ev[2 * q + 1] = rc.j;
+  b.sta[2 * q] = rc.g;
+  b.sta[2 * q + 1] = rc.g;
+  b.tau[q] = (double)rc.dt;
+  b.w[q] = rc.w;
+  // integer counts: the arrival order only decides where an entry is placed
+  // before its segment is sorted (no count array: indices only)
+  if (b.start) {
+    const int64_t kb = (int64_t)c * cat.M;
+    b.rank[2 * q] = atomicAdd(b.start + kb + rc.i, 1);
+    b.rank[2 * q + 1] = atomicAdd(b.start + kb + rc.j, 1);
+  }
+}
+
+// ---------------------------------------------------------------- CSR
+
+// Sort key of an entry inside its event's segment: (group, entry).
+__device__ inline uint64_t canon_key(int32_t g, int32_t e) {
+  return ((uint64_t)(uint32_t)g << 32) | (uint32_t)e;
+}
+
+// Each entry's sort key to its place in its (chain, event) segment.
+__global__ void k_csr_scatter(int64_t E, int64_t n, int M, BatchBufs b) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  const int64_t c = (e >> 1) / n;
+  b.ckey[b.start[c * M + b.ev[e]] + b.rank[e]] = canon_key(b.sta[e], (int32_t)e);
+}
+
+// Node bookkeeping of the sorted segment of event m, [p0, p0 + len), whose
+// sort keys are key(i): event and group of every position, head[p] = first
+// position of p's node (same group), nend at that first position, and
+// pos[e] with the single-entry bit.
+template <class Key>
+__device__ inline void mark_nodes(BatchBufs& b, int32_t p0, int32_t len, int32_t m, Key&& key) {
+  int32_t run0 = 0;
+  for (int32_t i = 0; i < len; ++i) {
+    const uint64_t ki = key(i);
+    const uint32_t gi = (uint32_t)(ki >> 32);
+    if (i > 0 && (uint32_t)(key(i - 1) >> 32) != gi) run0 = i;
+    const bool last = i == len - 1 || (uint32_t)(key(i + 1) >> 32) != gi;
+    b.pev[p0 + i] = m;
+    b.pgr[p0 + i] = (int32_t)gi;
+    b.head[p0 + i] = p0 + run0;
+    if (last) b.nend[p0 + run0] = p0 + i + 1;
+    const bool single = last && run0 == i;
+    b.pos[(int32_t)(uint32_t)ki] = (p0 + i) | (single ? kSingle : 0);
+  }
+}
+
+constexpr int kCanonTB = 128;
+constexpr int kCanonShort = 32;  // segments up to this length are sorted by one thread in LDS
+
+// One thread per (chain, event) key: its segment sorted by (group, entry)
+// with an insertion sort in LDS (element i of thread t at sh[i][t], so a
+// wave's accesses spread over the banks); longer segments are listed for
+// k_csr_canon_long (slot by atomic count: each is sorted on its own, so the
+// order of the list does not matter).
+__global__ __launch_bounds__(kCanonTB) void k_csr_canon(int64_t K, int M, BatchBufs b,
+                                                        int32_t* long_list, int32_t* long_count) {
+  __shared__ uint64_t sh[kCanonShort][kCanonTB];
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  const int32_t m = (int32_t)(k % M);
+  const int32_t p0 = b.start[k], p1 = b.start[k + 1];
+  const int32_t len = p1 - p0;
+  if (len <= 0) return;
+  if (len > kCanonShort) {
+    long_list[atomicAdd(long_count, 1)] = (int32_t)k;
+    return;
+  }
+  const int t = threadIdx.x;
+  for (int32_t i = 0; i < len; ++i) {
+    const uint64_t x = b.ckey[p0 + i];
+    int32_t j = i;
+    while (j > 0 && sh[j - 1][t] > x) {
+      sh[j][t] = sh[j - 1][t];
+      --j;
+    }
+    sh[j][t] = x;
+  }
+  for (int32_t i = 0; i < len; ++i) b.csr[p0 + i] = (int32_t)(uint32_t)sh[i][t];
+  mark_nodes(b, p0, len, m, [&](int32_t i) { return sh[i][t]; });
+}
+
+constexpr int kLongTB = 256;
+constexpr int kLongLds = 4096;  // segments up to this length sort in LDS
+
+// Ascending sort network for any length len (positions at or past len act as
+// +infinity, so comparators that touch them are skipped): bitonic stages in
+// which the first step of each merge compares mirrored pairs.  get/put are
+// the element accessors; all threads of the block call it.
+template <class Get, class Put>
+__device__ void block_sort_any(int32_t len, Get&& get, Put&& put) {
+  int32_t P2 = 1;
+  while (P2 < len) P2 <<= 1;
+  for (int32_t kk = 2; kk <= P2; kk <<= 1) {
+    for (int32_t i = threadIdx.x; i < P2 / 2; i += blockDim.x) {
+      const int32_t half = kk >> 1, blk = i / half, off = i % half;
+      const int32_t a = blk * kk + off, c = blk * kk + kk - 1 - off;
+      if (c < len) {
+        const uint64_t x = get(a), y = get(c);
+        if (x > y) {
+          put(a, y);
+          put(c, x);
+        }
+      }
+    }
+    __syncthreads();
+    for (int32_t j = kk >> 2; j >= 1; j >>= 1) {
+      for (int32_t i = threadIdx.x; i < P2 / 2; i += blockDim.x) {
+        const int32_t a = (i / j) * 2 * j + i % j, c = a + j;
+        if (c < len) {
+          const uint64_t x = get(a), y = get(c);
+          if (x > y) {
+            put(a, y);
+            put(c, x);
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// One workgroup per long segment (grid-stride over the list, so any grid
+// size drains it): sorted in LDS when it fits, else in place in global
+// memory with keys recomputed from the entries.
+__global__ __launch_bounds__(kLongTB) void k_csr_canon_long(const int32_t* long_list,
+                                                            const int32_t* long_count, int M,
+                                                            BatchBufs b) {
+  __shared__ uint64_t sh[kLongLds];
+  const int32_t nlong = *long_count;
+  for (int32_t li = blockIdx.x; li < nlong; li += gridDim.x) {
+    const int64_t k = long_list[li];
+    const int32_t m = (int32_t)(k % M);
+    const int32_t p0 = b.start[k], len = b.start[k + 1] - p0;
+    int32_t* seg = b.csr + p0;
+    uint64_t* keys = b.ckey + p0;
+    if (len <= kLongLds) {
+      for (int32_t i = threadIdx.x; i < len; i += blockDim.x) sh[i] = keys[i];
+      __syncthreads();
+      block_sort_any(len, [&](int32_t i) { return sh[i]; }, [&](int32_t i, uint64_t x) { sh[i] = x; });
+      for (int32_t i = threadIdx.x; i < len; i += blockDim.x) seg[i] = (int32_t)(uint32_t)sh[i];
+      __syncthreads();
+      if (threadIdx.x == 0) mark_nodes(b, p0, len, m, [&](int32_t i) { return sh[i]; });
+    } else {
+      block_sort_any(len, [&](int32_t i) { return keys[i]; },
+                     [&](int32_t i, uint64_t x) { keys[i] = x; });
+      for (int32_t i = threadIdx.x; i < len; i += blockDim.x) seg[i] = (int32_t)(uint32_t)keys[i];
+      if (threadIdx.x == 0) mark_nodes(b, p0, len, m, [&](int32_t i) { return keys[i]; });
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- two phases
+
+__global__ void k_phase_flags(int64_t E, BatchBufs b, int32_t L_p, int32_t* flags) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p > E) return;
+  flags[p] = p < E && b.pgr[p] < L_p ? 1 : 0;
+}
+
+// After the exclusive scan of the flags: the positions of P entries at their
+// rank, those of S entries after all P ones, both in CSR order; flags[E] =
+// the P count.
+__global__ void k_phase_rows(int64_t E, BatchBufs b, int32_t L_p, const int32_t* flags,
+                             int64_t* n_p) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= E) return;
+  const int32_t np = flags[E];
+  const int32_t rp = flags[p];
+  if (b.pgr[p] < L_p) b.rows[rp] = (int32_t)p;
+  else b.rows[np + (int32_t)(p - rp)] = (int32_t)p;
+  if (p == 0) *n_p = np;
+}
+
+// ---------------------------------------------------------------- assemble
+
+__global__ void k_assemble(CatView cat, NetView net, NetView net_s, int64_t n, const double* theta,
+                           int64_t theta_stride, const int32_t* rows, int64_t E, BatchBufs b) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= E) return;
+  const int32_t p = rows ? rows[v] : (int32_t)v;
+  const int32_t e = b.csr[p];
+  const int64_t c = p / (2 * n);  // chain c holds positions [2 n c, 2 n (c + 1))
+  const int32_t g = b.pgr[p];
+  const double4 xe = *(const double4*)(theta + c * theta_stride + (int64_t)b.pev[p] * 4);
+  const double* st = cat.stations + (int64_t)g * 3;
+  const double x[3] = {xe.x, xe.y, xe.z};
+  const double s[3] = {st[0], st[1], st[2]};
+  double T, gr[3];
+  assemble_tt(g >= cat.L_p ? net_s : net, x, s, b.net_out[v], T, gr);
+  b.T[e] = T + xe.w;  // with the event's origin time, for the residual
+  b.gT[(int64_t)p * 3 + 0] = gr[0];
+  b.gT[(int64_t)p * 3 + 1] = gr[1];
+  b.gT[(int64_t)p * 3 + 2] = gr[2];
+}
+
+// ---------------------------------------------------------------- residual
+
+__global__ void k_residual(CatView cat, int C, int64_t n, const double* theta, int64_t theta_stride,
+                           int whiten, BatchBufs b, int32_t* act) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= (int64_t)C * n) return;
+  // T of each entry carries its event's origin time: T_i + t_i - (T_j + t_j)
+  const double r = b.tau[q] - (b.T[2 * q] - b.T[2 * q + 1]);
+  b.r[q] = r;
+  const double s2 = cat.sigma * cat.sigma;
+  const double zs = b.sta[2 * q] >= cat.L_p ? cat.zscale_s : 1.0;
+  const int32_t pi = b.pos[2 * q], pj = b.pos[2 * q + 1];
+  double z;
+  if (whiten == kWhitenL1) {
+    z = r > 0.0 ? 1.0 : (r < 0.0 ? -1.0 : 0.0);  // d|r|/dr, 0 at 0
+  } else if (whiten == 0 || cat.kappa == 0.0) {
+    z = r / s2 * zs;
+  } else if (whiten == 1 || ((pi & pj) & kSingle)) {
+    // diagonal whitening, or (exact) an edge alone in its two nodes: Sigma_B
+    // restricted to it is sigma^2 + 2 kappa^2 w
+    z = r / (s2 + 2.0 * cat.kappa * cat.kappa * b.w[q]) * zs;
+  } else {
+    b.wr[q] = make_double2(b.w[q], r);
+    act[b.head[pi & kPosMask]] = 1;
+    act[b.head[pj & kPosMask]] = 1;
+    return;  // z from the solve (k_exact_z)
+  }
+  b.z[q] = z;
+  b.zp[pi & kPosMask] = z;
+  b.zp[pj & kPosMask] = z;
+}
+
+// ---------------------------------------------------------------- exact whitening
+// Sigma_B = s2 I + k2 U U^T, U = W^{1/2} A_B.  z = (r - U y)/s2 with
+// (lambda I + U^T U) y = U^T r, lambda = s2/k2.  U^T U is the w-weighted
+// Laplacian of the batch's event graph in each group: one system per
+// (chain, group).  The nodes taken here are those of the observations that
+// share a node with another one (every neighbour of such a node is one too).
+
+constexpr int32_t kActive = -1;
+constexpr int32_t kCore = 1 << 30;  // solved by CG after the peeling rounds
+constexpr int kListTB = 256;
+
+// The system lists: block (b, c) of the grid covers positions [2 n c + b span,
+// ...) of chain c; pass 1 counts its marked nodes per group in LDS and writes
+// the counts to sys[(c L + g) nb + b]; after the scan, pass 2 places each
+// node in its system's list (slot from an LDS counter: the order within a
+// list does not matter to the solver) and initialises it: the diagonal
+// lambda + sum w and right-hand side (U^T r) = sum +-sqrt(w) r over its
+// entries in CSR order, and per entry the node at the other end and the
+// weight.  hist: L ints of dynamic LDS.
+__global__ __launch_bounds__(kListTB) void k_list_count(int64_t n, int L, int64_t nb, int64_t span,
+                                                       BatchBufs b, SolveBufs sv) {
+  extern __shared__ int32_t hist[];
+  const int64_t c = blockIdx.y, bk = blockIdx.x;
+  for (int g = threadIdx.x; g < L; g += kListTB) hist[g] = 0;
+  __syncthreads();
+  const int64_t p0 = 2 * n * c + bk * span;
+  const int64_t p1 = min(2 * n * (c + 1), p0 + span);
+  for (int64_t p = p0 + threadIdx.x; p < p1; p += kListTB)
+    if (sv.act[p]) atomicAdd(&hist[b.pgr[p]], 1);
+  __syncthreads();
+  for (int g = threadIdx.x; g < L; g += kListTB) sv.sys[(c * L + g) * nb + bk] = hist[g];
+  if (c == 0 && bk == 0 && threadIdx.x == 0) sv.sys[(int64_t)gridDim.y * L * nb] = 0;
+}
+
+__global__ __launch_bounds__(kListTB) void k_list_fill(int64_t n, int L, int64_t nb, int64_t span,
+                                                      double lambda, int64_t E, BatchBufs b,
+                                                      SolveBufs sv) {
+  extern __shared__ int32_t hist[];
+  const int64_t c = blockIdx.y, bk = blockIdx.x;
+  for (int g = threadIdx.x; g < L; g += kListTB) hist[g] = 0;
+  __syncthreads();
+  const int64_t p0 = 2 * n * c + bk * span;
+  const int64_t p1 = min(2 * n * (c + 1), p0 + span);
+  for (int64_t p = p0 + threadIdx.x; p < p1; p += kListTB) {
+    if (!sv.act[p]) continue;
+    const int32_t g = b.pgr[p];
+    const int32_t slot = atomicAdd(&hist[g], 1);
+    sv.list[sv.sys[(c * L + g) * nb + bk] + slot] = (int32_t)p;
+    double A = lambda, rhs = 0.0;
+    for (int32_t f = (int32_t)p; f < b.nend[p]; ++f) {
+      const int32_t e = b.csr[f];
+      const double2 x = b.wr[e >> 1];
+      A += x.x;
+      rhs += ((e & 1) ? -1.0 : 1.0) * sqrt(x.x) * x.y;
+      sv.nbr[f] = b.head[b.pos[e ^ 1] & kPosMask];
+      sv.wgt[f] = x.x;
+    }
+    sv.vec[p] = A;            // A
+    sv.vec[E + p] = rhs;      // b
+    sv.ivec[p] = kActive;     // state
+    sv.ivec[2 * E + p] = -1;  // par
+  }
+}
+
+struct SolveArgs {
+  const int32_t* nend;  // entries of node q: CSR positions [q, nend[q])
+  const int32_t* nbr;   // per position: the node at the other end of its edge
+  const double* wgt;    // per position: the edge weight w
+  const int32_t* sys;   // list offsets: system s starts at sys[s nb]
+  int64_t nb;
+  int32_t* list;        // nodes of each system (first positions)
+  double* A;            // diagonal, Schur-updated as leaves are eliminated
+  double* b;            // right-hand side, Schur-updated
+  double* y;            // solution
+  double* Wp;           // weight to the parent at elimination
+  double* rr;           // CG vectors for the nodes left on cycles
+  double* p;
+  double* ap;
+  int32_t* state;       // kActive, kCore, or the round in which the node was removed
+  int32_t* nstate;
+  int32_t* par;         // parent of an eliminated node (-1: solved on its own)
+  int32_t* next;        // scratch: the next round's list (same offsets as list)
+  int32_t* elim;        // scratch: the elimination order (same offsets as list)
+  double lambda;
+  int max_rounds;
+  int max_iter;
+  double tol2;     // CG stops once |res|^2 <= tol2 |rhs|^2
+  double accept2;  // after its passes, |res|^2 > accept2 |rhs|^2 raises kErrSolve
+  int* err;        // error bits of the step
+};
+
+constexpr int kMaxRounds = 64;
+constexpr int kTreeBlock = 1024;  // threads per (chain, group) system
+constexpr int kCoreLds = 4096;    // cores up to this size are sorted in LDS
+
+// Appends, in order, the n items item(k) that satisfy keep(k) to out: thread
+// t handles the contiguous items [t per, (t + 1) per), an exclusive scan of
+// the per-thread counts over the block (butterfly within waves, then the wave
+// totals) gives each thread its first output slot.  Returns the number
+// appended.  All threads of the block call it; scan holds TB / 64 ints.
+template <int TB, class Keep, class Item>
+__device__ int32_t block_compact(int32_t n, Keep&& keep, Item&& item, int32_t* out,
+                                 int32_t* scan) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int32_t per = (n + TB - 1) / TB;
+  const int32_t k0 = t * per, k1 = min(n, k0 + per);
+  int32_t cnt = 0;
+  for (int32_t k = k0; k < k1; ++k) cnt += keep(k) ? 1 : 0;
+  int32_t incl = cnt;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int32_t x = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += x;
+  }
+  if (lane == 63) scan[w] = incl;
+  __syncthreads();
+  int32_t before = 0, total = 0;
+#pragma unroll
+  for (int v = 0; v < TB / 64; ++v) {
+    const int32_t x = scan[v];
+    if (v < w) before += x;
+    total += x;
+  }
+  int32_t o = before + incl - cnt;
+  for (int32_t k = k0; k < k1; ++k)
+    if (keep(k)) out[o++] = item(k);
+  __syncthreads();
+  return total;
+}
+
+// One workgroup per (chain, group) system of (lambda I + L) y = U^T r over
+// its listed nodes (the list's order is arbitrary; nothing below depends on
+// it except the CG sums, which run over the core sorted by node):
+//  1. Peel leaves in rounds: a node whose active neighbours are all one node
+//     p (possibly over several parallel edges of total weight W) is
+//     eliminated into p (Schur complement: A_p -= W^2/A_q, b_p += W b_q/A_q);
+//     of two nodes that are each other's only neighbour the larger one is
+//     eliminated; a node with no active neighbour is solved, y = b/A.
+//     Parents gather their leaves' updates in entry order (deterministic).
+//  2. Nodes left on cycles after the rounds: Jacobi-preconditioned CG on
+//     the Schur-complemented system of those nodes only.
+//  3. Back substitution in reverse round order: y_q = (b_q + W y_p)/A_q.
+// Exact up to FP64 rounding for forests; the minibatch graphs are forests
+// of small trees apart from rare cycles.
+template <int TB>
+__global__ __launch_bounds__(TB) void k_tree_solve(SolveArgs a) {
+  __shared__ double sh[TB / 64];
+  __shared__ int32_t warp_base[TB / 64];
+  __shared__ int32_t elim_start[kMaxRounds + 2];
+  __shared__ int32_t core_sh[kCoreLds];
+  const int32_t off = a.sys[blockIdx.x * a.nb];
+  int32_t nl = a.sys[(blockIdx.x + 1) * a.nb] - off;
+  if (nl <= 0) return;
+  const int t = threadIdx.x;
+  int32_t* act = a.list + off;
+  int32_t* act_next = a.next + off;
+  int32_t* elim = a.elim + off;
+  int32_t n_elim = 0;
+
+  // ---- 1. peeling rounds over the active nodes
+  int rounds = 0;
+  for (; rounds < a.max_rounds && nl > 0; ++rounds) {
+    if (t == 0) elim_start[rounds] = n_elim;
+    int changed = 0;
+    for (int32_t k = t; k < nl; k += TB) {
+      const int32_t q = act[k];
+      int32_t p0 = -1;
+      double W = 0.0;
+      bool multi = false;
+      for (int32_t e = q; e < a.nend[q]; ++e) {
+        const int32_t pn = a.nbr[e];
+        if (a.state[pn] != kActive) continue;
+        if (p0 < 0) {
+          p0 = pn;
+          W = a.wgt[e];
+        } else if (pn == p0) {
+          W += a.wgt[e];
+        } else {
+          multi = true;
+          break;
+        }
+      }
+      int32_t ns = kActive;
+      if (p0 < 0) {
+        ns = rounds;  // isolated: solved directly
+        a.par[q] = -1;
+      } else if (!multi) {
+        bool p0_other = false;
+        for (int32_t e = p0; e < a.nend[p0]; ++e) {
+          const int32_t pn = a.nbr[e];
+          if (pn != q && a.state[pn] == kActive) {
+            p0_other = true;
+            break;
+          }
+        }
+        if (p0_other || q > p0) {
+          ns = rounds;
+          a.par[q] = p0;
+          a.Wp[q] = W;
+        }
+      }
+      a.nstate[q] = ns;
+      changed |= (ns != kActive);
+    }
+    changed = __syncthreads_or(changed);
+    if (!changed) break;
+    // parents gather the Schur updates of this round's leaves
+    for (int32_t k = t; k < nl; k += TB) {
+      const int32_t q = act[k];
+      if (a.nstate[q] == kActive) {
+        const int32_t e0 = q, e1 = a.nend[q];
+        double dA = 0.0, db = 0.0;
+        for (int32_t e = e0; e < e1; ++e) {
+          const int32_t pn = a.nbr[e];
+          if (a.nstate[pn] != rounds || a.par[pn] != q) continue;
+          bool first = true;
+          for (int32_t f = e0; f < e; ++f)
+            if (a.nbr[f] == pn) {
+              first = false;
+              break;
+            }
+          if (!first) continue;
+          const double Ap = a.A[pn], Wn = a.Wp[pn];
+          dA += Wn * Wn / Ap;
+          db += Wn * a.b[pn] / Ap;
+        }
+        a.A[q] -= dA;
+        a.b[q] += db;
+      }
+    }
+    __syncthreads();
+    for (int32_t k = t; k < nl; k += TB) {
+      const int32_t q = act[k];
+      a.state[q] = a.nstate[q];
+    }
+    __syncthreads();
+    n_elim += block_compact<TB>(
+        nl, [&](int32_t k) { return a.state[act[k]] != kActive; }, [&](int32_t k) { return act[k]; },
+        elim + n_elim, warp_base);
+    nl = block_compact<TB>(
+        nl, [&](int32_t k) { return a.state[act[k]] == kActive; }, [&](int32_t k) { return act[k]; },
+        act_next, warp_base);
+    int32_t* tmp = act;
+    act = act_next;
+    act_next = tmp;
+  }
+  if (t == 0) elim_start[rounds] = n_elim;
+  __syncthreads();
+
+  // ---- 2. nodes still active sit on cycles (or on paths longer than the
+  // round cap): CG on them only, over the core sorted by node (the sums then
+  // run in a fixed order).  Each pass starts from the true residual b - A y
+  // of the current y (the first from y = 0), so later passes correct the
+  // drift of CG's recursively updated residual.
+  int32_t* core = act;
+  const int32_t ncore = nl;
+  if (ncore > 0) {
+    if (ncore <= kCoreLds) {
+      for (int32_t k = t; k < ncore; k += TB) core_sh[k] = core[k];
+      __syncthreads();
+      block_sort_any(ncore, [&](int32_t i) { return (uint64_t)(uint32_t)core_sh[i]; },
+                     [&](int32_t i, uint64_t x) { core_sh[i] = (int32_t)x; });
+      for (int32_t k = t; k < ncore; k += TB) core[k] = core_sh[k];
+    } else {
+      block_sort_any(ncore, [&](int32_t i) { return (uint64_t)(uint32_t)core[i]; },
+                     [&](int32_t i, uint64_t x) { core[i] = (int32_t)x; });
+    }
+    __syncthreads();
+    double bb = 0.0;
+    for (int32_t k = t; k < ncore; k += TB) {
+      const int32_t q = core[k];
+      a.y[q] = 0.0;
+      bb += a.b[q] * a.b[q];
+    }
+    bb = block_sum<TB>(bb, sh);
+    double rn = bb;
+    for (int pass = 0; pass < 3 && bb > 0.0; ++pass) {
+      double rz = 0.0;
+      rn = 0.0;
+      for (int32_t k = t; k < ncore; k += TB) {
+        const int32_t q = core[k];
+        double v = a.b[q] - a.A[q] * a.y[q];
+        for (int32_t e = q; e < a.nend[q]; ++e) {
+          const int32_t pn = a.nbr[e];
+          if (a.state[pn] == kActive) v += a.wgt[e] * a.y[pn];
+        }
+        a.rr[q] = v;
+        a.p[q] = v / a.A[q];
+        rn += v * v;
+        rz += v * v / a.A[q];
+      }
+      rn = block_sum<TB>(rn, sh);
+      rz = block_sum<TB>(rz, sh);
+      if (rn <= a.tol2 * bb) break;
+      for (int it = 0; it < a.max_iter; ++it) {
+        double pap = 0.0;
+        for (int32_t k = t; k < ncore; k += TB) {
+          const int32_t q = core[k];
+          double v = a.A[q] * a.p[q];
+          for (int32_t e = q; e < a.nend[q]; ++e) {
+            const int32_t pn = a.nbr[e];
+            if (a.state[pn] == kActive) v -= a.wgt[e] * a.p[pn];
+          }
+          a.ap[q] = v;
+          pap += a.p[q] * v;
+        }
+        pap = block_sum<TB>(pap, sh);
+        const double alpha = rz / pap;
+        double rz_new = 0.0;
+        rn = 0.0;
+        for (int32_t k = t; k < ncore; k += TB) {
+          const int32_t q = core[k];
+          a.y[q] += alpha * a.p[q];
+          const double rq = a.rr[q] - alpha * a.ap[q];
+          a.rr[q] = rq;
+          rn += rq * rq;
+          rz_new += rq * rq / a.A[q];
+        }
+        rn = block_sum<TB>(rn, sh);
+        rz_new = block_sum<TB>(rz_new, sh);
+        if (rn <= a.tol2 * bb) break;
+        const double beta = rz_new / rz;
+        rz = rz_new;
+        for (int32_t k = t; k < ncore; k += TB) {
+          const int32_t q = core[k];
+          a.p[q] = a.rr[q] / a.A[q] + beta * a.p[q];
+        }
+        __syncthreads();
+      }
+    }
+    if (t == 0 && bb > 0.0 && !(rn <= a.accept2 * bb)) atomicOr(a.err, kErrSolve);
+    for (int32_t k = t; k < ncore; k += TB) a.state[core[k]] = kCore;
+    __syncthreads();
+  }
+
+  // ---- 3. back substitution in reverse elimination order, one round at a time
+  for (int rnd = rounds - 1; rnd >= 0; --rnd) {
+    for (int32_t k = elim_start[rnd] + t; k < elim_start[rnd + 1]; k += TB) {
+      const int32_t q = elim[k];
+      const int32_t pn = a.par[q];
+      a.y[q] = pn < 0 ? a.b[q] / a.A[q] : (a.b[q] + a.Wp[q] * a.y[pn]) / a.A[q];
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_exact_z(int64_t Q, CatView cat, BatchBufs b, const double* y) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= Q) return;
+  const int32_t pi = b.pos[2 * q], pj = b.pos[2 * q + 1];
+  if ((pi & pj) & kSingle) return;  // solved in closed form by k_residual
+  const double yi = y[b.head[pi & kPosMask]];
+  const double yj = y[b.head[pj & kPosMask]];
+  const double2 wr = b.wr[q];
+  const double zs = b.sta[2 * q] >= cat.L_p ? cat.zscale_s : 1.0;
+  const double z = (wr.y - sqrt(wr.x) * (yi - yj)) / (cat.sigma * cat.sigma) * zs;
+  b.z[q] = z;
+  b.zp[pi & kPosMask] = z;
+  b.zp[pj & kPosMask] = z;
+}
+
+// ---------------------------------------------------------------- reduce
+
+__global__ void k_reduce(int64_t K, double scale, BatchBufs b, double* G) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  const int32_t p0 = b.start[k], p1 = b.start[k + 1];
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  for (int32_t p = p0; p < p1; ++p) {
+    const double cz = ((b.csr[p] & 1) ? -scale : scale) * b.zp[p];
+    const double* g = b.gT + (int64_t)p * 3;
+    s0 += cz * g[0];
+    s1 += cz * g[1];
+    s2 += cz * g[2];
+    s3 += cz;
+  }
+  double4* out = (double4*)(G + k * 4);
+  *out = make_double4(s0, s1, s2, s3);
+}
+
+// ---------------------------------------------------------------- per-slot outputs
+
+__global__ void k_batch_terms_out(int64_t n, BatchBufs b, const double* theta, double* Ti,
+                                  double* Tj, double* gi, double* gj, double* r, double* z) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  // b.T holds T + t of each entry
+  if (Ti) Ti[q] = b.T[2 * q] - theta[(int64_t)b.ev[2 * q] * 4 + 3];
+  if (Tj) Tj[q] = b.T[2 * q + 1] - theta[(int64_t)b.ev[2 * q + 1] * 4 + 3];
+  const int64_t pi = b.pos[2 * q] & kPosMask, pj = b.pos[2 * q + 1] & kPosMask;
+  for (int a = 0; a < 3; ++a) {
+    if (gi) gi[q * 3 + a] = b.gT[pi * 3 + a];
+    if (gj) gj[q * 3 + a] = b.gT[pj * 3 + a];
+  }
+  if (r) r[q] = b.r[q];
+  if (z) z[q] = b.z[q];
+}
+
+// Adds the block's sum of k (one value per thread) to *count.
+__device__ void block_count_add(unsigned int k, unsigned long long* count) {
+  __shared__ unsigned int sh[kBlock];
+  sh[threadIdx.x] = k;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && sh[0]) atomicAdd(count, (unsigned long long)sh[0]);
+}
+
+// Linear-regime test of the n slots of one chain's batch (entries 2q, 2q + 1
+// = events i, j): dT = T_j - T_i, lin = grad T(x_i) . (x_j - x_i), keep[q] =
+// |dT - lin| <= e_max |dT|; the kept count is added to *count.
+__global__ void k_linear_keep(const BatchBufs b, const double* theta, int64_t n, double e_max,
+                              uint8_t* keep, unsigned long long* count) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned int k = 0;
+  if (q < n) {
+    const double* xi = theta + (int64_t)b.ev[2 * q] * 4;
+    const double* xj = theta + (int64_t)b.ev[2 * q + 1] * 4;
+    const double* g = b.gT + (int64_t)(b.pos[2 * q] & kPosMask) * 3;
+    // b.T holds T + t of each entry
+    const double dT = (b.T[2 * q + 1] - xj[3]) - (b.T[2 * q] - xi[3]);
+    const double lin = g[0] * (xj[0] - xi[0]) + g[1] * (xj[1] - xi[1]) + g[2] * (xj[2] - xi[2]);
+    k = fabs(dT - lin) <= e_max * fabs(dT) ? 1u : 0u;
+    keep[q] = (uint8_t)k;
+  }
+  block_count_add(k, count);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+
+int64_t scan_part_size(int64_t len) { return ceil_div(len, kScanChunk) + 1; }
+
+void launch_scan(int32_t* a, int64_t len, int32_t* part, hipStream_t s) {
+  if (len <= 0) return;
+  const int64_t nb = ceil_div(len, kScanChunk);
+  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanTB), 0, s, a, len, part);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanTB), 0, s, part, nb);
+  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanTB), 0, s, a, len, part);
+}
+
+void launch_clear_counts(const BatchBufs& b, int64_t keys, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(keys + 1)), dim3(kBlock), 0, s, b.start, 0,
+                     keys + 1);
+}
+
+void launch_select(const CatView& cat, int C, int64_t n, const int64_t* idx, uint64_t seed,
+                   const int64_t* steps, int64_t step_scalar, int chain0, BatchBufs b,
+                   int* err_flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_select, dim3(grid_for((int64_t)C * n)), dim3(kBlock), 0, s, cat, C, n, idx,
+                     (uint32_t)seed, (uint32_t)(seed >> 32), steps, step_scalar, chain0, b,
+                     err_flag);
+}
+
+void launch_build_csr(const CatView& cat, int C, int64_t n, BatchBufs b, int32_t* scan_part,
+                      int32_t* long_list, hipStream_t s) {
+  const int64_t E = 2 * (int64_t)C * n;
+  const int64_t K = (int64_t)C * cat.M;
+  launch_scan(b.start, K + 1, scan_part, s);
+  hipLaunchKernelGGL(k_csr_scatter, dim3(grid_for(E)), dim3(kBlock), 0, s, E, n, cat.M, b);
+  // long-segment count in long_list[0], the list from long_list + 1
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, long_list, 0, (int64_t)1);
+  hipLaunchKernelGGL(k_csr_canon, dim3(grid_for(K, kCanonTB)), dim3(kCanonTB), 0, s, K, cat.M, b,
+                     long_list + 1, long_list);
+  hipLaunchKernelGGL(k_csr_canon_long, dim3(512), dim3(kLongTB), 0, s, long_list + 1, long_list,
+                     cat.M, b);
+}
+
+void launch_phase_rows(const CatView& cat, int64_t E, BatchBufs b, int32_t* flags,
+                       int32_t* scan_part, int64_t* n_p, hipStream_t s) {
+  hipLaunchKernelGGL(k_phase_flags, dim3(grid_for(E + 1)), dim3(kBlock), 0, s, E, b, cat.L_p,
+                     flags);
+  launch_scan(flags, E + 1, scan_part, s);
+  hipLaunchKernelGGL(k_phase_rows, dim3(grid_for(E)), dim3(kBlock), 0, s, E, b, cat.L_p, flags,
+                     n_p);
+}
+
+void launch_assemble(const CatView& cat, const NetView& net, const NetView& net_s, int C, int64_t n,
+                     const double* theta, int64_t theta_stride, const int32_t* rows, BatchBufs b,
+                     hipStream_t s) {
+  const int64_t E = 2 * (int64_t)C * n;
+  hipLaunchKernelGGL(k_assemble, dim3(grid_for(E)), dim3(kBlock), 0, s, cat, net, net_s, n, theta,
+                     theta_stride, rows, E, b);
+}
+
+void launch_residual(const CatView& cat, int C, int64_t n, const double* theta,
+                     int64_t theta_stride, int whiten, BatchBufs b, SolveBufs sv, hipStream_t s) {
+  const int64_t E = 2 * (int64_t)C * n;
+  if (whiten == kWhitenExact)
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(E)), dim3(kBlock), 0, s, sv.act, 0, E);
+  hipLaunchKernelGGL(k_residual, dim3(grid_for((int64_t)C * n)), dim3(kBlock), 0, s, cat, C, n,
+                     theta, theta_stride, whiten, b, sv.act);
+}
+
+int64_t list_blocks(int64_t C, int64_t n, int64_t L) {
+  int64_t nb = ceil_div(2 * n, 4096);
+  const int64_t cap = ((int64_t)1 << 22) / (C * L);
+  if (nb > cap) nb = cap;
+  return nb < 1 ? 1 : nb;
+}
+
+int64_t list_block_span(int64_t n, int64_t nb) { return ceil_div(2 * n, nb); }
+
+hipError_t exact_whiten(const CatView& cat, int C, int64_t n, BatchBufs b, SolveBufs sv, int* err,
+                        hipStream_t s) {
+  const int64_t E = 2 * (int64_t)C * n;
+  const int64_t S = (int64_t)C * cat.L;
+  const int64_t nb = list_blocks(C, n, cat.L), span = list_block_span(n, nb);
+  const double lambda = (cat.sigma * cat.sigma) / (cat.kappa * cat.kappa);
+  const size_t lds = (size_t)cat.L * 4;
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_list_count,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void*)k_list_fill, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_list_count, dim3((unsigned)nb, (unsigned)C), dim3(kListTB), lds, s, n,
+                     cat.L, nb, span, b, sv);
+  launch_scan(sv.sys, S * nb + 1, sv.scan_part, s);
+  hipLaunchKernelGGL(k_list_fill, dim3((unsigned)nb, (unsigned)C), dim3(kListTB), lds, s, n, cat.L,
+                     nb, span, lambda, E, b, sv);
+  SolveArgs a;
+  a.nend = b.nend;
+  a.nbr = sv.nbr;
+  a.wgt = sv.wgt;
+  a.sys = sv.sys;
+  a.nb = nb;
+  a.list = sv.list;
+  a.A = sv.vec;
+  a.b = sv.vec + E;
+  a.y = sv.vec + 2 * E;
+  a.Wp = sv.vec + 3 * E;
+  a.rr = sv.vec + 4 * E;
+  a.p = sv.vec + 5 * E;
+  a.ap = sv.vec + 6 * E;
+  a.state = sv.ivec;
+  a.nstate = sv.ivec + E;
+  a.par = sv.ivec + 2 * E;
+  a.next = sv.ivec + 3 * E;
+  a.elim = sv.ivec + 4 * E;
+  a.lambda = lambda;
+  a.max_rounds = kMaxRounds;
+  // CG to a relative residual of 1e-16 (z = (r - U y)/sigma^2 scales y
+  // errors by 1/sigma^2, so y is solved to FP64 rounding), at most 1,000
+  // iterations per pass and three passes; a core still above 1e-8 after them
+  // is an error
+  a.max_iter = 1000;
+  a.tol2 = 1e-32;
+  a.accept2 = 1e-16;
+  a.err = err;
+  hipLaunchKernelGGL(k_tree_solve<kTreeBlock>, dim3((unsigned)S), dim3(kTreeBlock), 0, s, a);
+  hipLaunchKernelGGL(k_exact_z, dim3(grid_for((int64_t)C * n)), dim3(kBlock), 0, s,
+                     (int64_t)C * n, cat, b, (const double*)a.y);
+  return hipGetLastError();
+}
+
+void launch_reduce(const CatView& cat, int C, int64_t n, double scale, BatchBufs b, double* G,
+                   hipStream_t s) {
+  (void)n;
+  const int64_t K = (int64_t)C * cat.M;
+  hipLaunchKernelGGL(k_reduce, dim3(grid_for(K)), dim3(kBlock), 0, s, K, scale, b, G);
+}
+
+void launch_batch_terms_out(int64_t n, const BatchBufs& b, const double* theta, double* T_i,
+                            double* T_j, double* gT_i, double* gT_j, double* r, double* z,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_terms_out, dim3(grid_for(n)), dim3(kBlock), 0, s, n, b, theta, T_i,
+                     T_j, gT_i, gT_j, r, z);
+}
+
+void launch_linear_keep(const BatchBufs& b, const double* theta, int64_t n, double e_max,
+                        uint8_t* keep, unsigned long long* count, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_linear_keep, dim3(grid_for(n)), dim3(kBlock), 0, s, b, theta, n, e_max,
+                     keep, count);
+}
+
+}  // namespace spider

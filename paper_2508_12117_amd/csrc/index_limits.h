@@ -9,6 +9,9 @@
 namespace spider {
 
 constexpr int64_t kMaxEntries = 2147483647;  // INT32_MAX
+// Station-phase groups of a catalog: the exact whitening counts each
+// position block's nodes per group in LDS (4 bytes a group, 160 KB).
+constexpr int32_t kMaxGroups = 40960;
 
 // True iff `chains` chains with minibatch `batch` each fit the 32-bit entry
 // numbering (2 chains batch <= kMaxEntries), for chains, batch >= 1.

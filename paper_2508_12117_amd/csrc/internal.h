@@ -46,40 +46,61 @@ struct CatView {
   double prior_sigma[4], centroid_sigma[4];
 };
 
-// Minibatch buffers of C chains x n slots.  Slot q = c * n + k; entry/row
-// 2q is event i of the slot and 2q + 1 is event j.
+// Minibatch buffers of one chain set, C chains x n slots.  Slot q = c n + k;
+// entry e = 2q is event i of the slot and e = 2q + 1 event j (E = 2 C n
+// entries).  The entries are also held in CSR order: grouped by (chain,
+// event) key c M + m, and inside each event's segment by (group, entry), so
+// that the entries of one (chain, group, event) node of the whitening are
+// contiguous and every sum over a segment or a node runs in a fixed order.
 struct BatchBufs {
   int64_t* obs;     // [C n] observation index
-  int32_t* ev;      // [2 C n] event of each row
-  int32_t* sta;     // [2 C n] station (= group) of each row
+  int32_t* ev;      // [E] event of each entry
+  int32_t* sta;     // [E] group of each entry (station + L_p phase)
   double* tau;      // [C n] observed differential time
   double* w;        // [C n] normalised edge weight
-  RowOut* net_out;  // [2 C n]
-  double* T;        // [2 C n] travel time of each row
-  double* gT;       // [2 C n][3] source gradient of each row
+  int32_t* rank;    // [E] arrival rank of the entry in its (chain, event) count
+  int32_t* start;   // [C M + 1] counts, then the first CSR position of each key
+  int32_t* csr;     // [E] entry at each CSR position
+  uint64_t* ckey;   // [E] (group, entry) of each CSR position as scattered, then sorted
+  int32_t* pos;     // [E] CSR position of each entry; bit 31: its node has one entry
+  int32_t* pev;     // [E] event at each CSR position
+  int32_t* pgr;     // [E] group at each CSR position
+  int32_t* head;    // [E] per CSR position: first position of its node
+  int32_t* nend;    // [E] at a node's first position: one past its last
+  int32_t* rows;    // [E] network row order of two-phase catalogs (CSR positions, P first)
+  double* zp;       // [E] whitened residual of each CSR position's observation
+  RowOut* net_out;  // [E] network output of each row
+  double* T;        // [E] travel time plus origin time, T(x; s) + t, of each entry
+  double* gT;       // [E][3] source gradient at each CSR position
   double* r;        // [C n] residual
   double* z;        // [C n] whitened residual
-  double2* wr;      // [C n] (w, r) side by side, for the edge gathers of the solver
-  double4* xt;      // [2 C n] event state of each row, written by the network kernels
+  double2* wr;      // [C n] (w, r) side by side, for the node gathers of the solver
 };
 
-// Scratch of the exact whitening and the per-event reduction.
-struct SortBufs {
-  uint64_t* key_in;
-  uint64_t* key_out;
-  uint32_t* val_in;
-  uint32_t* val_out;
-  void* temp;
-  size_t temp_bytes;
-  int32_t* node_of;    // [2 C n] node of each entry
-  int32_t* node_start; // [2 C n + 1] first sorted position of each node
-  int32_t* seg_begin;  // [C L] first node of each (chain, group)
-  int32_t* seg_end;    // [C L]
-  int32_t* flags;      // [2 C n] scratch
-  double* vec;         // [8][2 C n] solver vectors
-  int32_t* ivec;       // [4][2 C n] solver node states and lists
-  int32_t* count;      // [1] device node count
+// Scratch of the exact whitening of one chain set (all arrays indexed by CSR
+// position unless stated; a node is stored at its first position).
+struct SolveBufs {
+  int32_t* act;       // [E] 1 at the first position of every node the solver takes
+  int32_t* sys;       // [C L nb + 1] nodes per (chain, group, position block), then list
+                      // offsets (system s = c L + g starts at sys[s nb])
+  int32_t* list;      // [E] nodes of each system (first positions)
+  int32_t* nbr;       // [E] node at the other end of each position's observation
+  double* wgt;        // [E] edge weight of each position's observation
+  double* vec;        // [7][E] A, b, y, Wp, rr, p, ap
+  int32_t* ivec;      // [5][E] state, nstate, par, next list, elimination order
+  int32_t* scan_part; // scratch of the scans
 };
+
+// Position blocks per chain of the exact whitening's system lists for
+// C chains of 2n entries and L groups (at most 2^22 list counts), and the
+// positions per block.
+int64_t list_blocks(int64_t C, int64_t n, int64_t L);
+int64_t list_block_span(int64_t n, int64_t nb);
+
+// Exclusive prefix sum of a[0..len) in place, a[len-1] receiving the sum of
+// all earlier entries (deterministic; part holds ceil(len / 4096) + 1 ints).
+void launch_scan(int32_t* a, int64_t len, int32_t* part, hipStream_t s);
+int64_t scan_part_size(int64_t len);
 
 // ---- launchers (each enqueues on stream s; errors surface via hipGetLastError)
 // Network kernels (mlp_*.hip).  Unsupported shapes return hipErrorNotSupported.
@@ -118,30 +139,51 @@ hipError_t group_inverse_mean(const Obs* obs, int64_t N, int L, const double* w_
 // out[c] = mean over rows of a [rows][4] array (c = 0..3); deterministic.
 void launch_mean4(const double* a, int64_t rows, double* out, hipStream_t s);
 
-// Step kernels (step.hip).
-// Minibatch of each chain: explicit indices idx (all chains) or, if idx is
-// null, the Feistel minibatch of chain chain0 + c at step steps[c] (device)
-// or, if steps is null, at step_scalar.  err_flag |= 1 on a failed walk.
-void launch_select(const CatView& cat, int C, int64_t n, const int64_t* idx, uint64_t seed,
-                   const int64_t* steps, int64_t step_scalar, int chain0, BatchBufs b,
-                   int* err_flag, hipStream_t s);
-void launch_residual(const CatView& cat, const NetView& net, const NetView& net_s, int C, int64_t n,
-                     const double* theta, int64_t theta_stride, int whiten, BatchBufs b,
-                     hipStream_t s);
 // Error bits a step sets in its device flag (read back by the host after
 // the call): a minibatch index outside [0, N) or a failed permutation walk,
 // and a CG solve of a cyclic core that did not converge.
 constexpr int kErrSelect = 1;
 constexpr int kErrSolve = 2;
-// Exact whitening z = Sigma_B^{-1} r by Woodbury + a per-(chain, group)
-// elimination solve of the batch graph system; err |= kErrSolve when a CG
-// core does not converge.
-hipError_t exact_whiten(const CatView& cat, int C, int64_t n, BatchBufs b, SortBufs sb, int* err,
+
+// Step kernels (batch_csr.hip).
+// Zeroes the (chain, event) counts of a chain set: start[0 .. C M].
+void launch_clear_counts(const BatchBufs& b, int64_t keys, hipStream_t s);
+// Minibatch of each chain: explicit indices idx (all chains) or, if idx is
+// null, the Feistel minibatch of chain chain0 + c at step steps[c] (device)
+// or, if steps is null, at step_scalar; counts each entry in b.start (after
+// launch_clear_counts) with its arrival rank.  err_flag |= kErrSelect on a
+// failed walk or an index outside [0, N).
+void launch_select(const CatView& cat, int C, int64_t n, const int64_t* idx, uint64_t seed,
+                   const int64_t* steps, int64_t step_scalar, int chain0, BatchBufs b,
+                   int* err_flag, hipStream_t s);
+// The CSR order of the entries (after launch_select): scan of the counts,
+// scatter, and each event's segment sorted by (group, entry); pos, head, nend.
+// scan_part: scan_part_size(C M + 1) ints; long_list: C M + 1 ints.
+void launch_build_csr(const CatView& cat, int C, int64_t n, BatchBufs b, int32_t* scan_part,
+                      int32_t* long_list, hipStream_t s);
+// Two-phase catalogs: b.rows = the entries in CSR order, those of P groups
+// first; *n_p (device) = their number.  flags: E + 1 ints of scratch.
+void launch_phase_rows(const CatView& cat, int64_t E, BatchBufs b, int32_t* flags,
+                       int32_t* scan_part, int64_t* n_p, hipStream_t s);
+// T and dT/dx of every entry from the network outputs (row v of the network
+// is entry rows[v], or csr[v] when rows is null).
+void launch_assemble(const CatView& cat, const NetView& net, const NetView& net_s, int C, int64_t n,
+                     const double* theta, int64_t theta_stride, const int32_t* rows, BatchBufs b,
+                     hipStream_t s);
+// Residuals; z for whitening none / diag / L1 and for the observations of
+// exact whitening whose two nodes have one entry each (z = r / (sigma^2 +
+// 2 kappa^2 w)); the others mark their nodes in sv.act (after a clear).
+void launch_residual(const CatView& cat, int C, int64_t n, const double* theta,
+                     int64_t theta_stride, int whiten, BatchBufs b, SolveBufs sv, hipStream_t s);
+// Exact whitening of the marked nodes: per (chain, group) lists, elimination
+// + CG solve of (lambda I + U^T U) y = U^T r, z = (r - U y)/sigma^2.
+// err |= kErrSolve when a CG core does not converge.
+hipError_t exact_whiten(const CatView& cat, int C, int64_t n, BatchBufs b, SolveBufs sv, int* err,
                         hipStream_t s);
-// G_lik[c][m] = scale * sum over the chain's batch of the event's terms.
-hipError_t reduce_events(const CatView& cat, int C, int64_t n, double scale, BatchBufs b,
-                         SortBufs sb, double* G, hipStream_t s);
-size_t sort_temp_bytes(int64_t entries);
+// G_lik[c][m] = scale * sum over the entries of (chain c, event m) of
+// +-z (dT/dx, 1), one CSR segment each, in CSR order.
+void launch_reduce(const CatView& cat, int C, int64_t n, double scale, BatchBufs b, double* G,
+                   hipStream_t s);
 // thetabar[c] = mean over events of theta[c] (4 values per chain).
 void launch_centroid(const double* theta, int C, int M, double* partial, double* thetabar,
                      hipStream_t s);
@@ -185,8 +227,11 @@ void launch_logpost(const CatView& cat, int64_t n, double scale, const double* r
 void launch_tt_assemble(const NetView& net, int64_t rows, const double* x, const double* s,
                         const RowOut* out, double* T, double* gradT, const double* vjp_w,
                         hipStream_t st);
-void launch_batch_terms_out(int64_t n, const BatchBufs& b, double* T_i, double* T_j, double* gT_i,
-                            double* gT_j, double* r, double* z, hipStream_t s);
+// Per-slot terms of the first n slots of one chain at state theta (T
+// without the origin time, gT gathered from CSR order).
+void launch_batch_terms_out(int64_t n, const BatchBufs& b, const double* theta, double* T_i,
+                            double* T_j, double* gT_i, double* gT_j, double* r, double* z,
+                            hipStream_t s);
 void launch_noise(const CatView& cat, uint64_t seed, int chain, int64_t step, double* eta,
                   hipStream_t s);
 void launch_finite(const double* a, int64_t count, int64_t per_chain, int* bad_chain,
@@ -205,13 +250,6 @@ void launch_keep(const double* r, int64_t N, double med, double thr, uint8_t* ke
 // |dT| with dT = T_j - T_i and lin = grad T(x_i) . (x_j - x_i).
 void launch_linear_keep(const BatchBufs& b, const double* theta, int64_t n, double e_max,
                         uint8_t* keep, unsigned long long* count, hipStream_t s);
-// Two-phase catalogs: list = the E rows with group < L_p (P) in order, then
-// the others (S) in reverse order; *count = the number of P rows.
-hipError_t partition_rows_by_phase(const int32_t* sta, int32_t L_p, int64_t E, int32_t* list,
-                                   uint64_t* count, void* temp, size_t* temp_bytes, hipStream_t s);
-// out[list[v]] = compact[v] for v < E.
-void launch_scatter_rows(const RowOut* compact, const int32_t* list, int64_t E, RowOut* out,
-                         hipStream_t s);
 // Diagnostics over stored samples [S][P] (sample-major).
 constexpr int kMaxEssChains = 64;
 constexpr int64_t kMaxQuantileSamples = 8192;

@@ -141,9 +141,13 @@ __device__ __forceinline__ void tanh_scaled(float y, float& a, float& d) {
 }
 
 // Derivative factors 1 - a^2 kept between the passes: FP32 registers, or in
-// the BF16 path BF16 pairs (round to nearest even), the first NLR layers in
-// registers and the rest in LDS, where each lane reads back only what it
-// wrote ([layer][pair][thread] uint32, conflict-free).
+// the BF16 path FP16 pairs (round to nearest even: 11 significant bits where
+// BF16 keeps 8, and 1 - a^2 lies in [0, 1], well inside FP16's range), the
+// first NLR layers in registers and the rest in LDS, where each lane reads
+// back only what it wrote ([layer][pair][thread] uint32, conflict-free).  The
+// backward pass multiplies by a factor with one mixed-precision FMA
+// (v_fma_mix_f32 reads the FP16 half in place), mul(l, rt, ct, i, x) =
+// d_l x.
 // First layer (6 inputs) on the FP32 matrix core, two v_mfma_f32_16x16x4_f32
 // per 16 x 16 tile: k = 0..3, then k = 4..7 with inputs 6 and 7 zero.  The
 // lane supplies the A element (neuron nr = tile + lane % 16, input k = 4 kk +
@@ -164,30 +168,44 @@ __device__ __forceinline__ floatx4 first_layer_mma(const float w[2], const float
 template <class P, int NL, int NLR, int RT, int CT, int NT>
 struct DStore {
   float v[NL][RT][CT][4];
-  __device__ void set4(int l, int rt, int ct, const float x[4]) {
+  // a: the activations, d: their 1 - a^2 in FP32
+  __device__ void set4(int l, int rt, int ct, const float a[4], const float d[4]) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) v[l][rt][ct][i] = x[i];
+    for (int i = 0; i < 4; ++i) v[l][rt][ct][i] = d[i];
   }
-  __device__ float get(int l, int rt, int ct, int i) const { return v[l][rt][ct][i]; }
+  __device__ float mul(int l, int rt, int ct, int i, float x) const { return x * v[l][rt][ct][i]; }
 };
+
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
 
 template <int NL, int NLR, int RT, int CT, int NT>
 struct DStore<PolBF16, NL, NLR, RT, CT, NT> {
   uint32_t v[NLR][RT][CT][2];
   uint32_t* lds;  // [NL - NLR][RT * CT * 2][NT]
   int tid;
-  __device__ void set4(int l, int rt, int ct, const float x[4]) {
+  // 1 - a^2 straight from the FP32 activations with one rounding to FP16
+  // (v_fma_mixlo/hi_f16: fma(-a, a, 1) in full precision), written out so
+  // that every tile variant rounds the same way
+  __device__ void set4(int l, int rt, int ct, const float a[4], const float d[4]) {
+    (void)d;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const uint32_t w = pack_bf16x2(x[2 * h], x[2 * h + 1]);
+      uint32_t w;
+      asm("v_fma_mixlo_f16 %0, -%1, %1, 1.0 op_sel_hi:[0,0,0]\n\t"
+          "v_fma_mixhi_f16 %0, -%2, %2, 1.0 op_sel_hi:[0,0,0]"
+          : "=&v"(w)
+          : "v"(a[2 * h]), "v"(a[2 * h + 1]));
       if (l < NLR) v[l][rt][ct][h] = w;
       else lds[(((l - NLR) * RT * CT + rt * CT + ct) * 2 + h) * NT + tid] = w;
     }
   }
-  __device__ float get(int l, int rt, int ct, int i) const {
+  __device__ float mul(int l, int rt, int ct, int i, float x) const {
     const uint32_t w = l < NLR ? v[l][rt][ct][i >> 1]
                                : lds[(((l - NLR) * RT * CT + rt * CT + ct) * 2 + (i >> 1)) * NT + tid];
-    return __uint_as_float((i & 1) ? (w & 0xFFFF0000u) : (w << 16));
+    const half2_t hv = __builtin_bit_cast(half2_t, w);
+    // fma with a +0 addend (not a product, which the compiler would not fuse
+    // with the conversion): d x exactly rounded, one v_fma_mix_f32
+    return __builtin_fmaf((float)((i & 1) ? hv.y : hv.x), x, 0.0f);
   }
 };
 
@@ -243,6 +261,32 @@ struct WRing {
   Pack16 w[PF][CT];
 };
 
+// Where a layer's packed operands come from: the pack as a buffer resource
+// (scalar base and range) and the layer's byte offset in it.  A 16-byte
+// chunk is then a buffer load with a scalar offset (layer, tile, chunk: all
+// uniform over the wave) and the lane's fixed 16-byte slot, so the weight
+// stream costs no per-lane address arithmetic.
+struct WSrc {
+  __amdgpu_buffer_rsrc_t rsrc;
+  int32_t off;
+};
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// The pack of `layers` hidden layers at p as a buffer resource.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t pack_rsrc(const void* p, int layers,
+                                                           int layer_bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, layers * layer_bytes,
+                                           0x00020000);
+}
+
+// Chunk `chunk` (tile-major index: tile * NQ + chunk within the tile) of a
+// layer, this lane's 16 bytes (voff = 16 lane).
+__device__ __forceinline__ uint4 wload(const WSrc& s, int chunk, int voff) {
+  const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(s.rsrc, voff, s.off + chunk * 1024, 0);
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+
 // Order of the K chunks.  BF16 products add their chunks starting at the
 // chunk of the output neuron's own 32-neuron block (n / 32) and wrapping
 // around, so that a wave can begin with the chunk it produced itself; the
@@ -261,13 +305,13 @@ __device__ __forceinline__ int chunk_start(int wave, int NQ) {
 
 // Prefetch ring slots j = 0 .. PF-1 with chunks s0 + j (mod NQ) of pl.
 template <int NQ, int PF, int CT>
-__device__ __forceinline__ void ring_prime(WRing<PF, CT>& r, const uint4* pl, int wave, int lane,
+__device__ __forceinline__ void ring_prime(WRing<PF, CT>& r, const WSrc& pl, int wave, int voff,
                                            int s0) {
 #pragma unroll
   for (int j = 0; j < PF; ++j)
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct)
-      r.w[j][ct].u = pl[((wave * CT + ct) * NQ + ((s0 + j) & (NQ - 1))) * 64 + lane];
+      r.w[j][ct].u = wload(pl, (wave * CT + ct) * NQ + ((s0 + j) & (NQ - 1)), voff);
 }
 
 // acc[rt][ct] += W[neuron tile wave*CT + ct][k] . X[16 rt + row][k] over the
@@ -280,9 +324,9 @@ __device__ __forceinline__ void ring_prime(WRing<PF, CT>& r, const uint4* pl, in
 // a branch around it, so the wait counts stay exact and the ring keeps PF
 // chunks in flight.
 template <class P, int RT, int CT, int NQ, int LDW, int SWM, int PF>
-__device__ __forceinline__ void layer_mma(const typename P::T* X, const uint4* pl,
-                                          const uint4* pl_next, WRing<PF, CT>& ring, int wave,
-                                          int lane, int c, int g, int s0,
+__device__ __forceinline__ void layer_mma(const typename P::T* X, const WSrc& pl,
+                                          const WSrc& pl_next, WRing<PF, CT>& ring, int wave,
+                                          int voff, int c, int g, int s0,
                                           floatx4 (&acc)[RT][CT]) {
   constexpr int ELEMS = Chunk<P>::ELEMS, SPC = Chunk<P>::SPC;
   static_assert(NQ % PF == 0, "chunks must split evenly over the prefetch ring");
@@ -320,9 +364,10 @@ __device__ __forceinline__ void layer_mma(const typename P::T* X, const uint4* p
             }
           }
       const bool here = q + PF < NQ;
-      const uint4* src = (here ? pl : pl_next) + ((s0 + q + PF) & (NQ - 1)) * 64 + lane;
+      const WSrc src = here ? pl : pl_next;
+      const int qc = (s0 + q + PF) & (NQ - 1);
 #pragma unroll
-      for (int ct = 0; ct < CT; ++ct) ring.w[j][ct].u = src[(wave * CT + ct) * NQ * 64];
+      for (int ct = 0; ct < CT; ++ct) ring.w[j][ct].u = wload(src, (wave * CT + ct) * NQ + qc, voff);
       // keep the refill here, right after the MFMAs that free the slot
       __builtin_amdgcn_sched_barrier(0);
     }
@@ -352,20 +397,24 @@ __global__ __launch_bounds__(NW * 64, MINB) void k_mlp(RowSource src, NetView ne
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  // the wave index is uniform over the wave: held in a scalar register, the
+  // weight-operand addresses become scalar base + per-lane offset
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int c = lane & 15;
   const int g = lane >> 4;
   const int64_t row0 = (int64_t)blockIdx.x * R;
 
   // hidden-layer operand stream: forward layers 1 .. D-1, then backward
   // layers D-1 .. 1; the ring starts filling now, under the first layer
-  const uint4* packf = (const uint4*)net.pack_fwd;
-  const uint4* packb = (const uint4*)net.pack_bwd;
-  constexpr size_t LSTRIDE = (size_t)(H / 16) * NQ * 64;  // uint4 per packed layer
+  constexpr int LBYTES = (H / 16) * NQ * 64 * 16;  // bytes per packed layer
+  constexpr int NLAY = D > 1 ? D - 1 : 1;
+  const __amdgpu_buffer_rsrc_t packf = pack_rsrc(net.pack_fwd, NLAY, LBYTES);
+  const __amdgpu_buffer_rsrc_t packb = pack_rsrc(net.pack_bwd, NLAY, LBYTES);
+  const int voff = lane * 16;
   constexpr int PFR = NQ < PF ? NQ : PF;
   WRing<PFR, CT> ring;
   const int s0 = chunk_start<P, CT>(wave, NQ);
-  if (D > 1) ring_prime<NQ, PFR, CT>(ring, packf, wave, lane, s0);
+  if (D > 1) ring_prime<NQ, PFR, CT>(ring, WSrc{packf, 0}, wave, voff, s0);
   // first-layer and output weights of the wave's neurons, loaded before the
   // row inputs so that both latencies overlap
   float w1[CT][2], b1[CT][4], wo[CT][4];
@@ -428,7 +477,7 @@ __global__ __launch_bounds__(NW * 64, MINB) void k_mlp(RowSource src, NetView ne
           acc[rt][ct][i] = av[i];
         }
         if (D > 1) {
-          dst.set4(0, rt, ct, dv);
+          dst.set4(0, rt, ct, av, dv);
           store_row4<T>(out_act, LDW, SWM, rt * 16 + c, n0, av);
         }
       }
@@ -450,9 +499,9 @@ __global__ __launch_bounds__(NW * 64, MINB) void k_mlp(RowSource src, NetView ne
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt) acc[rt][ct] = floatx4{bn.x, bn.y, bn.z, bn.w};
     }
-    const uint4* pl = packf + (size_t)(l - 1) * LSTRIDE;
-    const uint4* pn = l < D - 1 ? packf + (size_t)l * LSTRIDE : packb + (size_t)(D - 2) * LSTRIDE;
-    layer_mma<P, RT, CT, NQ, LDW, SWM, PFR>(in, pl, pn, ring, wave, lane, c, g, s0, acc);
+    const WSrc pl{packf, (l - 1) * LBYTES};
+    const WSrc pn = l < D - 1 ? WSrc{packf, l * LBYTES} : WSrc{packb, (D - 2) * LBYTES};
+    layer_mma<P, RT, CT, NQ, LDW, SWM, PFR>(in, pl, pn, ring, wave, voff, c, g, s0, acc);
     if constexpr (NBUF == 1) __syncthreads();  // every wave done reading `in`
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
@@ -467,7 +516,7 @@ __global__ __launch_bounds__(NW * 64, MINB) void k_mlp(RowSource src, NetView ne
           acc[rt][ct][i] = av[i];
         }
         if (l < D - 1) {
-          dst.set4(l, rt, ct, dv);
+          dst.set4(l, rt, ct, av, dv);
           store_row4<T>(outp, LDW, SWM, rt * 16 + c, n0, av);
         }
       }
@@ -513,8 +562,8 @@ __global__ __launch_bounds__(NW * 64, MINB) void k_mlp(RowSource src, NetView ne
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = floatx4{0, 0, 0, 0};
-    const uint4* pl = packb + (size_t)(l - 1) * LSTRIDE;
-    const uint4* pn = l > 1 ? packb + (size_t)(l - 2) * LSTRIDE : pl;
+    const WSrc pl{packb, (l - 1) * LBYTES};
+    const WSrc pn = l > 1 ? WSrc{packb, (l - 2) * LBYTES} : pl;
     if (l == 1) {
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) {
@@ -525,13 +574,13 @@ __global__ __launch_bounds__(NW * 64, MINB) void k_mlp(RowSource src, NetView ne
           for (int a = 0; a < 3; ++a) wg[ct][i][a] = net.W0[(n0 + i) * 6 + a];
       }
     }
-    layer_mma<P, RT, CT, NQ, LDW, SWM, PFR>(eb, pl, pn, ring, wave, lane, c, g, s0, acc);
+    layer_mma<P, RT, CT, NQ, LDW, SWM, PFR>(eb, pl, pn, ring, wave, voff, c, g, s0, acc);
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) eD[rt][ct][i] = acc[rt][ct][i] * dst.get(l - 1, rt, ct, i);
+        for (int i = 0; i < 4; ++i) eD[rt][ct][i] = dst.mul(l - 1, rt, ct, i, acc[rt][ct][i]);
     // with two buffers the next layer publishes into the other one, and the
     // barrier after that write orders it after every wave's reads of this one
     if constexpr (NBUF == 2) cur ^= 1;

@@ -56,7 +56,7 @@ struct ShapePP {
 // of the other half.
 template <class P, int h, int RT, int CT, int NQ, int LDW, int SWM, bool REFILL, class F>
 __device__ __forceinline__ void mma_half(const typename P::T* X, WRing<NQ, CT>& ring,
-                                         const uint4* refill, int wave, int lane, int c, int g,
+                                         const WSrc& refill, int wave, int voff, int c, int g,
                                          int s0, floatx4 (&acc)[RT][CT], F&& work) {
   constexpr int RH = RT / 2, ELEMS = Chunk<P>::ELEMS;
   const typename P::T* xr = X + (h * RH * 16 + c) * LDW;
@@ -83,7 +83,7 @@ __device__ __forceinline__ void mma_half(const typename P::T* X, WRing<NQ, CT>& 
     if constexpr (REFILL) {
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct)
-        ring.w[q][ct].u = refill[((wave * CT + ct) * NQ + ((s0 + q) & (NQ - 1))) * 64 + lane];
+        ring.w[q][ct].u = wload(refill, (wave * CT + ct) * NQ + ((s0 + q) & (NQ - 1)), voff);
     }
     work(q);
     __builtin_amdgcn_sched_barrier(0);
@@ -106,7 +106,7 @@ __global__ __launch_bounds__(NW * 64, 1) void k_mlp_pp(RowSource src, NetView ne
   constexpr int CT = S::CT, RT = S::RT, RH = S::RH, R = S::R, NQ = S::NQ, LDW = S::LDW;
   constexpr int SWM = S::SWM, NL = S::NL, NLR = S::NLR, NT = S::NT;
   constexpr int NF = RH * CT;  // epilogue fragments per half
-  constexpr size_t LSTRIDE = (size_t)(H / 16) * NQ * 64;
+  constexpr int LBYTES = (H / 16) * NQ * 64 * 16;  // bytes per packed layer
 
   __shared__ __attribute__((aligned(16))) T act[R * LDW];
   __shared__ uint32_t dlds[S::NLDS > 0 ? S::NLDS * RT * CT * 2 * NT : 1];
@@ -115,16 +115,19 @@ __global__ __launch_bounds__(NW * 64, 1) void k_mlp_pp(RowSource src, NetView ne
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  // the wave index is uniform over the wave: held in a scalar register, the
+  // weight-operand addresses become scalar base + per-lane offset
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int c = lane & 15;
   const int g = lane >> 4;
   const int64_t row0 = (int64_t)blockIdx.x * R;
 
-  const uint4* packf = (const uint4*)net.pack_fwd;
-  const uint4* packb = (const uint4*)net.pack_bwd;
+  const __amdgpu_buffer_rsrc_t packf = pack_rsrc(net.pack_fwd, D - 1, LBYTES);
+  const __amdgpu_buffer_rsrc_t packb = pack_rsrc(net.pack_bwd, D - 1, LBYTES);
+  const int voff = lane * 16;
   WRing<NQ, CT> ring;
   const int s0 = chunk_start<P, CT>(wave, NQ);
-  ring_prime<NQ, NQ, CT>(ring, packf, wave, lane, s0);
+  ring_prime<NQ, NQ, CT>(ring, WSrc{packf, 0}, wave, voff, s0);
   float w1[CT][2], b1[CT][4], wo[CT][4];
 #pragma unroll
   for (int ct = 0; ct < CT; ++ct) {
@@ -173,7 +176,7 @@ __global__ __launch_bounds__(NW * 64, 1) void k_mlp_pp(RowSource src, NetView ne
     float av[4], dv[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) tanh_scaled(z[i], av[i], dv[i]);
-    dst.set4(0, rt, ct, dv);
+    dst.set4(0, rt, ct, av, dv);
     store_row4<T>(act, LDW, SWM, rt * 16 + c, n0_of(f), av);
   };
   // epilogue of forward layer l (1 <= l <= D-1) for fragment f of half h
@@ -183,7 +186,7 @@ __global__ __launch_bounds__(NW * 64, 1) void k_mlp_pp(RowSource src, NetView ne
 #pragma unroll
     for (int i = 0; i < 4; ++i) tanh_scaled(acc[rt][ct][i], av[i], dv[i]);
     if (l < D - 1) {
-      dst.set4(l, rt, ct, dv);
+      dst.set4(l, rt, ct, av, dv);
       store_row4<T>(act, LDW, SWM, rt * 16 + c, n0_of(f), av);
     } else {
       // output layer partial and the backward seed e_D = w_out * d_D
@@ -202,7 +205,7 @@ __global__ __launch_bounds__(NW * 64, 1) void k_mlp_pp(RowSource src, NetView ne
     const int rt = h * RH + f / CT, ct = f % CT;
     float e[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) e[i] = acc[rt][ct][i] * dst.get(l - 1, rt, ct, i);
+    for (int i = 0; i < 4; ++i) e[i] = dst.mul(l - 1, rt, ct, i, acc[rt][ct][i]);
     if (l > 1) {
       store_row4<T>(act, LDW, SWM, rt * 16 + c, n0_of(f), e);
     } else {
@@ -241,11 +244,11 @@ __global__ __launch_bounds__(NW * 64, 1) void k_mlp_pp(RowSource src, NetView ne
   // ---- forward hidden layers
 #pragma unroll
   for (int l = 1; l < D; ++l) {
-    const uint4* pl = packf + (size_t)(l - 1) * LSTRIDE;
-    const uint4* pn = l < D - 1 ? packf + (size_t)l * LSTRIDE : packb + (size_t)(D - 2) * LSTRIDE;
+    const WSrc pl{packf, (l - 1) * LBYTES};
+    const WSrc pn = l < D - 1 ? WSrc{packf, l * LBYTES} : WSrc{packb, (D - 2) * LBYTES};
     // job F(l)A with the epilogue of the previous job (first layer B, or F(l-1)B)
     set_bias(0);
-    mma_half<P, 0, RT, CT, NQ, LDW, SWM, false>(act, ring, pl, wave, lane, c, g, s0, acc, [&](int q) {
+    mma_half<P, 0, RT, CT, NQ, LDW, SWM, false>(act, ring, pl, wave, voff, c, g, s0, acc, [&](int q) {
       spread<NQ, NF>(q, [&](int f) {
         if (l == 1) first_layer(1, f);
         else fwd_epi(l - 1, 1, f);
@@ -255,7 +258,7 @@ __global__ __launch_bounds__(NW * 64, 1) void k_mlp_pp(RowSource src, NetView ne
     // job F(l)B with the epilogue of F(l)A; the ring refills with the next layer
     set_bias(1);
     if (l + 1 < D) load_bias(l + 1);
-    mma_half<P, 1, RT, CT, NQ, LDW, SWM, true>(act, ring, pn, wave, lane, c, g, s0, acc, [&](int q) {
+    mma_half<P, 1, RT, CT, NQ, LDW, SWM, true>(act, ring, pn, wave, voff, c, g, s0, acc, [&](int q) {
       spread<NQ, NF>(q, [&](int f) { fwd_epi(l, 0, f); });
     });
     __syncthreads();
@@ -264,10 +267,10 @@ __global__ __launch_bounds__(NW * 64, 1) void k_mlp_pp(RowSource src, NetView ne
   // ---- backward layers D-1 .. 1
 #pragma unroll
   for (int l = D - 1; l >= 1; --l) {
-    const uint4* pl = packb + (size_t)(l - 1) * LSTRIDE;
-    const uint4* pn = l > 1 ? packb + (size_t)(l - 2) * LSTRIDE : pl;
+    const WSrc pl{packb, (l - 1) * LBYTES};
+    const WSrc pn = l > 1 ? WSrc{packb, (l - 2) * LBYTES} : pl;
     set_zero(0);
-    mma_half<P, 0, RT, CT, NQ, LDW, SWM, false>(act, ring, pl, wave, lane, c, g, s0, acc, [&](int q) {
+    mma_half<P, 0, RT, CT, NQ, LDW, SWM, false>(act, ring, pl, wave, voff, c, g, s0, acc, [&](int q) {
       spread<NQ, NF>(q, [&](int f) {
         if (l == D - 1) fwd_epi(D - 1, 1, f);
         else bwd_epi(l + 1, 1, f);
@@ -276,12 +279,12 @@ __global__ __launch_bounds__(NW * 64, 1) void k_mlp_pp(RowSource src, NetView ne
     __syncthreads();
     set_zero(1);
     if (l > 1) {
-      mma_half<P, 1, RT, CT, NQ, LDW, SWM, true>(act, ring, pn, wave, lane, c, g, s0, acc, [&](int q) {
+      mma_half<P, 1, RT, CT, NQ, LDW, SWM, true>(act, ring, pn, wave, voff, c, g, s0, acc, [&](int q) {
         spread<NQ, NF>(q, [&](int f) { bwd_epi(l, 0, f); });
       });
       __syncthreads();
     } else {
-      mma_half<P, 1, RT, CT, NQ, LDW, SWM, false>(act, ring, pn, wave, lane, c, g, s0, acc, [&](int q) {
+      mma_half<P, 1, RT, CT, NQ, LDW, SWM, false>(act, ring, pn, wave, voff, c, g, s0, acc, [&](int q) {
         spread<NQ, NF>(q, [&](int f) { bwd_epi(1, 0, f); });
       });
     }

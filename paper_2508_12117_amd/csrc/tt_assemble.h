@@ -1,0 +1,29 @@
+// Travel time and source gradient of one row in FP64 from the network
+// output (o, do/du_src): T = T0 f with T0 = |x - s|/v0 and f = softplus(o)/ln 2
+// (o = 0 is the homogeneous medium of Sec. 2.1); dT/dx = f (x - s)/(v0 |x - s|)
+// + T0 sigmoid(o)/ln 2 do/dx, with do/dx = do/du_src / h.
+#pragma once
+#include "net_rows.h"
+
+namespace spider {
+
+constexpr double kLn2 = 0.69314718055994530941723212145818;
+
+__device__ inline void assemble_tt(const NetView& net, const double x[3], const double s[3],
+                                   const RowOut& no, double& T, double g[3]) {
+  const double d0 = x[0] - s[0], d1 = x[1] - s[1], d2 = x[2] - s[2];
+  const double dist = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+  const double T0 = dist / net.v0;
+  const double o = (double)no.o;
+  const double sp = fmax(o, 0.0) + log1p(exp(-fabs(o)));                          // softplus
+  const double sg = o >= 0.0 ? 1.0 / (1.0 + exp(-o)) : exp(o) / (1.0 + exp(o));  // sigmoid
+  const double f = sp / kLn2;
+  T = T0 * f;
+  const double a = f / (net.v0 * dist);
+  const double bsc = T0 * sg / kLn2;
+  g[0] = a * d0 + bsc * ((double)no.d0 * net.inv_half[0]);
+  g[1] = a * d1 + bsc * ((double)no.d1 * net.inv_half[1]);
+  g[2] = a * d2 + bsc * ((double)no.d2 * net.inv_half[2]);
+}
+
+}  // namespace spider

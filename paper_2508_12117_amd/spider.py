@@ -95,6 +95,7 @@ _SIGS = {
     "spider_noise": ([_P, ct.c_int32, ct.c_uint64, ct.c_int32, ct.c_int64, _P], ct.c_int),
     "spider_reset_chains": ([_P, ct.c_int32, ct.c_int32], ct.c_int),
     "spider_sgld_steps": ([_P, ct.POINTER(ChainSet), ct.c_int32, ct.POINTER(SgldCfg)], ct.c_int),
+    "spider_set_graphs": ([_P, ct.c_int], ct.c_int),
     "spider_map_steps": ([_P, ct.POINTER(ChainSet), ct.c_int32, ct.POINTER(MapCfg)], ct.c_int),
     "spider_outliers": ([_P, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_double, _P,
                          ct.POINTER(ct.c_int64), ct.POINTER(ct.c_double), ct.POINTER(ct.c_double)],
@@ -329,6 +330,11 @@ class Context:
                       burn_in=burn_in, thin=thin, seed=seed,
                       noise_scale_end=noise_scale_end if ramp else 0.0)
         self._check(lib().spider_sgld_steps(self._h, arr, len(sets), ct.byref(cfg)))
+
+    def set_graphs(self, enable: bool):
+        """Replay sampler steps from a captured HIP graph (default) or launch
+        every step on the stream."""
+        self._check(lib().spider_set_graphs(self._h, 1 if enable else 0))
 
     def map_steps(self, sets, n_steps, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, seed=0):
         """Stage 1: Adam on the minibatch L1 loss of the dd residuals, no priors.
