@@ -32,12 +32,16 @@ HBM_PEAK = 8000.0                             # GB/s
 NETWORK_TRAFFIC = {
     "kernel_sources": ["paper_2508_12117_amd/csrc/mlp_mfma.h", "paper_2508_12117_amd/csrc/mlp_pp.h",
                        "paper_2508_12117_amd/csrc/net_rows.h"],
-    "sha256": "1c88f808c37dd726b298b5fab521402efaa847f077beb951117d4de7ea615ad3",
-    "variant": {"waves": 8, "row_tiles": 4, "schedule": 1},
+    "sha256": "f1da3c6efa44228aef2fe5c48c9c6304eb16eea8ef8d8643d8371558b5675613",
+    "variant": {"waves": 8, "row_tiles": 4, "schedule": 2},
     "rows": 16777216,
-    "fetch_bytes": 229275776,
+    "fetch_bytes": 229268608,
     "write_bytes": 268435456,
 }
+
+
+SCHEDULES = {0: "barrier per layer", 1: "row-half ping-pong",
+             2: "row-half ping-pong, 1.5-layer weight ring"}
 
 
 def network_traffic(rows, variant):
@@ -353,7 +357,7 @@ def main():
                       ms_per_step_stream=wall_stream * 1e3 / args.steps, net_ms=ms,
                       net_launches=launches, net_avg_ms=avg_ms, achieved=achieved, traffic=traffic,
                       variant={"waves_per_workgroup": waves, "rows_per_workgroup": 16 * tiles,
-                               "schedule": ["barrier per layer", "row-half ping-pong"][sched]},
+                               "schedule": SCHEDULES.get(sched, str(sched))},
                       error=sample_error(ctx, spider, cat, net, nid, code))
         log(f"{p}: {dd / wall:.4g} dd-obs/s, {wall * 1e3 / args.steps:.2f} ms/step, network "
             f"{avg_ms:.3f} ms/launch = {achieved:.2f} TFLOP/s, tiles {waves} waves x {16 * tiles} rows")

@@ -13,9 +13,12 @@ using mfma::PolBF16;
 // shallower weight prefetch ring
 #define SPIDER_VP(H, D, NW, RT, PF) \
   MlpVariant { NW, RT, 0, &launch_variant<PolBF16, H, D, NW, RT, PF, 1> }
-// row halves in ping-pong
+// row halves in ping-pong, weight ring of one layer (schedule 1) or one and
+// a half layers (schedule 2)
 #define SPIDER_PP(H, D, NW, RT) \
-  MlpVariant { NW, RT, 1, &mfma::launch_pp<PolBF16, H, D, NW, RT> }
+  MlpVariant { NW, RT, 1, &mfma::launch_pp<PolBF16, H, D, NW, RT, H / 32> }
+#define SPIDER_PP3(H, D, NW, RT) \
+  MlpVariant { NW, RT, 2, &mfma::launch_pp<PolBF16, H, D, NW, RT, 3 * H / 64> }
 
 int mlp_variants_bf16(int H, int D, const MlpVariant** list) {
   static const MlpVariant h32d2[] = {SPIDER_V(32, 2, 2, 4)};
@@ -30,7 +33,8 @@ int mlp_variants_bf16(int H, int D, const MlpVariant** list) {
   static const MlpVariant h256d4[] = {SPIDER_V(256, 4, 8, 4), SPIDER_PP(256, 4, 8, 4)};
   static const MlpVariant h256d5[] = {SPIDER_V(256, 5, 8, 4), SPIDER_PP(256, 5, 8, 4)};
   static const MlpVariant h256d6[] = {SPIDER_V(256, 6, 8, 4), SPIDER_PP(256, 6, 8, 4),
-                                      SPIDER_V(256, 6, 8, 2), SPIDER_VP(256, 6, 8, 4, 2)};
+                                      SPIDER_V(256, 6, 8, 2), SPIDER_VP(256, 6, 8, 4, 2),
+                                      SPIDER_PP3(256, 6, 8, 4)};
   static const MlpVariant h256d7[] = {SPIDER_V(256, 7, 8, 4), SPIDER_PP(256, 7, 8, 4)};
   // eight layers: the 64-row tiles spill registers (seven stored derivative
   // layers); the 32-row ping-pong and the shallower ring do not

@@ -274,13 +274,19 @@ struct WSrc {
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // The pack of `layers` hidden layers at p as a buffer resource.
+// The resource covers the wave's own column tiles only: it starts at tile
+// wave_tile0 (tiles of NQ 1 KB chunks), so that every operand offset below
+// is a compile-time constant.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t pack_rsrc(const void* p, int layers,
-                                                           int layer_bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, layers * layer_bytes,
-                                           0x00020000);
+                                                           int layer_bytes, int wave_tile0,
+                                                           int NQ) {
+  const int skip = wave_tile0 * NQ * 1024;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>((const char*)p + skip), 0,
+                                           layers * layer_bytes - skip, 0x00020000);
 }
 
-// Chunk `chunk` (tile-major index: tile * NQ + chunk within the tile) of a
+// Chunk `chunk` (index ct * NQ + position within the wave's tile ct; the
+// packing stores a tile's chunks in the order the kernels use them) of a
 // layer, this lane's 16 bytes (voff = 16 lane).
 __device__ __forceinline__ uint4 wload(const WSrc& s, int chunk, int voff) {
   const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(s.rsrc, voff, s.off + chunk * 1024, 0);
@@ -292,26 +298,26 @@ __device__ __forceinline__ uint4 wload(const WSrc& s, int chunk, int voff) {
 // around, so that a wave can begin with the chunk it produced itself; the
 // order depends on the neuron only, so every tile variant adds in the same
 // order (waves own at most one 32-neuron block: CT <= 2).  FP32 products add
-// chunks in index order.
+// chunks in index order.  The packs store each column tile's chunks in this
+// order (tile_chunk_start).
+__host__ __device__ constexpr int tile_chunk_start(bool bf16, int tile, int NQ) {
+  return bf16 ? (tile / 2) & (NQ - 1) : 0;
+}
 template <class P, int CT>
 __device__ __forceinline__ int chunk_start(int wave, int NQ) {
-  if constexpr (P::kBF16) {
-    static_assert(CT <= 2, "a wave's neurons lie in one 32-neuron block");
-    return ((wave * CT) / 2) & (NQ - 1);
-  } else {
-    return 0;
-  }
+  static_assert(!P::kBF16 || CT <= 2, "a wave's neurons lie in one 32-neuron block");
+  return tile_chunk_start(P::kBF16, wave * CT, NQ);
 }
 
-// Prefetch ring slots j = 0 .. PF-1 with chunks s0 + j (mod NQ) of pl.
-template <int NQ, int PF, int CT>
-__device__ __forceinline__ void ring_prime(WRing<PF, CT>& r, const WSrc& pl, int wave, int voff,
-                                           int s0) {
+// Prefetch ring slots j = 0 .. PF-1 with the first PF chunks (in the order
+// of use) of pl.
+template <int NQ, int PF, int CT, int SLOTS>
+__device__ __forceinline__ void ring_prime(WRing<SLOTS, CT>& r, const WSrc& pl, int voff) {
+  static_assert(PF <= SLOTS, "ring too small");
 #pragma unroll
   for (int j = 0; j < PF; ++j)
 #pragma unroll
-    for (int ct = 0; ct < CT; ++ct)
-      r.w[j][ct].u = wload(pl, (wave * CT + ct) * NQ + ((s0 + j) & (NQ - 1)), voff);
+    for (int ct = 0; ct < CT; ++ct) r.w[j][ct].u = wload(pl, ct * NQ + j, voff);
 }
 
 // acc[rt][ct] += W[neuron tile wave*CT + ct][k] . X[16 rt + row][k] over the
@@ -325,9 +331,8 @@ __device__ __forceinline__ void ring_prime(WRing<PF, CT>& r, const WSrc& pl, int
 // chunks in flight.
 template <class P, int RT, int CT, int NQ, int LDW, int SWM, int PF>
 __device__ __forceinline__ void layer_mma(const typename P::T* X, const WSrc& pl,
-                                          const WSrc& pl_next, WRing<PF, CT>& ring, int wave,
-                                          int voff, int c, int g, int s0,
-                                          floatx4 (&acc)[RT][CT]) {
+                                          const WSrc& pl_next, WRing<PF, CT>& ring, int voff,
+                                          int c, int g, int s0, floatx4 (&acc)[RT][CT]) {
   constexpr int ELEMS = Chunk<P>::ELEMS, SPC = Chunk<P>::SPC;
   static_assert(NQ % PF == 0, "chunks must split evenly over the prefetch ring");
   static_assert(PF % 2 == 0 || PF == NQ, "the B double buffer alternates with the chunk parity");
@@ -365,9 +370,9 @@ __device__ __forceinline__ void layer_mma(const typename P::T* X, const WSrc& pl
           }
       const bool here = q + PF < NQ;
       const WSrc src = here ? pl : pl_next;
-      const int qc = (s0 + q + PF) & (NQ - 1);
+      const int qc = (q + PF) & (NQ - 1);  // position in the order of use
 #pragma unroll
-      for (int ct = 0; ct < CT; ++ct) ring.w[j][ct].u = wload(src, (wave * CT + ct) * NQ + qc, voff);
+      for (int ct = 0; ct < CT; ++ct) ring.w[j][ct].u = wload(src, ct * NQ + qc, voff);
       // keep the refill here, right after the MFMAs that free the slot
       __builtin_amdgcn_sched_barrier(0);
     }
@@ -408,13 +413,13 @@ __global__ __launch_bounds__(NW * 64, MINB) void k_mlp(RowSource src, NetView ne
   // layers D-1 .. 1; the ring starts filling now, under the first layer
   constexpr int LBYTES = (H / 16) * NQ * 64 * 16;  // bytes per packed layer
   constexpr int NLAY = D > 1 ? D - 1 : 1;
-  const __amdgpu_buffer_rsrc_t packf = pack_rsrc(net.pack_fwd, NLAY, LBYTES);
-  const __amdgpu_buffer_rsrc_t packb = pack_rsrc(net.pack_bwd, NLAY, LBYTES);
+  const __amdgpu_buffer_rsrc_t packf = pack_rsrc(net.pack_fwd, NLAY, LBYTES, wave * CT, NQ);
+  const __amdgpu_buffer_rsrc_t packb = pack_rsrc(net.pack_bwd, NLAY, LBYTES, wave * CT, NQ);
   const int voff = lane * 16;
   constexpr int PFR = NQ < PF ? NQ : PF;
   WRing<PFR, CT> ring;
   const int s0 = chunk_start<P, CT>(wave, NQ);
-  if (D > 1) ring_prime<NQ, PFR, CT>(ring, WSrc{packf, 0}, wave, voff, s0);
+  if (D > 1) ring_prime<NQ, PFR, CT>(ring, WSrc{packf, 0}, voff);
   // first-layer and output weights of the wave's neurons, loaded before the
   // row inputs so that both latencies overlap
   float w1[CT][2], b1[CT][4], wo[CT][4];
@@ -501,7 +506,7 @@ __global__ __launch_bounds__(NW * 64, MINB) void k_mlp(RowSource src, NetView ne
     }
     const WSrc pl{packf, (l - 1) * LBYTES};
     const WSrc pn = l < D - 1 ? WSrc{packf, l * LBYTES} : WSrc{packb, (D - 2) * LBYTES};
-    layer_mma<P, RT, CT, NQ, LDW, SWM, PFR>(in, pl, pn, ring, wave, voff, c, g, s0, acc);
+    layer_mma<P, RT, CT, NQ, LDW, SWM, PFR>(in, pl, pn, ring, voff, c, g, s0, acc);
     if constexpr (NBUF == 1) __syncthreads();  // every wave done reading `in`
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
@@ -574,7 +579,7 @@ __global__ __launch_bounds__(NW * 64, MINB) void k_mlp(RowSource src, NetView ne
           for (int a = 0; a < 3; ++a) wg[ct][i][a] = net.W0[(n0 + i) * 6 + a];
       }
     }
-    layer_mma<P, RT, CT, NQ, LDW, SWM, PFR>(eb, pl, pn, ring, wave, voff, c, g, s0, acc);
+    layer_mma<P, RT, CT, NQ, LDW, SWM, PFR>(eb, pl, pn, ring, voff, c, g, s0, acc);
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
@@ -654,12 +659,13 @@ void pack_layer(int H, const float* W, double fscale, unsigned char* fwd, unsign
   const int NQ = chunks_per_layer<P>(H);
   const size_t esz = sizeof(T);
   for (int ct = 0; ct < H / 16; ++ct)
-    for (int q = 0; q < NQ; ++q)
+    for (int pos = 0; pos < NQ; ++pos)  // position pos holds the chunk used pos-th
       for (int lane = 0; lane < 64; ++lane)
         for (int e = 0; e < ELEMS; ++e) {
+          const int q = (tile_chunk_start(P::kBF16, ct, NQ) + pos) & (NQ - 1);
           const int n = ct * 16 + (lane & 15);
           const int k = (4 * q + (lane >> 4)) * ELEMS + e;
-          const size_t off = ((((size_t)ct * NQ + q) * 64 + lane) * ELEMS + e) * esz;
+          const size_t off = ((((size_t)ct * NQ + pos) * 64 + lane) * ELEMS + e) * esz;
           // forward: A[n][k] = W[n][k]; backward: A[n][k] = W[k][n]
           const float vf = (float)(fscale * (double)W[(size_t)n * H + k]);
           const float vb = W[(size_t)k * H + n];

@@ -15,8 +15,9 @@
 // phase read the other half: one activation buffer serves the whole pass.
 //
 // Weights.  The ring holds all chunks of the current layer's operands (both
-// halves use them); job ..B refills each chunk, as it frees it, with the next
-// layer's chunk, so the next layer's operands stream in one phase ahead.
+// halves use them).  With one layer of slots, job ..B refills each chunk, as
+// it frees it, with the next layer's chunk; with one and a half layers, the
+// next layer's operands stream in during both jobs (see mma_half).
 #pragma once
 #include "mlp_mfma.h"
 
@@ -49,16 +50,35 @@ struct ShapePP {
   static_assert(ACT_BYTES + FIXED_BYTES + NLDS * LAYER_BYTES <= 160 * 1024, "LDS budget");
 };
 
-// The layer product of row half h (rows 16 (h RH + i) + c) over all NQ chunks
-// of the ring, slot q holding chunk s0 + q (mod NQ).  With REFILL, slot q is
-// replaced after its MFMAs by the same chunk of the next layer's stream
-// `refill`.  work(q) runs after the MFMAs of slot q: the interleaved epilogue
-// of the other half.
-template <class P, int h, int RT, int CT, int NQ, int LDW, int SWM, bool REFILL, class F>
-__device__ __forceinline__ void mma_half(const typename P::T* X, WRing<NQ, CT>& ring,
-                                         const WSrc& refill, int wave, int voff, int c, int g,
-                                         int s0, floatx4 (&acc)[RT][CT], F&& work) {
-  constexpr int RH = RT / 2, ELEMS = Chunk<P>::ELEMS;
+// Weight ring of NS slots.  With NS = NQ (one layer), slot q holds the chunk
+// of step q and half B refills it with the next layer product's chunk right
+// after reading it: a whole layer's loads in every second phase.  With
+// NS = 3 NQ / 2, three slot groups of NQ/2 chunks: layer product j (the j-th
+// job pair of the schedule: forward layers, then backward layers) reads its
+// chunks q < NQ/2 from group first(j) and the others from group second(j);
+// the third group, spare(j), is free.  While job j's half A runs, the next
+// product's chunks q < NQ/2 stream into spare(j); while half B runs, its
+// chunks q >= NQ/2 stream into first(j), each slot refilled once half B has
+// read it.  So first(j+1) = spare(j), second(j+1) = first(j) and
+// spare(j+1) = second(j): the roles rotate with period three, and every phase
+// issues the same number of weight loads.
+__device__ __forceinline__ constexpr int ring_first(int j) { return (3 - j % 3) % 3; }
+__device__ __forceinline__ constexpr int ring_slot(int j, int q, int NQ, int NS) {
+  return NS == NQ ? q : ((ring_first(j) + (q < NQ / 2 ? 0 : 1)) % 3) * (NQ / 2) + q % (NQ / 2);
+}
+
+// The layer product of row half h (rows 16 (h RH + i) + c) of layer product
+// j over all NQ chunks, chunk s0 + q (mod NQ) at step q, its operands in ring
+// slot ring_slot(j, q).  LOADS = 1 (half A) or 2 (half B) streams the next
+// layer product's operands from `next` as described above; 0 loads nothing.
+// work(q) runs after the MFMAs of step q: the interleaved epilogue of the
+// other half.
+template <class P, int h, int RT, int CT, int NQ, int LDW, int SWM, int LOADS, int NS, class F>
+__device__ __forceinline__ void mma_half(const typename P::T* X, WRing<NS, CT>& ring, int j,
+                                         const WSrc& next, int voff, int c, int g, int s0,
+                                         floatx4 (&acc)[RT][CT], F&& work) {
+  static_assert(NS == NQ || NS == 3 * NQ / 2, "ring of one or one and a half layers");
+  constexpr int RH = RT / 2, ELEMS = Chunk<P>::ELEMS, HQ = NQ / 2, ITEMS = HQ * CT;
   const typename P::T* xr = X + (h * RH * 16 + c) * LDW;
   const int sw = c & SWM;
   Pack16 x[2][RH];
@@ -75,15 +95,27 @@ __device__ __forceinline__ void mma_half(const typename P::T* X, WRing<NQ, CT>& 
             *(const uint4*)(xr + i * 16 * LDW + ((4 * ((s0 + q + 1) & (NQ - 1)) + g) ^ sw) * ELEMS);
     }
     __builtin_amdgcn_sched_barrier(0);
+    const int sq = ring_slot(j, q, NQ, NS);
 #pragma unroll
     for (int i = 0; i < RH; ++i)
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct)
-        acc[h * RH + i][ct] = P::mma(ring.w[q][ct].b, x[b][i].b, acc[h * RH + i][ct]);
-    if constexpr (REFILL) {
+        acc[h * RH + i][ct] = P::mma(ring.w[sq][ct].b, x[b][i].b, acc[h * RH + i][ct]);
+    if constexpr (NS == NQ) {
+      if constexpr (LOADS == 2) {
 #pragma unroll
-      for (int ct = 0; ct < CT; ++ct)
-        ring.w[q][ct].u = wload(refill, (wave * CT + ct) * NQ + ((s0 + q) & (NQ - 1)), voff);
+        for (int ct = 0; ct < CT; ++ct) ring.w[q][ct].u = wload(next, ct * NQ + q, voff);
+      }
+    } else if constexpr (LOADS != 0) {
+      // the ITEMS loads of this phase, spread evenly over its NQ steps: item
+      // it = (chunk q' - base, tile ct) at step 2 it / CT; in half B the
+      // slot of step q' - HQ has been read by then (q' - HQ <= step)
+#pragma unroll
+      for (int it = 0; it < ITEMS; ++it) {
+        if (it * 2 / CT != q) continue;
+        const int qn = (LOADS == 1 ? 0 : HQ) + it / CT, ct = it % CT;
+        ring.w[ring_slot(j + 1, qn, NQ, NS)][ct].u = wload(next, ct * NQ + qn, voff);
+      }
     }
     work(q);
     __builtin_amdgcn_sched_barrier(0);
@@ -98,7 +130,7 @@ __device__ __forceinline__ void spread(int q, E&& epi) {
     if (f >= (q * NF) / NQ && f < ((q + 1) * NF) / NQ) epi(f);
 }
 
-template <class P, int H, int D, int NW, int RT_>
+template <class P, int H, int D, int NW, int RT_, int NS>
 __global__ __launch_bounds__(NW * 64, 1) void k_mlp_pp(RowSource src, NetView net, RowOut* out) {
   static_assert(P::kBF16, "the ping-pong kernel is BF16 only");
   using S = ShapePP<P, H, D, NW, RT_>;
@@ -122,12 +154,13 @@ __global__ __launch_bounds__(NW * 64, 1) void k_mlp_pp(RowSource src, NetView ne
   const int g = lane >> 4;
   const int64_t row0 = (int64_t)blockIdx.x * R;
 
-  const __amdgpu_buffer_rsrc_t packf = pack_rsrc(net.pack_fwd, D - 1, LBYTES);
-  const __amdgpu_buffer_rsrc_t packb = pack_rsrc(net.pack_bwd, D - 1, LBYTES);
+  const __amdgpu_buffer_rsrc_t packf = pack_rsrc(net.pack_fwd, D - 1, LBYTES, wave * CT, NQ);
+  const __amdgpu_buffer_rsrc_t packb = pack_rsrc(net.pack_bwd, D - 1, LBYTES, wave * CT, NQ);
   const int voff = lane * 16;
-  WRing<NQ, CT> ring;
+  WRing<NS, CT> ring;
   const int s0 = chunk_start<P, CT>(wave, NQ);
-  ring_prime<NQ, NQ, CT>(ring, WSrc{packf, 0}, wave, voff, s0);
+  // layer product 0 in slots 0 .. NQ-1 (groups first(0) = 0, second(0) = 1)
+  ring_prime<NQ, NQ, CT>(ring, WSrc{packf, 0}, voff);
   float w1[CT][2], b1[CT][4], wo[CT][4];
 #pragma unroll
   for (int ct = 0; ct < CT; ++ct) {
@@ -241,52 +274,52 @@ __global__ __launch_bounds__(NW * 64, 1) void k_mlp_pp(RowSource src, NetView ne
   for (int f = 0; f < NF; ++f) first_layer(0, f);
   __syncthreads();
 
-  // ---- forward hidden layers
+  // ---- forward hidden layers (layer products j = l - 1)
 #pragma unroll
   for (int l = 1; l < D; ++l) {
-    const WSrc pl{packf, (l - 1) * LBYTES};
+    const int j = l - 1;
+    // the next layer product: forward layer l + 1, or the last backward layer
     const WSrc pn = l < D - 1 ? WSrc{packf, l * LBYTES} : WSrc{packb, (D - 2) * LBYTES};
     // job F(l)A with the epilogue of the previous job (first layer B, or F(l-1)B)
     set_bias(0);
-    mma_half<P, 0, RT, CT, NQ, LDW, SWM, false>(act, ring, pl, wave, voff, c, g, s0, acc, [&](int q) {
+    mma_half<P, 0, RT, CT, NQ, LDW, SWM, 1, NS>(act, ring, j, pn, voff, c, g, s0, acc, [&](int q) {
       spread<NQ, NF>(q, [&](int f) {
         if (l == 1) first_layer(1, f);
         else fwd_epi(l - 1, 1, f);
       });
     });
     __syncthreads();
-    // job F(l)B with the epilogue of F(l)A; the ring refills with the next layer
+    // job F(l)B with the epilogue of F(l)A
     set_bias(1);
     if (l + 1 < D) load_bias(l + 1);
-    mma_half<P, 1, RT, CT, NQ, LDW, SWM, true>(act, ring, pn, wave, voff, c, g, s0, acc, [&](int q) {
+    mma_half<P, 1, RT, CT, NQ, LDW, SWM, 2, NS>(act, ring, j, pn, voff, c, g, s0, acc, [&](int q) {
       spread<NQ, NF>(q, [&](int f) { fwd_epi(l, 0, f); });
     });
     __syncthreads();
   }
 
-  // ---- backward layers D-1 .. 1
+  // ---- backward layers D-1 .. 1 (layer products j = 2 D - 2 - l)
 #pragma unroll
   for (int l = D - 1; l >= 1; --l) {
-    const WSrc pl{packb, (l - 1) * LBYTES};
-    const WSrc pn = l > 1 ? WSrc{packb, (l - 2) * LBYTES} : pl;
+    const int j = 2 * D - 2 - l;
+    const WSrc pn{packb, (l > 1 ? l - 2 : 0) * LBYTES};
     set_zero(0);
-    mma_half<P, 0, RT, CT, NQ, LDW, SWM, false>(act, ring, pl, wave, voff, c, g, s0, acc, [&](int q) {
+    auto epi_a = [&](int q) {
       spread<NQ, NF>(q, [&](int f) {
         if (l == D - 1) fwd_epi(D - 1, 1, f);
         else bwd_epi(l + 1, 1, f);
       });
-    });
+    };
+    if (l > 1) mma_half<P, 0, RT, CT, NQ, LDW, SWM, 1, NS>(act, ring, j, pn, voff, c, g, s0, acc, epi_a);
+    else mma_half<P, 0, RT, CT, NQ, LDW, SWM, 0, NS>(act, ring, j, pn, voff, c, g, s0, acc, epi_a);
     __syncthreads();
     set_zero(1);
+    auto epi_b = [&](int q) { spread<NQ, NF>(q, [&](int f) { bwd_epi(l, 0, f); }); };
     if (l > 1) {
-      mma_half<P, 1, RT, CT, NQ, LDW, SWM, true>(act, ring, pn, wave, voff, c, g, s0, acc, [&](int q) {
-        spread<NQ, NF>(q, [&](int f) { bwd_epi(l, 0, f); });
-      });
+      mma_half<P, 1, RT, CT, NQ, LDW, SWM, 2, NS>(act, ring, j, pn, voff, c, g, s0, acc, epi_b);
       __syncthreads();
     } else {
-      mma_half<P, 1, RT, CT, NQ, LDW, SWM, false>(act, ring, pn, wave, voff, c, g, s0, acc, [&](int q) {
-        spread<NQ, NF>(q, [&](int f) { bwd_epi(1, 0, f); });
-      });
+      mma_half<P, 1, RT, CT, NQ, LDW, SWM, 0, NS>(act, ring, j, pn, voff, c, g, s0, acc, epi_b);
     }
   }
   // ---- epilogue of B1B
@@ -338,12 +371,13 @@ __global__ __launch_bounds__(NW * 64, 1) void k_mlp_pp(RowSource src, NetView ne
   }
 }
 
-template <class P, int H, int D, int NW, int RT>
+// NS: weight ring slots, NQ (one layer) or 3 NQ / 2
+template <class P, int H, int D, int NW, int RT, int NS>
 hipError_t launch_pp(const RowSource& src, const NetView& net, RowOut* out, hipStream_t s) {
   using Sh = ShapePP<P, H, D, NW, RT>;
   const int64_t blocks = ceil_div(src.rows, Sh::R);
-  hipLaunchKernelGGL((k_mlp_pp<P, H, D, NW, RT>), dim3((unsigned)blocks), dim3(NW * 64), 0, s, src,
-                     net, out);
+  hipLaunchKernelGGL((k_mlp_pp<P, H, D, NW, RT, NS>), dim3((unsigned)blocks), dim3(NW * 64), 0, s,
+                     src, net, out);
   return hipGetLastError();
 }
 

@@ -29,8 +29,6 @@ struct RowSource {
   const double* x;
   const double* s;
   const int32_t* list;  // mode 3: row r of the launch is catalog row list[r]
-  double4* xt;          // modes 0, 3 (may be null): receives each row's event state
-                        // (x, y, z, t), which the residual kernel reads in row order
 };
 
 // Network as the kernels see it (device pointers).
@@ -83,7 +81,6 @@ __device__ inline void row_inputs(const RowSource& src_in, const NetView& net, i
     x[1] = e.y;
     x[2] = e.z;
     for (int a = 0; a < 3; ++a) s[a] = st[a];
-    if (src.xt) src.xt[r] = e;
   } else {
     for (int a = 0; a < 3; ++a) {
       x[a] = src.x[r * 3 + a];

@@ -792,18 +792,21 @@ def test_bf16_sampler_runs_and_is_deterministic(ctx, tiny_setup):
     assert np.abs(outs[0] - cat.hypo0).max() > 0
 
 
+@pytest.mark.parametrize("rows", [3001, 70001])
 @pytest.mark.parametrize("H,D", [(256, 6), (128, 4), (256, 8), (256, 4)])
 @pytest.mark.parametrize("prec", [spider.BF16, spider.FP32])
-def test_kernel_variants_agree_bitwise(ctx, monkeypatch, H, D, prec):
-    """Every tile variant the autotuner may pick computes the same bits."""
+def test_kernel_variants_agree_bitwise(ctx, monkeypatch, H, D, prec, rows):
+    """Every tile variant the autotuner may pick computes the same bits; with
+    70,001 rows (1,094 blocks of 64 rows, the last one ragged) each workgroup
+    of the persistent kernels runs several row blocks."""
     net = synth.make_net(H, D, center=[5.0, 5.0, 4.0], half_extent=[10.0, 10.0, 6.0], seed=3)
     nid = ctx.load_net(net)
-    x, s = _points(3001, 9)
+    x, s = _points(rows, 9)
     outs, shapes = [], []
     for k in range(6):  # indices past the list pick variant 0
         monkeypatch.setenv("SPIDER_MLP_VARIANT", str(k))
-        T = torch.empty(3001, dtype=torch.float64, device="cuda")
-        g = torch.empty(3001, 3, dtype=torch.float64, device="cuda")
+        T = torch.empty(rows, dtype=torch.float64, device="cuda")
+        g = torch.empty(rows, 3, dtype=torch.float64, device="cuda")
         ctx.travel_time(nid, dev(x), dev(s), T, g, precision=prec)
         outs.append((host(T), host(g)))
         shapes.append(ctx.network_variant(nid, prec))
