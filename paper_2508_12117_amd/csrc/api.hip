@@ -130,16 +130,17 @@ struct Net {
 // (obs_total slots); the count and system arrays hold each set's keys and
 // systems side by side; the solver scratch holds one set at a time.
 struct Workspace {
-  DevBuf obs, ev, sta, tau, w, rank, start, csr, ckey, pos, pev, pgr, head, nend, rows, net_out,
-      T, gT, r, z, zp, wr;
-  DevBuf act, sys, list, nbr, wgt, vec, ivec, scan_part, long_list, phase_flags, n_p;
+  DevBuf obs, ev, sta, tau, w, start, csr, ckey, pos, pev, pgr, head, nend, rows, net_out, T, gT,
+      r, z, zp, wr;
+  DevBuf act, sys, list, nbr, wgt, vec, ivec, scan_part, bucket, phase_flags, n_p;
   DevBuf G, partial, thetabar, lp_tmp, err;
+  int64_t e_cur = 0;  // entries of the last reserve: the layout of ivec
 
   // obs_total: slots of all sets; keys_total: sum of (C M + 1); sys_total:
   // the largest set's system-list counts (C L nb + 1); C, CM: the largest
-  // set's chains and C M
+  // set's chains and C M; bucket_words: the largest set's CSR-build buckets
   hipError_t reserve(int64_t C, int64_t obs_total, int64_t keys_total, int64_t sys_total,
-                     int64_t CM) {
+                     int64_t CM, int64_t bucket_words) {
     const int64_t Cn = obs_total, E = 2 * obs_total;
     hipError_t e;
 #define RES(buf, bytes)                                     \
@@ -149,7 +150,6 @@ struct Workspace {
     RES(sta, E * 4);
     RES(tau, Cn * 8);
     RES(w, Cn * 8);
-    RES(rank, E * 4);
     RES(start, keys_total * 4);
     RES(csr, E * 4);
     RES(ckey, E * 8);
@@ -172,12 +172,14 @@ struct Workspace {
     RES(nbr, E * 4);
     RES(wgt, E * 8);
     RES(vec, E * 8 * 7);
-    RES(ivec, E * 4 * 5);
+    RES(ivec, E * 4 * 6 + sys_total * 4);
+    e_cur = E;
     int64_t sp = scan_part_size(E + 1);
     if (scan_part_size(keys_total) > sp) sp = scan_part_size(keys_total);
     if (scan_part_size(sys_total) > sp) sp = scan_part_size(sys_total);
+    if (scan_part_size(bucket_words) > sp) sp = scan_part_size(bucket_words);
     RES(scan_part, sp * 4);
-    RES(long_list, (keys_total + 1) * 4);
+    RES(bucket, bucket_words * 4);
     RES(phase_flags, (E + 1) * 4);
     RES(n_p, 16);
     RES(G, CM * 32);
@@ -196,7 +198,6 @@ struct Workspace {
     b.sta = sta.as<int32_t>();
     b.tau = tau.as<double>();
     b.w = w.as<double>();
-    b.rank = rank.as<int32_t>();
     b.start = start.as<int32_t>();
     b.csr = csr.as<int32_t>();
     b.ckey = ckey.as<uint64_t>();
@@ -224,6 +225,8 @@ struct Workspace {
     v.wgt = wgt.as<double>();
     v.vec = vec.as<double>();
     v.ivec = ivec.as<int32_t>();
+    v.lidx = ivec.as<int32_t>() + 5 * e_cur;
+    v.spill = ivec.as<int32_t>() + 6 * e_cur;
     v.scan_part = scan_part.as<int32_t>();
     return v;
   }
@@ -440,7 +443,6 @@ BatchBufs batch_at(const BatchBufs& b, int64_t obs_off, int64_t key_off) {
   o.wr += obs_off;
   o.ev += 2 * obs_off;
   o.sta += 2 * obs_off;
-  o.rank += 2 * obs_off;
   o.csr += 2 * obs_off;
   o.ckey += 2 * obs_off;
   o.pos += 2 * obs_off;
@@ -463,10 +465,9 @@ void pre_network(spider_ctx* ctx, const Catalog& cat, int C, int64_t n, const in
                  const BatchBufs& b) {
   Workspace& ws = ctx->ws;
   const CatView cv = cat.view();
-  launch_clear_counts(b, (int64_t)C * cat.M, ctx->stream);
   launch_select(cv, C, n, idx, seed, steps_dev, step_scalar, chain0, b, ws.err.as<int>(),
                 ctx->stream);
-  launch_build_csr(cv, C, n, b, ws.scan_part.as<int32_t>(), ws.long_list.as<int32_t>(),
+  launch_build_csr(cv, C, n, b, ws.bucket.as<int32_t>(), ws.scan_part.as<int32_t>(),
                    ctx->stream);
 }
 
@@ -516,8 +517,11 @@ int run_batch(spider_ctx* ctx, Catalog& cat, Net& net, int prec, int C, int64_t 
               bool l1 = false) {
   Workspace& ws = ctx->ws;
   const int64_t Cn = (int64_t)C * n, E = 2 * Cn;
+  const BucketShape bs = bucket_shape(C, n, cat.M);
+  if (!bs.ok) return fail(ctx, SPIDER_E_UNSUPPORTED, "chains x events too large for the CSR build");
   HIPCK(ws.reserve(C, Cn, (int64_t)C * cat.M + 1,
-                   (int64_t)C * cat.L * list_blocks(C, n, cat.L) + 1, (int64_t)C * cat.M),
+                   (int64_t)C * cat.L * list_blocks(C, n, cat.L) + 1, (int64_t)C * cat.M,
+                   bs.words),
         "workspace");
   const BatchBufs b = ws.batch();
   pre_network(ctx, cat, C, n, idx, seed, steps_dev, step_scalar, chain0, b);
@@ -576,7 +580,7 @@ struct FusedSets {
 };
 
 int prepare_fused(spider_ctx* ctx, const spider_chainset* sets, int n_sets, FusedSets& f) {
-  int64_t maxC = 1, maxCM = 1, maxS = 1;
+  int64_t maxC = 1, maxCM = 1, maxS = 1, maxB = 1;
   f.obs_off.assign(n_sets + 1, 0);
   f.key_off.assign(n_sets + 1, 0);
   for (int k = 0; k < n_sets; ++k) {
@@ -587,10 +591,14 @@ int prepare_fused(spider_ctx* ctx, const spider_chainset* sets, int n_sets, Fuse
     maxC = std::max(maxC, C);
     maxCM = std::max(maxCM, C * cat.M);
     maxS = std::max(maxS, C * cat.L * list_blocks(C, sets[k].batch, cat.L) + 1);
+    const BucketShape bs = bucket_shape(C, sets[k].batch, cat.M);
+    if (!bs.ok)
+      return fail(ctx, SPIDER_E_UNSUPPORTED, "chains x events too large for the CSR build");
+    maxB = std::max(maxB, bs.words);
   }
   f.total_obs = f.obs_off[n_sets];
   Workspace& ws = ctx->ws;
-  HIPCK(ws.reserve(maxC, f.total_obs, f.key_off[n_sets], maxS, maxCM), "workspace");
+  HIPCK(ws.reserve(maxC, f.total_obs, f.key_off[n_sets], maxS, maxCM, maxB), "workspace");
   const BatchBufs b = ws.batch();
   std::vector<RowSource> subs(n_sets);
   std::vector<int64_t> row0(n_sets + 1);
@@ -1234,7 +1242,7 @@ int spider_batch_indices(spider_ctx* ctx, int32_t cat_id, uint64_t seed, int32_t
     return fail(ctx, SPIDER_E_UNSUPPORTED, "minibatch above 2^30 - 1 observations");
   int rc = reset_err_flag(ctx);
   if (rc) return rc;
-  HIPCK(ctx->ws.reserve(1, n, (int64_t)cat->M + 1, 1, cat->M), "workspace");
+  HIPCK(ctx->ws.reserve(1, n, (int64_t)cat->M + 1, 1, cat->M, 1), "workspace");
   BatchBufs b = ctx->ws.batch();
   b.start = nullptr;  // indices only: no (chain, event) counts
   launch_select(cat->view(), 1, n, nullptr, seed, nullptr, step, chain, b, ctx->ws.err.as<int>(),

@@ -21,6 +21,8 @@
 //             (chain, event), in CSR order
 // No floating-point atomics anywhere: every sum runs in a fixed order, so a
 // step is bitwise reproducible.
+#include <cstdlib>
+
 #include "device_rng.h"
 #include "internal.h"
 #include "tt_assemble.h"
@@ -162,88 +164,94 @@ __global__ void k_select(CatView cat, int C, int64_t n, const int64_t* idx, uint
   b.sta[2 * q + 1] = rc.g;
   b.tau[q] = (double)rc.dt;
   b.w[q] = rc.w;
-  // integer counts: the arrival order only decides where an entry is placed
-  // before its segment is sorted (no count array: indices only)
-  if (b.start) {
-    const int64_t kb = (int64_t)c * cat.M;
-    b.rank[2 * q] = atomicAdd(b.start + kb + rc.i, 1);
-    b.rank[2 * q + 1] = atomicAdd(b.start + kb + rc.j, 1);
-  }
 }
 
 // ---------------------------------------------------------------- CSR
 
 // Sort key of an entry inside its event's segment: (group, entry).
-__device__ inline uint64_t canon_key(int32_t g, int32_t e) {
-  return ((uint64_t)(uint32_t)g << 32) | (uint32_t)e;
+// ---------------------------------------------------------------- CSR build
+//
+// The CSR order is unique: chain, then event, then (group, entry) within the
+// event.  Entries are first gathered into buckets of (chain, block of 2^sb
+// consecutive events), bucket-major: a counting pass histograms the buckets
+// in LDS per block of kBucketHB entries, a prefix over those blocks and a scan
+// of the bucket totals give every (bucket, block) its first slot, and a
+// scatter pass appends each entry's record there (LDS atomics decide the
+// order within a block, which the next pass erases).  One workgroup per
+// bucket then orders the bucket in LDS: counting sort by event, each event's
+// segment by (group, entry), and writes the CSR arrays; nothing depends on
+// the arrival order, and no global atomics are used.
+
+constexpr int64_t kBucketHB = 65536;  // entries per counting block (within one chain)
+constexpr int kBucketTB = 1024;       // threads of the counting and scatter blocks
+constexpr int64_t kBucketMax = 16384; // buckets per chain (LDS counters)
+constexpr int kBucketMaxSB = 13;      // at most 8,192 events per bucket
+constexpr int kSortTB = 256;          // threads per bucket
+constexpr int kSegShort = 32;         // event segments up to this length: one thread
+
+// A record: event within its bucket (bits 48..60), group (32..47), entry.
+__device__ inline uint64_t bucket_record(int32_t m_local, int32_t g, int32_t e) {
+  return ((uint64_t)(uint32_t)m_local << 48) | ((uint64_t)(uint32_t)g << 32) | (uint32_t)e;
 }
 
-// Each entry's sort key to its place in its (chain, event) segment.
-__global__ void k_csr_scatter(int64_t E, int64_t n, int M, BatchBufs b) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= E) return;
-  const int64_t c = (e >> 1) / n;
-  b.ckey[b.start[c * M + b.ev[e]] + b.rank[e]] = canon_key(b.sta[e], (int32_t)e);
+// Block (j, c) of the counting and scatter passes: entries [2 n c + j HB,
+// ...) of chain c; its counts at counts[(c hbc + j) nbk + k] for the chain's
+// buckets k.
+__global__ __launch_bounds__(kBucketTB) void k_bucket_count(int64_t n, int sb, int64_t nbk,
+                                                           const int32_t* ev, int32_t* counts) {
+  extern __shared__ int32_t h[];
+  for (int64_t k = threadIdx.x; k < nbk; k += kBucketTB) h[k] = 0;
+  __syncthreads();
+  const int64_t c = blockIdx.y;
+  const int64_t e0 = 2 * n * c + (int64_t)blockIdx.x * kBucketHB;
+  const int64_t e1 = min(2 * n * (c + 1), e0 + kBucketHB);
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += kBucketTB) atomicAdd(&h[ev[e] >> sb], 1);
+  __syncthreads();
+  int32_t* row = counts + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * nbk;
+  for (int64_t k = threadIdx.x; k < nbk; k += kBucketTB) row[k] = h[k];
 }
 
-// Node bookkeeping of the sorted segment of event m, [p0, p0 + len), whose
-// sort keys are key(i): event and group of every position, head[p] = first
-// position of p's node (same group), nend at that first position, and
-// pos[e] with the single-entry bit.
-template <class Key>
-__device__ inline void mark_nodes(BatchBufs& b, int32_t p0, int32_t len, int32_t m, Key&& key) {
-  int32_t run0 = 0;
-  for (int32_t i = 0; i < len; ++i) {
-    const uint64_t ki = key(i);
-    const uint32_t gi = (uint32_t)(ki >> 32);
-    if (i > 0 && (uint32_t)(key(i - 1) >> 32) != gi) run0 = i;
-    const bool last = i == len - 1 || (uint32_t)(key(i + 1) >> 32) != gi;
-    b.pev[p0 + i] = m;
-    b.pgr[p0 + i] = (int32_t)gi;
-    b.head[p0 + i] = p0 + run0;
-    if (last) b.nend[p0 + run0] = p0 + i + 1;
-    const bool single = last && run0 == i;
-    b.pos[(int32_t)(uint32_t)ki] = (p0 + i) | (single ? kSingle : 0);
+// Per bucket (chain c, block k of events): the counts of the chain's
+// counting blocks become offsets within the bucket (in block order) and the
+// bucket total goes to tot[c nbk + k]; tot[nb] = 0 and start[keys] = E for
+// what follows.
+__global__ void k_bucket_prefix(int64_t nbk, int64_t nb, int64_t hbc, int32_t* counts,
+                                int32_t* tot, int32_t* start, int64_t keys, int64_t E) {
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id == 0) {
+    tot[nb] = 0;
+    start[keys] = (int32_t)E;
+  }
+  if (id >= nb) return;
+  const int64_t c = id / nbk, k = id - c * nbk;
+  int32_t* col = counts + c * hbc * nbk + k;
+  int32_t run = 0;
+  for (int64_t j = 0; j < hbc; ++j) {
+    const int32_t x = col[j * nbk];
+    col[j * nbk] = run;
+    run += x;
+  }
+  tot[id] = run;
+}
+
+__global__ __launch_bounds__(kBucketTB) void k_bucket_scatter(int64_t n, int sb, int64_t nbk,
+                                                             const int32_t* counts,
+                                                             const int32_t* base, BatchBufs b) {
+  extern __shared__ int32_t cur[];
+  const int64_t c = blockIdx.y;
+  const int32_t* row = counts + (c * gridDim.x + blockIdx.x) * nbk;
+  const int32_t* bb = base + c * nbk;
+  for (int64_t k = threadIdx.x; k < nbk; k += kBucketTB) cur[k] = bb[k] + row[k];
+  __syncthreads();
+  const int64_t e0 = 2 * n * c + (int64_t)blockIdx.x * kBucketHB;
+  const int64_t e1 = min(2 * n * (c + 1), e0 + kBucketHB);
+  const int32_t mask = (1 << sb) - 1;
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += kBucketTB) {
+    const int32_t m = b.ev[e];
+    const int32_t slot = atomicAdd(&cur[m >> sb], 1);
+    b.ckey[slot] = bucket_record(m & mask, b.sta[e], (int32_t)e);
   }
 }
-
-constexpr int kCanonTB = 128;
-constexpr int kCanonShort = 32;  // segments up to this length are sorted by one thread in LDS
-
-// One thread per (chain, event) key: its segment sorted by (group, entry)
-// with an insertion sort in LDS (element i of thread t at sh[i][t], so a
-// wave's accesses spread over the banks); longer segments are listed for
-// k_csr_canon_long (slot by atomic count: each is sorted on its own, so the
-// order of the list does not matter).
-__global__ __launch_bounds__(kCanonTB) void k_csr_canon(int64_t K, int M, BatchBufs b,
-                                                        int32_t* long_list, int32_t* long_count) {
-  __shared__ uint64_t sh[kCanonShort][kCanonTB];
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= K) return;
-  const int32_t m = (int32_t)(k % M);
-  const int32_t p0 = b.start[k], p1 = b.start[k + 1];
-  const int32_t len = p1 - p0;
-  if (len <= 0) return;
-  if (len > kCanonShort) {
-    long_list[atomicAdd(long_count, 1)] = (int32_t)k;
-    return;
-  }
-  const int t = threadIdx.x;
-  for (int32_t i = 0; i < len; ++i) {
-    const uint64_t x = b.ckey[p0 + i];
-    int32_t j = i;
-    while (j > 0 && sh[j - 1][t] > x) {
-      sh[j][t] = sh[j - 1][t];
-      --j;
-    }
-    sh[j][t] = x;
-  }
-  for (int32_t i = 0; i < len; ++i) b.csr[p0 + i] = (int32_t)(uint32_t)sh[i][t];
-  mark_nodes(b, p0, len, m, [&](int32_t i) { return sh[i][t]; });
-}
-
-constexpr int kLongTB = 256;
-constexpr int kLongLds = 4096;  // segments up to this length sort in LDS
 
 // Ascending sort network for any length len (positions at or past len act as
 // +infinity, so comparators that touch them are skipped): bitonic stages in
@@ -282,34 +290,131 @@ __device__ void block_sort_any(int32_t len, Get&& get, Put&& put) {
   }
 }
 
-// One workgroup per long segment (grid-stride over the list, so any grid
-// size drains it): sorted in LDS when it fits, else in place in global
-// memory with keys recomputed from the entries.
-__global__ __launch_bounds__(kLongTB) void k_csr_canon_long(const int32_t* long_list,
-                                                            const int32_t* long_count, int M,
-                                                            BatchBufs b) {
-  __shared__ uint64_t sh[kLongLds];
-  const int32_t nlong = *long_count;
-  for (int32_t li = blockIdx.x; li < nlong; li += gridDim.x) {
-    const int64_t k = long_list[li];
-    const int32_t m = (int32_t)(k % M);
-    const int32_t p0 = b.start[k], len = b.start[k + 1] - p0;
-    int32_t* seg = b.csr + p0;
-    uint64_t* keys = b.ckey + p0;
-    if (len <= kLongLds) {
-      for (int32_t i = threadIdx.x; i < len; i += blockDim.x) sh[i] = keys[i];
-      __syncthreads();
-      block_sort_any(len, [&](int32_t i) { return sh[i]; }, [&](int32_t i, uint64_t x) { sh[i] = x; });
-      for (int32_t i = threadIdx.x; i < len; i += blockDim.x) seg[i] = (int32_t)(uint32_t)sh[i];
-      __syncthreads();
-      if (threadIdx.x == 0) mark_nodes(b, p0, len, m, [&](int32_t i) { return sh[i]; });
-    } else {
-      block_sort_any(len, [&](int32_t i) { return keys[i]; },
-                     [&](int32_t i, uint64_t x) { keys[i] = x; });
-      for (int32_t i = threadIdx.x; i < len; i += blockDim.x) seg[i] = (int32_t)(uint32_t)keys[i];
-      if (threadIdx.x == 0) mark_nodes(b, p0, len, m, [&](int32_t i) { return keys[i]; });
+// One workgroup per bucket: the bucket's records in (event, group, entry)
+// order, then per position the entry (csr), its event and group, its node's
+// first position (head) and, at that position, one past the node's last
+// (nend), and pos[e] with the single-entry bit; start[] of the bucket's
+// events.  A bucket of up to cap records (held in registers after one read)
+// is ordered in LDS: when no event holds more than kSegShort of them, by a
+// counting sort on the event (placement order within an event from LDS
+// atomics) and an insertion sort of each event's segment by one thread;
+// otherwise by a sort network over the bucket.  A larger bucket is sorted in
+// place in global memory.  Dynamic LDS: cap records, then 2 (2^sb + 1) ints.
+template <int RPT>  // records per thread held in registers: cap = RPT kSortTB
+__global__ __launch_bounds__(kSortTB) void k_bucket_sort(int64_t nbk, int sb, int M,
+                                                        const int32_t* base, BatchBufs b) {
+  constexpr int cap = RPT * kSortTB;
+  extern __shared__ uint64_t dyn[];
+  uint64_t* k_sh = dyn;
+  int32_t* soff = (int32_t*)(dyn + cap);  // [2^sb + 1] offsets, then cursors
+  int32_t* cur = soff + (1 << sb) + 1;
+  __shared__ int32_t wsum[kSortTB / 64];
+  const int t = threadIdx.x;
+  const int64_t bk = blockIdx.x;
+  const int64_t c = bk / nbk;
+  const int32_t m0 = (int32_t)((bk - c * nbk) << sb);
+  const int32_t nev = min(1 << sb, M - m0);
+  const int32_t r0 = base[bk], len = base[bk + 1] - r0;
+  uint64_t* rec = b.ckey + r0;
+  const bool in_lds = len <= cap;
+
+  uint64_t reg[RPT];
+#pragma unroll
+  for (int u = 0; u < RPT; ++u) {
+    const int32_t i = t + u * kSortTB;
+    reg[u] = (in_lds && i < len) ? rec[i] : 0;
+  }
+  for (int32_t m = t; m <= nev; m += kSortTB) soff[m] = 0;
+  __syncthreads();
+  if (in_lds) {
+#pragma unroll
+    for (int u = 0; u < RPT; ++u)
+      if (t + u * kSortTB < len) atomicAdd(&soff[(int32_t)(reg[u] >> 48)], 1);
+  } else {
+    for (int32_t i = t; i < len; i += kSortTB) atomicAdd(&soff[(int32_t)(rec[i] >> 48)], 1);
+  }
+  __syncthreads();
+  // ---- segment offsets (exclusive scan over contiguous chunks, wave scans,
+  // wave totals) and start[] of the bucket's events
+  int longest = 0;
+  {
+    const int lane = t & 63, w = t >> 6;
+    const int32_t per = (nev + kSortTB - 1) / kSortTB;
+    const int32_t k0 = t * per, k1 = min(nev, k0 + per);
+    int32_t cnt = 0;
+    for (int32_t k = k0; k < k1; ++k) {
+      cnt += soff[k];
+      longest = max(longest, soff[k]);
     }
+    int32_t incl = cnt;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int32_t x = __shfl_up(incl, d, 64);
+      if (lane >= d) incl += x;
+    }
+    if (lane == 63) wsum[w] = incl;
     __syncthreads();
+    int32_t before = 0;
+#pragma unroll
+    for (int v = 0; v < kSortTB / 64; ++v)
+      if (v < w) before += wsum[v];
+    int32_t o = before + incl - cnt;
+    for (int32_t k = k0; k < k1; ++k) {
+      const int32_t x = soff[k];
+      soff[k] = o;
+      cur[k] = o;
+      o += x;
+    }
+    if (t == 0) soff[nev] = len;
+  }
+  const bool short_segs = !__syncthreads_or(longest > kSegShort);
+  int32_t* key_start = b.start + c * M + m0;
+  for (int32_t m = t; m < nev; m += kSortTB) key_start[m] = r0 + soff[m];
+
+  // ---- the order
+  if (in_lds && short_segs) {
+#pragma unroll
+    for (int u = 0; u < RPT; ++u)
+      if (t + u * kSortTB < len) k_sh[atomicAdd(&cur[(int32_t)(reg[u] >> 48)], 1)] = reg[u];
+    __syncthreads();
+    for (int32_t m = t; m < nev; m += kSortTB) {
+      const int32_t p0 = soff[m], p1 = soff[m + 1];
+      for (int32_t i = p0 + 1; i < p1; ++i) {
+        const uint64_t x = k_sh[i];
+        int32_t j = i;
+        while (j > p0 && k_sh[j - 1] > x) {
+          k_sh[j] = k_sh[j - 1];
+          --j;
+        }
+        k_sh[j] = x;
+      }
+    }
+  } else if (in_lds) {
+#pragma unroll
+    for (int u = 0; u < RPT; ++u)
+      if (t + u * kSortTB < len) k_sh[t + u * kSortTB] = reg[u];
+    __syncthreads();
+    block_sort_any(len, [&](int32_t i) { return k_sh[i]; }, [&](int32_t i, uint64_t x) { k_sh[i] = x; });
+  } else {
+    block_sort_any(len, [&](int32_t i) { return rec[i]; }, [&](int32_t i, uint64_t x) { rec[i] = x; });
+  }
+  __syncthreads();
+
+  // ---- per position: node runs are the positions of equal (event, group)
+  auto key_at = [&](int32_t i) { return in_lds ? k_sh[i] : rec[i]; };
+  for (int32_t i = t; i < len; i += kSortTB) {
+    const uint64_t x = key_at(i);
+    const uint64_t eg = x >> 32;  // (event, group)
+    int32_t j = i;
+    while (j > 0 && (key_at(j - 1) >> 32) == eg) --j;
+    const bool last = i + 1 == len || (key_at(i + 1) >> 32) != eg;
+    const int32_t p = r0 + i, e = (int32_t)(uint32_t)x;
+    b.csr[p] = e;
+    b.pev[p] = m0 + (int32_t)(x >> 48);
+    b.pgr[p] = (int32_t)(eg & 0xFFFF);
+    b.head[p] = r0 + j;
+    if (last) b.nend[r0 + j] = p + 1;
+    b.pos[e] = p | ((last && j == i) ? kSingle : 0);
   }
 }
 
@@ -436,7 +541,9 @@ __global__ __launch_bounds__(kListTB) void k_list_fill(int64_t n, int L, int64_t
     if (!sv.act[p]) continue;
     const int32_t g = b.pgr[p];
     const int32_t slot = atomicAdd(&hist[g], 1);
-    sv.list[sv.sys[(c * L + g) * nb + bk] + slot] = (int32_t)p;
+    const int32_t at = sv.sys[(c * L + g) * nb + bk] + slot;
+    sv.list[at] = (int32_t)p;
+    sv.lidx[p] = at - sv.sys[(c * L + g) * nb];
     double A = lambda, rhs = 0.0;
     for (int32_t f = (int32_t)p; f < b.nend[p]; ++f) {
       const int32_t e = b.csr[f];
@@ -478,9 +585,14 @@ struct SolveArgs {
   double tol2;     // CG stops once |res|^2 <= tol2 |rhs|^2
   double accept2;  // after its passes, |res|^2 > accept2 |rhs|^2 raises kErrSolve
   int* err;        // error bits of the step
+  const int32_t* lidx;  // index of a node in its system's list (at its first position)
+  int32_t* spill;       // per system: 1 if k_tree_solve takes it
+  int lds_off;          // 1: every system to k_tree_solve (SPIDER_TREE_GLOBAL, for tests)
 };
 
 constexpr int kMaxRounds = 64;
+constexpr int kWaveCore = 64;  // cores up to this size: CG in one wave
+constexpr int kWaveNb = 8;     // core entries per node held for the one-wave CG
 constexpr int kTreeBlock = 1024;  // threads per (chain, group) system
 constexpr int kCoreLds = 4096;    // cores up to this size are sorted in LDS
 
@@ -489,9 +601,8 @@ constexpr int kCoreLds = 4096;    // cores up to this size are sorted in LDS
 // the per-thread counts over the block (butterfly within waves, then the wave
 // totals) gives each thread its first output slot.  Returns the number
 // appended.  All threads of the block call it; scan holds TB / 64 ints.
-template <int TB, class Keep, class Item>
-__device__ int32_t block_compact(int32_t n, Keep&& keep, Item&& item, int32_t* out,
-                                 int32_t* scan) {
+template <int TB, class Keep, class Item, class Out>
+__device__ int32_t block_compact(int32_t n, Keep&& keep, Item&& item, Out* out, int32_t* scan) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int32_t per = (n + TB - 1) / TB;
   const int32_t k0 = t * per, k1 = min(n, k0 + per);
@@ -533,12 +644,216 @@ __device__ int32_t block_compact(int32_t n, Keep&& keep, Item&& item, int32_t* o
 //  3. Back substitution in reverse round order: y_q = (b_q + W y_p)/A_q.
 // Exact up to FP64 rounding for forests; the minibatch graphs are forests
 // of small trees apart from rare cycles.
+// Jacobi-CG on a core of n <= 64 nodes in one wave (the workgroup's first):
+// lane k holds the k-th smallest node and its core entries (lane of the other
+// end, weight) in its own LDS row; the neighbours' values are shuffles and the
+// sums xor butterflies (the same bits in every lane), so an iteration costs no
+// barrier and no memory round trip.  The same passes, tolerances and error
+// bit as the workgroup CG.  Returns false, having written nothing, when a
+// node has more than kWaveNb core entries.
+__device__ bool wave_core_cg(const SolveArgs& a, const int32_t* core, int32_t n,
+                             int32_t (*nb_sh)[kWaveNb], double (*w_sh)[kWaveNb]) {
+  const int lane = threadIdx.x & 63;
+  const bool on = lane < n;
+  const int32_t mine = on ? core[lane] : INT32_MAX;
+  int rank = 0;
+  for (int i = 0; i < n; ++i) rank += __shfl(mine, i, 64) < mine ? 1 : 0;
+  int32_t q = INT32_MAX;
+  for (int i = 0; i < n; ++i) {
+    const int ri = __shfl(rank, i, 64);
+    const int32_t vi = __shfl(mine, i, 64);
+    if (ri == lane) q = vi;
+  }
+  int cnt = 0;
+  bool over = false;
+  if (on) {
+    const int32_t e1 = a.nend[q];
+    for (int32_t e = q; e < e1; ++e) {
+      const int32_t pn = a.nbr[e];
+      if (a.state[pn] != kActive) continue;
+      if (cnt == kWaveNb) {
+        over = true;
+        break;
+      }
+      nb_sh[lane][cnt] = pn;
+      w_sh[lane][cnt] = a.wgt[e];
+      ++cnt;
+    }
+  }
+  if (__any(over)) return false;
+  int maxc = cnt;
+  for (int m = 32; m > 0; m >>= 1) maxc = max(maxc, __shfl_xor(maxc, m, 64));
+  // entries' other ends as lanes: lower bound in the sorted nodes (a
+  // wave-uniform number of steps, so every lane takes part in each shuffle)
+  for (int s = 0; s < maxc; ++s) {
+    const int32_t target = s < cnt ? nb_sh[lane][s] : INT32_MAX;
+    int pos = 0;
+    for (int step = 32; step >= 1; step >>= 1) {
+      const int cand = pos + step;
+      const int32_t v = __shfl(q, (cand - 1) & 63, 64);
+      if (cand <= n && v < target) pos = cand;
+    }
+    if (s < cnt) nb_sh[lane][s] = pos;
+  }
+  auto wsum = [](double v) {
+    for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+  };
+  const double Aq = on ? a.A[q] : 1.0;
+  const double bq = on ? a.b[q] : 0.0;
+  double y = 0.0, rr = 0.0, p = 0.0;
+  const double bb = wsum(bq * bq);
+  double rn = bb;
+  for (int pass = 0; pass < 3 && bb > 0.0; ++pass) {
+    // the true residual b - A y of the current y
+    double v = bq - Aq * y;
+    for (int s = 0; s < maxc; ++s) {
+      const double yv = __shfl(y, s < cnt ? nb_sh[lane][s] : lane, 64);
+      if (s < cnt) v += w_sh[lane][s] * yv;
+    }
+    rr = on ? v : 0.0;
+    p = rr / Aq;
+    rn = wsum(rr * rr);
+    double rz = wsum(rr * rr / Aq);
+    if (rn <= a.tol2 * bb) break;
+    for (int it = 0; it < a.max_iter; ++it) {
+      double ap = Aq * p;
+      for (int s = 0; s < maxc; ++s) {
+        const double pv = __shfl(p, s < cnt ? nb_sh[lane][s] : lane, 64);
+        if (s < cnt) ap -= w_sh[lane][s] * pv;
+      }
+      if (!on) ap = 0.0;
+      const double pap = wsum(p * ap);
+      const double alpha = rz / pap;
+      y += alpha * p;
+      rr -= alpha * ap;
+      rn = wsum(rr * rr);
+      const double rz_new = wsum(rr * rr / Aq);
+      if (rn <= a.tol2 * bb) break;
+      const double beta = rz_new / rz;
+      rz = rz_new;
+      p = rr / Aq + beta * p;
+    }
+  }
+  if (lane == 0 && bb > 0.0 && !(rn <= a.accept2 * bb)) atomicOr(a.err, kErrSolve);
+  if (on) {
+    a.y[q] = y;
+    a.state[q] = kCore;
+  }
+  return true;
+}
+
+// The one-wave core CG of k_tree_lds: nodes are indices into the system's
+// list (positions gpos), entries in LDS (eoff, snb), state sst; y replaces b
+// in sB.  Same ordering (by CSR position), arithmetic and tolerances as
+// wave_core_cg.
+__device__ bool wave_core_cg_lds(const SolveArgs& a, const uint16_t* core, int32_t n,
+                                 const int32_t* gpos, const uint16_t* eoff, const uint16_t* snb,
+                                 uint8_t* sst, const double* sA, double* sB,
+                                 double (*w_sh)[kWaveNb], int32_t (*nb_sh)[kWaveNb]) {
+  constexpr uint8_t kActiveL = 255, kCoreL = 254;
+  const int lane = threadIdx.x & 63;
+  const bool on = lane < n;
+  const int32_t mine_i = on ? core[lane] : 0;
+  const int32_t mine = on ? gpos[mine_i] : INT32_MAX;
+  int rank = 0;
+  for (int k = 0; k < n; ++k) rank += __shfl(mine, k, 64) < mine ? 1 : 0;
+  int32_t node = 0, key = INT32_MAX;  // this lane's node (list index) and position
+  for (int k = 0; k < n; ++k) {
+    const int rk = __shfl(rank, k, 64);
+    const int32_t ik = __shfl(mine_i, k, 64);
+    const int32_t vk = __shfl(mine, k, 64);
+    if (rk == lane) {
+      node = ik;
+      key = vk;
+    }
+  }
+  int cnt = 0;
+  bool over = false;
+  if (on) {
+    const int32_t e0 = eoff[node], e1 = eoff[node + 1];
+    for (int32_t x = e0; x < e1; ++x) {
+      const int32_t pn = snb[x];
+      if (sst[pn] != kActiveL) continue;
+      if (cnt == kWaveNb) {
+        over = true;
+        break;
+      }
+      nb_sh[lane][cnt] = gpos[pn];
+      w_sh[lane][cnt] = a.wgt[key + (x - e0)];
+      ++cnt;
+    }
+  }
+  if (__any(over)) return false;
+  int maxc = cnt;
+  for (int m = 32; m > 0; m >>= 1) maxc = max(maxc, __shfl_xor(maxc, m, 64));
+  for (int s = 0; s < maxc; ++s) {
+    const int32_t target = s < cnt ? nb_sh[lane][s] : INT32_MAX;
+    int pos = 0;
+    for (int step = 32; step >= 1; step >>= 1) {
+      const int cand = pos + step;
+      const int32_t v = __shfl(key, (cand - 1) & 63, 64);
+      if (cand <= n && v < target) pos = cand;
+    }
+    if (s < cnt) nb_sh[lane][s] = pos;
+  }
+  auto wsum = [](double v) {
+    for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+  };
+  const double Aq = on ? sA[node] : 1.0;
+  const double bq = on ? sB[node] : 0.0;
+  double y = 0.0, rr = 0.0, p = 0.0;
+  const double bb = wsum(bq * bq);
+  double rn = bb;
+  for (int pass = 0; pass < 3 && bb > 0.0; ++pass) {
+    double v = bq - Aq * y;
+    for (int s = 0; s < maxc; ++s) {
+      const double yv = __shfl(y, s < cnt ? nb_sh[lane][s] : lane, 64);
+      if (s < cnt) v += w_sh[lane][s] * yv;
+    }
+    rr = on ? v : 0.0;
+    p = rr / Aq;
+    rn = wsum(rr * rr);
+    double rz = wsum(rr * rr / Aq);
+    if (rn <= a.tol2 * bb) break;
+    for (int it = 0; it < a.max_iter; ++it) {
+      double ap = Aq * p;
+      for (int s = 0; s < maxc; ++s) {
+        const double pv = __shfl(p, s < cnt ? nb_sh[lane][s] : lane, 64);
+        if (s < cnt) ap -= w_sh[lane][s] * pv;
+      }
+      if (!on) ap = 0.0;
+      const double pap = wsum(p * ap);
+      const double alpha = rz / pap;
+      y += alpha * p;
+      rr -= alpha * ap;
+      rn = wsum(rr * rr);
+      const double rz_new = wsum(rr * rr / Aq);
+      if (rn <= a.tol2 * bb) break;
+      const double beta = rz_new / rz;
+      rz = rz_new;
+      p = rr / Aq + beta * p;
+    }
+  }
+  if (lane == 0 && bb > 0.0 && !(rn <= a.accept2 * bb)) atomicOr(a.err, kErrSolve);
+  if (on) {
+    sB[node] = y;
+    sst[node] = kCoreL;
+  }
+  return true;
+}
+
 template <int TB>
 __global__ __launch_bounds__(TB) void k_tree_solve(SolveArgs a) {
   __shared__ double sh[TB / 64];
   __shared__ int32_t warp_base[TB / 64];
   __shared__ int32_t elim_start[kMaxRounds + 2];
   __shared__ int32_t core_sh[kCoreLds];
+  __shared__ int32_t wc_nb[kWaveCore][kWaveNb];
+  __shared__ double wc_w[kWaveCore][kWaveNb];
+  __shared__ int wc_done;
+  if (!a.spill[blockIdx.x]) return;  // solved in LDS by k_tree_lds
   const int32_t off = a.sys[blockIdx.x * a.nb];
   int32_t nl = a.sys[(blockIdx.x + 1) * a.nb] - off;
   if (nl <= 0) return;
@@ -645,7 +960,16 @@ __global__ __launch_bounds__(TB) void k_tree_solve(SolveArgs a) {
   // drift of CG's recursively updated residual.
   int32_t* core = act;
   const int32_t ncore = nl;
-  if (ncore > 0) {
+  bool core_done = false;
+  if (ncore > 0 && ncore <= kWaveCore) {
+    if (t < 64) {
+      const bool ok = wave_core_cg(a, core, ncore, wc_nb, wc_w);
+      if (t == 0) wc_done = ok ? 1 : 0;
+    }
+    __syncthreads();
+    core_done = wc_done != 0;
+  }
+  if (ncore > 0 && !core_done) {
     if (ncore <= kCoreLds) {
       for (int32_t k = t; k < ncore; k += TB) core_sh[k] = core[k];
       __syncthreads();
@@ -819,6 +1143,283 @@ __global__ void k_linear_keep(const BatchBufs b, const double* theta, int64_t n,
   block_count_add(k, count);
 }
 
+// ---- the same solve with the system held in LDS.  A system of up to
+// kLdsNodes nodes and kLdsEntries entries whose cycle core fits the one-wave
+// CG is loaded once (node data, and each entry's other end as an index into
+// the system's list), peeled, solved and back-substituted without touching
+// global memory, and only y is written back; any other system is flagged in
+// spill and left to k_tree_solve.  The arithmetic is that of k_tree_solve:
+// the same elimination rule (ties broken by CSR position), sums in entry
+// order, the same back substitution and core CG, so either kernel gives the
+// same y.
+constexpr int kLdsNodes = 3328;
+constexpr int kLdsEntries = 8192;
+constexpr uint8_t kLActive = 255, kLCore = 254;
+constexpr uint16_t kLNoPar = 0xFFFF;
+
+template <int TB>
+__global__ __launch_bounds__(TB) void k_tree_lds(SolveArgs a) {
+  static_assert(kLdsEntries % TB == 0 && kMaxRounds < kLCore, "LDS solver shape");
+  __shared__ double sA[kLdsNodes], sB[kLdsNodes], sW[kLdsNodes];
+  __shared__ int32_t gpos[kLdsNodes];
+  __shared__ uint16_t eoff[kLdsNodes + 2];
+  __shared__ uint16_t snb[kLdsEntries];
+  __shared__ uint16_t spar[kLdsNodes];
+  __shared__ uint8_t sst[kLdsNodes], snst[kLdsNodes];
+  __shared__ __attribute__((aligned(16))) uint16_t lst[3][kLdsNodes];
+  __shared__ int32_t scan[TB / 64];
+  __shared__ int32_t elim_start[kMaxRounds + 2];
+  __shared__ int flag;
+  const int t = threadIdx.x;
+  const int64_t sys_id = blockIdx.x;
+  const int32_t off = a.sys[sys_id * a.nb];
+  const int32_t N = a.sys[(sys_id + 1) * a.nb] - off;
+  if (N <= 0 || N > kLdsNodes || a.lds_off) {
+    if (t == 0) a.spill[sys_id] = N > 0 ? 1 : 0;
+    return;
+  }
+
+  // ---- 1. nodes (first position, entry count clamped above kLdsEntries, A,
+  // b), then the entry offsets by an exclusive scan over contiguous chunks;
+  // each thread issues the list reads of all its nodes, then their dependent
+  // reads, so that a thread waits for two memory latencies, not two per node
+  {
+    constexpr int KN = (kLdsNodes + TB - 1) / TB;
+    int32_t q[KN], ne[KN];
+    double va[KN], vb[KN];
+#pragma unroll
+    for (int u = 0; u < KN; ++u) {
+      const int32_t i = t + u * TB;
+      q[u] = i < N ? a.list[off + i] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < KN; ++u) {
+      const int32_t i = t + u * TB;
+      ne[u] = i < N ? a.nend[q[u]] : 0;
+      va[u] = i < N ? a.A[q[u]] : 0.0;
+      vb[u] = i < N ? a.b[q[u]] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < KN; ++u) {
+      const int32_t i = t + u * TB;
+      if (i >= N) continue;
+      gpos[i] = q[u];
+      eoff[i] = (uint16_t)min(ne[u] - q[u], kLdsEntries + 1);
+      sA[i] = va[u];
+      sB[i] = vb[u];
+      sst[i] = kLActive;
+      snst[i] = kLActive;
+    }
+  }
+  __syncthreads();
+  int32_t total;
+  {
+    const int lane = t & 63, w = t >> 6;
+    const int32_t per = (N + TB - 1) / TB;
+    const int32_t k0 = t * per, k1 = min(N, k0 + per);
+    int32_t cnt = 0;
+    for (int32_t k = k0; k < k1; ++k) cnt += eoff[k];
+    int32_t incl = cnt;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int32_t x = __shfl_up(incl, d, 64);
+      if (lane >= d) incl += x;
+    }
+    if (lane == 63) scan[w] = incl;
+    __syncthreads();
+    int32_t before = 0;
+    total = 0;
+#pragma unroll
+    for (int v = 0; v < TB / 64; ++v) {
+      const int32_t x = scan[v];
+      if (v < w) before += x;
+      total += x;
+    }
+    if (total <= kLdsEntries) {
+      int32_t o = before + incl - cnt;
+      for (int32_t k = k0; k < k1; ++k) {
+        const int32_t x = eoff[k];
+        eoff[k] = (uint16_t)o;
+        o += x;
+      }
+      if (t == 0) eoff[N] = (uint16_t)total;
+    }
+  }
+  if (total > kLdsEntries) {
+    if (t == 0) a.spill[sys_id] = 1;
+    return;
+  }
+  __syncthreads();
+
+  // ---- 2. each entry's other end as an index into the list: the loads of
+  // a thread's (at most kLdsEntries / TB) entries are all issued before the
+  // first is used
+  {
+    constexpr int KE = kLdsEntries / TB;
+    int32_t other[KE];
+#pragma unroll
+    for (int u = 0; u < KE; ++u) {
+      const int32_t x = t + u * TB;
+      other[u] = 0;
+      if (x < total) {
+        int32_t lo = 0, hi = N - 1;  // the node of entry x: last i with eoff[i] <= x
+        while (lo < hi) {
+          const int32_t mid = (lo + hi + 1) >> 1;
+          if (eoff[mid] <= x) lo = mid;
+          else hi = mid - 1;
+        }
+        other[u] = a.nbr[gpos[lo] + (x - eoff[lo])];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < KE; ++u) {
+      const int32_t x = t + u * TB;
+      if (x < total) other[u] = a.lidx[other[u]];
+    }
+    // every entry of a listed node ends at a listed node of the same system;
+    // anything else leaves the system to k_tree_solve
+    int bad = 0;
+#pragma unroll
+    for (int u = 0; u < KE; ++u) {
+      const int32_t x = t + u * TB;
+      if (x >= total) continue;
+      if ((uint32_t)other[u] >= (uint32_t)N) bad = 1;
+      else snb[x] = (uint16_t)other[u];
+    }
+    if (__syncthreads_or(bad)) {
+      if (t == 0) a.spill[sys_id] = 1;
+      return;
+    }
+  }
+  uint16_t* act = lst[0];
+  uint16_t* nxt = lst[1];
+  uint16_t* elim = lst[2];
+  for (int32_t i = t; i < N; i += TB) act[i] = (uint16_t)i;
+  __syncthreads();
+
+  // ---- 3. peeling rounds
+  int32_t nl = N, n_elim = 0;
+  int rounds = 0;
+  for (; rounds < a.max_rounds && nl > 0; ++rounds) {
+    if (t == 0) elim_start[rounds] = n_elim;
+    int changed = 0;
+    for (int32_t k = t; k < nl; k += TB) {
+      const int32_t i = act[k];
+      const int32_t e0 = eoff[i], e1 = eoff[i + 1];
+      int32_t p0 = -1;
+      bool multi = false;
+      for (int32_t x = e0; x < e1; ++x) {
+        const int32_t pn = snb[x];
+        if (sst[pn] != kLActive) continue;
+        if (p0 < 0) {
+          p0 = pn;
+        } else if (pn != p0) {
+          multi = true;
+          break;
+        }
+      }
+      uint8_t ns = kLActive;
+      if (p0 < 0) {
+        ns = (uint8_t)rounds;  // isolated: solved directly
+        spar[i] = kLNoPar;
+      } else if (!multi) {
+        bool p0_other = false;
+        for (int32_t x = eoff[p0]; x < eoff[p0 + 1]; ++x) {
+          const int32_t pn = snb[x];
+          if (pn != i && sst[pn] == kLActive) {
+            p0_other = true;
+            break;
+          }
+        }
+        if (p0_other || gpos[i] > gpos[p0]) {
+          ns = (uint8_t)rounds;
+          spar[i] = (uint16_t)p0;
+          // weight to the parent: its entries' weights in entry order
+          double W = 0.0;
+          bool first = true;
+          for (int32_t x = e0; x < e1; ++x) {
+            if (snb[x] != p0) continue;
+            const double wv = a.wgt[gpos[i] + (x - e0)];
+            W = first ? wv : W + wv;
+            first = false;
+          }
+          sW[i] = W;
+        }
+      }
+      snst[i] = ns;
+      changed |= (ns != kLActive);
+    }
+    changed = __syncthreads_or(changed);
+    if (!changed) break;
+    // parents gather the Schur updates of this round's leaves
+    for (int32_t k = t; k < nl; k += TB) {
+      const int32_t i = act[k];
+      if (snst[i] != kLActive) continue;
+      const int32_t e0 = eoff[i], e1 = eoff[i + 1];
+      double dA = 0.0, db = 0.0;
+      for (int32_t x = e0; x < e1; ++x) {
+        const int32_t pn = snb[x];
+        if (snst[pn] != rounds || spar[pn] != i) continue;
+        bool first = true;
+        for (int32_t f = e0; f < x; ++f)
+          if (snb[f] == pn) {
+            first = false;
+            break;
+          }
+        if (!first) continue;
+        const double Ap = sA[pn], Wn = sW[pn];
+        dA += Wn * Wn / Ap;
+        db += Wn * sB[pn] / Ap;
+      }
+      sA[i] -= dA;
+      sB[i] += db;
+    }
+    __syncthreads();
+    for (int32_t k = t; k < nl; k += TB) sst[act[k]] = snst[act[k]];
+    __syncthreads();
+    n_elim += block_compact<TB>(
+        nl, [&](int32_t k) { return sst[act[k]] != kLActive; }, [&](int32_t k) { return act[k]; },
+        elim + n_elim, scan);
+    nl = block_compact<TB>(
+        nl, [&](int32_t k) { return sst[act[k]] == kLActive; }, [&](int32_t k) { return act[k]; },
+        nxt, scan);
+    uint16_t* tmp = act;
+    act = nxt;
+    nxt = tmp;
+  }
+  if (t == 0) elim_start[rounds] = n_elim;
+  __syncthreads();
+
+  // ---- 4. the cycle core: one-wave CG, or the whole system to k_tree_solve
+  if (nl > 0) {
+    if (t == 0) flag = 0;
+    __syncthreads();
+    if (nl <= kWaveCore && t < 64) {
+      const bool ok = wave_core_cg_lds(a, act, nl, gpos, eoff, snb, sst, sA, sB,
+                                       (double (*)[kWaveNb])nxt,
+                                       (int32_t (*)[kWaveNb])(nxt + 4 * kWaveCore * kWaveNb));
+      if (t == 0) flag = ok ? 1 : 0;
+    }
+    __syncthreads();
+    if (!flag) {
+      if (t == 0) a.spill[sys_id] = 1;
+      return;
+    }
+  }
+
+  // ---- 5. back substitution in reverse elimination order (y replaces b)
+  for (int rnd = rounds - 1; rnd >= 0; --rnd) {
+    for (int32_t k = elim_start[rnd] + t; k < elim_start[rnd + 1]; k += TB) {
+      const int32_t i = elim[k];
+      const int32_t pn = spar[i];
+      sB[i] = pn == kLNoPar ? sB[i] / sA[i] : (sB[i] + sW[i] * sB[pn]) / sA[i];
+    }
+    __syncthreads();
+  }
+  for (int32_t i = t; i < N; i += TB) a.y[gpos[i]] = sB[i];
+  if (t == 0) a.spill[sys_id] = 0;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
@@ -833,11 +1434,6 @@ void launch_scan(int32_t* a, int64_t len, int32_t* part, hipStream_t s) {
   hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanTB), 0, s, a, len, part);
 }
 
-void launch_clear_counts(const BatchBufs& b, int64_t keys, hipStream_t s) {
-  hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(keys + 1)), dim3(kBlock), 0, s, b.start, 0,
-                     keys + 1);
-}
-
 void launch_select(const CatView& cat, int C, int64_t n, const int64_t* idx, uint64_t seed,
                    const int64_t* steps, int64_t step_scalar, int chain0, BatchBufs b,
                    int* err_flag, hipStream_t s) {
@@ -846,18 +1442,53 @@ void launch_select(const CatView& cat, int C, int64_t n, const int64_t* idx, uin
                      err_flag);
 }
 
-void launch_build_csr(const CatView& cat, int C, int64_t n, BatchBufs b, int32_t* scan_part,
-                      int32_t* long_list, hipStream_t s) {
+BucketShape bucket_shape(int64_t C, int64_t n, int64_t M) {
+  BucketShape bs;
+  // about 512 entries per bucket on average (2 n 2^sb / M per chain)
+  int sb = 0;
+  while (sb < kBucketMaxSB && (2 * n << (sb + 1)) / std::max<int64_t>(M, 1) <= 512) ++sb;
+  while (sb < kBucketMaxSB && ceil_div(M, (int64_t)1 << sb) > kBucketMax) ++sb;
+  bs.sb = sb;
+  bs.nbk = ceil_div(M, (int64_t)1 << sb);
+  bs.nb = C * bs.nbk;
+  bs.hb = std::max<int64_t>(ceil_div(2 * n, kBucketHB), 1);  // counting blocks per chain
+  bs.words = C * bs.hb * bs.nbk + bs.nb + 1;
+  bs.ok = bs.nbk <= kBucketMax;
+  return bs;
+}
+
+template <int RPT>
+void launch_bucket_sort(const BucketShape& bs, int M, const int32_t* base, const BatchBufs& b,
+                        hipStream_t s) {
+  const size_t lds = (size_t)RPT * kSortTB * 8 + (size_t)2 * (((size_t)1 << bs.sb) + 1) * 4;
+  if (lds > 64 * 1024)
+    (void)hipFuncSetAttribute((const void*)k_bucket_sort<RPT>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(k_bucket_sort<RPT>, dim3((unsigned)bs.nb), dim3(kSortTB), lds, s, bs.nbk, bs.sb,
+                     M, base, b);
+}
+
+void launch_build_csr(const CatView& cat, int C, int64_t n, BatchBufs b, int32_t* bucket_buf,
+                      int32_t* scan_part, hipStream_t s) {
   const int64_t E = 2 * (int64_t)C * n;
-  const int64_t K = (int64_t)C * cat.M;
-  launch_scan(b.start, K + 1, scan_part, s);
-  hipLaunchKernelGGL(k_csr_scatter, dim3(grid_for(E)), dim3(kBlock), 0, s, E, n, cat.M, b);
-  // long-segment count in long_list[0], the list from long_list + 1
-  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, long_list, 0, (int64_t)1);
-  hipLaunchKernelGGL(k_csr_canon, dim3(grid_for(K, kCanonTB)), dim3(kCanonTB), 0, s, K, cat.M, b,
-                     long_list + 1, long_list);
-  hipLaunchKernelGGL(k_csr_canon_long, dim3(512), dim3(kLongTB), 0, s, long_list + 1, long_list,
-                     cat.M, b);
+  const BucketShape bs = bucket_shape(C, n, cat.M);
+  int32_t* counts = bucket_buf;                         // [C][hb][nbk]
+  int32_t* tot = bucket_buf + (int64_t)C * bs.hb * bs.nbk;  // [nb + 1] totals, then bases
+  const size_t lds_count = (size_t)bs.nbk * 4;
+  const dim3 grid((unsigned)bs.hb, (unsigned)C);
+  hipLaunchKernelGGL(k_bucket_count, grid, dim3(kBucketTB), lds_count, s, n, bs.sb, bs.nbk,
+                     (const int32_t*)b.ev, counts);
+  hipLaunchKernelGGL(k_bucket_prefix, dim3(grid_for(bs.nb)), dim3(kBlock), 0, s, bs.nbk, bs.nb,
+                     bs.hb, counts, tot, b.start, (int64_t)C * cat.M, E);
+  launch_scan(tot, bs.nb + 1, scan_part, s);
+  hipLaunchKernelGGL(k_bucket_scatter, grid, dim3(kBucketTB), lds_count, s, n, bs.sb, bs.nbk,
+                     (const int32_t*)counts, (const int32_t*)tot, b);
+  // records held per thread: about four times the average bucket, 1,024 to 8,192
+  const int64_t avg = ceil_div(E, bs.nb);
+  if (avg <= 256) launch_bucket_sort<4>(bs, cat.M, tot, b, s);
+  else if (avg <= 512) launch_bucket_sort<8>(bs, cat.M, tot, b, s);
+  else if (avg <= 1024) launch_bucket_sort<16>(bs, cat.M, tot, b, s);
+  else launch_bucket_sort<32>(bs, cat.M, tot, b, s);
 }
 
 void launch_phase_rows(const CatView& cat, int64_t E, BatchBufs b, int32_t* flags,
@@ -944,6 +1575,11 @@ hipError_t exact_whiten(const CatView& cat, int C, int64_t n, BatchBufs b, Solve
   a.tol2 = 1e-32;
   a.accept2 = 1e-16;
   a.err = err;
+  a.lidx = sv.lidx;
+  a.spill = sv.spill;
+  const char* tg = std::getenv("SPIDER_TREE_GLOBAL");
+  a.lds_off = (tg && tg[0] == '1') ? 1 : 0;
+  hipLaunchKernelGGL(k_tree_lds<kTreeBlock>, dim3((unsigned)S), dim3(kTreeBlock), 0, s, a);
   hipLaunchKernelGGL(k_tree_solve<kTreeBlock>, dim3((unsigned)S), dim3(kTreeBlock), 0, s, a);
   hipLaunchKernelGGL(k_exact_z, dim3(grid_for((int64_t)C * n)), dim3(kBlock), 0, s,
                      (int64_t)C * n, cat, b, (const double*)a.y);

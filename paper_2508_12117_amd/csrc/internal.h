@@ -58,10 +58,9 @@ struct BatchBufs {
   int32_t* sta;     // [E] group of each entry (station + L_p phase)
   double* tau;      // [C n] observed differential time
   double* w;        // [C n] normalised edge weight
-  int32_t* rank;    // [E] arrival rank of the entry in its (chain, event) count
-  int32_t* start;   // [C M + 1] counts, then the first CSR position of each key
+  int32_t* start;   // [C M + 1] first CSR position of each (chain, event) key
   int32_t* csr;     // [E] entry at each CSR position
-  uint64_t* ckey;   // [E] (group, entry) of each CSR position as scattered, then sorted
+  uint64_t* ckey;   // [E] bucket records (event in bucket, group, entry) of the CSR build
   int32_t* pos;     // [E] CSR position of each entry; bit 31: its node has one entry
   int32_t* pev;     // [E] event at each CSR position
   int32_t* pgr;     // [E] group at each CSR position
@@ -88,6 +87,8 @@ struct SolveBufs {
   double* wgt;        // [E] edge weight of each position's observation
   double* vec;        // [7][E] A, b, y, Wp, rr, p, ap
   int32_t* ivec;      // [5][E] state, nstate, par, next list, elimination order
+  int32_t* lidx;      // [E] at a node's first position: its index in its system's list
+  int32_t* spill;     // [C L] 1: the system is solved from global memory (too large for LDS)
   int32_t* scan_part; // scratch of the scans
 };
 
@@ -146,21 +147,29 @@ constexpr int kErrSelect = 1;
 constexpr int kErrSolve = 2;
 
 // Step kernels (batch_csr.hip).
-// Zeroes the (chain, event) counts of a chain set: start[0 .. C M].
-void launch_clear_counts(const BatchBufs& b, int64_t keys, hipStream_t s);
 // Minibatch of each chain: explicit indices idx (all chains) or, if idx is
 // null, the Feistel minibatch of chain chain0 + c at step steps[c] (device)
-// or, if steps is null, at step_scalar; counts each entry in b.start (after
-// launch_clear_counts) with its arrival rank.  err_flag |= kErrSelect on a
-// failed walk or an index outside [0, N).
+// or, if steps is null, at step_scalar.  err_flag |= kErrSelect on a failed
+// walk or an index outside [0, N).
 void launch_select(const CatView& cat, int C, int64_t n, const int64_t* idx, uint64_t seed,
                    const int64_t* steps, int64_t step_scalar, int chain0, BatchBufs b,
                    int* err_flag, hipStream_t s);
-// The CSR order of the entries (after launch_select): scan of the counts,
-// scatter, and each event's segment sorted by (group, entry); pos, head, nend.
-// scan_part: scan_part_size(C M + 1) ints; long_list: C M + 1 ints.
-void launch_build_csr(const CatView& cat, int C, int64_t n, BatchBufs b, int32_t* scan_part,
-                      int32_t* long_list, hipStream_t s);
+// Buckets of the CSR build for C chains of n observations over M events:
+// (chain, block of 2^sb events), nb of them, counted over hb blocks of
+// entries; words: ints of the count matrix and bucket bases.  ok = false
+// when C M is too large for the bucket counters.
+struct BucketShape {
+  int sb;
+  int64_t nbk, nb, hb, words;
+  bool ok;
+};
+BucketShape bucket_shape(int64_t C, int64_t n, int64_t M);
+// The CSR order of the entries (after launch_select): entries bucketed by
+// (chain, event block), each bucket ordered by (event, group, entry) in LDS;
+// csr, pos, pev, pgr, head, nend and start.  bucket_buf: bucket_shape's
+// words ints; scan_part: scan_part_size(nb + 1) ints.
+void launch_build_csr(const CatView& cat, int C, int64_t n, BatchBufs b, int32_t* bucket_buf,
+                      int32_t* scan_part, hipStream_t s);
 // Two-phase catalogs: b.rows = the entries in CSR order, those of P groups
 // first; *n_p (device) = their number.  flags: E + 1 ints of scratch.
 void launch_phase_rows(const CatView& cat, int64_t E, BatchBufs b, int32_t* flags,

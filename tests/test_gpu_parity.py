@@ -226,6 +226,33 @@ def test_exact_whitening_large_batches(ctx, faults_setup, n, C):
         assert err < 1e-10 and err < 2 * floor + 1e-11
 
 
+@pytest.mark.parametrize("which,n", [("tiny", 4096), ("faults10k", 65536), ("faults10k", 1 << 18)])
+def test_exact_whitening_lds_solver_equals_global(ctx, tiny_setup, faults_setup, monkeypatch,
+                                                  which, n):
+    """The LDS-resident solver (systems up to 3,328 nodes and 8,192 entries
+    with a core of at most 64 nodes) and the global-memory one give the same
+    z bit for bit: on tiny at n = 4096 some groups keep cores too large for
+    the one-wave CG and go to the global solver inside the same launch pair;
+    faults10k at 2^16 fits in LDS everywhere; at 2^18 the groups exceed it.
+    Both runs also meet T4 (within 1e-10 of the batch system)."""
+    cat, _, cid, nid = tiny_setup if which == "tiny" else faults_setup
+    prob = lk.load(cat)
+    theta = synth.random_theta(cat, 33)
+    outs = []
+    for forced in ("0", "1"):
+        monkeypatch.setenv("SPIDER_TREE_GLOBAL", forced)
+        out = ctx.batch_terms(cid, nid, dev(theta), None, n=n, seed=11, chain=0, step=2)
+        outs.append((host(out["r"]), host(out["z"])))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    idx = obatch.batch_indices(11, 3 if which == "tiny" else 5, 0, 2, cat.N, n)
+    ev_i, ev_j, g, _, w = lk.gather(prob, idx)
+    r, z = outs[0]
+    Sz = sigma_apply(z, w, g, ev_i, ev_j, prob.M, prob.sigma, prob.kappa, lk.WHITEN_EXACT)
+    err = float(np.max(np.abs(Sz - r) / (np.abs(r) + 1e-3)))
+    print(f"whitening {which} n={n}: LDS and global solvers equal, error {err:.3e}")
+    assert err < 1e-10
+
+
 # ----------------------------------------------------------------- gradient
 
 @pytest.mark.parametrize("which,n", [("tiny", 1024), ("tiny", 1), ("tiny", 32000),
