@@ -133,7 +133,7 @@ struct Workspace {
   DevBuf obs, ev, sta, tau, w, start, csr, ckey, pos, pev, pgr, head, nend, rows, net_out, T, gT,
       r, z, zp, wr;
   DevBuf act, sys, list, nbr, wgt, vec, ivec, scan_part, bucket, phase_flags, n_p;
-  DevBuf G, partial, thetabar, lp_tmp, err;
+  DevBuf G, partial, thetabar, lp_tmp, err, rpart;
   int64_t e_cur = 0;  // entries of the last reserve: the layout of ivec
 
   // obs_total: slots of all sets; keys_total: sum of (C M + 1); sys_total:
@@ -183,6 +183,7 @@ struct Workspace {
     RES(phase_flags, (E + 1) * 4);
     RES(n_p, 16);
     RES(G, CM * 32);
+    RES(rpart, reduce_part_bytes(2 * obs_total));
     RES(partial, (CM / 4096 + C + 1) * 32);
     RES(thetabar, C * 32);
     RES(lp_tmp, 4096 * 8);
@@ -503,7 +504,7 @@ int post_network(spider_ctx* ctx, const Catalog& cat, const Net& net, const Net&
   launch_residual(cv, C, n, theta, theta_stride, whiten, b, sv, ctx->stream);
   if (whiten == SPIDER_WHITEN_EXACT)
     HIPCK(exact_whiten(cv, C, n, b, sv, ws.err.as<int>(), ctx->stream), "exact whitening");
-  if (grad) launch_reduce(cv, C, n, scale, b, ws.G.as<double>(), ctx->stream);
+  if (grad) launch_reduce(cv, C, n, scale, b, ws.G.as<double>(), ws.rpart.p, ctx->stream);
   HIPCK(hipGetLastError(), "step kernels");
   return SPIDER_OK;
 }

@@ -1076,21 +1076,91 @@ __global__ void k_exact_z(int64_t Q, CatView cat, BatchBufs b, const double* y) 
 
 // ---------------------------------------------------------------- reduce
 
-__global__ void k_reduce(int64_t K, double scale, BatchBufs b, double* G) {
+// Per-event gradient sums over the CSR segments, read position by position
+// (coalesced).  Pass A: each wave takes 64 consecutive positions, forms
+// v = s z (dT/dx, 1) per position (s = +scale for the entry of event i, -scale
+// for event j) and runs a segmented inclusive scan over its lanes (fixed
+// shuffle order); a segment that starts and ends inside the wave is written
+// to G at its last lane, the wave's first and last segment sums go to
+// part[w] = {head, tail} when they reach past the wave.  Pass B: every key
+// whose segment spans waves sums tail(first wave) + head(next waves) in wave
+// order; empty keys get 0.  Every sum has a fixed order.
+constexpr int kReduceTB = 256;
+
+__global__ __launch_bounds__(kReduceTB) void k_reduce_waves(int64_t E, int64_t n, int M,
+                                                           double scale, BatchBufs b, double* G,
+                                                           double4* part) {
+  const int64_t p = (int64_t)blockIdx.x * kReduceTB + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int64_t w = p >> 6, wave0 = w << 6;
+  // keys are >= 0; outside [0, E) the sentinels -1 (before) and -2 (after),
+  // -3 for a lane past the end
+  auto key_of = [&](int64_t q) -> int64_t {
+    return q < 0 ? -1 : q >= E ? -2 : (q / (2 * n)) * (int64_t)M + b.pev[q];
+  };
+  const bool valid = p < E;
+  const int64_t key = valid ? key_of(p) : -3;
+  double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+  if (valid) {
+    const double cz = ((b.csr[p] & 1) ? -scale : scale) * b.zp[p];
+    const double* g = b.gT + p * 3;
+    v0 = cz * g[0];
+    v1 = cz * g[1];
+    v2 = cz * g[2];
+    v3 = cz;
+  }
+  const int64_t prev = __shfl_up(key, 1, 64), next = __shfl_down(key, 1, 64);
+  const bool head = lane == 0 || prev != key;
+  const bool tail = lane == 63 || next != key;
+  // lane of this lane's segment head within the wave (inclusive max scan)
+  int hl = head ? lane : 0;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(hl, d, 64);
+    if (lane >= d) hl = max(hl, y);
+  }
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const double y0 = __shfl_up(v0, d, 64), y1 = __shfl_up(v1, d, 64);
+    const double y2 = __shfl_up(v2, d, 64), y3 = __shfl_up(v3, d, 64);
+    if (lane - d >= hl) {
+      v0 = y0 + v0;
+      v1 = y1 + v1;
+      v2 = y2 + v2;
+      v3 = y3 + v3;
+    }
+  }
+  if (!valid || !tail) return;
+  // does the segment reach past the wave's first or last position?
+  const bool open_left = hl == 0 && key_of(wave0 - 1) == key;
+  const bool open_right = lane == 63 && key_of(p + 1) == key;
+  if (!open_left && !open_right) {
+    *(double4*)(G + key * 4) = make_double4(v0, v1, v2, v3);
+    return;
+  }
+  if (open_left) part[2 * w] = make_double4(v0, v1, v2, v3);       // head of the wave
+  if (open_right) part[2 * w + 1] = make_double4(v0, v1, v2, v3);  // tail of the wave
+}
+
+__global__ void k_reduce_keys(int64_t K, BatchBufs b, double* G, const double4* part) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= K) return;
-  const int32_t p0 = b.start[k], p1 = b.start[k + 1];
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  for (int32_t p = p0; p < p1; ++p) {
-    const double cz = ((b.csr[p] & 1) ? -scale : scale) * b.zp[p];
-    const double* g = b.gT + (int64_t)p * 3;
-    s0 += cz * g[0];
-    s1 += cz * g[1];
-    s2 += cz * g[2];
-    s3 += cz;
+  const int64_t p0 = b.start[k], p1 = b.start[k + 1];
+  if (p1 == p0) {
+    *(double4*)(G + k * 4) = make_double4(0.0, 0.0, 0.0, 0.0);
+    return;
   }
-  double4* out = (double4*)(G + k * 4);
-  *out = make_double4(s0, s1, s2, s3);
+  const int64_t w0 = p0 >> 6, w1 = (p1 - 1) >> 6;
+  if (w0 == w1) return;  // written by k_reduce_waves
+  double4 s = part[2 * w0 + 1];
+  for (int64_t w = w0 + 1; w <= w1; ++w) {
+    const double4 h = part[2 * w];
+    s.x += h.x;
+    s.y += h.y;
+    s.z += h.z;
+    s.w += h.w;
+  }
+  *(double4*)(G + k * 4) = s;
 }
 
 // ---------------------------------------------------------------- per-slot outputs
@@ -1586,11 +1656,15 @@ hipError_t exact_whiten(const CatView& cat, int C, int64_t n, BatchBufs b, Solve
   return hipGetLastError();
 }
 
+int64_t reduce_part_bytes(int64_t E) { return (ceil_div(E, 64) + 1) * 2 * (int64_t)sizeof(double4); }
+
 void launch_reduce(const CatView& cat, int C, int64_t n, double scale, BatchBufs b, double* G,
-                   hipStream_t s) {
-  (void)n;
-  const int64_t K = (int64_t)C * cat.M;
-  hipLaunchKernelGGL(k_reduce, dim3(grid_for(K)), dim3(kBlock), 0, s, K, scale, b, G);
+                   void* part, hipStream_t s) {
+  const int64_t K = (int64_t)C * cat.M, E = 2 * (int64_t)C * n;
+  hipLaunchKernelGGL(k_reduce_waves, dim3((unsigned)ceil_div(E, kReduceTB)), dim3(kReduceTB), 0, s,
+                     E, n, cat.M, scale, b, G, (double4*)part);
+  hipLaunchKernelGGL(k_reduce_keys, dim3(grid_for(K)), dim3(kBlock), 0, s, K, b, G,
+                     (const double4*)part);
 }
 
 void launch_batch_terms_out(int64_t n, const BatchBufs& b, const double* theta, double* T_i,

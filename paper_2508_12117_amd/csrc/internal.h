@@ -190,9 +190,12 @@ void launch_residual(const CatView& cat, int C, int64_t n, const double* theta,
 hipError_t exact_whiten(const CatView& cat, int C, int64_t n, BatchBufs b, SolveBufs sv, int* err,
                         hipStream_t s);
 // G_lik[c][m] = scale * sum over the entries of (chain c, event m) of
-// +-z (dT/dx, 1), one CSR segment each, in CSR order.
+// +-z (dT/dx, 1), one CSR segment each, summed in a fixed order (scans over
+// waves of 64 positions, then the waves in order).
 void launch_reduce(const CatView& cat, int C, int64_t n, double scale, BatchBufs b, double* G,
-                   hipStream_t s);
+                   void* part, hipStream_t s);
+// Scratch bytes of launch_reduce's part for E entries.
+int64_t reduce_part_bytes(int64_t E);
 // thetabar[c] = mean over events of theta[c] (4 values per chain).
 void launch_centroid(const double* theta, int C, int M, double* partial, double* thetabar,
                      hipStream_t s);

@@ -15,8 +15,9 @@ __device__ inline void assemble_tt(const NetView& net, const double x[3], const 
   const double dist = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
   const double T0 = dist / net.v0;
   const double o = (double)no.o;
-  const double sp = fmax(o, 0.0) + log1p(exp(-fabs(o)));                          // softplus
-  const double sg = o >= 0.0 ? 1.0 / (1.0 + exp(-o)) : exp(o) / (1.0 + exp(o));  // sigmoid
+  const double ex = exp(-fabs(o));                                // one exponential for both
+  const double sp = fmax(o, 0.0) + log1p(ex);                     // softplus
+  const double sg = o >= 0.0 ? 1.0 / (1.0 + ex) : ex / (1.0 + ex);  // sigmoid
   const double f = sp / kLn2;
   T = T0 * f;
   const double a = f / (net.v0 * dist);
