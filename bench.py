@@ -79,6 +79,9 @@ def parse():
                          "10) and compare the BF16 and FP32 posterior moments (0: skip)")
     ap.add_argument("--no-graph-compare", action="store_true",
                     help="skip the graph-against-stream rates of the tiny catalog")
+    ap.add_argument("--configs", action="store_true",
+                    help="instead of the bench line: rates and errors of the tiny and "
+                         "faults10k workloads on the GPU (FP32, BF16) and in the oracle")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="first copy BYTES between two device buffers (one device-to-device "
                          "copy of known size, to calibrate HBM byte counters in a profile)")
@@ -296,6 +299,86 @@ def cpu_baseline(cat, net, n, seed):
                             "sample": f"one pSGLD step of 1 chain, batch {n1} ({dt1:.1f} s)"}}
 
 
+def config_table(spider, seed=23, steps=200, burn=100):
+    """The small workloads, each one chain from the initial locations with the
+    batch and noise streams of `seed`, `steps` pSGLD steps, moments over the
+    states after steps burn .. steps-1: tiny (200 events, 32,000 observations,
+    minibatch 1,024, 6-32x3-1) and faults10k (10,000 events, 5,000,000
+    observations, minibatch 65,536, 6-128x4-1).  Per precision: the GPU rate
+    (graph replay, dd-obs/s), travel-time errors on 4,096 sampled rows, and
+    the posterior-moment errors against the FP64 oracle's run of the same
+    streams (tiny: run here, whole; faults10k: the stored 200-step run of
+    tests/golden for its 500 sampled events).  The oracle rate is timed on
+    the whole tiny run and on a 3-step prefix of faults10k."""
+    import numpy as np
+    import torch
+    from threadpoolctl import threadpool_info
+
+    from oracle import likelihood as lk
+    from oracle import sampler
+    from paper_2508_12117_amd import synth
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    golden = os.path.join(ROOT, "tests", "golden", "trajectory_faults10k.txt")
+    diag = [0, 4, 7, 9]
+    out = {"host": host_description()}
+    for name, stream, oracle_steps in (("tiny", 3, steps), ("faults10k", 5, 3)):
+        cat = synth.make_catalog(name)
+        net = synth.net_for(cat)
+        prob = lk.load(cat)
+        n = cat.wl.batch
+        cfg = sampler.SamplerConfig(step=cat.wl.step_size, beta2=cat.wl.beta2, eps_p=cat.wl.eps_p,
+                                    seed=seed, burn_in=burn, thin=1)
+        log(f"{name}: oracle, {oracle_steps} steps")
+        t0 = time.perf_counter()
+        ch, _ = sampler.run(prob, net, cfg, n, oracle_steps, stream=stream, chain_id=0)
+        t_or = time.perf_counter() - t0
+        if oracle_steps == steps:
+            ev = np.arange(cat.M)
+            mean_o, cov_o = ch.mom.mean, sampler.covariance(ch.mom)
+        else:
+            ref = np.loadtxt(golden)
+            ev = ref[:, 0].astype(np.int64)
+            mean_o, cov_o = ref[:, 1:5], ref[:, 5:15]
+        sd = np.sqrt(cov_o[:, diag])
+        row = {"events": cat.M, "observations": cat.N, "batch": n, "steps": steps,
+               "net": f"6-{net.H}x{net.D}-1",
+               "oracle": {"dd_obs_per_s": n * oracle_steps / t_or, "steps_timed": oracle_steps,
+                          "cores": int(threads)},
+               "moment_events": int(len(ev))}
+        with spider.Context(0) as ctx:
+            cid = ctx.load_catalog(cat, whiten=spider.WHITEN_EXACT, stream_id=stream)
+            nid = ctx.load_net(net)
+            for pname, prec in (("fp32", spider.FP32), ("bf16", spider.BF16)):
+                sets = [(cid, nid, 1, n, prec)]
+                walls = []
+                for _ in range(2):  # the second run is timed (the first tunes and warms)
+                    ctx.reset_chains(cid, 1)
+                    ctx.sync()
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    ctx.sgld_steps(sets, steps, step=cat.wl.step_size, beta2=cat.wl.beta2,
+                                   eps_p=cat.wl.eps_p, seed=seed, burn_in=burn, thin=1)
+                    ctx.sync()
+                    torch.cuda.synchronize()
+                    walls.append(time.perf_counter() - t0)
+                mean = torch.empty(cat.M, 4, dtype=torch.float64, device="cuda")
+                cov = torch.empty(cat.M, 10, dtype=torch.float64, device="cuda")
+                ctx.moments(cid, 0, mean, cov)
+                mean, cov = mean.cpu().numpy()[ev], cov.cpu().numpy()[ev]
+                em = np.abs(mean - mean_o) / sd
+                ec = np.linalg.norm(cov - cov_o, axis=1) / np.linalg.norm(cov_o, axis=1)
+                row[pname] = {
+                    "dd_obs_per_s": n * steps / walls[-1], "ms_per_step": 1e3 * walls[-1] / steps,
+                    "T1_T2": sample_error(ctx, spider, cat, net, nid, prec),
+                    "T6_mean_diff_over_sd": {"median": float(np.median(em)),
+                                             "p99": float(np.percentile(em, 99)),
+                                             "max": float(em.max())},
+                    "T7_cov_rel": {"median": float(np.median(ec)), "max": float(ec.max())}}
+                log(f"{name} {pname}: {row[pname]['dd_obs_per_s']:.3e} dd-obs/s")
+        out[name] = row
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -305,6 +388,9 @@ def main():
     import torch
 
     from paper_2508_12117_amd import spider, synth
+    if args.configs:
+        config_table(spider)
+        return
     if args.copy_probe > 0:
         a = torch.ones(args.copy_probe, dtype=torch.uint8, device="cuda")
         b = torch.empty_like(a)
