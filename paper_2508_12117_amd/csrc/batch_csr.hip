@@ -186,7 +186,8 @@ constexpr int64_t kBucketHB = 65536;  // entries per counting block (within one 
 constexpr int kBucketTB = 1024;       // threads of the counting and scatter blocks
 constexpr int64_t kBucketMax = 16384; // buckets per chain (LDS counters)
 constexpr int kBucketMaxSB = 13;      // at most 8,192 events per bucket
-constexpr int kSortTB = 256;          // threads per bucket
+constexpr int kSortTB = 512;          // threads per bucket
+constexpr int64_t kBucketTarget = 4096;  // average records per bucket aimed at
 constexpr int kSegShort = 32;         // event segments up to this length: one thread
 
 // A record: event within its bucket (bits 48..60), group (32..47), entry.
@@ -295,11 +296,11 @@ __device__ void block_sort_any(int32_t len, Get&& get, Put&& put) {
 // first position (head) and, at that position, one past the node's last
 // (nend), and pos[e] with the single-entry bit; start[] of the bucket's
 // events.  A bucket of up to cap records (held in registers after one read)
-// is ordered in LDS: when no event holds more than kSegShort of them, by a
-// counting sort on the event (placement order within an event from LDS
-// atomics) and an insertion sort of each event's segment by one thread;
-// otherwise by a sort network over the bucket.  A larger bucket is sorted in
-// place in global memory.  Dynamic LDS: cap records, then 2 (2^sb + 1) ints.
+// is ordered in LDS: by a counting sort on the event (placement order within
+// an event from LDS atomics), then an insertion sort of each event's segment by one thread, or
+// for a segment longer than kSegShort by every record's rank within it.  A
+// larger bucket is sorted in place in global memory by a sort network.
+// Dynamic LDS: cap records, then 2 (2^sb + 1) ints.
 template <int RPT>  // records per thread held in registers: cap = RPT kSortTB
 __global__ __launch_bounds__(kSortTB) void k_bucket_sort(int64_t nbk, int sb, int M,
                                                         const int32_t* base, BatchBufs b) {
@@ -372,13 +373,15 @@ __global__ __launch_bounds__(kSortTB) void k_bucket_sort(int64_t nbk, int sb, in
   for (int32_t m = t; m < nev; m += kSortTB) key_start[m] = r0 + soff[m];
 
   // ---- the order
-  if (in_lds && short_segs) {
+  if (in_lds) {
 #pragma unroll
     for (int u = 0; u < RPT; ++u)
       if (t + u * kSortTB < len) k_sh[atomicAdd(&cur[(int32_t)(reg[u] >> 48)], 1)] = reg[u];
     __syncthreads();
+    // short segments: insertion sort by one thread each
     for (int32_t m = t; m < nev; m += kSortTB) {
       const int32_t p0 = soff[m], p1 = soff[m + 1];
+      if (p1 - p0 > kSegShort) continue;
       for (int32_t i = p0 + 1; i < p1; ++i) {
         const uint64_t x = k_sh[i];
         int32_t j = i;
@@ -389,12 +392,31 @@ __global__ __launch_bounds__(kSortTB) void k_bucket_sort(int64_t nbk, int sb, in
         k_sh[j] = x;
       }
     }
-  } else if (in_lds) {
+    if (!short_segs) {
+      // longer ones: every record's rank among its segment's (the records
+      // are distinct: they hold the entry), then each moves to its rank
+      int32_t dst[RPT];
+      uint64_t val[RPT];
 #pragma unroll
-    for (int u = 0; u < RPT; ++u)
-      if (t + u * kSortTB < len) k_sh[t + u * kSortTB] = reg[u];
-    __syncthreads();
-    block_sort_any(len, [&](int32_t i) { return k_sh[i]; }, [&](int32_t i, uint64_t x) { k_sh[i] = x; });
+      for (int u = 0; u < RPT; ++u) {
+        const int32_t i = t + u * kSortTB;
+        dst[u] = -1;
+        val[u] = 0;
+        if (i >= len) continue;
+        const uint64_t x = k_sh[i];
+        const int32_t m = (int32_t)(x >> 48);
+        const int32_t p0 = soff[m], p1 = soff[m + 1];
+        if (p1 - p0 <= kSegShort) continue;
+        int32_t rank = 0;
+        for (int32_t j = p0; j < p1; ++j) rank += k_sh[j] < x ? 1 : 0;
+        dst[u] = p0 + rank;
+        val[u] = x;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < RPT; ++u)
+        if (dst[u] >= 0) k_sh[dst[u]] = val[u];
+    }
   } else {
     block_sort_any(len, [&](int32_t i) { return rec[i]; }, [&](int32_t i, uint64_t x) { rec[i] = x; });
   }
@@ -1514,9 +1536,11 @@ void launch_select(const CatView& cat, int C, int64_t n, const int64_t* idx, uin
 
 BucketShape bucket_shape(int64_t C, int64_t n, int64_t M) {
   BucketShape bs;
-  // about 512 entries per bucket on average (2 n 2^sb / M per chain)
+  // about kBucketTarget / 2 .. kBucketTarget entries per bucket on average
+  // (2 n 2^sb / M per chain): few enough buckets that the scatter writes runs
+  // of records, one workgroup of kSortTB threads per bucket
   int sb = 0;
-  while (sb < kBucketMaxSB && (2 * n << (sb + 1)) / std::max<int64_t>(M, 1) <= 512) ++sb;
+  while (sb < kBucketMaxSB && (2 * n << (sb + 1)) / std::max<int64_t>(M, 1) <= kBucketTarget) ++sb;
   while (sb < kBucketMaxSB && ceil_div(M, (int64_t)1 << sb) > kBucketMax) ++sb;
   bs.sb = sb;
   bs.nbk = ceil_div(M, (int64_t)1 << sb);
@@ -1553,11 +1577,12 @@ void launch_build_csr(const CatView& cat, int C, int64_t n, BatchBufs b, int32_t
   launch_scan(tot, bs.nb + 1, scan_part, s);
   hipLaunchKernelGGL(k_bucket_scatter, grid, dim3(kBucketTB), lds_count, s, n, bs.sb, bs.nbk,
                      (const int32_t*)counts, (const int32_t*)tot, b);
-  // records held per thread: about four times the average bucket, 1,024 to 8,192
-  const int64_t avg = ceil_div(E, bs.nb);
-  if (avg <= 256) launch_bucket_sort<4>(bs, cat.M, tot, b, s);
-  else if (avg <= 512) launch_bucket_sort<8>(bs, cat.M, tot, b, s);
-  else if (avg <= 1024) launch_bucket_sort<16>(bs, cat.M, tot, b, s);
+  // records held per thread: room for three times the average bucket, 2,048
+  // to 16,384 (a larger bucket is sorted in global memory)
+  const int64_t need = 3 * ceil_div(E, bs.nb);
+  if (need <= 4 * kSortTB) launch_bucket_sort<4>(bs, cat.M, tot, b, s);
+  else if (need <= 8 * kSortTB) launch_bucket_sort<8>(bs, cat.M, tot, b, s);
+  else if (need <= 16 * kSortTB) launch_bucket_sort<16>(bs, cat.M, tot, b, s);
   else launch_bucket_sort<32>(bs, cat.M, tot, b, s);
 }
 
