@@ -132,7 +132,7 @@ struct Net {
 struct Workspace {
   DevBuf obs, ev, sta, tau, w, start, csr, ckey, pos, pev, pgr, head, nend, rows, net_out, T, gT,
       r, z, zp, wr;
-  DevBuf act, sys, list, nbr, wgt, vec, ivec, scan_part, bucket, phase_flags, n_p;
+  DevBuf act, sys, list, nbr, wgt, vec, ivec, nrec, scan_part, bucket, phase_flags, n_p;
   DevBuf G, partial, thetabar, lp_tmp, err, rpart;
   int64_t e_cur = 0;  // entries of the last reserve: the layout of ivec
 
@@ -173,6 +173,7 @@ struct Workspace {
     RES(wgt, E * 8);
     RES(vec, E * 8 * 7);
     RES(ivec, E * 4 * 6 + sys_total * 4);
+    RES(nrec, E * sizeof(NodeRec));
     e_cur = E;
     int64_t sp = scan_part_size(E + 1);
     if (scan_part_size(keys_total) > sp) sp = scan_part_size(keys_total);
@@ -228,6 +229,7 @@ struct Workspace {
     v.ivec = ivec.as<int32_t>();
     v.lidx = ivec.as<int32_t>() + 5 * e_cur;
     v.spill = ivec.as<int32_t>() + 6 * e_cur;
+    v.nrec = nrec.as<NodeRec>();
     v.scan_part = scan_part.as<int32_t>();
     return v;
   }

@@ -575,10 +575,12 @@ __global__ __launch_bounds__(kListTB) void k_list_fill(int64_t n, int L, int64_t
       sv.nbr[f] = b.head[b.pos[e ^ 1] & kPosMask];
       sv.wgt[f] = x.x;
     }
-    sv.vec[p] = A;            // A
-    sv.vec[E + p] = rhs;      // b
-    sv.ivec[p] = kActive;     // state
-    sv.ivec[2 * E + p] = -1;  // par
+    NodeRec nr;
+    nr.A = A;
+    nr.b = rhs;
+    nr.q = (int32_t)p;
+    nr.ne = b.nend[p] - (int32_t)p;
+    sv.nrec[at] = nr;  // list order: the LDS solver reads its system in one stream
   }
 }
 
@@ -608,6 +610,7 @@ struct SolveArgs {
   double accept2;  // after its passes, |res|^2 > accept2 |rhs|^2 raises kErrSolve
   int* err;        // error bits of the step
   const int32_t* lidx;  // index of a node in its system's list (at its first position)
+  const NodeRec* nrec;  // the nodes in list order
   int32_t* spill;       // per system: 1 if k_tree_solve takes it
   int lds_off;          // 1: every system to k_tree_solve (SPIDER_TREE_GLOBAL, for tests)
 };
@@ -880,6 +883,15 @@ __global__ __launch_bounds__(TB) void k_tree_solve(SolveArgs a) {
   int32_t nl = a.sys[(blockIdx.x + 1) * a.nb] - off;
   if (nl <= 0) return;
   const int t = threadIdx.x;
+  // the system's nodes at their first positions: A, b, active, no parent
+  for (int32_t k = t; k < nl; k += TB) {
+    const NodeRec nr = a.nrec[off + k];
+    a.A[nr.q] = nr.A;
+    a.b[nr.q] = nr.b;
+    a.state[nr.q] = kActive;
+    a.par[nr.q] = -1;
+  }
+  __syncthreads();
   int32_t* act = a.list + off;
   int32_t* act_next = a.next + off;
   int32_t* elim = a.elim + off;
@@ -1272,33 +1284,24 @@ __global__ __launch_bounds__(TB) void k_tree_lds(SolveArgs a) {
   }
 
   // ---- 1. nodes (first position, entry count clamped above kLdsEntries, A,
-  // b), then the entry offsets by an exclusive scan over contiguous chunks;
-  // each thread issues the list reads of all its nodes, then their dependent
-  // reads, so that a thread waits for two memory latencies, not two per node
+  // b) from the list-ordered records, one coalesced stream per system, then
+  // the entry offsets by an exclusive scan over contiguous chunks
   {
     constexpr int KN = (kLdsNodes + TB - 1) / TB;
-    int32_t q[KN], ne[KN];
-    double va[KN], vb[KN];
+    NodeRec nr[KN];
 #pragma unroll
     for (int u = 0; u < KN; ++u) {
       const int32_t i = t + u * TB;
-      q[u] = i < N ? a.list[off + i] : 0;
-    }
-#pragma unroll
-    for (int u = 0; u < KN; ++u) {
-      const int32_t i = t + u * TB;
-      ne[u] = i < N ? a.nend[q[u]] : 0;
-      va[u] = i < N ? a.A[q[u]] : 0.0;
-      vb[u] = i < N ? a.b[q[u]] : 0.0;
+      if (i < N) nr[u] = a.nrec[off + i];
     }
 #pragma unroll
     for (int u = 0; u < KN; ++u) {
       const int32_t i = t + u * TB;
       if (i >= N) continue;
-      gpos[i] = q[u];
-      eoff[i] = (uint16_t)min(ne[u] - q[u], kLdsEntries + 1);
-      sA[i] = va[u];
-      sB[i] = vb[u];
+      gpos[i] = nr[u].q;
+      eoff[i] = (uint16_t)min(nr[u].ne, kLdsEntries + 1);
+      sA[i] = nr[u].A;
+      sB[i] = nr[u].b;
       sst[i] = kLActive;
       snst[i] = kLActive;
     }
@@ -1671,6 +1674,7 @@ hipError_t exact_whiten(const CatView& cat, int C, int64_t n, BatchBufs b, Solve
   a.accept2 = 1e-16;
   a.err = err;
   a.lidx = sv.lidx;
+  a.nrec = sv.nrec;
   a.spill = sv.spill;
   const char* tg = std::getenv("SPIDER_TREE_GLOBAL");
   a.lds_off = (tg && tg[0] == '1') ? 1 : 0;

@@ -76,6 +76,15 @@ struct BatchBufs {
   double2* wr;      // [C n] (w, r) side by side, for the node gathers of the solver
 };
 
+// A node of the exact whitening in its system's list order: the diagonal A,
+// the right-hand side b, its first CSR position and its number of entries.
+struct NodeRec {
+  double A;
+  double b;
+  int32_t q;
+  int32_t ne;
+};
+
 // Scratch of the exact whitening of one chain set (all arrays indexed by CSR
 // position unless stated; a node is stored at its first position).
 struct SolveBufs {
@@ -88,6 +97,7 @@ struct SolveBufs {
   double* vec;        // [7][E] A, b, y, Wp, rr, p, ap
   int32_t* ivec;      // [5][E] state, nstate, par, next list, elimination order
   int32_t* lidx;      // [E] at a node's first position: its index in its system's list
+  NodeRec* nrec;      // [E] the nodes in list order (same offsets as list)
   int32_t* spill;     // [C L] 1: the system is solved from global memory (too large for LDS)
   int32_t* scan_part; // scratch of the scans
 };
