@@ -165,7 +165,7 @@ struct Workspace {
     RES(r, Cn * 8);
     RES(z, Cn * 8);
     RES(zp, E * 8);
-    RES(wr, Cn * 16);
+    RES(wr, Cn * sizeof(WRec));
     RES(act, E * 4);
     RES(sys, sys_total * 4);
     RES(list, E * 4);
@@ -215,7 +215,7 @@ struct Workspace {
     b.r = r.as<double>();
     b.z = z.as<double>();
     b.zp = zp.as<double>();
-    b.wr = wr.as<double2>();
+    b.wr = wr.as<WRec>();
     return b;
   }
   SolveBufs solve(int64_t sys_off) const {

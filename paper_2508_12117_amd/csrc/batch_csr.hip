@@ -506,9 +506,15 @@ __global__ void k_residual(CatView cat, int C, int64_t n, const double* theta, i
     // restricted to it is sigma^2 + 2 kappa^2 w
     z = r / (s2 + 2.0 * cat.kappa * cat.kappa * b.w[q]) * zs;
   } else {
-    b.wr[q] = make_double2(b.w[q], r);
-    act[b.head[pi & kPosMask]] = 1;
-    act[b.head[pj & kPosMask]] = 1;
+    WRec x;
+    x.w = b.w[q];
+    x.r = r;
+    x.hi = b.head[pi & kPosMask];
+    x.hj = b.head[pj & kPosMask];
+    x.pad[0] = x.pad[1] = 0;
+    b.wr[q] = x;
+    act[x.hi] = 1;
+    act[x.hj] = 1;
     return;  // z from the solve (k_exact_z)
   }
   b.z[q] = z;
@@ -569,11 +575,11 @@ __global__ __launch_bounds__(kListTB) void k_list_fill(int64_t n, int L, int64_t
     double A = lambda, rhs = 0.0;
     for (int32_t f = (int32_t)p; f < b.nend[p]; ++f) {
       const int32_t e = b.csr[f];
-      const double2 x = b.wr[e >> 1];
-      A += x.x;
-      rhs += ((e & 1) ? -1.0 : 1.0) * sqrt(x.x) * x.y;
-      sv.nbr[f] = b.head[b.pos[e ^ 1] & kPosMask];
-      sv.wgt[f] = x.x;
+      const WRec x = b.wr[e >> 1];  // one gather: weight, residual, both nodes
+      A += x.w;
+      rhs += ((e & 1) ? -1.0 : 1.0) * sqrt(x.w) * x.r;
+      sv.nbr[f] = (e & 1) ? x.hi : x.hj;  // the node at the other end
+      sv.wgt[f] = x.w;
     }
     NodeRec nr;
     nr.A = A;
@@ -1091,6 +1097,13 @@ __global__ __launch_bounds__(TB) void k_tree_solve(SolveArgs a) {
     }
     __syncthreads();
   }
+  // y at each position of its node as well (see k_tree_lds)
+  const int32_t n_sys = a.sys[(blockIdx.x + 1) * a.nb] - off;
+  for (int32_t k = t; k < n_sys; k += TB) {
+    const NodeRec nr = a.nrec[off + k];
+    const double yq = a.y[nr.q];
+    for (int32_t x = 1; x < nr.ne; ++x) a.y[nr.q + x] = yq;
+  }
 }
 
 __global__ void k_exact_z(int64_t Q, CatView cat, BatchBufs b, const double* y) {
@@ -1098,11 +1111,11 @@ __global__ void k_exact_z(int64_t Q, CatView cat, BatchBufs b, const double* y) 
   if (q >= Q) return;
   const int32_t pi = b.pos[2 * q], pj = b.pos[2 * q + 1];
   if ((pi & pj) & kSingle) return;  // solved in closed form by k_residual
-  const double yi = y[b.head[pi & kPosMask]];
-  const double yj = y[b.head[pj & kPosMask]];
-  const double2 wr = b.wr[q];
+  const WRec wr = b.wr[q];
+  const double yi = y[pi & kPosMask];  // the solvers leave y at every position of a node
+  const double yj = y[pj & kPosMask];
   const double zs = b.sta[2 * q] >= cat.L_p ? cat.zscale_s : 1.0;
-  const double z = (wr.y - sqrt(wr.x) * (yi - yj)) / (cat.sigma * cat.sigma) * zs;
+  const double z = (wr.r - sqrt(wr.w) * (yi - yj)) / (cat.sigma * cat.sigma) * zs;
   b.z[q] = z;
   b.zp[pi & kPosMask] = z;
   b.zp[pj & kPosMask] = z;
@@ -1511,7 +1524,12 @@ __global__ __launch_bounds__(TB) void k_tree_lds(SolveArgs a) {
     }
     __syncthreads();
   }
-  for (int32_t i = t; i < N; i += TB) a.y[gpos[i]] = sB[i];
+  // y of every node at each of its positions, so that the whitened residual
+  // of an observation reads it at its entries' positions
+  for (int32_t i = t; i < N; i += TB) {
+    const int32_t ne = eoff[i + 1] - eoff[i];
+    for (int32_t x = 0; x < ne; ++x) a.y[gpos[i] + x] = sB[i];
+  }
   if (t == 0) a.spill[sys_id] = 0;
 }
 

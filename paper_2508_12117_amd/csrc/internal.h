@@ -52,6 +52,17 @@ struct CatView {
 // event) key c M + m, and inside each event's segment by (group, entry), so
 // that the entries of one (chain, group, event) node of the whitening are
 // contiguous and every sum over a segment or a node runs in a fixed order.
+// One observation of the exact whitening as its solver gathers it, in one
+// 32-byte record: weight, residual and the first CSR positions of the nodes
+// of its two entries.
+struct WRec {
+  double w;
+  double r;
+  int32_t hi;
+  int32_t hj;
+  int32_t pad[2];
+};
+
 struct BatchBufs {
   int64_t* obs;     // [C n] observation index
   int32_t* ev;      // [E] event of each entry
@@ -73,7 +84,7 @@ struct BatchBufs {
   double* gT;       // [E][3] source gradient at each CSR position
   double* r;        // [C n] residual
   double* z;        // [C n] whitened residual
-  double2* wr;      // [C n] (w, r) side by side, for the node gathers of the solver
+  WRec* wr;         // [C n] per observation taken by the solver: (w, r, its two nodes)
 };
 
 // A node of the exact whitening in its system's list order: the diagonal A,
