@@ -136,6 +136,69 @@ struct Workspace {
   DevBuf G, partial, thetabar, lp_tmp, err, rpart;
   int64_t e_cur = 0;  // entries of the last reserve: the layout of ivec
 
+  // A second copy of what the selection and the CSR build write (and their
+  // scratch), so that the next step's minibatch can be built while the
+  // current step still reads its own (graph replays of sampler steps).
+  struct Ahead {
+    DevBuf obs, ev, sta, tau, w, start, csr, ckey, pos, pev, pgr, head, nend, bucket, scan_part;
+    DevBuf scan_part0;  // scan scratch of a side-0 build beside the whitening's scans
+  } ahead;
+  hipError_t reserve_ahead(int64_t obs_total, int64_t keys_total, int64_t bucket_words) {
+    const int64_t Cn = obs_total, E = 2 * obs_total;
+    hipError_t e;
+#define RES(buf, bytes)                                     \
+  if ((e = buf.reserve((size_t)(bytes))) != hipSuccess) return e;
+    RES(ahead.obs, Cn * 8);
+    RES(ahead.ev, E * 4);
+    RES(ahead.sta, E * 4);
+    RES(ahead.tau, Cn * 8);
+    RES(ahead.w, Cn * 8);
+    RES(ahead.start, keys_total * 4);
+    RES(ahead.csr, E * 4);
+    RES(ahead.ckey, E * 8);
+    RES(ahead.pos, E * 4);
+    RES(ahead.pev, E * 4);
+    RES(ahead.pgr, E * 4);
+    RES(ahead.head, E * 4);
+    RES(ahead.nend, E * 4);
+    RES(ahead.bucket, bucket_words * 4);
+    int64_t sp = scan_part_size(bucket_words);
+    if (scan_part_size(keys_total) > sp) sp = scan_part_size(keys_total);
+    RES(ahead.scan_part, sp * 4);
+    RES(ahead.scan_part0, sp * 4);
+#undef RES
+    return hipSuccess;
+  }
+  // the batch buffers with the selection and CSR arrays of side 0 (the
+  // usual ones) or side 1 (ahead)
+  BatchBufs batch_side(int side) const {
+    BatchBufs b = batch();
+    if (side == 0) return b;
+    b.obs = ahead.obs.as<int64_t>();
+    b.ev = ahead.ev.as<int32_t>();
+    b.sta = ahead.sta.as<int32_t>();
+    b.tau = ahead.tau.as<double>();
+    b.w = ahead.w.as<double>();
+    b.start = ahead.start.as<int32_t>();
+    b.csr = ahead.csr.as<int32_t>();
+    b.ckey = ahead.ckey.as<uint64_t>();
+    b.pos = ahead.pos.as<int32_t>();
+    b.pev = ahead.pev.as<int32_t>();
+    b.pgr = ahead.pgr.as<int32_t>();
+    b.head = ahead.head.as<int32_t>();
+    b.nend = ahead.nend.as<int32_t>();
+    return b;
+  }
+  // CSR-build scratch of a side: side 0 outside the look-ahead branch uses
+  // the common scan scratch, inside it (beside the whitening) its own
+  int32_t* bucket_side(int side) const {
+    return side == 0 ? bucket.as<int32_t>() : ahead.bucket.as<int32_t>();
+  }
+  int32_t* scan_part_side(int side, bool branch = false) const {
+    return side == 1 ? ahead.scan_part.as<int32_t>()
+                     : branch ? ahead.scan_part0.as<int32_t>() : scan_part.as<int32_t>();
+  }
+
   // obs_total: slots of all sets; keys_total: sum of (C M + 1); sys_total:
   // the largest set's system-list counts (C L nb + 1); C, CM: the largest
   // set's chains and C M; bucket_words: the largest set's CSR-build buckets
@@ -252,6 +315,8 @@ struct spider_ctx {
   RowOut* noalloc_scratch = nullptr;  // this device's copy of the static scratch array
   bool graphs = true;                 // replay sampler steps from a captured HIP graph
   hipStream_t cap_stream = nullptr;   // the stream graphs are captured on
+  hipStream_t side_stream = nullptr;  // a second branch of the captured step
+  hipEvent_t fork = nullptr, join = nullptr;
 };
 
 namespace {
@@ -465,12 +530,12 @@ BatchBufs batch_at(const BatchBufs& b, int64_t obs_off, int64_t key_off) {
 // Before the network: the minibatch of each chain and its CSR order.
 void pre_network(spider_ctx* ctx, const Catalog& cat, int C, int64_t n, const int64_t* idx,
                  uint64_t seed, const int64_t* steps_dev, int64_t step_scalar, int chain0,
-                 const BatchBufs& b) {
+                 const BatchBufs& b, int side = 0, bool branch = false) {
   Workspace& ws = ctx->ws;
   const CatView cv = cat.view();
   launch_select(cv, C, n, idx, seed, steps_dev, step_scalar, chain0, b, ws.err.as<int>(),
                 ctx->stream);
-  launch_build_csr(cv, C, n, b, ws.bucket.as<int32_t>(), ws.scan_part.as<int32_t>(),
+  launch_build_csr(cv, C, n, b, ws.bucket_side(side), ws.scan_part_side(side, branch),
                    ctx->stream);
 }
 
@@ -579,8 +644,28 @@ struct FusedSets {
   std::vector<int64_t> obs_off;  // first slot of each set in the workspace
   std::vector<int64_t> key_off;  // first (chain, event) count of each set
   int64_t total_obs = 0;
+  int64_t bucket_words = 0;      // the largest set's CSR-build buckets
   DevBuf subs, row0;             // device RowSource table and its row offsets
+  DevBuf subs_ahead;             // the same over the second buffer side
 };
+
+// The network's row-source table of the fused sets over the selection and
+// CSR arrays of one buffer side.
+int upload_subs(spider_ctx* ctx, const spider_chainset* sets, int n_sets, const FusedSets& f,
+                int side, DevBuf& dst) {
+  const BatchBufs b = ctx->ws.batch_side(side);
+  std::vector<RowSource> subs(n_sets);
+  for (int k = 0; k < n_sets; ++k) {
+    const Catalog& cat = *get_cat(ctx, sets[k].cat_id);
+    const BatchBufs bk = batch_at(b, f.obs_off[k], f.key_off[k]);
+    subs[k] = csr_rows(cat, sets[k].batch, 2 * (f.obs_off[k + 1] - f.obs_off[k]),
+                       cat.theta.as<double>(), (int64_t)cat.M * 4, bk);
+  }
+  HIPCK(upload(dst, subs.data(), subs.size() * sizeof(RowSource), SPIDER_MEM_HOST, ctx->stream),
+        "row sources");
+  HIPCK(hipStreamSynchronize(ctx->stream), "row sources");
+  return SPIDER_OK;
+}
 
 int prepare_fused(spider_ctx* ctx, const spider_chainset* sets, int n_sets, FusedSets& f) {
   int64_t maxC = 1, maxCM = 1, maxS = 1, maxB = 1;
@@ -600,6 +685,7 @@ int prepare_fused(spider_ctx* ctx, const spider_chainset* sets, int n_sets, Fuse
     maxB = std::max(maxB, bs.words);
   }
   f.total_obs = f.obs_off[n_sets];
+  f.bucket_words = maxB;
   Workspace& ws = ctx->ws;
   HIPCK(ws.reserve(maxC, f.total_obs, f.key_off[n_sets], maxS, maxCM, maxB), "workspace");
   const BatchBufs b = ws.batch();
@@ -658,15 +744,72 @@ int fused_step(spider_ctx* ctx, const spider_chainset* sets, int n_sets, const F
   return SPIDER_OK;
 }
 
-// n fused steps replayed from one HIP graph of a step, captured on the
-// context's capture stream and launched on its stream.  Every kernel of a
-// step reads the chains' step counters on the device, so each replay is the
-// next step; the step holds no host synchronisation, allocation or memset.
-int graph_steps(spider_ctx* ctx, const spider_chainset* sets, int n_sets, const FusedSets& f,
-                const UpdateArgs& ua, int64_t n) {
-  if (n <= 0) return SPIDER_OK;
-  if (!ctx->cap_stream)
-    HIPCK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking), "capture stream");
+// One fused step whose selection and CSR arrays are on buffer side `side`
+// (built by the previous step), which also builds the next step's on the
+// other side: after the network launch, the next minibatch's selection and
+// CSR build (step counter + 1) run on a second branch beside the residual,
+// whitening, reduction and update of this one, and the step counters
+// advance once both branches are done.  The results equal those of
+// fused_step: the same kernels on the same inputs.
+int fused_step_ahead(spider_ctx* ctx, const spider_chainset* sets, int n_sets, const FusedSets& f,
+                     const UpdateArgs& ua, int side) {
+  Workspace& ws = ctx->ws;
+  const BatchBufs b = ws.batch_side(side), bn = ws.batch_side(1 - side);
+  RowSource src;
+  std::memset(&src, 0, sizeof(src));
+  src.mode = 2;
+  src.nsub = n_sets;
+  src.sub = (side == 0 ? f.subs : f.subs_ahead).as<RowSource>();
+  src.sub_row0 = f.row0.as<int64_t>();
+  src.rows = 2 * f.total_obs;
+  int rc = run_network(ctx, *get_net(ctx, sets[0].net_id), sets[0].precision, src, b.net_out);
+  if (rc != SPIDER_OK) return rc;
+  // the second branch: the next step's minibatches and CSR orders
+  const hipStream_t main = ctx->stream;
+  HIPCK(hipEventRecord(ctx->fork, main), "fork");
+  HIPCK(hipStreamWaitEvent(ctx->side_stream, ctx->fork, 0), "fork");
+  ctx->stream = ctx->side_stream;
+  for (int k = 0; k < n_sets; ++k) {
+    const Catalog& cat = *get_cat(ctx, sets[k].cat_id);
+    pre_network(ctx, cat, sets[k].n_chains, sets[k].batch, nullptr, ua.seed,
+                cat.steps.as<int64_t>(), 1, 0, batch_at(bn, f.obs_off[k], f.key_off[k]),
+                1 - side, true);
+  }
+  ctx->stream = main;
+  const hipError_t eb = hipGetLastError();
+  HIPCK(hipEventRecord(ctx->join, ctx->side_stream), "join");
+  if (eb != hipSuccess) return hip_fail(ctx, eb, "next minibatch");
+  for (int k = 0; k < n_sets; ++k) {
+    const spider_chainset& st = sets[k];
+    Catalog& cat = *get_cat(ctx, st.cat_id);
+    const Net& net = *get_net(ctx, st.net_id);
+    const int C = st.n_chains;
+    const int64_t n = st.batch;
+    rc = post_network(ctx, cat, net, net, st.precision, C, n, cat.theta.as<double>(),
+                      (int64_t)cat.M * 4, nullptr, batch_at(b, f.obs_off[k], f.key_off[k]), true,
+                      (double)cat.N / (double)n, false);
+    if (rc != SPIDER_OK) return rc;
+    launch_centroid(cat.theta.as<double>(), C, cat.M, ws.partial.as<double>(),
+                    ws.thetabar.as<double>(), ctx->stream);
+    launch_update(cat.view(), C, cat.theta.as<double>(), cat.v.as<double>(), ws.G.as<double>(),
+                  ws.thetabar.as<double>(), cat.steps.as<int64_t>(), cat.mcount.as<int64_t>(),
+                  with_samples(ua, cat), cat.mean.as<double>(), cat.m2.as<double>(), ctx->stream,
+                  false);
+    HIPCK(hipGetLastError(), "update");
+  }
+  HIPCK(hipStreamWaitEvent(ctx->stream, ctx->join, 0), "join");
+  for (int k = 0; k < n_sets; ++k) {
+    Catalog& cat = *get_cat(ctx, sets[k].cat_id);
+    launch_advance(sets[k].n_chains, cat.steps.as<int64_t>(), cat.mcount.as<int64_t>(), ua,
+                   ctx->stream);
+  }
+  HIPCK(hipGetLastError(), "advance");
+  return SPIDER_OK;
+}
+
+// Captures fused_step_ahead(side) on the context's capture stream.
+int capture_ahead(spider_ctx* ctx, const spider_chainset* sets, int n_sets, const FusedSets& f,
+                  const UpdateArgs& ua, int side, hipGraphExec_t* out) {
   const hipStream_t main = ctx->stream;
   ctx->stream = ctx->cap_stream;
   hipError_t e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
@@ -674,7 +817,7 @@ int graph_steps(spider_ctx* ctx, const spider_chainset* sets, int n_sets, const 
     ctx->stream = main;
     return hip_fail(ctx, e, "graph capture");
   }
-  const int rc = fused_step(ctx, sets, n_sets, f, ua);
+  const int rc = fused_step_ahead(ctx, sets, n_sets, f, ua, side);
   hipGraph_t g = nullptr;
   e = hipStreamEndCapture(ctx->cap_stream, &g);
   ctx->stream = main;
@@ -682,16 +825,49 @@ int graph_steps(spider_ctx* ctx, const spider_chainset* sets, int n_sets, const 
     if (g) (void)hipGraphDestroy(g);
     return rc != SPIDER_OK ? rc : hip_fail(ctx, e, "graph capture");
   }
-  hipGraphExec_t x = nullptr;
-  e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
-  if (e != hipSuccess) {
-    (void)hipGraphDestroy(g);
-    return hip_fail(ctx, e, "graph instantiate");
-  }
-  for (int64_t t = 0; t < n && e == hipSuccess; ++t) e = hipGraphLaunch(x, main);
-  const hipError_t es = hipStreamSynchronize(main);
-  (void)hipGraphExecDestroy(x);
+  e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return hip_fail(ctx, e, "graph instantiate");
+  return SPIDER_OK;
+}
+
+// n fused steps replayed from HIP graphs, launched on the context's stream.
+// The minibatch of the first replayed step is built eagerly on buffer side
+// 1; then two graphs alternate: the one for side s runs the step on side s
+// and builds the next minibatch on side 1 - s (fused_step_ahead).  Every
+// kernel reads the chains' step counters on the device, so each replay is
+// the next step; a step holds no host synchronisation, allocation or memset.
+int graph_steps(spider_ctx* ctx, const spider_chainset* sets, int n_sets, FusedSets& f,
+                const UpdateArgs& ua, int64_t n) {
+  if (n <= 0) return SPIDER_OK;
+  if (!ctx->cap_stream)
+    HIPCK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking), "capture stream");
+  if (!ctx->side_stream)
+    HIPCK(hipStreamCreateWithFlags(&ctx->side_stream, hipStreamNonBlocking), "side stream");
+  if (!ctx->fork) HIPCK(hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming), "fork event");
+  if (!ctx->join) HIPCK(hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming), "join event");
+  Workspace& ws = ctx->ws;
+  HIPCK(ws.reserve_ahead(f.total_obs, f.key_off[n_sets], f.bucket_words), "workspace");
+  int rc = upload_subs(ctx, sets, n_sets, f, 1, f.subs_ahead);
+  if (rc) return rc;
+  // the first replayed step's minibatch, on side 1
+  const BatchBufs b1 = ws.batch_side(1);
+  for (int k = 0; k < n_sets; ++k) {
+    const Catalog& cat = *get_cat(ctx, sets[k].cat_id);
+    pre_network(ctx, cat, sets[k].n_chains, sets[k].batch, nullptr, ua.seed,
+                cat.steps.as<int64_t>(), 0, 0, batch_at(b1, f.obs_off[k], f.key_off[k]), 1);
+  }
+  HIPCK(hipGetLastError(), "next minibatch");
+  hipGraphExec_t x[2] = {nullptr, nullptr};
+  rc = capture_ahead(ctx, sets, n_sets, f, ua, 1, &x[1]);
+  if (rc == SPIDER_OK) rc = capture_ahead(ctx, sets, n_sets, f, ua, 0, &x[0]);
+  hipError_t e = hipSuccess;
+  if (rc == SPIDER_OK)
+    for (int64_t t = 0; t < n && e == hipSuccess; ++t) e = hipGraphLaunch(x[t % 2 == 0 ? 1 : 0], ctx->stream);
+  const hipError_t es = hipStreamSynchronize(ctx->stream);
+  for (int k = 0; k < 2; ++k)
+    if (x[k]) (void)hipGraphExecDestroy(x[k]);
+  if (rc != SPIDER_OK) return rc;
   if (e != hipSuccess) return hip_fail(ctx, e, "graph launch");
   if (es != hipSuccess) return hip_fail(ctx, es, "graph steps");
   return SPIDER_OK;
@@ -810,6 +986,9 @@ void spider_destroy(spider_ctx* ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   clear_profile(ctx);
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+  if (ctx->side_stream) (void)hipStreamDestroy(ctx->side_stream);
+  if (ctx->fork) (void)hipEventDestroy(ctx->fork);
+  if (ctx->join) (void)hipEventDestroy(ctx->join);
   delete ctx;
 }
 

@@ -144,7 +144,7 @@ __global__ void k_select(CatView cat, int C, int64_t n, const int64_t* idx, uint
   if (idx) {
     o = idx[k];
   } else {
-    const int64_t t = steps ? steps[c] : step_scalar;
+    const int64_t t = (steps ? steps[c] : 0) + step_scalar;
     const int64_t B = cat.N / n;
     const int64_t epoch = t / B;
     const int64_t j = t - epoch * B;

@@ -169,9 +169,9 @@ constexpr int kErrSolve = 2;
 
 // Step kernels (batch_csr.hip).
 // Minibatch of each chain: explicit indices idx (all chains) or, if idx is
-// null, the Feistel minibatch of chain chain0 + c at step steps[c] (device)
-// or, if steps is null, at step_scalar.  err_flag |= kErrSelect on a failed
-// walk or an index outside [0, N).
+// null, the Feistel minibatch of chain chain0 + c at step steps[c] +
+// step_scalar (steps on the device; step_scalar alone if steps is null).
+// err_flag |= kErrSelect on a failed walk or an index outside [0, N).
 void launch_select(const CatView& cat, int C, int64_t n, const int64_t* idx, uint64_t seed,
                    const int64_t* steps, int64_t step_scalar, int chain0, BatchBufs b,
                    int* err_flag, hipStream_t s);
@@ -248,7 +248,10 @@ struct UpdateArgs {
 // recording steps).
 void launch_update(const CatView& cat, int C, double* theta, double* v, const double* G,
                    const double* thetabar, int64_t* steps, int64_t* mcount, const UpdateArgs& a,
-                   double* mean, double* m2, hipStream_t s);
+                   double* mean, double* m2, hipStream_t s, bool advance = true);
+// The step counters of C chains advance by one (and the moment counters
+// where the step was recorded); launch_update does this unless told not to.
+void launch_advance(int C, int64_t* steps, int64_t* mcount, const UpdateArgs& a, hipStream_t s);
 void launch_grad_finish(const CatView& cat, const double* theta, const double* G,
                         const double* thetabar, unsigned flags, double* grad_out, hipStream_t s);
 // logpost = -scale/2 sum r z + priors (flags), deterministic; tmp >= 2 * 1024 doubles.

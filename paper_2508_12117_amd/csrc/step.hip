@@ -500,9 +500,14 @@ void launch_centroid(const double* theta, int C, int M, double* partial, double*
   hipLaunchKernelGGL(k_centroid_final, dim3(C), dim3(64), 0, s, partial, nchunk, M, thetabar);
 }
 
+void launch_advance(int C, int64_t* steps, int64_t* mcount, const UpdateArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_advance, dim3(grid_for(C, 64)), dim3(64), 0, s, C, steps, mcount, a.burn,
+                     a.thin);
+}
+
 void launch_update(const CatView& cat, int C, double* theta, double* v, const double* G,
                    const double* thetabar, int64_t* steps, int64_t* mcount, const UpdateArgs& a,
-                   double* mean, double* m2, hipStream_t s) {
+                   double* mean, double* m2, hipStream_t s, bool advance) {
   UpdateKArgs k;
   k.step = a.step;
   k.beta2 = a.beta2;
@@ -518,8 +523,7 @@ void launch_update(const CatView& cat, int C, double* theta, double* v, const do
   k.sample_C = a.sample_C;
   hipLaunchKernelGGL(k_update, dim3(grid_for((int64_t)C * cat.M)), dim3(kBlock), 0, s, cat, C,
                      theta, v, G, thetabar, steps, mcount, k, mean, m2);
-  hipLaunchKernelGGL(k_advance, dim3(grid_for(C, 64)), dim3(64), 0, s, C, steps, mcount, a.burn,
-                     a.thin);
+  if (advance) launch_advance(C, steps, mcount, a, s);
 }
 
 void launch_adam(int C, int M, double* theta, double* m, double* v, const double* G,
