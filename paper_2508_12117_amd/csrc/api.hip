@@ -125,6 +125,16 @@ struct Net {
   }
 };
 
+// Where one chain set of a fused step keeps its step scratch: offsets of its
+// part of the entry-indexed solver arrays (e_off = its first entry), of the
+// system lists, spill flags and scan scratch, and of the per-event gradient
+// (in (chain, event) keys), reduction parts (bytes), centroid partials and
+// centroids (double4 units).  Sets with disjoint parts can run side by side.
+struct SetLayout {
+  int64_t e_off = 0, sys_off = 0, spill_off = 0, scan_off = 0, g_off = 0, rpart_off = 0,
+          partial_off = 0, tb_off = 0;
+};
+
 // Scratch of one minibatch pipeline, grown on demand.  Entry- and
 // slot-indexed arrays hold every chain set of a fused step side by side
 // (obs_total slots); the count and system arrays hold each set's keys and
@@ -281,6 +291,39 @@ struct Workspace {
     b.wr = wr.as<WRec>();
     return b;
   }
+  // a chain set's part of the step scratch (see SetLayout)
+  struct SetScratch {
+    SolveBufs sv;
+    double* G;
+    void* rpart;
+    double* partial;
+    double* thetabar;
+  };
+  SetScratch set_scratch(const SetLayout& l) const {
+    SetScratch x;
+    x.sv = solve(l.sys_off);
+    x.sv.act += l.e_off;
+    x.sv.list += l.e_off;
+    x.sv.nbr += l.e_off;
+    x.sv.wgt += l.e_off;
+    x.sv.vec += 7 * l.e_off;   // its seven arrays of its own entry count
+    x.sv.ivec += 5 * l.e_off;  // its five arrays of its own entry count
+    x.sv.lidx += l.e_off;
+    x.sv.spill += l.spill_off;
+    x.sv.nrec += l.e_off;
+    x.sv.scan_part += l.scan_off;
+    x.G = G.as<double>() + 4 * l.g_off;
+    x.rpart = rpart.as<char>() + l.rpart_off;
+    x.partial = partial.as<double>() + 4 * l.partial_off;
+    x.thetabar = thetabar.as<double>() + 4 * l.tb_off;
+    return x;
+  }
+  // grows the reduction parts and the scan scratch to the totals of the sets
+  hipError_t reserve_sets(int64_t rpart_bytes, int64_t scan_ints) {
+    hipError_t e = rpart.reserve((size_t)rpart_bytes);
+    if (e == hipSuccess) e = scan_part.reserve((size_t)scan_ints * 4);
+    return e;
+  }
   SolveBufs solve(int64_t sys_off) const {
     SolveBufs v;
     v.act = act.as<int32_t>();
@@ -317,6 +360,9 @@ struct spider_ctx {
   hipStream_t cap_stream = nullptr;   // the stream graphs are captured on
   hipStream_t side_stream = nullptr;  // a second branch of the captured step
   hipEvent_t fork = nullptr, join = nullptr;
+  // branches of the fused sets' post-network work (besides the main stream)
+  hipStream_t branch[2] = {nullptr, nullptr};
+  hipEvent_t bjoin[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -561,17 +607,18 @@ RowSource csr_rows(const Catalog& cat, int64_t n, int64_t E, const double* theta
 // order when it is not the CSR order (two-phase catalogs), else null.
 int post_network(spider_ctx* ctx, const Catalog& cat, const Net& net, const Net& net_s, int prec,
                  int C, int64_t n, const double* theta, int64_t theta_stride, const int32_t* rows,
-                 const BatchBufs& b, bool grad, double scale, bool l1) {
+                 const BatchBufs& b, bool grad, double scale, bool l1,
+                 const Workspace::SetScratch* sc = nullptr) {
   Workspace& ws = ctx->ws;
+  const Workspace::SetScratch x = sc ? *sc : ws.set_scratch(SetLayout{});
   const CatView cv = cat.view();
   launch_assemble(cv, net.view(prec), net_s.view(prec), C, n, theta, theta_stride, rows, b,
                   ctx->stream);
   const int whiten = l1 ? kWhitenL1 : cat.kappa == 0.0 ? SPIDER_WHITEN_NONE : cat.whiten;
-  const SolveBufs sv = ws.solve(0);
-  launch_residual(cv, C, n, theta, theta_stride, whiten, b, sv, ctx->stream);
+  launch_residual(cv, C, n, theta, theta_stride, whiten, b, x.sv, ctx->stream);
   if (whiten == SPIDER_WHITEN_EXACT)
-    HIPCK(exact_whiten(cv, C, n, b, sv, ws.err.as<int>(), ctx->stream), "exact whitening");
-  if (grad) launch_reduce(cv, C, n, scale, b, ws.G.as<double>(), ws.rpart.p, ctx->stream);
+    HIPCK(exact_whiten(cv, C, n, b, x.sv, ws.err.as<int>(), ctx->stream), "exact whitening");
+  if (grad) launch_reduce(cv, C, n, scale, b, x.G, x.rpart, ctx->stream);
   HIPCK(hipGetLastError(), "step kernels");
   return SPIDER_OK;
 }
@@ -647,7 +694,14 @@ struct FusedSets {
   int64_t bucket_words = 0;      // the largest set's CSR-build buckets
   DevBuf subs, row0;             // device RowSource table and its row offsets
   DevBuf subs_ahead;             // the same over the second buffer side
+  std::vector<SetLayout> lay;    // each set's part of the step scratch
+  std::vector<int> branch;       // graph branch of each set's post-network work
+  int n_branches = 1;
 };
+
+// Graph branches over which the post-network work of fused sets is spread
+// (each a stream of its own while capturing; the hardware runs four queues).
+constexpr int kPostBranches = 3;
 
 // The network's row-source table of the fused sets over the selection and
 // CSR arrays of one buffer side.
@@ -668,26 +722,58 @@ int upload_subs(spider_ctx* ctx, const spider_chainset* sets, int n_sets, const 
 }
 
 int prepare_fused(spider_ctx* ctx, const spider_chainset* sets, int n_sets, FusedSets& f) {
-  int64_t maxC = 1, maxCM = 1, maxS = 1, maxB = 1;
+  int64_t sumC = 0, maxB = 1;
   f.obs_off.assign(n_sets + 1, 0);
   f.key_off.assign(n_sets + 1, 0);
+  f.lay.assign(n_sets, SetLayout{});
+  SetLayout end;  // the running offsets: the totals after the last set
   for (int k = 0; k < n_sets; ++k) {
     const Catalog& cat = *get_cat(ctx, sets[k].cat_id);
-    const int64_t C = sets[k].n_chains, Cn = C * sets[k].batch;
+    const int64_t C = sets[k].n_chains, n = sets[k].batch, Cn = C * n;
     f.obs_off[k + 1] = f.obs_off[k] + Cn;
     f.key_off[k + 1] = f.key_off[k] + C * cat.M + 1;
-    maxC = std::max(maxC, C);
-    maxCM = std::max(maxCM, C * cat.M);
-    maxS = std::max(maxS, C * cat.L * list_blocks(C, sets[k].batch, cat.L) + 1);
-    const BucketShape bs = bucket_shape(C, sets[k].batch, cat.M);
+    sumC += C;
+    const int64_t S = C * cat.L * list_blocks(C, n, cat.L) + 1;
+    SetLayout& l = f.lay[k];
+    l = end;
+    l.e_off = 2 * f.obs_off[k];
+    end.sys_off += S;
+    end.spill_off += C * cat.L;
+    end.scan_off += scan_part_size(S);
+    end.g_off += C * cat.M;
+    end.rpart_off += reduce_part_bytes(2 * Cn);
+    end.partial_off += C * cat.M / 4096 + C + 1;
+    end.tb_off += C;
+    const BucketShape bs = bucket_shape(C, n, cat.M);
     if (!bs.ok)
       return fail(ctx, SPIDER_E_UNSUPPORTED, "chains x events too large for the CSR build");
     maxB = std::max(maxB, bs.words);
   }
   f.total_obs = f.obs_off[n_sets];
   f.bucket_words = maxB;
+  // post-network branches: the sets by decreasing entries, each to the
+  // least loaded branch
+  f.n_branches = std::min(n_sets, kPostBranches);
+  f.branch.assign(n_sets, 0);
+  {
+    std::vector<int> order(n_sets);
+    for (int k = 0; k < n_sets; ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+      return f.obs_off[a + 1] - f.obs_off[a] > f.obs_off[b + 1] - f.obs_off[b];
+    });
+    std::vector<int64_t> load(f.n_branches, 0);
+    for (int k : order) {
+      const int br = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      f.branch[k] = br;
+      load[br] += f.obs_off[k + 1] - f.obs_off[k];
+    }
+  }
   Workspace& ws = ctx->ws;
-  HIPCK(ws.reserve(maxC, f.total_obs, f.key_off[n_sets], maxS, maxCM, maxB), "workspace");
+  // sizes: every set's part side by side (the partial and centroid counts
+  // of reserve take sum C + n_sets chains)
+  HIPCK(ws.reserve(sumC + n_sets, f.total_obs, f.key_off[n_sets], end.sys_off, end.g_off, maxB),
+        "workspace");
+  HIPCK(ws.reserve_sets(end.rpart_off, end.scan_off), "workspace");
   const BatchBufs b = ws.batch();
   std::vector<RowSource> subs(n_sets);
   std::vector<int64_t> row0(n_sets + 1);
@@ -730,15 +816,15 @@ int fused_step(spider_ctx* ctx, const spider_chainset* sets, int n_sets, const F
     const Net& net = *get_net(ctx, st.net_id);
     const int C = st.n_chains;
     const int64_t n = st.batch;
+    const Workspace::SetScratch sc = ws.set_scratch(f.lay[k]);
     rc = post_network(ctx, cat, net, net, st.precision, C, n, cat.theta.as<double>(),
                       (int64_t)cat.M * 4, nullptr, batch_at(b, f.obs_off[k], f.key_off[k]), true,
-                      (double)cat.N / (double)n, false);
+                      (double)cat.N / (double)n, false, &sc);
     if (rc != SPIDER_OK) return rc;
-    launch_centroid(cat.theta.as<double>(), C, cat.M, ws.partial.as<double>(),
-                    ws.thetabar.as<double>(), ctx->stream);
-    launch_update(cat.view(), C, cat.theta.as<double>(), cat.v.as<double>(), ws.G.as<double>(),
-                  ws.thetabar.as<double>(), cat.steps.as<int64_t>(), cat.mcount.as<int64_t>(),
-                  with_samples(ua, cat), cat.mean.as<double>(), cat.m2.as<double>(), ctx->stream);
+    launch_centroid(cat.theta.as<double>(), C, cat.M, sc.partial, sc.thetabar, ctx->stream);
+    launch_update(cat.view(), C, cat.theta.as<double>(), cat.v.as<double>(), sc.G, sc.thetabar,
+                  cat.steps.as<int64_t>(), cat.mcount.as<int64_t>(), with_samples(ua, cat),
+                  cat.mean.as<double>(), cat.m2.as<double>(), ctx->stream);
     HIPCK(hipGetLastError(), "update");
   }
   return SPIDER_OK;
@@ -779,23 +865,39 @@ int fused_step_ahead(spider_ctx* ctx, const spider_chainset* sets, int n_sets, c
   const hipError_t eb = hipGetLastError();
   HIPCK(hipEventRecord(ctx->join, ctx->side_stream), "join");
   if (eb != hipSuccess) return hip_fail(ctx, eb, "next minibatch");
-  for (int k = 0; k < n_sets; ++k) {
-    const spider_chainset& st = sets[k];
-    Catalog& cat = *get_cat(ctx, st.cat_id);
-    const Net& net = *get_net(ctx, st.net_id);
-    const int C = st.n_chains;
-    const int64_t n = st.batch;
-    rc = post_network(ctx, cat, net, net, st.precision, C, n, cat.theta.as<double>(),
-                      (int64_t)cat.M * 4, nullptr, batch_at(b, f.obs_off[k], f.key_off[k]), true,
-                      (double)cat.N / (double)n, false);
-    if (rc != SPIDER_OK) return rc;
-    launch_centroid(cat.theta.as<double>(), C, cat.M, ws.partial.as<double>(),
-                    ws.thetabar.as<double>(), ctx->stream);
-    launch_update(cat.view(), C, cat.theta.as<double>(), cat.v.as<double>(), ws.G.as<double>(),
-                  ws.thetabar.as<double>(), cat.steps.as<int64_t>(), cat.mcount.as<int64_t>(),
-                  with_samples(ua, cat), cat.mean.as<double>(), cat.m2.as<double>(), ctx->stream,
-                  false);
-    HIPCK(hipGetLastError(), "update");
+  // the sets' residual, whitening, reduction and update: branch 0 on the
+  // main stream, the others on branch streams (each set has its own scratch)
+  for (int br = 0; br < f.n_branches; ++br) {
+    const hipStream_t bs = br == 0 ? main : ctx->branch[br - 1];
+    if (br > 0) HIPCK(hipStreamWaitEvent(bs, ctx->fork, 0), "fork");
+    ctx->stream = bs;
+    for (int k = 0; k < n_sets; ++k) {
+      if (f.branch[k] != br) continue;
+      const spider_chainset& st = sets[k];
+      Catalog& cat = *get_cat(ctx, st.cat_id);
+      const Net& net = *get_net(ctx, st.net_id);
+      const int C = st.n_chains;
+      const int64_t n = st.batch;
+      const Workspace::SetScratch sc = ws.set_scratch(f.lay[k]);
+      rc = post_network(ctx, cat, net, net, st.precision, C, n, cat.theta.as<double>(),
+                        (int64_t)cat.M * 4, nullptr, batch_at(b, f.obs_off[k], f.key_off[k]),
+                        true, (double)cat.N / (double)n, false, &sc);
+      if (rc != SPIDER_OK) {
+        ctx->stream = main;
+        return rc;
+      }
+      launch_centroid(cat.theta.as<double>(), C, cat.M, sc.partial, sc.thetabar, ctx->stream);
+      launch_update(cat.view(), C, cat.theta.as<double>(), cat.v.as<double>(), sc.G, sc.thetabar,
+                    cat.steps.as<int64_t>(), cat.mcount.as<int64_t>(), with_samples(ua, cat),
+                    cat.mean.as<double>(), cat.m2.as<double>(), ctx->stream, false);
+    }
+    ctx->stream = main;
+    const hipError_t eu = hipGetLastError();
+    if (eu != hipSuccess) return hip_fail(ctx, eu, "update");
+    if (br > 0) {
+      HIPCK(hipEventRecord(ctx->bjoin[br - 1], bs), "join");
+      HIPCK(hipStreamWaitEvent(main, ctx->bjoin[br - 1], 0), "join");
+    }
   }
   HIPCK(hipStreamWaitEvent(ctx->stream, ctx->join, 0), "join");
   for (int k = 0; k < n_sets; ++k) {
@@ -846,6 +948,12 @@ int graph_steps(spider_ctx* ctx, const spider_chainset* sets, int n_sets, FusedS
     HIPCK(hipStreamCreateWithFlags(&ctx->side_stream, hipStreamNonBlocking), "side stream");
   if (!ctx->fork) HIPCK(hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming), "fork event");
   if (!ctx->join) HIPCK(hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming), "join event");
+  for (int k = 0; k + 1 < kPostBranches; ++k) {
+    if (!ctx->branch[k])
+      HIPCK(hipStreamCreateWithFlags(&ctx->branch[k], hipStreamNonBlocking), "branch stream");
+    if (!ctx->bjoin[k])
+      HIPCK(hipEventCreateWithFlags(&ctx->bjoin[k], hipEventDisableTiming), "branch event");
+  }
   Workspace& ws = ctx->ws;
   HIPCK(ws.reserve_ahead(f.total_obs, f.key_off[n_sets], f.bucket_words), "workspace");
   int rc = upload_subs(ctx, sets, n_sets, f, 1, f.subs_ahead);
@@ -989,6 +1097,10 @@ void spider_destroy(spider_ctx* ctx) {
   if (ctx->side_stream) (void)hipStreamDestroy(ctx->side_stream);
   if (ctx->fork) (void)hipEventDestroy(ctx->fork);
   if (ctx->join) (void)hipEventDestroy(ctx->join);
+  for (int k = 0; k < 2; ++k) {
+    if (ctx->branch[k]) (void)hipStreamDestroy(ctx->branch[k]);
+    if (ctx->bjoin[k]) (void)hipEventDestroy(ctx->bjoin[k]);
+  }
   delete ctx;
 }
 
