@@ -460,7 +460,8 @@ int spider_profile(spider_ctx* ctx, int enable);
 /* Tile shape of the matrix-core network kernel this context uses for a
  * network and precision: *waves per workgroup, *row_tiles of 16 rows per
  * workgroup and *schedule (0: one workgroup barrier per layer, 1: row halves
- * in ping-pong); 0, 0, 0 when the shape has no matrix-core kernel.  The
+ * in ping-pong with a weight ring of one layer, 2: the same with one and a
+ * half layers); 0, 0, 0 when the shape has no matrix-core kernel.  The
  * variant is chosen by timing every compiled one on the first launch of at
  * least 65,536 rows (all variants give identical results).  Any output
  * pointer may be NULL.  Errors: SPIDER_E_INVALID (unknown network id). */

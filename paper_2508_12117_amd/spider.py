@@ -467,7 +467,8 @@ class Context:
         return w.value, r.value
 
     def network_schedule(self, net_id, precision=FP32):
-        """Schedule of the chosen kernel: 0 one barrier per layer, 1 row-half ping-pong."""
+        """Schedule of the chosen kernel: 0 one barrier per layer, 1 row-half
+        ping-pong with a one-layer weight ring, 2 the same with a 1.5-layer ring."""
         sc = ct.c_int32()
         self._check(lib().spider_network_variant(self._h, net_id, precision, None, None,
                                                  ct.byref(sc)))
