@@ -82,6 +82,10 @@ def parse():
     ap.add_argument("--configs", action="store_true",
                     help="instead of the bench line: rates and errors of the tiny and "
                          "faults10k workloads on the GPU (FP32, BF16) and in the oracle")
+    ap.add_argument("--stream-only", action="store_true",
+                    help="launch every step on the stream, graphs off, and time only that pass "
+                         "(per-kernel profiles: no graph branch overlaps one step's kernels "
+                         "with the next step's)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="first copy BYTES between two device buffers (one device-to-device "
                          "copy of known size, to calibrate HBM byte counters in a profile)")
@@ -92,7 +96,7 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def run_precision(ctx, spider, base_sets, step_size, prec, steps, warmup, seed):
+def run_precision(ctx, spider, base_sets, step_size, prec, steps, warmup, seed, graphs=True):
     """base_sets: (cat_id, net_id, chains, batch) per catalog; several catalogs
     advance together in the library's fused steps.  Two timed passes of
     `steps` steps from the same warmed-up start: the step as the library runs
@@ -100,7 +104,8 @@ def run_precision(ctx, spider, base_sets, step_size, prec, steps, warmup, seed):
     throughput, then with the network launches bracketed by HIP events on the
     library's stream (profiling launches every step on the stream) for the
     network kernel's time.  Returns (graph wall s, stream wall s, network ms,
-    launches, rows)."""
+    launches, rows).  With graphs off the first pass is skipped and its wall
+    time is that of the second."""
     import torch
     sets = [(cid, nid, C, n, prec) for cid, nid, C, n in base_sets]
 
@@ -111,12 +116,15 @@ def run_precision(ctx, spider, base_sets, step_size, prec, steps, warmup, seed):
         ctx.sync()
         torch.cuda.synchronize()
 
-    fresh()
-    t0 = time.perf_counter()
-    ctx.sgld_steps(sets, steps, step=step_size, seed=seed)
-    ctx.sync()
-    torch.cuda.synchronize()
-    wall_graph = time.perf_counter() - t0
+    ctx.set_graphs(graphs)
+    wall_graph = None
+    if graphs:
+        fresh()
+        t0 = time.perf_counter()
+        ctx.sgld_steps(sets, steps, step=step_size, seed=seed)
+        ctx.sync()
+        torch.cuda.synchronize()
+        wall_graph = time.perf_counter() - t0
     fresh()
     ctx.profile(True)
     t0 = time.perf_counter()
@@ -126,7 +134,8 @@ def run_precision(ctx, spider, base_sets, step_size, prec, steps, warmup, seed):
     wall_stream = time.perf_counter() - t0
     ms, launches, rows = ctx.profile_read()
     ctx.profile(False)
-    return wall_graph, wall_stream, ms, launches, rows
+    ctx.set_graphs(True)
+    return wall_graph if graphs else wall_stream, wall_stream, ms, launches, rows
 
 
 def small_catalog_rates(spider, seed, steps=2000):
@@ -430,7 +439,7 @@ def main():
         code = spider.BF16 if p == "bf16" else spider.FP32
         wall, wall_stream, ms, launches, rows = run_precision(ctx, spider, base_sets, wl.step_size,
                                                               code, args.steps, args.warmup,
-                                                              args.seed)
+                                                              args.seed, not args.stream_only)
         dd = dd_per_step * args.steps
         fl = flops_per_eval(wl.H, wl.D)
         avg_ms = ms / max(launches, 1)

@@ -140,9 +140,9 @@ struct SetLayout {
 // (obs_total slots); the count and system arrays hold each set's keys and
 // systems side by side; the solver scratch holds one set at a time.
 struct Workspace {
-  DevBuf obs, ev, sta, tau, w, start, csr, ckey, pos, pev, pgr, head, nend, rows, net_out, T, gT,
+  DevBuf obs, ev, sta, tau, w, start, csr, ckey, pos, pev, pgr, nend, rows, net_out, T, gT,
       r, z, zp, wr;
-  DevBuf act, sys, list, nbr, wgt, vec, ivec, nrec, scan_part, bucket, phase_flags, n_p;
+  DevBuf act, sys, list, ent, vec, ivec, nrec, scan_part, bucket, phase_flags, n_p;
   DevBuf G, partial, thetabar, lp_tmp, err, rpart;
   int64_t e_cur = 0;  // entries of the last reserve: the layout of ivec
 
@@ -150,7 +150,7 @@ struct Workspace {
   // scratch), so that the next step's minibatch can be built while the
   // current step still reads its own (graph replays of sampler steps).
   struct Ahead {
-    DevBuf obs, ev, sta, tau, w, start, csr, ckey, pos, pev, pgr, head, nend, bucket, scan_part;
+    DevBuf obs, ev, sta, tau, w, start, csr, ckey, pos, pev, pgr, nend, bucket, scan_part;
     DevBuf scan_part0;  // scan scratch of a side-0 build beside the whitening's scans
   } ahead;
   hipError_t reserve_ahead(int64_t obs_total, int64_t keys_total, int64_t bucket_words) {
@@ -166,10 +166,9 @@ struct Workspace {
     RES(ahead.start, keys_total * 4);
     RES(ahead.csr, E * 4);
     RES(ahead.ckey, E * 8);
-    RES(ahead.pos, E * 4);
+    RES(ahead.pos, E * 8);
     RES(ahead.pev, E * 4);
     RES(ahead.pgr, E * 4);
-    RES(ahead.head, E * 4);
     RES(ahead.nend, E * 4);
     RES(ahead.bucket, bucket_words * 4);
     int64_t sp = scan_part_size(bucket_words);
@@ -192,10 +191,9 @@ struct Workspace {
     b.start = ahead.start.as<int32_t>();
     b.csr = ahead.csr.as<int32_t>();
     b.ckey = ahead.ckey.as<uint64_t>();
-    b.pos = ahead.pos.as<int32_t>();
+    b.pos = ahead.pos.as<int2>();
     b.pev = ahead.pev.as<int32_t>();
     b.pgr = ahead.pgr.as<int32_t>();
-    b.head = ahead.head.as<int32_t>();
     b.nend = ahead.nend.as<int32_t>();
     return b;
   }
@@ -226,10 +224,9 @@ struct Workspace {
     RES(start, keys_total * 4);
     RES(csr, E * 4);
     RES(ckey, E * 8);
-    RES(pos, E * 4);
+    RES(pos, E * 8);
     RES(pev, E * 4);
     RES(pgr, E * 4);
-    RES(head, E * 4);
     RES(nend, E * 4);
     RES(rows, E * 4);
     RES(net_out, E * sizeof(RowOut));
@@ -242,8 +239,7 @@ struct Workspace {
     RES(act, E * 4);
     RES(sys, sys_total * 4);
     RES(list, E * 4);
-    RES(nbr, E * 4);
-    RES(wgt, E * 8);
+    RES(ent, E * sizeof(ERec));
     RES(vec, E * 8 * 7);
     RES(ivec, E * 4 * 6 + sys_total * 4);
     RES(nrec, E * sizeof(NodeRec));
@@ -276,10 +272,9 @@ struct Workspace {
     b.start = start.as<int32_t>();
     b.csr = csr.as<int32_t>();
     b.ckey = ckey.as<uint64_t>();
-    b.pos = pos.as<int32_t>();
+    b.pos = pos.as<int2>();
     b.pev = pev.as<int32_t>();
     b.pgr = pgr.as<int32_t>();
-    b.head = head.as<int32_t>();
     b.nend = nend.as<int32_t>();
     b.rows = rows.as<int32_t>();
     b.net_out = net_out.as<RowOut>();
@@ -304,8 +299,7 @@ struct Workspace {
     x.sv = solve(l.sys_off);
     x.sv.act += l.e_off;
     x.sv.list += l.e_off;
-    x.sv.nbr += l.e_off;
-    x.sv.wgt += l.e_off;
+    x.sv.ent += l.e_off;
     x.sv.vec += 7 * l.e_off;   // its seven arrays of its own entry count
     x.sv.ivec += 5 * l.e_off;  // its five arrays of its own entry count
     x.sv.lidx += l.e_off;
@@ -329,8 +323,7 @@ struct Workspace {
     v.act = act.as<int32_t>();
     v.sys = sys.as<int32_t>() + sys_off;
     v.list = list.as<int32_t>();
-    v.nbr = nbr.as<int32_t>();
-    v.wgt = wgt.as<double>();
+    v.ent = ent.as<ERec>();
     v.vec = vec.as<double>();
     v.ivec = ivec.as<int32_t>();
     v.lidx = ivec.as<int32_t>() + 5 * e_cur;
@@ -563,7 +556,6 @@ BatchBufs batch_at(const BatchBufs& b, int64_t obs_off, int64_t key_off) {
   o.pev += 2 * obs_off;
   o.pgr += 2 * obs_off;
   o.zp += 2 * obs_off;
-  o.head += 2 * obs_off;
   o.nend += 2 * obs_off;
   o.rows += 2 * obs_off;
   o.net_out += 2 * obs_off;
@@ -1500,6 +1492,7 @@ int spider_grad(spider_ctx* ctx, int32_t cat_id, int32_t net_id, int32_t precisi
   launch_grad_finish(cv, theta, ws.G.as<double>(), ws.thetabar.as<double>(), flags, grad_out,
                      ctx->stream);
   // L1: -(1/n) sum |r| = -(scale/2) r.z with z = sign(r) and scale = 2/n
+  if (logpost_out) launch_obs_z(n, ws.batch(), ctx->stream);
   if (logpost_out)
     launch_logpost(cv, n, l1 ? 2.0 / (double)n : (double)cat->N / (double)n, ws.r.as<double>(),
                    ws.z.as<double>(), theta, ws.thetabar.as<double>(), flags,

@@ -16,7 +16,8 @@
 //   whitening exact Sigma_B^{-1} r (Sec. 3.1, eq:marginal_sigma) for the
 //             other observations: by Woodbury, z = (r - U y)/sigma^2 with
 //             (lambda I + U^T U) y = U^T r per (chain, group) system, solved
-//             by leaf elimination and CG on the cyclic core
+//             by leaf elimination and CG on the cyclic core; the solver
+//             writes z at both entries of each of its observations
 //   reduce    per-event gradient (eq:sgd): the sum over one CSR segment per
 //             (chain, event), in CSR order
 // No floating-point atomics anywhere: every sum runs in a fixed order, so a
@@ -292,9 +293,10 @@ __device__ void block_sort_any(int32_t len, Get&& get, Put&& put) {
 }
 
 // One workgroup per bucket: the bucket's records in (event, group, entry)
-// order, then per position the entry (csr), its event and group, its node's
-// first position (head) and, at that position, one past the node's last
-// (nend), and pos[e] with the single-entry bit; start[] of the bucket's
+// order, then per position the entry (csr), its event and group and, at
+// its node's first position, one past the node's last (nend), and per entry
+// pos[e] = (position with the single-entry bit, the node's first position),
+// one 8-byte write; start[] of the bucket's
 // events.  A bucket of up to cap records (held in registers after one read)
 // is ordered in LDS: by a counting sort on the event (placement order within
 // an event from LDS atomics), then an insertion sort of each event's segment by one thread, or
@@ -434,9 +436,8 @@ __global__ __launch_bounds__(kSortTB) void k_bucket_sort(int64_t nbk, int sb, in
     b.csr[p] = e;
     b.pev[p] = m0 + (int32_t)(x >> 48);
     b.pgr[p] = (int32_t)(eg & 0xFFFF);
-    b.head[p] = r0 + j;
     if (last) b.nend[r0 + j] = p + 1;
-    b.pos[e] = p | ((last && j == i) ? kSingle : 0);
+    b.pos[e] = make_int2(p | ((last && j == i) ? kSingle : 0), r0 + j);
   }
 }
 
@@ -495,7 +496,8 @@ __global__ void k_residual(CatView cat, int C, int64_t n, const double* theta, i
   b.r[q] = r;
   const double s2 = cat.sigma * cat.sigma;
   const double zs = b.sta[2 * q] >= cat.L_p ? cat.zscale_s : 1.0;
-  const int32_t pi = b.pos[2 * q], pj = b.pos[2 * q + 1];
+  const int4 pp = *(const int4*)(b.pos + 2 * q);  // both entries: position, node head
+  const int32_t pi = pp.x, pj = pp.z;
   double z;
   if (whiten == kWhitenL1) {
     z = r > 0.0 ? 1.0 : (r < 0.0 ? -1.0 : 0.0);  // d|r|/dr, 0 at 0
@@ -509,17 +511,16 @@ __global__ void k_residual(CatView cat, int C, int64_t n, const double* theta, i
     WRec x;
     x.w = b.w[q];
     x.r = r;
-    x.hi = b.head[pi & kPosMask];
-    x.hj = b.head[pj & kPosMask];
+    x.hi = pp.y;
+    x.hj = pp.w;
     x.pad[0] = x.pad[1] = 0;
     b.wr[q] = x;
     act[x.hi] = 1;
     act[x.hj] = 1;
-    return;  // z from the solve (k_exact_z)
+    return;  // z from the solve (k_tree_lds or k_tree_solve)
   }
-  b.z[q] = z;
-  b.zp[pi & kPosMask] = z;
-  b.zp[pj & kPosMask] = z;
+  b.zp[pi & kPosMask] = z;  // the sign of each entry's term in the per-event sums
+  b.zp[pj & kPosMask] = -z;
 }
 
 // ---------------------------------------------------------------- exact whitening
@@ -539,8 +540,8 @@ constexpr int kListTB = 256;
 // node in its system's list (slot from an LDS counter: the order within a
 // list does not matter to the solver) and initialises it: the diagonal
 // lambda + sum w and right-hand side (U^T r) = sum +-sqrt(w) r over its
-// entries in CSR order, and per entry the node at the other end and the
-// weight.  hist: L ints of dynamic LDS.
+// entries in CSR order, and per entry its record (weight, signed residual,
+// the node at the other end).  hist: L ints of dynamic LDS.
 __global__ __launch_bounds__(kListTB) void k_list_count(int64_t n, int L, int64_t nb, int64_t span,
                                                        BatchBufs b, SolveBufs sv) {
   extern __shared__ int32_t hist[];
@@ -578,8 +579,12 @@ __global__ __launch_bounds__(kListTB) void k_list_fill(int64_t n, int L, int64_t
       const WRec x = b.wr[e >> 1];  // one gather: weight, residual, both nodes
       A += x.w;
       rhs += ((e & 1) ? -1.0 : 1.0) * sqrt(x.w) * x.r;
-      sv.nbr[f] = (e & 1) ? x.hi : x.hj;  // the node at the other end
-      sv.wgt[f] = x.w;
+      ERec en;
+      en.w = x.w;
+      en.rs = (e & 1) ? -x.r : x.r;
+      en.nbr = (e & 1) ? x.hi : x.hj;  // the node at the other end
+      en.pad = 0;
+      sv.ent[f] = en;
     }
     NodeRec nr;
     nr.A = A;
@@ -592,8 +597,7 @@ __global__ __launch_bounds__(kListTB) void k_list_fill(int64_t n, int L, int64_t
 
 struct SolveArgs {
   const int32_t* nend;  // entries of node q: CSR positions [q, nend[q])
-  const int32_t* nbr;   // per position: the node at the other end of its edge
-  const double* wgt;    // per position: the edge weight w
+  const ERec* ent;      // per position: weight, signed residual, node at the other end
   const int32_t* sys;   // list offsets: system s starts at sys[s nb]
   int64_t nb;
   int32_t* list;        // nodes of each system (first positions)
@@ -619,7 +623,21 @@ struct SolveArgs {
   const NodeRec* nrec;  // the nodes in list order
   int32_t* spill;       // per system: 1 if k_tree_solve takes it
   int lds_off;          // 1: every system to k_tree_solve (SPIDER_TREE_GLOBAL, for tests)
+  double* zp;           // per position: the whitened residual, negated at the second entry
+  double sigma;         // sigma of the catalog's P groups
+  double zscale_s;      // z scale of S groups (system s has group s mod L)
+  int L, L_p;
 };
+
+// The whitened residual z = (r - sqrt(w) (y_i - y_j)) / sigma^2 (times the
+// group's scale) at one entry of an observation, negated at its second
+// entry: with rs and the two y taken from that entry's side (rs = -r and
+// the node's own y first at the second entry) the value is exactly -z,
+// since every step of the expression is odd in (rs, y_own - y_other).
+__device__ __forceinline__ double signed_z(double rs, double w, double y_own, double y_other,
+                                           double sigma, double zs) {
+  return (rs - sqrt(w) * (y_own - y_other)) / (sigma * sigma) * zs;
+}
 
 constexpr int kMaxRounds = 64;
 constexpr int kWaveCore = 64;  // cores up to this size: CG in one wave
@@ -700,14 +718,14 @@ __device__ bool wave_core_cg(const SolveArgs& a, const int32_t* core, int32_t n,
   if (on) {
     const int32_t e1 = a.nend[q];
     for (int32_t e = q; e < e1; ++e) {
-      const int32_t pn = a.nbr[e];
+      const int32_t pn = a.ent[e].nbr;
       if (a.state[pn] != kActive) continue;
       if (cnt == kWaveNb) {
         over = true;
         break;
       }
       nb_sh[lane][cnt] = pn;
-      w_sh[lane][cnt] = a.wgt[e];
+      w_sh[lane][cnt] = a.ent[e].w;
       ++cnt;
     }
   }
@@ -811,7 +829,7 @@ __device__ bool wave_core_cg_lds(const SolveArgs& a, const uint16_t* core, int32
         break;
       }
       nb_sh[lane][cnt] = gpos[pn];
-      w_sh[lane][cnt] = a.wgt[key + (x - e0)];
+      w_sh[lane][cnt] = a.ent[key + (x - e0)].w;
       ++cnt;
     }
   }
@@ -914,13 +932,13 @@ __global__ __launch_bounds__(TB) void k_tree_solve(SolveArgs a) {
       double W = 0.0;
       bool multi = false;
       for (int32_t e = q; e < a.nend[q]; ++e) {
-        const int32_t pn = a.nbr[e];
+        const int32_t pn = a.ent[e].nbr;
         if (a.state[pn] != kActive) continue;
         if (p0 < 0) {
           p0 = pn;
-          W = a.wgt[e];
+          W = a.ent[e].w;
         } else if (pn == p0) {
-          W += a.wgt[e];
+          W += a.ent[e].w;
         } else {
           multi = true;
           break;
@@ -933,7 +951,7 @@ __global__ __launch_bounds__(TB) void k_tree_solve(SolveArgs a) {
       } else if (!multi) {
         bool p0_other = false;
         for (int32_t e = p0; e < a.nend[p0]; ++e) {
-          const int32_t pn = a.nbr[e];
+          const int32_t pn = a.ent[e].nbr;
           if (pn != q && a.state[pn] == kActive) {
             p0_other = true;
             break;
@@ -957,11 +975,11 @@ __global__ __launch_bounds__(TB) void k_tree_solve(SolveArgs a) {
         const int32_t e0 = q, e1 = a.nend[q];
         double dA = 0.0, db = 0.0;
         for (int32_t e = e0; e < e1; ++e) {
-          const int32_t pn = a.nbr[e];
+          const int32_t pn = a.ent[e].nbr;
           if (a.nstate[pn] != rounds || a.par[pn] != q) continue;
           bool first = true;
           for (int32_t f = e0; f < e; ++f)
-            if (a.nbr[f] == pn) {
+            if (a.ent[f].nbr == pn) {
               first = false;
               break;
             }
@@ -1036,8 +1054,8 @@ __global__ __launch_bounds__(TB) void k_tree_solve(SolveArgs a) {
         const int32_t q = core[k];
         double v = a.b[q] - a.A[q] * a.y[q];
         for (int32_t e = q; e < a.nend[q]; ++e) {
-          const int32_t pn = a.nbr[e];
-          if (a.state[pn] == kActive) v += a.wgt[e] * a.y[pn];
+          const int32_t pn = a.ent[e].nbr;
+          if (a.state[pn] == kActive) v += a.ent[e].w * a.y[pn];
         }
         a.rr[q] = v;
         a.p[q] = v / a.A[q];
@@ -1053,8 +1071,8 @@ __global__ __launch_bounds__(TB) void k_tree_solve(SolveArgs a) {
           const int32_t q = core[k];
           double v = a.A[q] * a.p[q];
           for (int32_t e = q; e < a.nend[q]; ++e) {
-            const int32_t pn = a.nbr[e];
-            if (a.state[pn] == kActive) v -= a.wgt[e] * a.p[pn];
+            const int32_t pn = a.ent[e].nbr;
+            if (a.state[pn] == kActive) v -= a.ent[e].w * a.p[pn];
           }
           a.ap[q] = v;
           pap += a.p[q] * v;
@@ -1097,28 +1115,25 @@ __global__ __launch_bounds__(TB) void k_tree_solve(SolveArgs a) {
     }
     __syncthreads();
   }
-  // y at each position of its node as well (see k_tree_lds)
+  // z at every entry of the system's nodes (y at the nodes' first positions)
   const int32_t n_sys = a.sys[(blockIdx.x + 1) * a.nb] - off;
+  const int g = (int)(blockIdx.x % a.L);
+  const double zs = g >= a.L_p ? a.zscale_s : 1.0;
   for (int32_t k = t; k < n_sys; k += TB) {
     const NodeRec nr = a.nrec[off + k];
     const double yq = a.y[nr.q];
-    for (int32_t x = 1; x < nr.ne; ++x) a.y[nr.q + x] = yq;
+    for (int32_t x = 0; x < nr.ne; ++x) {
+      const int32_t f = nr.q + x;
+      const ERec en = a.ent[f];
+      a.zp[f] = signed_z(en.rs, en.w, yq, a.y[en.nbr], a.sigma, zs);
+    }
   }
 }
 
-__global__ void k_exact_z(int64_t Q, CatView cat, BatchBufs b, const double* y) {
+__global__ void k_obs_z(int64_t Q, BatchBufs b) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= Q) return;
-  const int32_t pi = b.pos[2 * q], pj = b.pos[2 * q + 1];
-  if ((pi & pj) & kSingle) return;  // solved in closed form by k_residual
-  const WRec wr = b.wr[q];
-  const double yi = y[pi & kPosMask];  // the solvers leave y at every position of a node
-  const double yj = y[pj & kPosMask];
-  const double zs = b.sta[2 * q] >= cat.L_p ? cat.zscale_s : 1.0;
-  const double z = (wr.r - sqrt(wr.w) * (yi - yj)) / (cat.sigma * cat.sigma) * zs;
-  b.z[q] = z;
-  b.zp[pi & kPosMask] = z;
-  b.zp[pj & kPosMask] = z;
+  b.z[q] = b.zp[b.pos[2 * q].x & kPosMask];  // the first entry carries +z
 }
 
 // ---------------------------------------------------------------- reduce
@@ -1149,7 +1164,7 @@ __global__ __launch_bounds__(kReduceTB) void k_reduce_waves(int64_t E, int64_t n
   const int64_t key = valid ? key_of(p) : -3;
   double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
   if (valid) {
-    const double cz = ((b.csr[p] & 1) ? -scale : scale) * b.zp[p];
+    const double cz = scale * b.zp[p];  // zp is negated at an observation's second entry
     const double* g = b.gT + p * 3;
     v0 = cz * g[0];
     v1 = cz * g[1];
@@ -1219,13 +1234,13 @@ __global__ void k_batch_terms_out(int64_t n, BatchBufs b, const double* theta, d
   // b.T holds T + t of each entry
   if (Ti) Ti[q] = b.T[2 * q] - theta[(int64_t)b.ev[2 * q] * 4 + 3];
   if (Tj) Tj[q] = b.T[2 * q + 1] - theta[(int64_t)b.ev[2 * q + 1] * 4 + 3];
-  const int64_t pi = b.pos[2 * q] & kPosMask, pj = b.pos[2 * q + 1] & kPosMask;
+  const int64_t pi = b.pos[2 * q].x & kPosMask, pj = b.pos[2 * q + 1].x & kPosMask;
   for (int a = 0; a < 3; ++a) {
     if (gi) gi[q * 3 + a] = b.gT[pi * 3 + a];
     if (gj) gj[q * 3 + a] = b.gT[pj * 3 + a];
   }
   if (r) r[q] = b.r[q];
-  if (z) z[q] = b.z[q];
+  if (z) z[q] = b.zp[pi];  // the first entry carries +z
 }
 
 // Adds the block's sum of k (one value per thread) to *count.
@@ -1250,7 +1265,7 @@ __global__ void k_linear_keep(const BatchBufs b, const double* theta, int64_t n,
   if (q < n) {
     const double* xi = theta + (int64_t)b.ev[2 * q] * 4;
     const double* xj = theta + (int64_t)b.ev[2 * q + 1] * 4;
-    const double* g = b.gT + (int64_t)(b.pos[2 * q] & kPosMask) * 3;
+    const double* g = b.gT + (int64_t)(b.pos[2 * q].x & kPosMask) * 3;
     // b.T holds T + t of each entry
     const double dT = (b.T[2 * q + 1] - xj[3]) - (b.T[2 * q] - xi[3]);
     const double lin = g[0] * (xj[0] - xi[0]) + g[1] * (xj[1] - xi[1]) + g[2] * (xj[2] - xi[2]);
@@ -1264,7 +1279,8 @@ __global__ void k_linear_keep(const BatchBufs b, const double* theta, int64_t n,
 // kLdsNodes nodes and kLdsEntries entries whose cycle core fits the one-wave
 // CG is loaded once (node data, and each entry's other end as an index into
 // the system's list), peeled, solved and back-substituted without touching
-// global memory, and only y is written back; any other system is flagged in
+// global memory, and only z at the system's entries is written back (from
+// y and the entry records); any other system is flagged in
 // spill and left to k_tree_solve.  The arithmetic is that of k_tree_solve:
 // the same elimination rule (ties broken by CSR position), sums in entry
 // order, the same back substitution and core CG, so either kernel gives the
@@ -1361,22 +1377,32 @@ __global__ __launch_bounds__(TB) void k_tree_lds(SolveArgs a) {
 
   // ---- 2. each entry's other end as an index into the list: the loads of
   // a thread's (at most kLdsEntries / TB) entries are all issued before the
-  // first is used
+  // first is used.  The thread keeps its entries' weights and signed
+  // residuals in registers until it writes their z.
+  constexpr int KE = kLdsEntries / TB;
+  double ew[KE], ers[KE];
+  auto node_of = [&](int32_t x) {  // the node of entry x: last i with eoff[i] <= x
+    int32_t lo = 0, hi = N - 1;
+    while (lo < hi) {
+      const int32_t mid = (lo + hi + 1) >> 1;
+      if (eoff[mid] <= x) lo = mid;
+      else hi = mid - 1;
+    }
+    return lo;
+  };
   {
-    constexpr int KE = kLdsEntries / TB;
     int32_t other[KE];
 #pragma unroll
     for (int u = 0; u < KE; ++u) {
       const int32_t x = t + u * TB;
       other[u] = 0;
+      ew[u] = ers[u] = 0.0;
       if (x < total) {
-        int32_t lo = 0, hi = N - 1;  // the node of entry x: last i with eoff[i] <= x
-        while (lo < hi) {
-          const int32_t mid = (lo + hi + 1) >> 1;
-          if (eoff[mid] <= x) lo = mid;
-          else hi = mid - 1;
-        }
-        other[u] = a.nbr[gpos[lo] + (x - eoff[lo])];
+        const int32_t lo = node_of(x);
+        const ERec en = a.ent[gpos[lo] + (x - eoff[lo])];
+        other[u] = en.nbr;
+        ew[u] = en.w;
+        ers[u] = en.rs;
       }
     }
 #pragma unroll
@@ -1447,7 +1473,7 @@ __global__ __launch_bounds__(TB) void k_tree_lds(SolveArgs a) {
           bool first = true;
           for (int32_t x = e0; x < e1; ++x) {
             if (snb[x] != p0) continue;
-            const double wv = a.wgt[gpos[i] + (x - e0)];
+            const double wv = a.ent[gpos[i] + (x - e0)].w;
             W = first ? wv : W + wv;
             first = false;
           }
@@ -1524,11 +1550,16 @@ __global__ __launch_bounds__(TB) void k_tree_lds(SolveArgs a) {
     }
     __syncthreads();
   }
-  // y of every node at each of its positions, so that the whitened residual
-  // of an observation reads it at its entries' positions
-  for (int32_t i = t; i < N; i += TB) {
-    const int32_t ne = eoff[i + 1] - eoff[i];
-    for (int32_t x = 0; x < ne; ++x) a.y[gpos[i] + x] = sB[i];
+  // z at every entry of the system, one entry per thread as in step 2, both
+  // ends' y from LDS
+  const int g = (int)(sys_id % a.L);
+  const double zs = g >= a.L_p ? a.zscale_s : 1.0;
+#pragma unroll
+  for (int u = 0; u < KE; ++u) {
+    const int32_t x = t + u * TB;
+    if (x >= total) continue;
+    const int32_t i = node_of(x);
+    a.zp[gpos[i] + (x - eoff[i])] = signed_z(ers[u], ew[u], sB[i], sB[snb[x]], a.sigma, zs);
   }
   if (t == 0) a.spill[sys_id] = 0;
 }
@@ -1664,8 +1695,7 @@ hipError_t exact_whiten(const CatView& cat, int C, int64_t n, BatchBufs b, Solve
                      nb, span, lambda, E, b, sv);
   SolveArgs a;
   a.nend = b.nend;
-  a.nbr = sv.nbr;
-  a.wgt = sv.wgt;
+  a.ent = sv.ent;
   a.sys = sv.sys;
   a.nb = nb;
   a.list = sv.list;
@@ -1694,12 +1724,15 @@ hipError_t exact_whiten(const CatView& cat, int C, int64_t n, BatchBufs b, Solve
   a.lidx = sv.lidx;
   a.nrec = sv.nrec;
   a.spill = sv.spill;
+  a.zp = b.zp;
+  a.sigma = cat.sigma;
+  a.zscale_s = cat.zscale_s;
+  a.L = cat.L;
+  a.L_p = cat.L_p;
   const char* tg = std::getenv("SPIDER_TREE_GLOBAL");
   a.lds_off = (tg && tg[0] == '1') ? 1 : 0;
   hipLaunchKernelGGL(k_tree_lds<kTreeBlock>, dim3((unsigned)S), dim3(kTreeBlock), 0, s, a);
   hipLaunchKernelGGL(k_tree_solve<kTreeBlock>, dim3((unsigned)S), dim3(kTreeBlock), 0, s, a);
-  hipLaunchKernelGGL(k_exact_z, dim3(grid_for((int64_t)C * n)), dim3(kBlock), 0, s,
-                     (int64_t)C * n, cat, b, (const double*)a.y);
   return hipGetLastError();
 }
 
@@ -1712,6 +1745,11 @@ void launch_reduce(const CatView& cat, int C, int64_t n, double scale, BatchBufs
                      E, n, cat.M, scale, b, G, (double4*)part);
   hipLaunchKernelGGL(k_reduce_keys, dim3(grid_for(K)), dim3(kBlock), 0, s, K, b, G,
                      (const double4*)part);
+}
+
+void launch_obs_z(int64_t Q, const BatchBufs& b, hipStream_t s) {
+  if (Q <= 0) return;
+  hipLaunchKernelGGL(k_obs_z, dim3(grid_for(Q)), dim3(kBlock), 0, s, Q, b);
 }
 
 void launch_batch_terms_out(int64_t n, const BatchBufs& b, const double* theta, double* T_i,

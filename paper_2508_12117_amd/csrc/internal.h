@@ -72,19 +72,31 @@ struct BatchBufs {
   int32_t* start;   // [C M + 1] first CSR position of each (chain, event) key
   int32_t* csr;     // [E] entry at each CSR position
   uint64_t* ckey;   // [E] bucket records (event in bucket, group, entry) of the CSR build
-  int32_t* pos;     // [E] CSR position of each entry; bit 31: its node has one entry
+  int2* pos;        // [E] per entry: x its CSR position (bit 31: its node has one entry),
+                    //     y the first CSR position of its node
   int32_t* pev;     // [E] event at each CSR position
   int32_t* pgr;     // [E] group at each CSR position
-  int32_t* head;    // [E] per CSR position: first position of its node
   int32_t* nend;    // [E] at a node's first position: one past its last
   int32_t* rows;    // [E] network row order of two-phase catalogs (CSR positions, P first)
-  double* zp;       // [E] whitened residual of each CSR position's observation
+  double* zp;       // [E] whitened residual of each CSR position's observation, negated at
+                    //     the observation's second entry (event j)
   RowOut* net_out;  // [E] network output of each row
   double* T;        // [E] travel time plus origin time, T(x; s) + t, of each entry
   double* gT;       // [E][3] source gradient at each CSR position
   double* r;        // [C n] residual
-  double* z;        // [C n] whitened residual
+  double* z;        // [C n] whitened residual (filled from zp by launch_obs_z when asked)
   WRec* wr;         // [C n] per observation taken by the solver: (w, r, its two nodes)
+};
+
+// One entry of a node of the exact whitening, stored at the entry's CSR
+// position: the observation's weight w, its residual r (negated at the
+// observation's second entry, event j) and the first position of the node
+// at the entry's other end.
+struct ERec {
+  double w;
+  double rs;
+  int32_t nbr;
+  int32_t pad;
 };
 
 // A node of the exact whitening in its system's list order: the diagonal A,
@@ -103,8 +115,7 @@ struct SolveBufs {
   int32_t* sys;       // [C L nb + 1] nodes per (chain, group, position block), then list
                       // offsets (system s = c L + g starts at sys[s nb])
   int32_t* list;      // [E] nodes of each system (first positions)
-  int32_t* nbr;       // [E] node at the other end of each position's observation
-  double* wgt;        // [E] edge weight of each position's observation
+  ERec* ent;          // [E] per position of a listed node: its observation's entry record
   double* vec;        // [7][E] A, b, y, Wp, rr, p, ap
   int32_t* ivec;      // [5][E] state, nstate, par, next list, elimination order
   int32_t* lidx;      // [E] at a node's first position: its index in its system's list
@@ -206,12 +217,13 @@ void launch_assemble(const CatView& cat, const NetView& net, const NetView& net_
 void launch_residual(const CatView& cat, int C, int64_t n, const double* theta,
                      int64_t theta_stride, int whiten, BatchBufs b, SolveBufs sv, hipStream_t s);
 // Exact whitening of the marked nodes: per (chain, group) lists, elimination
-// + CG solve of (lambda I + U^T U) y = U^T r, z = (r - U y)/sigma^2.
+// + CG solve of (lambda I + U^T U) y = U^T r, z = (r - U y)/sigma^2, which
+// the solvers write to zp at both entries of each observation they take.
 // err |= kErrSolve when a CG core does not converge.
 hipError_t exact_whiten(const CatView& cat, int C, int64_t n, BatchBufs b, SolveBufs sv, int* err,
                         hipStream_t s);
 // G_lik[c][m] = scale * sum over the entries of (chain c, event m) of
-// +-z (dT/dx, 1), one CSR segment each, summed in a fixed order (scans over
+// zp (dT/dx, 1) (zp carries the entry's sign), one CSR segment each, summed in a fixed order (scans over
 // waves of 64 positions, then the waves in order).
 void launch_reduce(const CatView& cat, int C, int64_t n, double scale, BatchBufs b, double* G,
                    void* part, hipStream_t s);
@@ -263,6 +275,9 @@ void launch_logpost(const CatView& cat, int64_t n, double scale, const double* r
 void launch_tt_assemble(const NetView& net, int64_t rows, const double* x, const double* s,
                         const RowOut* out, double* T, double* gradT, const double* vjp_w,
                         hipStream_t st);
+// z[q] of the first Q observations in slot order, from zp at their first
+// entries (for the calls that return or sum z per observation).
+void launch_obs_z(int64_t Q, const BatchBufs& b, hipStream_t s);
 // Per-slot terms of the first n slots of one chain at state theta (T
 // without the origin time, gT gathered from CSR order).
 void launch_batch_terms_out(int64_t n, const BatchBufs& b, const double* theta, double* T_i,
