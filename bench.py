@@ -32,7 +32,7 @@ HBM_PEAK = 8000.0                             # GB/s
 NETWORK_TRAFFIC = {
     "kernel_sources": ["paper_2508_12117_amd/csrc/mlp_mfma.h", "paper_2508_12117_amd/csrc/mlp_pp.h",
                        "paper_2508_12117_amd/csrc/net_rows.h"],
-    "sha256": "f1da3c6efa44228aef2fe5c48c9c6304eb16eea8ef8d8643d8371558b5675613",
+    "sha256": "f6d4994416d9a8bbedd13597551fbd8d90bbf36d0d08403b8ccf5b4d3c01070e",
     "variant": {"waves": 8, "row_tiles": 4, "schedule": 2},
     "rows": 16777216,
     "fetch_bytes": 229268608,

@@ -114,6 +114,7 @@ struct Net {
     v.wout = wout.as<float>();
     v.bout = bout;
     v.v0 = v0;
+    v.inv_v0 = 1.0 / v0;
     for (int a = 0; a < 3; ++a) {
       v.center[a] = center[a];
       v.half[a] = half[a];
@@ -140,7 +141,7 @@ struct SetLayout {
 // (obs_total slots); the count and system arrays hold each set's keys and
 // systems side by side; the solver scratch holds one set at a time.
 struct Workspace {
-  DevBuf obs, ev, sta, tau, w, start, csr, ckey, pos, pev, pgr, nend, rows, net_out, T, gT,
+  DevBuf obs, ev, sta, tau, w, start, csr, ckey, hd, pev, pgr, nend, rows, net_out, tr, gT,
       r, z, zp, wr;
   DevBuf act, sys, list, ent, vec, ivec, nrec, scan_part, bucket, phase_flags, n_p;
   DevBuf G, partial, thetabar, lp_tmp, err, rpart;
@@ -150,7 +151,7 @@ struct Workspace {
   // scratch), so that the next step's minibatch can be built while the
   // current step still reads its own (graph replays of sampler steps).
   struct Ahead {
-    DevBuf obs, ev, sta, tau, w, start, csr, ckey, pos, pev, pgr, nend, bucket, scan_part;
+    DevBuf obs, ev, sta, tau, w, start, csr, ckey, hd, pev, pgr, nend, bucket, scan_part;
     DevBuf scan_part0;  // scan scratch of a side-0 build beside the whitening's scans
   } ahead;
   hipError_t reserve_ahead(int64_t obs_total, int64_t keys_total, int64_t bucket_words) {
@@ -166,7 +167,7 @@ struct Workspace {
     RES(ahead.start, keys_total * 4);
     RES(ahead.csr, E * 4);
     RES(ahead.ckey, E * 8);
-    RES(ahead.pos, E * 8);
+    RES(ahead.hd, E * 4);
     RES(ahead.pev, E * 4);
     RES(ahead.pgr, E * 4);
     RES(ahead.nend, E * 4);
@@ -191,7 +192,7 @@ struct Workspace {
     b.start = ahead.start.as<int32_t>();
     b.csr = ahead.csr.as<int32_t>();
     b.ckey = ahead.ckey.as<uint64_t>();
-    b.pos = ahead.pos.as<int2>();
+    b.hd = ahead.hd.as<int32_t>();
     b.pev = ahead.pev.as<int32_t>();
     b.pgr = ahead.pgr.as<int32_t>();
     b.nend = ahead.nend.as<int32_t>();
@@ -224,13 +225,13 @@ struct Workspace {
     RES(start, keys_total * 4);
     RES(csr, E * 4);
     RES(ckey, E * 8);
-    RES(pos, E * 8);
+    RES(hd, E * 4);
     RES(pev, E * 4);
     RES(pgr, E * 4);
     RES(nend, E * 4);
     RES(rows, E * 4);
     RES(net_out, E * sizeof(RowOut));
-    RES(T, E * 8);
+    RES(tr, E * sizeof(TRec));
     RES(gT, E * 24);
     RES(r, Cn * 8);
     RES(z, Cn * 8);
@@ -272,13 +273,13 @@ struct Workspace {
     b.start = start.as<int32_t>();
     b.csr = csr.as<int32_t>();
     b.ckey = ckey.as<uint64_t>();
-    b.pos = pos.as<int2>();
+    b.hd = hd.as<int32_t>();
     b.pev = pev.as<int32_t>();
     b.pgr = pgr.as<int32_t>();
     b.nend = nend.as<int32_t>();
     b.rows = rows.as<int32_t>();
     b.net_out = net_out.as<RowOut>();
-    b.T = T.as<double>();
+    b.tr = tr.as<TRec>();
     b.gT = gT.as<double>();
     b.r = r.as<double>();
     b.z = z.as<double>();
@@ -552,17 +553,23 @@ BatchBufs batch_at(const BatchBufs& b, int64_t obs_off, int64_t key_off) {
   o.sta += 2 * obs_off;
   o.csr += 2 * obs_off;
   o.ckey += 2 * obs_off;
-  o.pos += 2 * obs_off;
+  o.hd += 2 * obs_off;
   o.pev += 2 * obs_off;
   o.pgr += 2 * obs_off;
   o.zp += 2 * obs_off;
   o.nend += 2 * obs_off;
   o.rows += 2 * obs_off;
   o.net_out += 2 * obs_off;
-  o.T += 2 * obs_off;
+  o.tr += 2 * obs_off;
   o.gT += 6 * obs_off;
   o.start += key_off;
   return o;
+}
+
+// The same buffers with the residuals not kept (sampler steps read only z).
+BatchBufs without_r(BatchBufs b) {
+  b.r = nullptr;
+  return b;
 }
 
 // Before the network: the minibatch of each chain and its CSR order.
@@ -810,7 +817,8 @@ int fused_step(spider_ctx* ctx, const spider_chainset* sets, int n_sets, const F
     const int64_t n = st.batch;
     const Workspace::SetScratch sc = ws.set_scratch(f.lay[k]);
     rc = post_network(ctx, cat, net, net, st.precision, C, n, cat.theta.as<double>(),
-                      (int64_t)cat.M * 4, nullptr, batch_at(b, f.obs_off[k], f.key_off[k]), true,
+                      (int64_t)cat.M * 4, nullptr,
+                      without_r(batch_at(b, f.obs_off[k], f.key_off[k])), true,
                       (double)cat.N / (double)n, false, &sc);
     if (rc != SPIDER_OK) return rc;
     launch_centroid(cat.theta.as<double>(), C, cat.M, sc.partial, sc.thetabar, ctx->stream);
@@ -872,8 +880,9 @@ int fused_step_ahead(spider_ctx* ctx, const spider_chainset* sets, int n_sets, c
       const int64_t n = st.batch;
       const Workspace::SetScratch sc = ws.set_scratch(f.lay[k]);
       rc = post_network(ctx, cat, net, net, st.precision, C, n, cat.theta.as<double>(),
-                        (int64_t)cat.M * 4, nullptr, batch_at(b, f.obs_off[k], f.key_off[k]),
-                        true, (double)cat.N / (double)n, false, &sc);
+                        (int64_t)cat.M * 4, nullptr,
+                        without_r(batch_at(b, f.obs_off[k], f.key_off[k])), true,
+                        (double)cat.N / (double)n, false, &sc);
       if (rc != SPIDER_OK) {
         ctx->stream = main;
         return rc;

@@ -293,11 +293,10 @@ __device__ void block_sort_any(int32_t len, Get&& get, Put&& put) {
 }
 
 // One workgroup per bucket: the bucket's records in (event, group, entry)
-// order, then per position the entry (csr), its event and group and, at
-// its node's first position, one past the node's last (nend), and per entry
-// pos[e] = (position with the single-entry bit, the node's first position),
-// one 8-byte write; start[] of the bucket's
-// events.  A bucket of up to cap records (held in registers after one read)
+// order, then per position the entry (csr), its event and group, its node's
+// first position with the single-entry bit (hd) and, at that position, one
+// past the node's last (nend), all written in CSR order; start[] of the
+// bucket's events.  A bucket of up to cap records (held in registers after one read)
 // is ordered in LDS: by a counting sort on the event (placement order within
 // an event from LDS atomics), then an insertion sort of each event's segment by one thread, or
 // for a segment longer than kSegShort by every record's rank within it.  A
@@ -436,8 +435,8 @@ __global__ __launch_bounds__(kSortTB) void k_bucket_sort(int64_t nbk, int sb, in
     b.csr[p] = e;
     b.pev[p] = m0 + (int32_t)(x >> 48);
     b.pgr[p] = (int32_t)(eg & 0xFFFF);
+    b.hd[p] = (r0 + j) | ((last && j == i) ? kSingle : 0);
     if (last) b.nend[r0 + j] = p + 1;
-    b.pos[e] = make_int2(p | ((last && j == i) ? kSingle : 0), r0 + j);
   }
 }
 
@@ -479,7 +478,12 @@ __global__ void k_assemble(CatView cat, NetView net, NetView net_s, int64_t n, c
   const double s[3] = {st[0], st[1], st[2]};
   double T, gr[3];
   assemble_tt(g >= cat.L_p ? net_s : net, x, s, b.net_out[v], T, gr);
-  b.T[e] = T + xe.w;  // with the event's origin time, for the residual
+  const int32_t h = b.hd[p];
+  TRec o;
+  o.T = T + xe.w;  // with the event's origin time, for the residual
+  o.p = p | (h & kSingle);
+  o.head = h & kPosMask;
+  b.tr[e] = o;
   b.gT[(int64_t)p * 3 + 0] = gr[0];
   b.gT[(int64_t)p * 3 + 1] = gr[1];
   b.gT[(int64_t)p * 3 + 2] = gr[2];
@@ -492,12 +496,12 @@ __global__ void k_residual(CatView cat, int C, int64_t n, const double* theta, i
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= (int64_t)C * n) return;
   // T of each entry carries its event's origin time: T_i + t_i - (T_j + t_j)
-  const double r = b.tau[q] - (b.T[2 * q] - b.T[2 * q + 1]);
-  b.r[q] = r;
+  const TRec ti = b.tr[2 * q], tj = b.tr[2 * q + 1];  // both entries, one 32-byte read
+  const double r = b.tau[q] - (ti.T - tj.T);
+  if (b.r) b.r[q] = r;
   const double s2 = cat.sigma * cat.sigma;
   const double zs = b.sta[2 * q] >= cat.L_p ? cat.zscale_s : 1.0;
-  const int4 pp = *(const int4*)(b.pos + 2 * q);  // both entries: position, node head
-  const int32_t pi = pp.x, pj = pp.z;
+  const int32_t pi = ti.p, pj = tj.p;
   double z;
   if (whiten == kWhitenL1) {
     z = r > 0.0 ? 1.0 : (r < 0.0 ? -1.0 : 0.0);  // d|r|/dr, 0 at 0
@@ -511,8 +515,8 @@ __global__ void k_residual(CatView cat, int C, int64_t n, const double* theta, i
     WRec x;
     x.w = b.w[q];
     x.r = r;
-    x.hi = pp.y;
-    x.hj = pp.w;
+    x.hi = ti.head;
+    x.hj = tj.head;
     x.pad[0] = x.pad[1] = 0;
     b.wr[q] = x;
     act[x.hi] = 1;
@@ -532,7 +536,8 @@ __global__ void k_residual(CatView cat, int C, int64_t n, const double* theta, i
 
 constexpr int32_t kActive = -1;
 constexpr int32_t kCore = 1 << 30;  // solved by CG after the peeling rounds
-constexpr int kListTB = 256;
+constexpr int kListTB = 512;
+constexpr int kListU = 4;  // positions per thread whose loads are in flight together
 
 // The system lists: block (b, c) of the grid covers positions [2 n c + b span,
 // ...) of chain c; pass 1 counts its marked nodes per group in LDS and writes
@@ -541,7 +546,9 @@ constexpr int kListTB = 256;
 // list does not matter to the solver) and initialises it: the diagonal
 // lambda + sum w and right-hand side (U^T r) = sum +-sqrt(w) r over its
 // entries in CSR order, and per entry its record (weight, signed residual,
-// the node at the other end).  hist: L ints of dynamic LDS.
+// the node at the other end).  hist: L ints of dynamic LDS.  Both passes
+// take the block's positions kListU per thread at a time and issue each
+// stage's loads for all of them before the first is used.
 __global__ __launch_bounds__(kListTB) void k_list_count(int64_t n, int L, int64_t nb, int64_t span,
                                                        BatchBufs b, SolveBufs sv) {
   extern __shared__ int32_t hist[];
@@ -550,8 +557,20 @@ __global__ __launch_bounds__(kListTB) void k_list_count(int64_t n, int L, int64_
   __syncthreads();
   const int64_t p0 = 2 * n * c + bk * span;
   const int64_t p1 = min(2 * n * (c + 1), p0 + span);
-  for (int64_t p = p0 + threadIdx.x; p < p1; p += kListTB)
-    if (sv.act[p]) atomicAdd(&hist[b.pgr[p]], 1);
+  for (int64_t base = p0 + threadIdx.x; base < p1; base += (int64_t)kListTB * kListU) {
+    int32_t on[kListU], g[kListU];
+#pragma unroll
+    for (int u = 0; u < kListU; ++u) {
+      const int64_t p = base + u * kListTB;
+      on[u] = p < p1 ? sv.act[p] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kListU; ++u)
+      if (on[u]) g[u] = b.pgr[base + u * kListTB];
+#pragma unroll
+    for (int u = 0; u < kListU; ++u)
+      if (on[u]) atomicAdd(&hist[g[u]], 1);
+  }
   __syncthreads();
   for (int g = threadIdx.x; g < L; g += kListTB) sv.sys[(c * L + g) * nb + bk] = hist[g];
   if (c == 0 && bk == 0 && threadIdx.x == 0) sv.sys[(int64_t)gridDim.y * L * nb] = 0;
@@ -566,32 +585,55 @@ __global__ __launch_bounds__(kListTB) void k_list_fill(int64_t n, int L, int64_t
   __syncthreads();
   const int64_t p0 = 2 * n * c + bk * span;
   const int64_t p1 = min(2 * n * (c + 1), p0 + span);
-  for (int64_t p = p0 + threadIdx.x; p < p1; p += kListTB) {
-    if (!sv.act[p]) continue;
-    const int32_t g = b.pgr[p];
-    const int32_t slot = atomicAdd(&hist[g], 1);
-    const int32_t at = sv.sys[(c * L + g) * nb + bk] + slot;
-    sv.list[at] = (int32_t)p;
-    sv.lidx[p] = at - sv.sys[(c * L + g) * nb];
-    double A = lambda, rhs = 0.0;
-    for (int32_t f = (int32_t)p; f < b.nend[p]; ++f) {
-      const int32_t e = b.csr[f];
-      const WRec x = b.wr[e >> 1];  // one gather: weight, residual, both nodes
-      A += x.w;
-      rhs += ((e & 1) ? -1.0 : 1.0) * sqrt(x.w) * x.r;
-      ERec en;
-      en.w = x.w;
-      en.rs = (e & 1) ? -x.r : x.r;
-      en.nbr = (e & 1) ? x.hi : x.hj;  // the node at the other end
-      en.pad = 0;
-      sv.ent[f] = en;
+  for (int64_t base = p0 + threadIdx.x; base < p1; base += (int64_t)kListTB * kListU) {
+    // the flags; then group, end and first entry of each marked node; then
+    // that entry's record (weight, residual, both nodes)
+    int32_t on[kListU], g[kListU], pe[kListU], e0[kListU];
+    WRec x0[kListU];
+#pragma unroll
+    for (int u = 0; u < kListU; ++u) {
+      const int64_t p = base + u * kListTB;
+      on[u] = p < p1 ? sv.act[p] : 0;
     }
-    NodeRec nr;
-    nr.A = A;
-    nr.b = rhs;
-    nr.q = (int32_t)p;
-    nr.ne = b.nend[p] - (int32_t)p;
-    sv.nrec[at] = nr;  // list order: the LDS solver reads its system in one stream
+#pragma unroll
+    for (int u = 0; u < kListU; ++u) {
+      if (!on[u]) continue;
+      const int64_t p = base + u * kListTB;
+      g[u] = b.pgr[p];
+      pe[u] = b.nend[p];
+      e0[u] = b.csr[p];
+    }
+#pragma unroll
+    for (int u = 0; u < kListU; ++u)
+      if (on[u]) x0[u] = b.wr[e0[u] >> 1];
+#pragma unroll
+    for (int u = 0; u < kListU; ++u) {
+      if (!on[u]) continue;
+      const int32_t p = (int32_t)(base + u * kListTB);
+      const int32_t slot = atomicAdd(&hist[g[u]], 1);
+      const int32_t at = sv.sys[(c * L + g[u]) * nb + bk] + slot;
+      sv.list[at] = p;
+      sv.lidx[p] = at - sv.sys[(c * L + g[u]) * nb];
+      double A = lambda, rhs = 0.0;
+      for (int32_t f = p; f < pe[u]; ++f) {
+        const int32_t e = f == p ? e0[u] : b.csr[f];
+        const WRec x = f == p ? x0[u] : b.wr[e >> 1];
+        A += x.w;
+        rhs += ((e & 1) ? -1.0 : 1.0) * sqrt(x.w) * x.r;
+        ERec en;
+        en.w = x.w;
+        en.rs = (e & 1) ? -x.r : x.r;
+        en.nbr = (e & 1) ? x.hi : x.hj;  // the node at the other end
+        en.pad = 0;
+        sv.ent[f] = en;
+      }
+      NodeRec nr;
+      nr.A = A;
+      nr.b = rhs;
+      nr.q = p;
+      nr.ne = pe[u] - p;
+      sv.nrec[at] = nr;  // list order: the LDS solver reads its system in one stream
+    }
   }
 }
 
@@ -1133,7 +1175,7 @@ __global__ __launch_bounds__(TB) void k_tree_solve(SolveArgs a) {
 __global__ void k_obs_z(int64_t Q, BatchBufs b) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= Q) return;
-  b.z[q] = b.zp[b.pos[2 * q].x & kPosMask];  // the first entry carries +z
+  b.z[q] = b.zp[b.tr[2 * q].p & kPosMask];  // the first entry carries +z
 }
 
 // ---------------------------------------------------------------- reduce
@@ -1231,10 +1273,11 @@ __global__ void k_batch_terms_out(int64_t n, BatchBufs b, const double* theta, d
                                   double* Tj, double* gi, double* gj, double* r, double* z) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= n) return;
-  // b.T holds T + t of each entry
-  if (Ti) Ti[q] = b.T[2 * q] - theta[(int64_t)b.ev[2 * q] * 4 + 3];
-  if (Tj) Tj[q] = b.T[2 * q + 1] - theta[(int64_t)b.ev[2 * q + 1] * 4 + 3];
-  const int64_t pi = b.pos[2 * q].x & kPosMask, pj = b.pos[2 * q + 1].x & kPosMask;
+  // tr holds T + t of each entry
+  const TRec ti = b.tr[2 * q], tj = b.tr[2 * q + 1];
+  if (Ti) Ti[q] = ti.T - theta[(int64_t)b.ev[2 * q] * 4 + 3];
+  if (Tj) Tj[q] = tj.T - theta[(int64_t)b.ev[2 * q + 1] * 4 + 3];
+  const int64_t pi = ti.p & kPosMask, pj = tj.p & kPosMask;
   for (int a = 0; a < 3; ++a) {
     if (gi) gi[q * 3 + a] = b.gT[pi * 3 + a];
     if (gj) gj[q * 3 + a] = b.gT[pj * 3 + a];
@@ -1265,9 +1308,9 @@ __global__ void k_linear_keep(const BatchBufs b, const double* theta, int64_t n,
   if (q < n) {
     const double* xi = theta + (int64_t)b.ev[2 * q] * 4;
     const double* xj = theta + (int64_t)b.ev[2 * q + 1] * 4;
-    const double* g = b.gT + (int64_t)(b.pos[2 * q].x & kPosMask) * 3;
-    // b.T holds T + t of each entry
-    const double dT = (b.T[2 * q + 1] - xj[3]) - (b.T[2 * q] - xi[3]);
+    const double* g = b.gT + (int64_t)(b.tr[2 * q].p & kPosMask) * 3;
+    // tr holds T + t of each entry
+    const double dT = (b.tr[2 * q + 1].T - xj[3]) - (b.tr[2 * q].T - xi[3]);
     const double lin = g[0] * (xj[0] - xi[0]) + g[1] * (xj[1] - xi[1]) + g[2] * (xj[2] - xi[2]);
     k = fabs(dT - lin) <= e_max * fabs(dT) ? 1u : 0u;
     keep[q] = (uint8_t)k;

@@ -63,6 +63,15 @@ struct WRec {
   int32_t pad[2];
 };
 
+// Per entry, written in one 16-byte store by the assembly (entry order): the
+// travel time plus the event's origin time, the entry's CSR position (bit
+// 31: its node holds this entry only) and its node's first CSR position.
+struct TRec {
+  double T;
+  int32_t p;
+  int32_t head;
+};
+
 struct BatchBufs {
   int64_t* obs;     // [C n] observation index
   int32_t* ev;      // [E] event of each entry
@@ -72,8 +81,8 @@ struct BatchBufs {
   int32_t* start;   // [C M + 1] first CSR position of each (chain, event) key
   int32_t* csr;     // [E] entry at each CSR position
   uint64_t* ckey;   // [E] bucket records (event in bucket, group, entry) of the CSR build
-  int2* pos;        // [E] per entry: x its CSR position (bit 31: its node has one entry),
-                    //     y the first CSR position of its node
+  int32_t* hd;      // [E] per CSR position: the first position of its node; bit 31: the
+                    //     node has this entry only
   int32_t* pev;     // [E] event at each CSR position
   int32_t* pgr;     // [E] group at each CSR position
   int32_t* nend;    // [E] at a node's first position: one past its last
@@ -81,9 +90,9 @@ struct BatchBufs {
   double* zp;       // [E] whitened residual of each CSR position's observation, negated at
                     //     the observation's second entry (event j)
   RowOut* net_out;  // [E] network output of each row
-  double* T;        // [E] travel time plus origin time, T(x; s) + t, of each entry
+  TRec* tr;         // [E] per entry: T(x; s) + t, its CSR position, its node's first one
   double* gT;       // [E][3] source gradient at each CSR position
-  double* r;        // [C n] residual
+  double* r;        // [C n] residual (null: not kept)
   double* z;        // [C n] whitened residual (filled from zp by launch_obs_z when asked)
   WRec* wr;         // [C n] per observation taken by the solver: (w, r, its two nodes)
 };

@@ -42,6 +42,7 @@ struct NetView {
   const float* wout;   // [H]
   float bout;
   double v0;
+  double inv_v0;       // 1 / v0, rounded once on the host
   double center[3];
   double half[3];
   double inv_half[3];  // 1 / half, rounded once on the host
