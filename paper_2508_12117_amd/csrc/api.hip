@@ -141,7 +141,7 @@ struct SetLayout {
 // (obs_total slots); the count and system arrays hold each set's keys and
 // systems side by side; the solver scratch holds one set at a time.
 struct Workspace {
-  DevBuf obs, ev, sta, tau, w, start, csr, ckey, hd, pev, pgr, nend, rows, net_out, tr, gT,
+  DevBuf obs, ev, sta, tau, w, start, csr, ckey, hd, pev, pgr, nend, rows, net_out, tr, gT, gT64,
       r, z, zp, wr;
   DevBuf act, sys, list, ent, vec, ivec, nrec, scan_part, bucket, phase_flags, n_p;
   DevBuf G, partial, thetabar, lp_tmp, err, rpart;
@@ -232,7 +232,8 @@ struct Workspace {
     RES(rows, E * 4);
     RES(net_out, E * sizeof(RowOut));
     RES(tr, E * sizeof(TRec));
-    RES(gT, E * 24);
+    RES(gT, E * 12);
+    RES(gT64, E * 24);
     RES(r, Cn * 8);
     RES(z, Cn * 8);
     RES(zp, E * 8);
@@ -280,7 +281,8 @@ struct Workspace {
     b.rows = rows.as<int32_t>();
     b.net_out = net_out.as<RowOut>();
     b.tr = tr.as<TRec>();
-    b.gT = gT.as<double>();
+    b.gT = gT.as<float>();
+    b.gT64 = gT64.as<double>();
     b.r = r.as<double>();
     b.z = z.as<double>();
     b.zp = zp.as<double>();
@@ -562,6 +564,7 @@ BatchBufs batch_at(const BatchBufs& b, int64_t obs_off, int64_t key_off) {
   o.net_out += 2 * obs_off;
   o.tr += 2 * obs_off;
   o.gT += 6 * obs_off;
+  o.gT64 += 6 * obs_off;
   o.start += key_off;
   return o;
 }
@@ -569,6 +572,13 @@ BatchBufs batch_at(const BatchBufs& b, int64_t obs_off, int64_t key_off) {
 // The same buffers with the residuals not kept (sampler steps read only z).
 BatchBufs without_r(BatchBufs b) {
   b.r = nullptr;
+  return b;
+}
+
+// The same buffers with the selected observation indices not kept (sampler
+// steps use the gathered fields only).
+BatchBufs without_obs(BatchBufs b) {
+  b.obs = nullptr;
   return b;
 }
 
@@ -611,7 +621,8 @@ int post_network(spider_ctx* ctx, const Catalog& cat, const Net& net, const Net&
   Workspace& ws = ctx->ws;
   const Workspace::SetScratch x = sc ? *sc : ws.set_scratch(SetLayout{});
   const CatView cv = cat.view();
-  launch_assemble(cv, net.view(prec), net_s.view(prec), C, n, theta, theta_stride, rows, b,
+  // per-entry gradients in FP64 for the calls that return them (no gradient sums)
+  launch_assemble(cv, net.view(prec), net_s.view(prec), C, n, theta, theta_stride, rows, b, !grad,
                   ctx->stream);
   const int whiten = l1 ? kWhitenL1 : cat.kappa == 0.0 ? SPIDER_WHITEN_NONE : cat.whiten;
   launch_residual(cv, C, n, theta, theta_stride, whiten, b, x.sv, ctx->stream);
@@ -798,7 +809,8 @@ int fused_step(spider_ctx* ctx, const spider_chainset* sets, int n_sets, const F
   for (int k = 0; k < n_sets; ++k) {
     const Catalog& cat = *get_cat(ctx, sets[k].cat_id);
     pre_network(ctx, cat, sets[k].n_chains, sets[k].batch, nullptr, ua.seed,
-                cat.steps.as<int64_t>(), 0, 0, batch_at(b, f.obs_off[k], f.key_off[k]));
+                cat.steps.as<int64_t>(), 0, 0,
+                without_obs(batch_at(b, f.obs_off[k], f.key_off[k])));
   }
   RowSource src;
   std::memset(&src, 0, sizeof(src));
@@ -858,8 +870,8 @@ int fused_step_ahead(spider_ctx* ctx, const spider_chainset* sets, int n_sets, c
   for (int k = 0; k < n_sets; ++k) {
     const Catalog& cat = *get_cat(ctx, sets[k].cat_id);
     pre_network(ctx, cat, sets[k].n_chains, sets[k].batch, nullptr, ua.seed,
-                cat.steps.as<int64_t>(), 1, 0, batch_at(bn, f.obs_off[k], f.key_off[k]),
-                1 - side, true);
+                cat.steps.as<int64_t>(), 1, 0,
+                without_obs(batch_at(bn, f.obs_off[k], f.key_off[k])), 1 - side, true);
   }
   ctx->stream = main;
   const hipError_t eb = hipGetLastError();
@@ -964,7 +976,8 @@ int graph_steps(spider_ctx* ctx, const spider_chainset* sets, int n_sets, FusedS
   for (int k = 0; k < n_sets; ++k) {
     const Catalog& cat = *get_cat(ctx, sets[k].cat_id);
     pre_network(ctx, cat, sets[k].n_chains, sets[k].batch, nullptr, ua.seed,
-                cat.steps.as<int64_t>(), 0, 0, batch_at(b1, f.obs_off[k], f.key_off[k]), 1);
+                cat.steps.as<int64_t>(), 0, 0,
+                without_obs(batch_at(b1, f.obs_off[k], f.key_off[k])), 1);
   }
   HIPCK(hipGetLastError(), "next minibatch");
   hipGraphExec_t x[2] = {nullptr, nullptr};

@@ -158,7 +158,7 @@ __global__ void k_select(CatView cat, int C, int64_t n, const int64_t* idx, uint
     o = 0;
   }
   const ObsRec rc = cat.rec[o];
-  b.obs[q] = o;
+  if (b.obs) b.obs[q] = o;
   b.ev[2 * q] = rc.i;
   b.ev[2 * q + 1] = rc.j;
   b.sta[2 * q] = rc.g;
@@ -465,7 +465,8 @@ __global__ void k_phase_rows(int64_t E, BatchBufs b, int32_t L_p, const int32_t*
 // ---------------------------------------------------------------- assemble
 
 __global__ void k_assemble(CatView cat, NetView net, NetView net_s, int64_t n, const double* theta,
-                           int64_t theta_stride, const int32_t* rows, int64_t E, BatchBufs b) {
+                           int64_t theta_stride, const int32_t* rows, int64_t E, BatchBufs b,
+                           bool grad64) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= E) return;
   const int32_t p = rows ? rows[v] : (int32_t)v;
@@ -484,9 +485,15 @@ __global__ void k_assemble(CatView cat, NetView net, NetView net_s, int64_t n, c
   o.p = p | (h & kSingle);
   o.head = h & kPosMask;
   b.tr[e] = o;
-  b.gT[(int64_t)p * 3 + 0] = gr[0];
-  b.gT[(int64_t)p * 3 + 1] = gr[1];
-  b.gT[(int64_t)p * 3 + 2] = gr[2];
+  if (grad64) {
+    b.gT64[(int64_t)p * 3 + 0] = gr[0];
+    b.gT64[(int64_t)p * 3 + 1] = gr[1];
+    b.gT64[(int64_t)p * 3 + 2] = gr[2];
+  } else {
+    b.gT[(int64_t)p * 3 + 0] = (float)gr[0];
+    b.gT[(int64_t)p * 3 + 1] = (float)gr[1];
+    b.gT[(int64_t)p * 3 + 2] = (float)gr[2];
+  }
 }
 
 // ---------------------------------------------------------------- residual
@@ -1207,10 +1214,10 @@ __global__ __launch_bounds__(kReduceTB) void k_reduce_waves(int64_t E, int64_t n
   double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
   if (valid) {
     const double cz = scale * b.zp[p];  // zp is negated at an observation's second entry
-    const double* g = b.gT + p * 3;
-    v0 = cz * g[0];
-    v1 = cz * g[1];
-    v2 = cz * g[2];
+    const float* g = b.gT + p * 3;
+    v0 = cz * (double)g[0];
+    v1 = cz * (double)g[1];
+    v2 = cz * (double)g[2];
     v3 = cz;
   }
   const int64_t prev = __shfl_up(key, 1, 64), next = __shfl_down(key, 1, 64);
@@ -1279,8 +1286,8 @@ __global__ void k_batch_terms_out(int64_t n, BatchBufs b, const double* theta, d
   if (Tj) Tj[q] = tj.T - theta[(int64_t)b.ev[2 * q + 1] * 4 + 3];
   const int64_t pi = ti.p & kPosMask, pj = tj.p & kPosMask;
   for (int a = 0; a < 3; ++a) {
-    if (gi) gi[q * 3 + a] = b.gT[pi * 3 + a];
-    if (gj) gj[q * 3 + a] = b.gT[pj * 3 + a];
+    if (gi) gi[q * 3 + a] = b.gT64[pi * 3 + a];
+    if (gj) gj[q * 3 + a] = b.gT64[pj * 3 + a];
   }
   if (r) r[q] = b.r[q];
   if (z) z[q] = b.zp[pi];  // the first entry carries +z
@@ -1308,7 +1315,7 @@ __global__ void k_linear_keep(const BatchBufs b, const double* theta, int64_t n,
   if (q < n) {
     const double* xi = theta + (int64_t)b.ev[2 * q] * 4;
     const double* xj = theta + (int64_t)b.ev[2 * q + 1] * 4;
-    const double* g = b.gT + (int64_t)(b.tr[2 * q].p & kPosMask) * 3;
+    const double* g = b.gT64 + (int64_t)(b.tr[2 * q].p & kPosMask) * 3;
     // tr holds T + t of each entry
     const double dT = (b.tr[2 * q + 1].T - xj[3]) - (b.tr[2 * q].T - xi[3]);
     const double lin = g[0] * (xj[0] - xi[0]) + g[1] * (xj[1] - xi[1]) + g[2] * (xj[2] - xi[2]);
@@ -1692,10 +1699,10 @@ void launch_phase_rows(const CatView& cat, int64_t E, BatchBufs b, int32_t* flag
 
 void launch_assemble(const CatView& cat, const NetView& net, const NetView& net_s, int C, int64_t n,
                      const double* theta, int64_t theta_stride, const int32_t* rows, BatchBufs b,
-                     hipStream_t s) {
+                     bool grad64, hipStream_t s) {
   const int64_t E = 2 * (int64_t)C * n;
   hipLaunchKernelGGL(k_assemble, dim3(grid_for(E)), dim3(kBlock), 0, s, cat, net, net_s, n, theta,
-                     theta_stride, rows, E, b);
+                     theta_stride, rows, E, b, grad64);
 }
 
 void launch_residual(const CatView& cat, int C, int64_t n, const double* theta,

@@ -73,7 +73,7 @@ struct TRec {
 };
 
 struct BatchBufs {
-  int64_t* obs;     // [C n] observation index
+  int64_t* obs;     // [C n] observation index (null: not kept)
   int32_t* ev;      // [E] event of each entry
   int32_t* sta;     // [E] group of each entry (station + L_p phase)
   double* tau;      // [C n] observed differential time
@@ -91,7 +91,10 @@ struct BatchBufs {
                     //     the observation's second entry (event j)
   RowOut* net_out;  // [E] network output of each row
   TRec* tr;         // [E] per entry: T(x; s) + t, its CSR position, its node's first one
-  double* gT;       // [E][3] source gradient at each CSR position
+  float* gT;        // [E][3] source gradient at each CSR position (assembled in FP64, kept
+                    //     in FP32 for the per-event sums, which run in FP64)
+  double* gT64;     // [E][3] the same in FP64, written instead of gT for the calls that
+                    //     return per-entry terms
   double* r;        // [C n] residual (null: not kept)
   double* z;        // [C n] whitened residual (filled from zp by launch_obs_z when asked)
   WRec* wr;         // [C n] per observation taken by the solver: (w, r, its two nodes)
@@ -219,7 +222,7 @@ void launch_phase_rows(const CatView& cat, int64_t E, BatchBufs b, int32_t* flag
 // is entry rows[v], or csr[v] when rows is null).
 void launch_assemble(const CatView& cat, const NetView& net, const NetView& net_s, int C, int64_t n,
                      const double* theta, int64_t theta_stride, const int32_t* rows, BatchBufs b,
-                     hipStream_t s);
+                     bool grad64, hipStream_t s);
 // Residuals; z for whitening none / diag / L1 and for the observations of
 // exact whitening whose two nodes have one entry each (z = r / (sigma^2 +
 // 2 kappa^2 w)); the others mark their nodes in sv.act (after a clear).
