@@ -1189,14 +1189,50 @@ __global__ void k_obs_z(int64_t Q, BatchBufs b) {
 
 // Per-event gradient sums over the CSR segments, read position by position
 // (coalesced).  Pass A: each wave takes 64 consecutive positions, forms
-// v = s z (dT/dx, 1) per position (s = +scale for the entry of event i, -scale
-// for event j) and runs a segmented inclusive scan over its lanes (fixed
-// shuffle order); a segment that starts and ends inside the wave is written
+// v = scale z (dT/dx, 1) per position (z carries the entry's sign) and runs
+// a segmented inclusive scan over its lanes (a fixed order of DPP steps:
+// within 16-lane rows, then across rows); a segment that starts and ends
+// inside the wave is written
 // to G at its last lane, the wave's first and last segment sums go to
 // part[w] = {head, tail} when they reach past the wave.  Pass B: every key
 // whose segment spans waves sums tail(first wave) + head(next waves) in wave
 // order; empty keys get 0.  Every sum has a fixed order.
 constexpr int kReduceTB = 256;
+
+// Lane movement by DPP (no LDS): row_shr:D within each 16-lane row, and the
+// broadcasts of lane 15 of rows 0 and 2 into rows 1 and 3 (row_bcast:15) and
+// of lane 31 into rows 2 and 3 (row_bcast:31).  Lanes without a source, and
+// rows outside the mask, read 0.
+constexpr int kDppRowShr = 0x110, kDppBcast15 = 0x142, kDppBcast31 = 0x143;
+
+template <int Ctrl, int RowMask>
+__device__ __forceinline__ int dpp_i32(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, Ctrl, RowMask, 0xF, true);
+}
+
+template <int Ctrl, int RowMask>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int2 x = __builtin_bit_cast(int2, v);
+  int2 y;
+  y.x = dpp_i32<Ctrl, RowMask>(x.x);
+  y.y = dpp_i32<Ctrl, RowMask>(x.y);
+  return __builtin_bit_cast(double, y);
+}
+
+// One step of the segmented inclusive scan of four sums: each lane adds the
+// sums held at its DPP source when ok (the source lies in the lane's
+// segment), in the order source + own.
+template <int Ctrl, int RowMask>
+__device__ __forceinline__ void seg_step(bool ok, double& v0, double& v1, double& v2, double& v3) {
+  const double y0 = dpp_f64<Ctrl, RowMask>(v0), y1 = dpp_f64<Ctrl, RowMask>(v1);
+  const double y2 = dpp_f64<Ctrl, RowMask>(v2), y3 = dpp_f64<Ctrl, RowMask>(v3);
+  if (ok) {
+    v0 = y0 + v0;
+    v1 = y1 + v1;
+    v2 = y2 + v2;
+    v3 = y3 + v3;
+  }
+}
 
 __global__ __launch_bounds__(kReduceTB) void k_reduce_waves(int64_t E, int64_t n, int M,
                                                            double scale, BatchBufs b, double* G,
@@ -1205,9 +1241,10 @@ __global__ __launch_bounds__(kReduceTB) void k_reduce_waves(int64_t E, int64_t n
   const int lane = threadIdx.x & 63;
   const int64_t w = p >> 6, wave0 = w << 6;
   // keys are >= 0; outside [0, E) the sentinels -1 (before) and -2 (after),
-  // -3 for a lane past the end
+  // -3 for a lane past the end (positions fit in 32 bits: 32-bit division)
+  const uint32_t span = (uint32_t)(2 * n);
   auto key_of = [&](int64_t q) -> int64_t {
-    return q < 0 ? -1 : q >= E ? -2 : (q / (2 * n)) * (int64_t)M + b.pev[q];
+    return q < 0 ? -1 : q >= E ? -2 : (int64_t)((uint32_t)q / span) * M + b.pev[q];
   };
   const bool valid = p < E;
   const int64_t key = valid ? key_of(p) : -3;
@@ -1225,22 +1262,20 @@ __global__ __launch_bounds__(kReduceTB) void k_reduce_waves(int64_t E, int64_t n
   const bool tail = lane == 63 || next != key;
   // lane of this lane's segment head within the wave (inclusive max scan)
   int hl = head ? lane : 0;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const int y = __shfl_up(hl, d, 64);
-    if (lane >= d) hl = max(hl, y);
-  }
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const double y0 = __shfl_up(v0, d, 64), y1 = __shfl_up(v1, d, 64);
-    const double y2 = __shfl_up(v2, d, 64), y3 = __shfl_up(v3, d, 64);
-    if (lane - d >= hl) {
-      v0 = y0 + v0;
-      v1 = y1 + v1;
-      v2 = y2 + v2;
-      v3 = y3 + v3;
-    }
-  }
+  hl = max(hl, dpp_i32<kDppRowShr + 1, 0xF>(hl));
+  hl = max(hl, dpp_i32<kDppRowShr + 2, 0xF>(hl));
+  hl = max(hl, dpp_i32<kDppRowShr + 4, 0xF>(hl));
+  hl = max(hl, dpp_i32<kDppRowShr + 8, 0xF>(hl));
+  hl = max(hl, dpp_i32<kDppBcast15, 0xA>(hl));
+  hl = max(hl, dpp_i32<kDppBcast31, 0xC>(hl));
+  // the segmented scan: within each row, then across rows
+  const int r = lane & 15, row0 = lane & 48;
+  seg_step<kDppRowShr + 1, 0xF>(r >= 1 && lane - 1 >= hl, v0, v1, v2, v3);
+  seg_step<kDppRowShr + 2, 0xF>(r >= 2 && lane - 2 >= hl, v0, v1, v2, v3);
+  seg_step<kDppRowShr + 4, 0xF>(r >= 4 && lane - 4 >= hl, v0, v1, v2, v3);
+  seg_step<kDppRowShr + 8, 0xF>(r >= 8 && lane - 8 >= hl, v0, v1, v2, v3);
+  seg_step<kDppBcast15, 0xA>((row0 == 16 || row0 == 48) && hl < row0, v0, v1, v2, v3);
+  seg_step<kDppBcast31, 0xC>(row0 >= 32 && hl < 32, v0, v1, v2, v3);
   if (!valid || !tail) return;
   // does the segment reach past the wave's first or last position?
   const bool open_left = hl == 0 && key_of(wave0 - 1) == key;
