@@ -621,10 +621,11 @@ int post_network(spider_ctx* ctx, const Catalog& cat, const Net& net, const Net&
   Workspace& ws = ctx->ws;
   const Workspace::SetScratch x = sc ? *sc : ws.set_scratch(SetLayout{});
   const CatView cv = cat.view();
-  // per-entry gradients in FP64 for the calls that return them (no gradient sums)
-  launch_assemble(cv, net.view(prec), net_s.view(prec), C, n, theta, theta_stride, rows, b, !grad,
-                  ctx->stream);
   const int whiten = l1 ? kWhitenL1 : cat.kappa == 0.0 ? SPIDER_WHITEN_NONE : cat.whiten;
+  // per-entry gradients in FP64 for the calls that return them (no gradient
+  // sums); the assembly also clears the exact whitening's node flags
+  launch_assemble(cv, net.view(prec), net_s.view(prec), C, n, theta, theta_stride, rows, b, !grad,
+                  whiten == SPIDER_WHITEN_EXACT ? x.sv.act : nullptr, ctx->stream);
   launch_residual(cv, C, n, theta, theta_stride, whiten, b, x.sv, ctx->stream);
   if (whiten == SPIDER_WHITEN_EXACT)
     HIPCK(exact_whiten(cv, C, n, b, x.sv, ws.err.as<int>(), ctx->stream), "exact whitening");

@@ -59,11 +59,6 @@ __device__ inline double block_sum(double v, double* sh) {
   return r;
 }
 
-__global__ void k_fill_i32(int32_t* p, int32_t v, int64_t count) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < count) p[t] = v;
-}
-
 // ---------------------------------------------------------------- scan
 
 constexpr int kScanTB = 256;
@@ -185,6 +180,7 @@ __global__ void k_select(CatView cat, int C, int64_t n, const int64_t* idx, uint
 
 constexpr int64_t kBucketHB = 65536;  // entries per counting block (within one chain)
 constexpr int kBucketTB = 1024;       // threads of the counting and scatter blocks
+constexpr int kBucketU = 8;           // entries per thread whose loads are in flight together
 constexpr int64_t kBucketMax = 16384; // buckets per chain (LDS counters)
 constexpr int kBucketMaxSB = 13;      // at most 8,192 events per bucket
 constexpr int kSortTB = 512;          // threads per bucket
@@ -207,7 +203,18 @@ __global__ __launch_bounds__(kBucketTB) void k_bucket_count(int64_t n, int sb, i
   const int64_t c = blockIdx.y;
   const int64_t e0 = 2 * n * c + (int64_t)blockIdx.x * kBucketHB;
   const int64_t e1 = min(2 * n * (c + 1), e0 + kBucketHB);
-  for (int64_t e = e0 + threadIdx.x; e < e1; e += kBucketTB) atomicAdd(&h[ev[e] >> sb], 1);
+  // kBucketU entries per thread at a time, their loads issued together
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += (int64_t)kBucketTB * kBucketU) {
+    int32_t m[kBucketU];
+#pragma unroll
+    for (int u = 0; u < kBucketU; ++u) {
+      const int64_t x = e + u * kBucketTB;
+      m[u] = x < e1 ? ev[x] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < kBucketU; ++u)
+      if (m[u] >= 0) atomicAdd(&h[m[u] >> sb], 1);
+  }
   __syncthreads();
   int32_t* row = counts + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * nbk;
   for (int64_t k = threadIdx.x; k < nbk; k += kBucketTB) row[k] = h[k];
@@ -248,10 +255,23 @@ __global__ __launch_bounds__(kBucketTB) void k_bucket_scatter(int64_t n, int sb,
   const int64_t e0 = 2 * n * c + (int64_t)blockIdx.x * kBucketHB;
   const int64_t e1 = min(2 * n * (c + 1), e0 + kBucketHB);
   const int32_t mask = (1 << sb) - 1;
-  for (int64_t e = e0 + threadIdx.x; e < e1; e += kBucketTB) {
-    const int32_t m = b.ev[e];
-    const int32_t slot = atomicAdd(&cur[m >> sb], 1);
-    b.ckey[slot] = bucket_record(m & mask, b.sta[e], (int32_t)e);
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += (int64_t)kBucketTB * kBucketU) {
+    int32_t m[kBucketU], g[kBucketU];
+#pragma unroll
+    for (int u = 0; u < kBucketU; ++u) {
+      const int64_t x = e + u * kBucketTB;
+      m[u] = -1;
+      if (x < e1) {
+        m[u] = b.ev[x];
+        g[u] = b.sta[x];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kBucketU; ++u) {
+      if (m[u] < 0) continue;
+      const int32_t slot = atomicAdd(&cur[m[u] >> sb], 1);
+      b.ckey[slot] = bucket_record(m[u] & mask, g[u], (int32_t)(e + u * kBucketTB));
+    }
   }
 }
 
@@ -466,9 +486,10 @@ __global__ void k_phase_rows(int64_t E, BatchBufs b, int32_t L_p, const int32_t*
 
 __global__ void k_assemble(CatView cat, NetView net, NetView net_s, int64_t n, const double* theta,
                            int64_t theta_stride, const int32_t* rows, int64_t E, BatchBufs b,
-                           bool grad64) {
+                           bool grad64, int32_t* act_clear) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= E) return;
+  if (act_clear) act_clear[v] = 0;  // the exact whitening's node flags, set by k_residual
   const int32_t p = rows ? rows[v] : (int32_t)v;
   const int32_t e = b.csr[p];
   const int64_t c = p / (2 * n);  // chain c holds positions [2 n c, 2 n (c + 1))
@@ -1734,17 +1755,14 @@ void launch_phase_rows(const CatView& cat, int64_t E, BatchBufs b, int32_t* flag
 
 void launch_assemble(const CatView& cat, const NetView& net, const NetView& net_s, int C, int64_t n,
                      const double* theta, int64_t theta_stride, const int32_t* rows, BatchBufs b,
-                     bool grad64, hipStream_t s) {
+                     bool grad64, int32_t* act_clear, hipStream_t s) {
   const int64_t E = 2 * (int64_t)C * n;
   hipLaunchKernelGGL(k_assemble, dim3(grid_for(E)), dim3(kBlock), 0, s, cat, net, net_s, n, theta,
-                     theta_stride, rows, E, b, grad64);
+                     theta_stride, rows, E, b, grad64, act_clear);
 }
 
 void launch_residual(const CatView& cat, int C, int64_t n, const double* theta,
                      int64_t theta_stride, int whiten, BatchBufs b, SolveBufs sv, hipStream_t s) {
-  const int64_t E = 2 * (int64_t)C * n;
-  if (whiten == kWhitenExact)
-    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(E)), dim3(kBlock), 0, s, sv.act, 0, E);
   hipLaunchKernelGGL(k_residual, dim3(grid_for((int64_t)C * n)), dim3(kBlock), 0, s, cat, C, n,
                      theta, theta_stride, whiten, b, sv.act);
 }

@@ -222,10 +222,11 @@ void launch_phase_rows(const CatView& cat, int64_t E, BatchBufs b, int32_t* flag
 // is entry rows[v], or csr[v] when rows is null).
 void launch_assemble(const CatView& cat, const NetView& net, const NetView& net_s, int C, int64_t n,
                      const double* theta, int64_t theta_stride, const int32_t* rows, BatchBufs b,
-                     bool grad64, hipStream_t s);
+                     bool grad64, int32_t* act_clear, hipStream_t s);
 // Residuals; z for whitening none / diag / L1 and for the observations of
 // exact whitening whose two nodes have one entry each (z = r / (sigma^2 +
-// 2 kappa^2 w)); the others mark their nodes in sv.act (after a clear).
+// 2 kappa^2 w)); the others mark their nodes in sv.act (cleared by the
+// assembly, which is given it for exact whitening).
 void launch_residual(const CatView& cat, int C, int64_t n, const double* theta,
                      int64_t theta_stride, int whiten, BatchBufs b, SolveBufs sv, hipStream_t s);
 // Exact whitening of the marked nodes: per (chain, group) lists, elimination

@@ -164,11 +164,18 @@ __global__ void k_centroid_partial(const double* theta, int M, int nchunk, doubl
   const double* th = theta + (int64_t)c * M * 4;
   const int64_t m0 = (int64_t)chunk * kCentroidChunk;
   const int64_t m1 = min((int64_t)M, m0 + kCentroidChunk);
+  // one pass over the chunk's events, each read as one 32-byte load
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t m = m0 + threadIdx.x; m < m1; m += kBlock) {
+    const double4 x = *(const double4*)(th + m * 4);
+    s[0] += x.x;
+    s[1] += x.y;
+    s[2] += x.z;
+    s[3] += x.w;
+  }
   for (int a = 0; a < 4; ++a) {
-    double s = 0.0;
-    for (int64_t m = m0 + threadIdx.x; m < m1; m += kBlock) s += th[m * 4 + a];
-    s = block_sum(s, sh);
-    if (threadIdx.x == 0) partial[((int64_t)c * nchunk + chunk) * 4 + a] = s;
+    const double t = block_sum(s[a], sh);
+    if (threadIdx.x == 0) partial[((int64_t)c * nchunk + chunk) * 4 + a] = t;
   }
 }
 
