@@ -185,7 +185,6 @@ constexpr int64_t kBucketMax = 16384; // buckets per chain (LDS counters)
 constexpr int kBucketMaxSB = 13;      // at most 8,192 events per bucket
 constexpr int kSortTB = 512;          // threads per bucket
 constexpr int64_t kBucketTarget = 4096;  // average records per bucket aimed at
-constexpr int kSegShort = 32;         // event segments up to this length: one thread
 
 // A record: event within its bucket (bits 48..60), group (32..47), entry.
 __device__ inline uint64_t bucket_record(int32_t m_local, int32_t g, int32_t e) {
@@ -316,11 +315,11 @@ __device__ void block_sort_any(int32_t len, Get&& get, Put&& put) {
 // order, then per position the entry (csr), its event and group, its node's
 // first position with the single-entry bit (hd) and, at that position, one
 // past the node's last (nend), all written in CSR order; start[] of the
-// bucket's events.  A bucket of up to cap records (held in registers after one read)
-// is ordered in LDS: by a counting sort on the event (placement order within
-// an event from LDS atomics), then an insertion sort of each event's segment by one thread, or
-// for a segment longer than kSegShort by every record's rank within it.  A
-// larger bucket is sorted in place in global memory by a sort network.
+// bucket's events.  A bucket of up to cap records (held in registers after
+// one read) is ordered in LDS: by a counting sort on the event (placement
+// order within an event from LDS atomics), then each event's segment by
+// every record's rank within it.  A larger bucket is sorted in place in
+// global memory by a sort network.
 // Dynamic LDS: cap records, then 2 (2^sb + 1) ints.
 template <int RPT>  // records per thread held in registers: cap = RPT kSortTB
 __global__ __launch_bounds__(kSortTB) void k_bucket_sort(int64_t nbk, int sb, int M,
@@ -358,16 +357,12 @@ __global__ __launch_bounds__(kSortTB) void k_bucket_sort(int64_t nbk, int sb, in
   __syncthreads();
   // ---- segment offsets (exclusive scan over contiguous chunks, wave scans,
   // wave totals) and start[] of the bucket's events
-  int longest = 0;
   {
     const int lane = t & 63, w = t >> 6;
     const int32_t per = (nev + kSortTB - 1) / kSortTB;
     const int32_t k0 = t * per, k1 = min(nev, k0 + per);
     int32_t cnt = 0;
-    for (int32_t k = k0; k < k1; ++k) {
-      cnt += soff[k];
-      longest = max(longest, soff[k]);
-    }
+    for (int32_t k = k0; k < k1; ++k) cnt += soff[k];
     int32_t incl = cnt;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
@@ -389,7 +384,7 @@ __global__ __launch_bounds__(kSortTB) void k_bucket_sort(int64_t nbk, int sb, in
     }
     if (t == 0) soff[nev] = len;
   }
-  const bool short_segs = !__syncthreads_or(longest > kSegShort);
+  __syncthreads();
   int32_t* key_start = b.start + c * M + m0;
   for (int32_t m = t; m < nev; m += kSortTB) key_start[m] = r0 + soff[m];
 
@@ -399,45 +394,30 @@ __global__ __launch_bounds__(kSortTB) void k_bucket_sort(int64_t nbk, int sb, in
     for (int u = 0; u < RPT; ++u)
       if (t + u * kSortTB < len) k_sh[atomicAdd(&cur[(int32_t)(reg[u] >> 48)], 1)] = reg[u];
     __syncthreads();
-    // short segments: insertion sort by one thread each
-    for (int32_t m = t; m < nev; m += kSortTB) {
+    // each segment in (group, entry) order: every record's rank among its
+    // segment's (the records are distinct: they hold the entry), then each
+    // moves to its rank (every record ranks itself, all in parallel)
+    int32_t dst[RPT];
+    uint64_t val[RPT];
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+      const int32_t i = t + u * kSortTB;
+      dst[u] = -1;
+      val[u] = 0;
+      if (i >= len) continue;
+      const uint64_t x = k_sh[i];
+      const int32_t m = (int32_t)(x >> 48);
       const int32_t p0 = soff[m], p1 = soff[m + 1];
-      if (p1 - p0 > kSegShort) continue;
-      for (int32_t i = p0 + 1; i < p1; ++i) {
-        const uint64_t x = k_sh[i];
-        int32_t j = i;
-        while (j > p0 && k_sh[j - 1] > x) {
-          k_sh[j] = k_sh[j - 1];
-          --j;
-        }
-        k_sh[j] = x;
-      }
+      if (p1 - p0 == 1) continue;
+      int32_t rank = 0;
+      for (int32_t j = p0; j < p1; ++j) rank += k_sh[j] < x ? 1 : 0;
+      dst[u] = p0 + rank;
+      val[u] = x;
     }
-    if (!short_segs) {
-      // longer ones: every record's rank among its segment's (the records
-      // are distinct: they hold the entry), then each moves to its rank
-      int32_t dst[RPT];
-      uint64_t val[RPT];
+    __syncthreads();
 #pragma unroll
-      for (int u = 0; u < RPT; ++u) {
-        const int32_t i = t + u * kSortTB;
-        dst[u] = -1;
-        val[u] = 0;
-        if (i >= len) continue;
-        const uint64_t x = k_sh[i];
-        const int32_t m = (int32_t)(x >> 48);
-        const int32_t p0 = soff[m], p1 = soff[m + 1];
-        if (p1 - p0 <= kSegShort) continue;
-        int32_t rank = 0;
-        for (int32_t j = p0; j < p1; ++j) rank += k_sh[j] < x ? 1 : 0;
-        dst[u] = p0 + rank;
-        val[u] = x;
-      }
-      __syncthreads();
-#pragma unroll
-      for (int u = 0; u < RPT; ++u)
-        if (dst[u] >= 0) k_sh[dst[u]] = val[u];
-    }
+    for (int u = 0; u < RPT; ++u)
+      if (dst[u] >= 0) k_sh[dst[u]] = val[u];
   } else {
     block_sort_any(len, [&](int32_t i) { return rec[i]; }, [&](int32_t i, uint64_t x) { rec[i] = x; });
   }
