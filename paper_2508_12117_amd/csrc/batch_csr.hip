@@ -1385,9 +1385,8 @@ __global__ __launch_bounds__(TB) void k_tree_lds(SolveArgs a) {
   __shared__ uint16_t snb[kLdsEntries];
   __shared__ uint16_t spar[kLdsNodes];
   __shared__ uint8_t sst[kLdsNodes], snst[kLdsNodes];
-  __shared__ __attribute__((aligned(16))) uint16_t lst[3][kLdsNodes];
+  __shared__ __attribute__((aligned(16))) uint16_t lst[2][kLdsNodes];
   __shared__ int32_t scan[TB / 64];
-  __shared__ int32_t elim_start[kMaxRounds + 2];
   __shared__ int flag;
   const int t = threadIdx.x;
   const int64_t sys_id = blockIdx.x;
@@ -1513,15 +1512,13 @@ __global__ __launch_bounds__(TB) void k_tree_lds(SolveArgs a) {
   }
   uint16_t* act = lst[0];
   uint16_t* nxt = lst[1];
-  uint16_t* elim = lst[2];
   for (int32_t i = t; i < N; i += TB) act[i] = (uint16_t)i;
   __syncthreads();
 
-  // ---- 3. peeling rounds
-  int32_t nl = N, n_elim = 0;
+  // ---- 3. peeling rounds (a node eliminated in round r keeps state r)
+  int32_t nl = N;
   int rounds = 0;
   for (; rounds < a.max_rounds && nl > 0; ++rounds) {
-    if (t == 0) elim_start[rounds] = n_elim;
     int changed = 0;
     for (int32_t k = t; k < nl; k += TB) {
       const int32_t i = act[k];
@@ -1597,9 +1594,6 @@ __global__ __launch_bounds__(TB) void k_tree_lds(SolveArgs a) {
     __syncthreads();
     for (int32_t k = t; k < nl; k += TB) sst[act[k]] = snst[act[k]];
     __syncthreads();
-    n_elim += block_compact<TB>(
-        nl, [&](int32_t k) { return sst[act[k]] != kLActive; }, [&](int32_t k) { return act[k]; },
-        elim + n_elim, scan);
     nl = block_compact<TB>(
         nl, [&](int32_t k) { return sst[act[k]] == kLActive; }, [&](int32_t k) { return act[k]; },
         nxt, scan);
@@ -1607,7 +1601,6 @@ __global__ __launch_bounds__(TB) void k_tree_lds(SolveArgs a) {
     act = nxt;
     nxt = tmp;
   }
-  if (t == 0) elim_start[rounds] = n_elim;
   __syncthreads();
 
   // ---- 4. the cycle core: one-wave CG, or the whole system to k_tree_solve
@@ -1627,10 +1620,11 @@ __global__ __launch_bounds__(TB) void k_tree_lds(SolveArgs a) {
     }
   }
 
-  // ---- 5. back substitution in reverse elimination order (y replaces b)
+  // ---- 5. back substitution in reverse round order (y replaces b): the
+  // nodes of a round, found by their state, are independent of each other
   for (int rnd = rounds - 1; rnd >= 0; --rnd) {
-    for (int32_t k = elim_start[rnd] + t; k < elim_start[rnd + 1]; k += TB) {
-      const int32_t i = elim[k];
+    for (int32_t i = t; i < N; i += TB) {
+      if (sst[i] != rnd) continue;
       const int32_t pn = spar[i];
       sB[i] = pn == kLNoPar ? sB[i] / sA[i] : (sB[i] + sW[i] * sB[pn]) / sA[i];
     }
