@@ -846,15 +846,16 @@ __device__ bool wave_core_cg(const SolveArgs& a, const int32_t* core, int32_t n,
 // list (positions gpos), entries in LDS (eoff, snb), state sst; y replaces b
 // in sB.  Same ordering (by CSR position), arithmetic and tolerances as
 // wave_core_cg.
+template <class Q>
 __device__ bool wave_core_cg_lds(const SolveArgs& a, const uint16_t* core, int32_t n,
-                                 const int32_t* gpos, const uint16_t* eoff, const uint16_t* snb,
+                                 Q&& gpos, const uint16_t* eoff, const uint16_t* snb,
                                  uint8_t* sst, const double* sA, double* sB,
                                  double (*w_sh)[kWaveNb], int32_t (*nb_sh)[kWaveNb]) {
   constexpr uint8_t kActiveL = 255, kCoreL = 254;
   const int lane = threadIdx.x & 63;
   const bool on = lane < n;
   const int32_t mine_i = on ? core[lane] : 0;
-  const int32_t mine = on ? gpos[mine_i] : INT32_MAX;
+  const int32_t mine = on ? gpos(mine_i) : INT32_MAX;
   int rank = 0;
   for (int k = 0; k < n; ++k) rank += __shfl(mine, k, 64) < mine ? 1 : 0;
   int32_t node = 0, key = INT32_MAX;  // this lane's node (list index) and position
@@ -878,7 +879,7 @@ __device__ bool wave_core_cg_lds(const SolveArgs& a, const uint16_t* core, int32
         over = true;
         break;
       }
-      nb_sh[lane][cnt] = gpos[pn];
+      nb_sh[lane][cnt] = gpos(pn);
       w_sh[lane][cnt] = a.ent[key + (x - e0)].w;
       ++cnt;
     }
@@ -1370,38 +1371,52 @@ __global__ void k_linear_keep(const BatchBufs b, const double* theta, int64_t n,
 // spill and left to k_tree_solve.  The arithmetic is that of k_tree_solve:
 // the same elimination rule (ties broken by CSR position), sums in entry
 // order, the same back substitution and core CG, so either kernel gives the
-// same y.
-constexpr int kLdsNodes = 3328;
+// same y.  Two layouts: up to kLdsNodes nodes with each node's first
+// position held in LDS, and up to kLdsNodesLarge nodes with it read from the
+// node records in global memory (34 instead of 38 bytes of LDS per node);
+// the second launch takes only the systems the first one flagged for their
+// size.
+constexpr int kLdsNodes = 3840;
+constexpr int kLdsNodesLarge = 4288;
 constexpr int kLdsEntries = 8192;
 constexpr uint8_t kLActive = 255, kLCore = 254;
 constexpr uint16_t kLNoPar = 0xFFFF;
 
-template <int TB>
-__global__ __launch_bounds__(TB) void k_tree_lds(SolveArgs a) {
-  static_assert(kLdsEntries % TB == 0 && kMaxRounds < kLCore, "LDS solver shape");
-  __shared__ double sA[kLdsNodes], sB[kLdsNodes], sW[kLdsNodes];
-  __shared__ int32_t gpos[kLdsNodes];
-  __shared__ uint16_t eoff[kLdsNodes + 2];
+template <int TB, int NODES, bool POS_LDS>
+__global__ __launch_bounds__(TB) void k_tree_lds(SolveArgs a, int32_t min_nodes) {
+  static_assert(kLdsEntries % TB == 0 && kMaxRounds < kLCore && NODES < kLNoPar,
+                "LDS solver shape");
+  __shared__ double sA[NODES], sB[NODES], sW[NODES];
+  __shared__ int32_t gpos_sh[POS_LDS ? NODES : 1];
+  __shared__ uint16_t eoff[NODES + 2];
   __shared__ uint16_t snb[kLdsEntries];
-  __shared__ uint16_t spar[kLdsNodes];
-  __shared__ uint8_t sst[kLdsNodes], snst[kLdsNodes];
-  __shared__ __attribute__((aligned(16))) uint16_t lst[2][kLdsNodes];
+  __shared__ uint16_t spar[NODES];
+  __shared__ uint8_t sst[NODES], snst[NODES];
+  __shared__ __attribute__((aligned(16))) uint16_t lst[2][NODES];
   __shared__ int32_t scan[TB / 64];
   __shared__ int flag;
   const int t = threadIdx.x;
   const int64_t sys_id = blockIdx.x;
   const int32_t off = a.sys[sys_id * a.nb];
   const int32_t N = a.sys[(sys_id + 1) * a.nb] - off;
-  if (N <= 0 || N > kLdsNodes || a.lds_off) {
+  if (min_nodes > 0) {
+    // a retry of the systems flagged for their size only
+    if (a.lds_off || !a.spill[sys_id] || N < min_nodes || N > NODES) return;
+  } else if (N <= 0 || N > NODES || a.lds_off) {
     if (t == 0) a.spill[sys_id] = N > 0 ? 1 : 0;
     return;
   }
+  // first CSR position of node i
+  auto gpos = [&](int32_t i) -> int32_t {
+    if constexpr (POS_LDS) return gpos_sh[i];
+    else return a.nrec[off + i].q;
+  };
 
   // ---- 1. nodes (first position, entry count clamped above kLdsEntries, A,
   // b) from the list-ordered records, one coalesced stream per system, then
   // the entry offsets by an exclusive scan over contiguous chunks
   {
-    constexpr int KN = (kLdsNodes + TB - 1) / TB;
+    constexpr int KN = (NODES + TB - 1) / TB;
     NodeRec nr[KN];
 #pragma unroll
     for (int u = 0; u < KN; ++u) {
@@ -1412,7 +1427,7 @@ __global__ __launch_bounds__(TB) void k_tree_lds(SolveArgs a) {
     for (int u = 0; u < KN; ++u) {
       const int32_t i = t + u * TB;
       if (i >= N) continue;
-      gpos[i] = nr[u].q;
+      if constexpr (POS_LDS) gpos_sh[i] = nr[u].q;
       eoff[i] = (uint16_t)min(nr[u].ne, kLdsEntries + 1);
       sA[i] = nr[u].A;
       sB[i] = nr[u].b;
@@ -1484,7 +1499,7 @@ __global__ __launch_bounds__(TB) void k_tree_lds(SolveArgs a) {
       ew[u] = ers[u] = 0.0;
       if (x < total) {
         const int32_t lo = node_of(x);
-        const ERec en = a.ent[gpos[lo] + (x - eoff[lo])];
+        const ERec en = a.ent[gpos(lo) + (x - eoff[lo])];
         other[u] = en.nbr;
         ew[u] = en.w;
         ers[u] = en.rs;
@@ -1548,7 +1563,8 @@ __global__ __launch_bounds__(TB) void k_tree_lds(SolveArgs a) {
             break;
           }
         }
-        if (p0_other || gpos[i] > gpos[p0]) {
+        const int32_t qi = gpos(i);
+        if (p0_other || qi > gpos(p0)) {
           ns = (uint8_t)rounds;
           spar[i] = (uint16_t)p0;
           // weight to the parent: its entries' weights in entry order
@@ -1556,7 +1572,7 @@ __global__ __launch_bounds__(TB) void k_tree_lds(SolveArgs a) {
           bool first = true;
           for (int32_t x = e0; x < e1; ++x) {
             if (snb[x] != p0) continue;
-            const double wv = a.ent[gpos[i] + (x - e0)].w;
+            const double wv = a.ent[qi + (x - e0)].w;
             W = first ? wv : W + wv;
             first = false;
           }
@@ -1639,7 +1655,7 @@ __global__ __launch_bounds__(TB) void k_tree_lds(SolveArgs a) {
     const int32_t x = t + u * TB;
     if (x >= total) continue;
     const int32_t i = node_of(x);
-    a.zp[gpos[i] + (x - eoff[i])] = signed_z(ers[u], ew[u], sB[i], sB[snb[x]], a.sigma, zs);
+    a.zp[gpos(i) + (x - eoff[i])] = signed_z(ers[u], ew[u], sB[i], sB[snb[x]], a.sigma, zs);
   }
   if (t == 0) a.spill[sys_id] = 0;
 }
@@ -1808,7 +1824,10 @@ hipError_t exact_whiten(const CatView& cat, int C, int64_t n, BatchBufs b, Solve
   a.L_p = cat.L_p;
   const char* tg = std::getenv("SPIDER_TREE_GLOBAL");
   a.lds_off = (tg && tg[0] == '1') ? 1 : 0;
-  hipLaunchKernelGGL(k_tree_lds<kTreeBlock>, dim3((unsigned)S), dim3(kTreeBlock), 0, s, a);
+  hipLaunchKernelGGL((k_tree_lds<kTreeBlock, kLdsNodes, true>), dim3((unsigned)S), dim3(kTreeBlock),
+                     0, s, a, 0);
+  hipLaunchKernelGGL((k_tree_lds<kTreeBlock, kLdsNodesLarge, false>), dim3((unsigned)S),
+                     dim3(kTreeBlock), 0, s, a, kLdsNodes + 1);
   hipLaunchKernelGGL(k_tree_solve<kTreeBlock>, dim3((unsigned)S), dim3(kTreeBlock), 0, s, a);
   return hipGetLastError();
 }
