@@ -1371,25 +1371,32 @@ __global__ void k_linear_keep(const BatchBufs b, const double* theta, int64_t n,
 // spill and left to k_tree_solve.  The arithmetic is that of k_tree_solve:
 // the same elimination rule (ties broken by CSR position), sums in entry
 // order, the same back substitution and core CG, so either kernel gives the
-// same y.  Two layouts: up to kLdsNodes nodes with each node's first
-// position held in LDS, and up to kLdsNodesLarge nodes with it read from the
+// same y.  Three layouts: up to kLdsNodes nodes with each node's first
+// position held in LDS; up to kLdsNodesLarge nodes with it read from the
 // node records in global memory (34 instead of 38 bytes of LDS per node);
-// the second launch takes only the systems the first one flagged for their
-// size.
+// and up to kHybNodes nodes and kHybEntries entries with A, b and the
+// parent weight in global memory as well (8 bytes of LDS per node: the
+// graph, states and lists).  The later launches take only the systems an
+// earlier one flagged for their size (spill code 1; code 2 is a core the
+// one-wave CG does not take, for k_tree_solve).
 constexpr int kLdsNodes = 3840;
 constexpr int kLdsNodesLarge = 4288;
 constexpr int kLdsEntries = 8192;
+constexpr int kHybNodes = 10240;
+constexpr int kHybEntries = 20480;
 constexpr uint8_t kLActive = 255, kLCore = 254;
 constexpr uint16_t kLNoPar = 0xFFFF;
 
-template <int TB, int NODES, bool POS_LDS>
+template <int TB, int NODES, int ENTRIES, bool POS_LDS, bool VAL_LDS>
 __global__ __launch_bounds__(TB) void k_tree_lds(SolveArgs a, int32_t min_nodes) {
-  static_assert(kLdsEntries % TB == 0 && kMaxRounds < kLCore && NODES < kLNoPar,
+  static_assert(ENTRIES % TB == 0 && kMaxRounds < kLCore && NODES < kLNoPar &&
+                    ENTRIES < 0xFFFF && (VAL_LDS || !POS_LDS),
                 "LDS solver shape");
-  __shared__ double sA[NODES], sB[NODES], sW[NODES];
+  __shared__ double sA_sh[VAL_LDS ? NODES : 1], sB_sh[VAL_LDS ? NODES : 1],
+      sW_sh[VAL_LDS ? NODES : 1];
   __shared__ int32_t gpos_sh[POS_LDS ? NODES : 1];
   __shared__ uint16_t eoff[NODES + 2];
-  __shared__ uint16_t snb[kLdsEntries];
+  __shared__ uint16_t snb[ENTRIES];
   __shared__ uint16_t spar[NODES];
   __shared__ uint8_t sst[NODES], snst[NODES];
   __shared__ __attribute__((aligned(16))) uint16_t lst[2][NODES];
@@ -1401,10 +1408,24 @@ __global__ __launch_bounds__(TB) void k_tree_lds(SolveArgs a, int32_t min_nodes)
   const int32_t N = a.sys[(sys_id + 1) * a.nb] - off;
   if (min_nodes > 0) {
     // a retry of the systems flagged for their size only
-    if (a.lds_off || !a.spill[sys_id] || N < min_nodes || N > NODES) return;
+    if (a.lds_off || a.spill[sys_id] != 1 || N < min_nodes || N > NODES) return;
   } else if (N <= 0 || N > NODES || a.lds_off) {
     if (t == 0) a.spill[sys_id] = N > 0 ? 1 : 0;
     return;
+  }
+  // A, b (then y) and the weight to the parent of node i: LDS, or global
+  // memory at the system's list offsets
+  double* sA;
+  double* sB;
+  double* sW;
+  if constexpr (VAL_LDS) {
+    sA = sA_sh;
+    sB = sB_sh;
+    sW = sW_sh;
+  } else {
+    sA = a.A + off;
+    sB = a.b + off;
+    sW = a.Wp + off;
   }
   // first CSR position of node i
   auto gpos = [&](int32_t i) -> int32_t {
@@ -1415,7 +1436,7 @@ __global__ __launch_bounds__(TB) void k_tree_lds(SolveArgs a, int32_t min_nodes)
   // ---- 1. nodes (first position, entry count clamped above kLdsEntries, A,
   // b) from the list-ordered records, one coalesced stream per system, then
   // the entry offsets by an exclusive scan over contiguous chunks
-  {
+  if constexpr (VAL_LDS) {
     constexpr int KN = (NODES + TB - 1) / TB;
     NodeRec nr[KN];
 #pragma unroll
@@ -1428,9 +1449,18 @@ __global__ __launch_bounds__(TB) void k_tree_lds(SolveArgs a, int32_t min_nodes)
       const int32_t i = t + u * TB;
       if (i >= N) continue;
       if constexpr (POS_LDS) gpos_sh[i] = nr[u].q;
-      eoff[i] = (uint16_t)min(nr[u].ne, kLdsEntries + 1);
+      eoff[i] = (uint16_t)min(nr[u].ne, ENTRIES + 1);
       sA[i] = nr[u].A;
       sB[i] = nr[u].b;
+      sst[i] = kLActive;
+      snst[i] = kLActive;
+    }
+  } else {
+    for (int32_t i = t; i < N; i += TB) {
+      const NodeRec nr = a.nrec[off + i];
+      eoff[i] = (uint16_t)min(nr.ne, ENTRIES + 1);
+      sA[i] = nr.A;
+      sB[i] = nr.b;
       sst[i] = kLActive;
       snst[i] = kLActive;
     }
@@ -1459,7 +1489,7 @@ __global__ __launch_bounds__(TB) void k_tree_lds(SolveArgs a, int32_t min_nodes)
       if (v < w) before += x;
       total += x;
     }
-    if (total <= kLdsEntries) {
+    if (total <= ENTRIES) {
       int32_t o = before + incl - cnt;
       for (int32_t k = k0; k < k1; ++k) {
         const int32_t x = eoff[k];
@@ -1469,7 +1499,7 @@ __global__ __launch_bounds__(TB) void k_tree_lds(SolveArgs a, int32_t min_nodes)
       if (t == 0) eoff[N] = (uint16_t)total;
     }
   }
-  if (total > kLdsEntries) {
+  if (total > ENTRIES) {
     if (t == 0) a.spill[sys_id] = 1;
     return;
   }
@@ -1479,7 +1509,7 @@ __global__ __launch_bounds__(TB) void k_tree_lds(SolveArgs a, int32_t min_nodes)
   // a thread's (at most kLdsEntries / TB) entries are all issued before the
   // first is used.  The thread keeps its entries' weights and signed
   // residuals in registers until it writes their z.
-  constexpr int KE = kLdsEntries / TB;
+  constexpr int KE = VAL_LDS ? ENTRIES / TB : 1;
   double ew[KE], ers[KE];
   auto node_of = [&](int32_t x) {  // the node of entry x: last i with eoff[i] <= x
     int32_t lo = 0, hi = N - 1;
@@ -1490,7 +1520,20 @@ __global__ __launch_bounds__(TB) void k_tree_lds(SolveArgs a, int32_t min_nodes)
     }
     return lo;
   };
-  {
+  if constexpr (!VAL_LDS) {
+    // one entry per thread at a time; the epilogue reads the records again
+    int bad = 0;
+    for (int32_t x = t; x < total; x += TB) {
+      const int32_t lo = node_of(x);
+      const int32_t other = a.lidx[a.ent[gpos(lo) + (x - eoff[lo])].nbr];
+      if ((uint32_t)other >= (uint32_t)N) bad = 1;
+      else snb[x] = (uint16_t)other;
+    }
+    if (__syncthreads_or(bad)) {
+      if (t == 0) a.spill[sys_id] = 2;
+      return;
+    }
+  } else {
     int32_t other[KE];
 #pragma unroll
     for (int u = 0; u < KE; ++u) {
@@ -1521,7 +1564,7 @@ __global__ __launch_bounds__(TB) void k_tree_lds(SolveArgs a, int32_t min_nodes)
       else snb[x] = (uint16_t)other[u];
     }
     if (__syncthreads_or(bad)) {
-      if (t == 0) a.spill[sys_id] = 1;
+      if (t == 0) a.spill[sys_id] = 2;
       return;
     }
   }
@@ -1631,7 +1674,7 @@ __global__ __launch_bounds__(TB) void k_tree_lds(SolveArgs a, int32_t min_nodes)
     }
     __syncthreads();
     if (!flag) {
-      if (t == 0) a.spill[sys_id] = 1;
+      if (t == 0) a.spill[sys_id] = 2;
       return;
     }
   }
@@ -1647,15 +1690,24 @@ __global__ __launch_bounds__(TB) void k_tree_lds(SolveArgs a, int32_t min_nodes)
     __syncthreads();
   }
   // z at every entry of the system, one entry per thread as in step 2, both
-  // ends' y from LDS
+  // ends' y from the solved b
   const int g = (int)(sys_id % a.L);
   const double zs = g >= a.L_p ? a.zscale_s : 1.0;
+  if constexpr (VAL_LDS) {
 #pragma unroll
-  for (int u = 0; u < KE; ++u) {
-    const int32_t x = t + u * TB;
-    if (x >= total) continue;
-    const int32_t i = node_of(x);
-    a.zp[gpos(i) + (x - eoff[i])] = signed_z(ers[u], ew[u], sB[i], sB[snb[x]], a.sigma, zs);
+    for (int u = 0; u < KE; ++u) {
+      const int32_t x = t + u * TB;
+      if (x >= total) continue;
+      const int32_t i = node_of(x);
+      a.zp[gpos(i) + (x - eoff[i])] = signed_z(ers[u], ew[u], sB[i], sB[snb[x]], a.sigma, zs);
+    }
+  } else {
+    for (int32_t x = t; x < total; x += TB) {
+      const int32_t i = node_of(x);
+      const int32_t f = gpos(i) + (x - eoff[i]);
+      const ERec en = a.ent[f];
+      a.zp[f] = signed_z(en.rs, en.w, sB[i], sB[snb[x]], a.sigma, zs);
+    }
   }
   if (t == 0) a.spill[sys_id] = 0;
 }
@@ -1824,10 +1876,12 @@ hipError_t exact_whiten(const CatView& cat, int C, int64_t n, BatchBufs b, Solve
   a.L_p = cat.L_p;
   const char* tg = std::getenv("SPIDER_TREE_GLOBAL");
   a.lds_off = (tg && tg[0] == '1') ? 1 : 0;
-  hipLaunchKernelGGL((k_tree_lds<kTreeBlock, kLdsNodes, true>), dim3((unsigned)S), dim3(kTreeBlock),
-                     0, s, a, 0);
-  hipLaunchKernelGGL((k_tree_lds<kTreeBlock, kLdsNodesLarge, false>), dim3((unsigned)S),
-                     dim3(kTreeBlock), 0, s, a, kLdsNodes + 1);
+  hipLaunchKernelGGL((k_tree_lds<kTreeBlock, kLdsNodes, kLdsEntries, true, true>),
+                     dim3((unsigned)S), dim3(kTreeBlock), 0, s, a, 0);
+  hipLaunchKernelGGL((k_tree_lds<kTreeBlock, kLdsNodesLarge, kLdsEntries, false, true>),
+                     dim3((unsigned)S), dim3(kTreeBlock), 0, s, a, kLdsNodes + 1);
+  hipLaunchKernelGGL((k_tree_lds<kTreeBlock, kHybNodes, kHybEntries, false, false>),
+                     dim3((unsigned)S), dim3(kTreeBlock), 0, s, a, 1);
   hipLaunchKernelGGL(k_tree_solve<kTreeBlock>, dim3((unsigned)S), dim3(kTreeBlock), 0, s, a);
   return hipGetLastError();
 }

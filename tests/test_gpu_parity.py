@@ -231,14 +231,15 @@ def test_exact_whitening_large_batches(ctx, faults_setup, n, C):
 def test_exact_whitening_lds_solver_equals_global(ctx, tiny_setup, faults_setup, monkeypatch,
                                                   which, n):
     """The LDS-resident solver (systems up to 3,840 nodes, or 4,288 in its
-    second layout, and 8,192 entries, with a core of at most 64 nodes) and
-    the global-memory one give the same z bit for bit: on tiny at n = 4096
-    some groups keep cores too large for the one-wave CG and go to the
-    global solver inside the same launches; faults10k at 2^16 fits in the
-    first layout everywhere; at 215,000 most of its 50 groups hold 3,841 to
-    4,288 nodes (the second layout) and a few more (the global solver); at
-    2^18 the groups exceed 8,192 entries.  Both runs also meet T4 (within
-    1e-10 of the batch system)."""
+    second layout, and 8,192 entries, or 10,240 nodes and 20,480 entries in
+    its third, with a core of at most 64 nodes) and the global-memory one
+    give the same z bit for bit: on tiny at n = 4096 some groups keep cores
+    too large for the one-wave CG and go to the global solver inside the
+    same launches; faults10k at 2^16 fits in the first layout everywhere; at
+    215,000 most of its 50 groups hold 3,841 to 4,288 nodes (the second
+    layout) and a few more (the third); at 2^18 the groups exceed 8,192
+    entries (the third).  Both runs also meet T4 (within 1e-10 of the batch
+    system)."""
     cat, _, cid, nid = tiny_setup if which == "tiny" else faults_setup
     prob = lk.load(cat)
     theta = synth.random_theta(cat, 33)
