@@ -1362,23 +1362,23 @@ __global__ void k_linear_keep(const BatchBufs b, const double* theta, int64_t n,
   block_count_add(k, count);
 }
 
-// ---- the same solve with the system held in LDS.  A system of up to
-// kLdsNodes nodes and kLdsEntries entries whose cycle core fits the one-wave
-// CG is loaded once (node data, and each entry's other end as an index into
-// the system's list), peeled, solved and back-substituted without touching
-// global memory, and only z at the system's entries is written back (from
-// y and the entry records); any other system is flagged in
-// spill and left to k_tree_solve.  The arithmetic is that of k_tree_solve:
-// the same elimination rule (ties broken by CSR position), sums in entry
-// order, the same back substitution and core CG, so either kernel gives the
-// same y.  Three layouts: up to kLdsNodes nodes with each node's first
-// position held in LDS; up to kLdsNodesLarge nodes with it read from the
-// node records in global memory (34 instead of 38 bytes of LDS per node);
-// and up to kHybNodes nodes and kHybEntries entries with A, b and the
-// parent weight in global memory as well (8 bytes of LDS per node: the
-// graph, states and lists).  The later launches take only the systems an
-// earlier one flagged for their size (spill code 1; code 2 is a core the
-// one-wave CG does not take, for k_tree_solve).
+// ---- the same solve with the system held in LDS.  A system whose cycle
+// core fits the one-wave CG is loaded once (node data, and each entry's other
+// end as an index into the system's list), peeled, solved and
+// back-substituted, and only z at the system's entries is written back (from
+// y and the entry records); any other system is flagged in spill and left to
+// k_tree_solve.  The arithmetic is that of k_tree_solve: the same
+// elimination rule (ties broken by CSR position), sums in entry order, the
+// same back substitution and core CG, so either kernel gives the same y.
+// Three layouts, one launch each: up to kLdsNodes nodes and kLdsEntries
+// entries with everything in LDS (38 bytes per node); up to kLdsNodesLarge
+// nodes with each node's first position read from its record instead (34
+// bytes per node); and up to kHybNodes nodes and kHybEntries entries with A,
+// b and the parent weight in global memory too (10 bytes of LDS per node:
+// the graph, the states and the lists).  The later launches take only the
+// systems an earlier one flagged for their size (spill code 1; code 2 is a
+// core the one-wave CG does not take, or an entry outside the system, for
+// k_tree_solve).
 constexpr int kLdsNodes = 3840;
 constexpr int kLdsNodesLarge = 4288;
 constexpr int kLdsEntries = 8192;
