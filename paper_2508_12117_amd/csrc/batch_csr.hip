@@ -1362,6 +1362,113 @@ __global__ void k_linear_keep(const BatchBufs b, const double* theta, int64_t n,
   block_count_add(k, count);
 }
 
+// The block CG of k_tree_solve for a cycle core of 65..TB nodes held in LDS,
+// with the same arithmetic: one core node per thread in position order, the
+// same sums in the same order (each node's core entries in entry order, then
+// block_sum), y of the core in sB (b kept in a register) and p in sP.  Each
+// node's core entries (at most kWaveNb, else false) and their weights are
+// kept in registers.  order: n uint16 of scratch; cpos: TB ints of scratch;
+// red: TB / 64 doubles.
+template <int TB, class Q>
+__device__ bool block_core_cg_lds(const SolveArgs& a, const uint16_t* core, int32_t n, Q&& gpos,
+                                  const uint16_t* eoff, const uint16_t* snb, uint8_t* sst,
+                                  const double* sA, double* sB, double* sP, uint16_t* order,
+                                  int32_t* cpos, double* red) {
+  constexpr uint8_t kActiveB = 255, kCoreB = 254;  // the LDS solver's node states
+  const int t = threadIdx.x;
+  const bool on = t < n;
+  if (on) cpos[t] = gpos(core[t]);
+  __syncthreads();
+  if (on) {
+    const int32_t mine = cpos[t];
+    int32_t rank = 0;
+    for (int32_t k = 0; k < n; ++k) rank += cpos[k] < mine ? 1 : 0;
+    order[rank] = core[t];
+  }
+  __syncthreads();
+  const int32_t node = on ? order[t] : 0;
+  int32_t nbv[kWaveNb];
+  double wv[kWaveNb];
+  int over = 0;
+  {
+    const int32_t e0 = on ? eoff[node] : 0, e1 = on ? eoff[node + 1] : 0;
+    const int32_t q = on ? gpos(node) : 0;
+    int32_t x = e0;
+#pragma unroll
+    for (int k = 0; k < kWaveNb; ++k) {
+      while (x < e1 && sst[snb[x]] != kActiveB) ++x;
+      nbv[k] = -1;
+      wv[k] = 0.0;
+      if (x < e1) {
+        nbv[k] = snb[x];
+        wv[k] = a.ent[q + (x - e0)].w;
+        ++x;
+      }
+    }
+    while (x < e1 && sst[snb[x]] != kActiveB) ++x;
+    over = x < e1 ? 1 : 0;
+  }
+  if (__syncthreads_or(over)) return false;
+  const double Aq = on ? sA[node] : 1.0;
+  const double bq = on ? sB[node] : 0.0;
+  __syncthreads();
+  if (on) sB[node] = 0.0;  // y = 0
+  double bb = 0.0;
+  if (on) bb += bq * bq;
+  bb = block_sum<TB>(bb, red);
+  double rn = bb, rr = 0.0, ap = 0.0;
+  for (int pass = 0; pass < 3 && bb > 0.0; ++pass) {
+    double rz = 0.0;
+    rn = 0.0;
+    if (on) {
+      double v = bq - Aq * sB[node];
+#pragma unroll
+      for (int k = 0; k < kWaveNb; ++k)
+        if (nbv[k] >= 0) v += wv[k] * sB[nbv[k]];
+      rr = v;
+      sP[node] = v / Aq;
+      rn += v * v;
+      rz += v * v / Aq;
+    }
+    rn = block_sum<TB>(rn, red);
+    rz = block_sum<TB>(rz, red);
+    if (rn <= a.tol2 * bb) break;
+    for (int it = 0; it < a.max_iter; ++it) {
+      double pap = 0.0;
+      if (on) {
+        double v = Aq * sP[node];
+#pragma unroll
+        for (int k = 0; k < kWaveNb; ++k)
+          if (nbv[k] >= 0) v -= wv[k] * sP[nbv[k]];
+        ap = v;
+        pap += sP[node] * v;
+      }
+      pap = block_sum<TB>(pap, red);
+      const double alpha = rz / pap;
+      double rz_new = 0.0;
+      rn = 0.0;
+      if (on) {
+        sB[node] += alpha * sP[node];
+        const double rq = rr - alpha * ap;
+        rr = rq;
+        rn += rq * rq;
+        rz_new += rq * rq / Aq;
+      }
+      rn = block_sum<TB>(rn, red);
+      rz_new = block_sum<TB>(rz_new, red);
+      if (rn <= a.tol2 * bb) break;
+      const double beta = rz_new / rz;
+      rz = rz_new;
+      if (on) sP[node] = rr / Aq + beta * sP[node];
+      __syncthreads();
+    }
+  }
+  if (t == 0 && bb > 0.0 && !(rn <= a.accept2 * bb)) atomicOr(a.err, kErrSolve);
+  if (on) sst[node] = kCoreB;
+  __syncthreads();
+  return true;
+}
+
 // ---- the same solve with the system held in LDS.  A system whose cycle
 // core fits the one-wave CG is loaded once (node data, and each entry's other
 // end as an index into the system's list), peeled, solved and
@@ -1375,10 +1482,11 @@ __global__ void k_linear_keep(const BatchBufs b, const double* theta, int64_t n,
 // nodes with each node's first position read from its record instead (34
 // bytes per node); and up to kHybNodes nodes and kHybEntries entries with A,
 // b and the parent weight in global memory too (10 bytes of LDS per node:
-// the graph, the states and the lists).  The later launches take only the
-// systems an earlier one flagged for their size (spill code 1; code 2 is a
-// core the one-wave CG does not take, or an entry outside the system, for
-// k_tree_solve).
+// the graph, the states and the lists), which also runs the block CG for a
+// core of up to TB nodes.  The later launches take only the systems an
+// earlier one flagged for them (spill code 1: too large, or a core above
+// kWaveCore nodes; code 2 is a core no LDS layout takes, or an entry outside
+// the system, for k_tree_solve).
 constexpr int kLdsNodes = 3840;
 constexpr int kLdsNodesLarge = 4288;
 constexpr int kLdsEntries = 8192;
@@ -1401,6 +1509,8 @@ __global__ __launch_bounds__(TB) void k_tree_lds(SolveArgs a, int32_t min_nodes)
   __shared__ uint8_t sst[NODES], snst[NODES];
   __shared__ __attribute__((aligned(16))) uint16_t lst[2][NODES];
   __shared__ int32_t scan[TB / 64];
+  __shared__ double red[VAL_LDS ? 1 : TB / 64];
+  __shared__ int32_t cpos[VAL_LDS ? 1 : TB];
   __shared__ int flag;
   const int t = threadIdx.x;
   const int64_t sys_id = blockIdx.x;
@@ -1662,19 +1772,31 @@ __global__ __launch_bounds__(TB) void k_tree_lds(SolveArgs a, int32_t min_nodes)
   }
   __syncthreads();
 
-  // ---- 4. the cycle core: one-wave CG, or the whole system to k_tree_solve
+  // ---- 4. the cycle core: one-wave CG up to kWaveCore nodes; a larger core
+  // of up to TB nodes gets the block CG in the third layout (the first two
+  // flag it for that one, which keeps their registers free); anything else
+  // goes to k_tree_solve
   if (nl > 0) {
     if (t == 0) flag = 0;
     __syncthreads();
-    if (nl <= kWaveCore && t < 64) {
-      const bool ok = wave_core_cg_lds(a, act, nl, gpos, eoff, snb, sst, sA, sB,
-                                       (double (*)[kWaveNb])nxt,
-                                       (int32_t (*)[kWaveNb])(nxt + 4 * kWaveCore * kWaveNb));
-      if (t == 0) flag = ok ? 1 : 0;
+    if (nl <= kWaveCore) {
+      if (t < 64) {
+        const bool ok = wave_core_cg_lds(a, act, nl, gpos, eoff, snb, sst, sA, sB,
+                                         (double (*)[kWaveNb])nxt,
+                                         (int32_t (*)[kWaveNb])(nxt + 4 * kWaveCore * kWaveNb));
+        if (t == 0) flag = ok ? 1 : 0;
+      }
+    } else if (nl <= TB) {
+      if constexpr (!VAL_LDS) {
+        // p in sW: a core node has no parent weight
+        const bool ok = block_core_cg_lds<TB>(a, act, nl, gpos, eoff, snb, sst, sA, sB, sW,
+                                              nxt, cpos, red);
+        if (t == 0) flag = ok ? 1 : 0;
+      }
     }
     __syncthreads();
     if (!flag) {
-      if (t == 0) a.spill[sys_id] = 2;
+      if (t == 0) a.spill[sys_id] = (VAL_LDS && nl > kWaveCore && nl <= TB) ? 1 : 2;
       return;
     }
   }
