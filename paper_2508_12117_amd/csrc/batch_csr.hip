@@ -1621,6 +1621,7 @@ __global__ __launch_bounds__(TB) void k_tree_lds(SolveArgs a, int32_t min_nodes)
   // residuals in registers until it writes their z.
   constexpr int KE = VAL_LDS ? ENTRIES / TB : 1;
   double ew[KE], ers[KE];
+  int32_t enode[KE];  // the node of each of the thread's entries
   auto node_of = [&](int32_t x) {  // the node of entry x: last i with eoff[i] <= x
     int32_t lo = 0, hi = N - 1;
     while (lo < hi) {
@@ -1650,8 +1651,10 @@ __global__ __launch_bounds__(TB) void k_tree_lds(SolveArgs a, int32_t min_nodes)
       const int32_t x = t + u * TB;
       other[u] = 0;
       ew[u] = ers[u] = 0.0;
+      enode[u] = 0;
       if (x < total) {
         const int32_t lo = node_of(x);
+        enode[u] = lo;
         const ERec en = a.ent[gpos(lo) + (x - eoff[lo])];
         other[u] = en.nbr;
         ew[u] = en.w;
@@ -1820,7 +1823,7 @@ __global__ __launch_bounds__(TB) void k_tree_lds(SolveArgs a, int32_t min_nodes)
     for (int u = 0; u < KE; ++u) {
       const int32_t x = t + u * TB;
       if (x >= total) continue;
-      const int32_t i = node_of(x);
+      const int32_t i = enode[u];
       a.zp[gpos(i) + (x - eoff[i])] = signed_z(ers[u], ew[u], sB[i], sB[snb[x]], a.sigma, zs);
     }
   } else {
