@@ -508,7 +508,8 @@ __global__ void k_residual(CatView cat, int C, int64_t n, const double* theta, i
   const double r = b.tau[q] - (ti.T - tj.T);
   if (b.r) b.r[q] = r;
   const double s2 = cat.sigma * cat.sigma;
-  const double zs = b.sta[2 * q] >= cat.L_p ? cat.zscale_s : 1.0;
+  // S-phase scale; a catalog without S groups (L_p = L) never reads the group
+  const double zs = cat.L_p < cat.L && b.sta[2 * q] >= cat.L_p ? cat.zscale_s : 1.0;
   const int32_t pi = ti.p, pj = tj.p;
   double z;
   if (whiten == kWhitenL1) {
